@@ -1,0 +1,229 @@
+/*
+ * semlbm.h -- C ABI of the MI355X (gfx950) implementation of the two-phase spectral-element
+ * lattice Boltzmann time step of Zhao, Patel & Lee, "Spectral element lattice Boltzmann
+ * method for non-ideal gases with partial wetting boundary condition".
+ *
+ * One solve ("context") = one droplet problem on one unstructured GLL mesh.  The library
+ * advances the modified distributions f-bar of Eq. (5) through the collision of Eq. (4)
+ * and three SSP-RK3 stages of the weak-form streaming of Eqs. (6) and (12), with the
+ * chemical potential of Eq. (2) (weak Laplacian, Eq. (8)), the wetting condition of
+ * Sec. 2.2 and the flux bounce-back of Eq. (9).  All arithmetic is FP64 and every step of
+ * the time loop runs in the library's HIP kernels on the bound stream.
+ *
+ * Conventions shared by every call:
+ *   - Element-local node index n = i + (N+1) j (+ (N+1)^2 k); i runs along the first
+ *     reference direction.  Faces 0..2d-1 are xi-, xi+, eta-, eta+, zeta-, zeta+.
+ *   - Global node ids are the caller's: 0 .. n_global-1.  Every per-node array passed in
+ *     or out of the library is indexed by the caller's global id.
+ *   - Populations are ordered as follows (e_a, weight):
+ *       D2Q9  (lattice = 9):  0:(0,0) 4/9; 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 1/9;
+ *                             5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1) 1/36.
+ *       D3Q19 (lattice = 19): 0 rest 1/3; 1..6: +x,-x,+y,-y,+z,-z 1/18;
+ *                             7..18: (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),
+ *                             (1,0,-1),(-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1) 1/36.
+ *     The FP64 rest weight is 1 minus the exact sum of the others, so the weights sum to
+ *     exactly one.  c_s^2 = 1/3.
+ *   - Population arrays are [Q][n_global] (population-major), velocity arrays [d][n_global].
+ *   - Host pointers are read or written synchronously and stay owned by the caller.  Device
+ *     memory is the caller's workspace (slbm_bind); the library never frees it.
+ *   - No call throws; every call returns an slbm_status.  A context must be used from one
+ *     host thread at a time.  slbm_last_error() describes the last failure.
+ */
+#ifndef SEMLBM_H
+#define SEMLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int slbm_status;
+#define SLBM_OK 0
+#define SLBM_EINVAL (-1)    /* bad argument (sizes, ids, non-positive Jacobian, ...) */
+#define SLBM_ENOMEM (-2)    /* workspace too small or host allocation failed */
+#define SLBM_EDEVICE (-3)   /* HIP runtime error */
+#define SLBM_ESTATE (-4)    /* call out of order (e.g. step before bind) */
+#define SLBM_EDIVERGED (-5) /* non-finite state or kinetic energy above the limit */
+
+typedef struct slbm_params {
+    int lattice;      /* 9 = D2Q9 (2-D) or 19 = D3Q19 (3-D) */
+    int N;            /* GLL polynomial order: 2..16 in 2-D, 2..6 in 3-D */
+    double rho_l;     /* liquid bulk density (Appendix A: 1.0 in the paper) */
+    double rho_v;     /* vapour bulk density (Appendix A: 0.1) */
+    double delta;     /* interface thickness of Eq. (A.1) */
+    double sigma;     /* surface tension gamma; beta = 12 sigma/(delta drho^4),
+                         kappa = 3 sigma delta/(2 drho^2) solve Eqs. (A.4)-(A.5) */
+    double tau;       /* dimensionless relaxation time of Eq. (4) (0.5 in Sec. 3.3) */
+    double dt;        /* > 0: time step; otherwise dt = cfl * h_min */
+    double cfl;       /* h_min = smallest distance of neighbouring GLL nodes on element lines */
+    int ke_every;     /* slbm_step checks finiteness and KE_max every ke_every steps (0: never) */
+    double ke_limit;  /* KE_max above this (or non-finite) -> SLBM_EDIVERGED; <= 0: 1.0 */
+    uint64_t seed;    /* default seed of slbm_init_tanh noise */
+} slbm_params;
+
+typedef struct slbm_info {
+    double dt, beta, kappa, omega, h_min;
+    int64_t n_elements, n_local, n_global, n_wall_nodes, step;
+    size_t workspace_bytes;
+    int dim, Q, N;
+} slbm_info;
+
+typedef struct slbm_ctx slbm_ctx;
+
+/* Create a context from physical parameters (Appendix A, Eq. (4)).  *out is NULL on error. */
+slbm_status slbm_create(const slbm_params *p, slbm_ctx **out);
+
+/* Upload the mesh (Sec. 3: curved unstructured GLL meshes).
+ *   xyz       [E][(N+1)^d][d]  node coordinates; shared nodes carry equal coordinates
+ *                              (copies across a periodic wrap differ by the period)
+ *   gid       [E][(N+1)^d]     caller's global id of every element node; ids shared by
+ *                              several elements are summed by direct stiffness summation
+ *   wall_face [F][2]           (element, face) of every physical wall face
+ *   wall_cos  [F]              cos(theta_eq) imposed on the face (Eq. (7), Sec. 2.2)
+ *   wall_ub   [F][d] or NULL   wall velocity u_b of Eq. (9) (NULL: resting walls)
+ * The library copies everything and derives the metric terms (curl form in 3-D), the
+ * lumped mass, wall normals and weights, and the time step.  Errors: SLBM_EINVAL for bad
+ * sizes/ids or a non-positive Jacobian, SLBM_ESTATE if already bound. */
+slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, const int32_t *gid,
+                          int64_t n_global, int64_t n_wall_faces, const int32_t *wall_face,
+                          const double *wall_cos, const double *wall_ub);
+
+/* Device bytes needed by slbm_bind (valid after slbm_set_mesh; 0 before). */
+size_t slbm_workspace_bytes(const slbm_ctx *c);
+
+/* Bind caller-allocated device memory (256-byte aligned, >= slbm_workspace_bytes) and a
+ * HIP stream (hipStream_t; NULL = default stream).  Uploads the geometry tables and
+ * returns after they are resident.  The memory must outlive the context. */
+slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream);
+
+/* Initial condition of Eqs. (A.1)/(A.8)-(A.9): rho = (rl+rv)/2 - (rl-rv)/2 tanh(2 s/delta),
+ * s = |x - x0| - R (liquid inside), u = 0, f-bar = t_a rho; plus noise_amp (2U-1) per
+ * global node with U = (SplitMix64(seed xor gid) >> 11) 2^-53.  Node coordinates are those
+ * of the lowest local copy.  x0 has d entries.  Resets the step counter. */
+slbm_status slbm_init_tanh(slbm_ctx *c, const double *x0, double R, double noise_amp,
+                           uint64_t seed);
+
+/* rho [n_global] (host): f-bar = t_a rho, u = 0.  Resets the step counter. */
+slbm_status slbm_set_rho(slbm_ctx *c, const double *rho);
+
+/* Checkpoint: f-bar [Q][n_global] (host) and the step counter. */
+slbm_status slbm_get_state(slbm_ctx *c, double *f, int64_t *step);
+slbm_status slbm_set_state(slbm_ctx *c, const double *f, int64_t step);
+
+/* Advance n time steps (collision + 3 SSP-RK3 streaming stages each).  Asynchronous on the
+ * bound stream unless ke_every > 0, in which case it synchronises every ke_every steps
+ * and returns SLBM_EDIVERGED on a non-finite or too-large kinetic energy. */
+slbm_status slbm_step(slbm_ctx *c, int64_t n);
+
+/* Queries (synchronising).  rho [n_global] by Eq. (10); u [d][n_global] by Eq. (11);
+ * ke_max = max over nodes of rho |u|^2 / 2; mass = sum of lumped mass times rho. */
+slbm_status slbm_get_rho(slbm_ctx *c, double *rho);
+slbm_status slbm_get_u(slbm_ctx *c, double *u);
+slbm_status slbm_kinetic_energy(slbm_ctx *c, double *ke_max, double *mass);
+
+/* Geometric contact angle (Sec. 3.1): mid-density crossings along element lines, points
+ * within 2 delta of the wall dropped, algebraic (Kasa) circle/sphere fit, intersection
+ * angle with the wall measured through the liquid. */
+typedef struct slbm_wall_geom {
+    int kind;          /* 0 = plane, 1 = circle (2-D), 2 = sphere (3-D) */
+    double point[3];   /* plane: a point of it; circle/sphere: the centre */
+    double normal[3];  /* plane: unit normal pointing out of the fluid */
+    double radius;     /* circle/sphere radius */
+} slbm_wall_geom;
+slbm_status slbm_contact_angle(slbm_ctx *c, const slbm_wall_geom *w, double *theta_deg);
+
+slbm_status slbm_get_info(const slbm_ctx *c, slbm_info *info);
+const char *slbm_last_error(const slbm_ctx *c);
+void slbm_destroy(slbm_ctx *c);
+
+/* Operator entry points, each one kernel pass of the time step on host data (they use the
+ * context's workspace and leave the state untouched):
+ *   slbm_op_mu:      mu [n_global] of Eq. (2) with the weak Laplacian of Eq. (8) and the
+ *                    wetting boundary integral of Sec. 2.2, from rho [n_global]
+ *   slbm_op_grad:    lumped-mass average of element gradients, [d][n_global], of phi
+ *   slbm_op_stream:  L [Q][n_global], the assembled right-hand side of Eqs. (6)/(12) with
+ *                    the flux of Eq. (9) (L_0 = 0), from g [Q][n_global], rho, mu
+ *   slbm_op_collide: f* [Q][n_global] of Eq. (4) from f, rho, grad rho, grad mu
+ * Errors as for slbm_step; all of them synchronise. */
+slbm_status slbm_op_mu(slbm_ctx *c, const double *rho, double *mu);
+slbm_status slbm_op_grad(slbm_ctx *c, const double *phi, double *grad);
+slbm_status slbm_op_stream(slbm_ctx *c, const double *g, const double *rho, const double *mu,
+                           double *L);
+slbm_status slbm_op_collide(slbm_ctx *c, const double *f, const double *rho, const double *grho,
+                            const double *gmu, double *fstar);
+
+/* ------------------------------------------------------------------------------------ */
+/* Batching: many bound contexts (different meshes, N, dt) advanced together.  Each     */
+/* kernel of the step covers every member's elements or nodes in one launch, grouped by */
+/* (lattice, N); members keep their own workspace.                                      */
+/* ------------------------------------------------------------------------------------ */
+typedef struct slbm_batch slbm_batch;
+slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out);
+/* Add a bound context (must be bound to the batch's stream). */
+slbm_status slbm_batch_add(slbm_batch *b, slbm_ctx *c);
+slbm_status slbm_batch_remove(slbm_batch *b, slbm_ctx *c);
+int slbm_batch_size(const slbm_batch *b);
+/* Advance every member n steps (asynchronous). */
+slbm_status slbm_batch_step(slbm_batch *b, int64_t n);
+/* Per-member KE_max and mass into ke[size], mass[size] (member order of insertion). */
+slbm_status slbm_batch_kinetic_energy(slbm_batch *b, double *ke, double *mass);
+void slbm_batch_destroy(slbm_batch *b);
+
+/* ------------------------------------------------------------------------------------ */
+/* Serving: a continuous-batching request loop for contact-angle solves.                */
+/* ------------------------------------------------------------------------------------ */
+typedef struct slbm_server_cfg {
+    void *arena;          /* device memory the server sub-allocates workspaces from */
+    size_t arena_bytes;
+    void *hip_stream;     /* stream of every solve */
+    int max_slots;        /* concurrent solves */
+    int check_every;      /* KE check cadence in steps (paper: KE_max monitored in time) */
+    double ke_stop;       /* retire when KE_max < ke_stop (e.g. 1e-20) */
+    int64_t max_steps;    /* or after this many steps */
+} slbm_server_cfg;
+
+typedef struct slbm_request {
+    slbm_params params;
+    int64_t E;
+    const double *xyz;       /* copied at submit */
+    const int32_t *gid;
+    int64_t n_global;
+    int64_t n_wall_faces;
+    const int32_t *wall_face;
+    const double *wall_cos;
+    const double *wall_ub;   /* may be NULL */
+    double x0[3];
+    double R;
+    double noise_amp;
+    slbm_wall_geom wall;     /* for the contact angle at retirement */
+} slbm_request;
+
+typedef struct slbm_result {
+    slbm_status status;      /* SLBM_OK, SLBM_EDIVERGED, ... ; 1 = still pending */
+    double theta_deg;
+    double ke_max;
+    int64_t steps;
+    double t_arrive, t_admit, t_done; /* seconds on the server's clock */
+} slbm_result;
+
+typedef struct slbm_server slbm_server;
+slbm_status slbm_server_create(const slbm_server_cfg *cfg, slbm_server **out);
+/* Queue a request (inputs are copied); returns its id.  t_arrive is stamped now. */
+slbm_status slbm_server_submit(slbm_server *s, const slbm_request *r, uint64_t *id);
+/* Advance the server by one scheduling round: admit queued requests that fit (slots and
+ * arena bytes), run check_every steps of all active solves as one batch, retire finished
+ * ones.  Returns the number of active + queued requests in *pending. */
+slbm_status slbm_server_tick(slbm_server *s, int *pending);
+/* Result of a request (status 1 while pending). */
+slbm_status slbm_server_poll(slbm_server *s, uint64_t id, slbm_result *out);
+/* Tick until every submitted request is finished. */
+slbm_status slbm_server_drain(slbm_server *s);
+double slbm_server_clock(const slbm_server *s);
+void slbm_server_destroy(slbm_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEMLBM_H */

@@ -1,0 +1,221 @@
+"""Named, seeded synthetic workloads.
+
+Each case bundles a mesh from :mod:`synth.meshes` with the physical
+parameters, the droplet placement and the run length.  The five workloads of
+the benchmark suite are ``c1`` .. ``c5``; the ``small_*`` cases are shrunken
+versions with the same structure (walls, jitter, curvature) that a plain CPU
+implementation finishes in seconds.
+
+Droplet placements on walls follow Young's law for the imposed angle theta
+(measured through the liquid): a cap of radius R on a flat wall has its
+centre at distance -R cos(theta) from the wall; on a circle/sphere of radius
+Rw the centre distance d solves d^2 = Rw^2 + R^2 - 2 R Rw cos(theta).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import meshes
+
+LATTICE_D2Q9 = 9
+LATTICE_D3Q19 = 19
+
+
+@dataclass
+class Case:
+    name: str
+    mesh: meshes.Mesh
+    lattice: int
+    rho_l: float = 1.0
+    rho_v: float = 0.1
+    delta: float = 4.0
+    sigma: float = 0.01
+    tau: float = 0.5
+    cfl: float = 0.4
+    dt: float = 0.0               # > 0 overrides cfl
+    x0: tuple = (0.0, 0.0)
+    R: float = 16.0
+    noise: float = 0.0
+    seed: int = 1
+    steps: int = 1000
+    ke_every: int = 100
+    wall_geom: dict = field(default_factory=dict)
+    theta_deg: float | None = None
+
+    @property
+    def N(self) -> int:
+        return self.mesh.N
+
+    @property
+    def dim(self) -> int:
+        return self.mesh.dim
+
+
+def young_center_distance(Rw: float, R: float, theta_deg: float) -> float:
+    """Distance between wall-circle/sphere centre and droplet centre (Young cap)."""
+    c = math.cos(math.radians(theta_deg))
+    return math.sqrt(Rw * Rw + R * R - 2.0 * R * Rw * c)
+
+
+def c1() -> Case:
+    """D2Q9 isolated droplet: periodic 64x64 box, 8x8 quads, N=4, R=16, 1e-4 noise."""
+    m = meshes.box2d(8, 8, 4, 64.0, 64.0, periodic=(True, True), name="c1")
+    return Case("c1", m, LATTICE_D2Q9, x0=(32.0, 32.0), R=16.0, noise=1e-4, seed=1,
+                steps=1000)
+
+
+def c2(theta_deg: float = 60.0) -> Case:
+    """D2Q9 sessile droplet on a flat wall: 128x64, 32x16 jittered quads, N=6."""
+    cb = math.cos(math.radians(theta_deg))
+    m = meshes.box2d(32, 16, 6, 128.0, 64.0, periodic=(False, False), jitter=0.2, seed=2,
+                     cos_theta={"bottom": cb}, name="c2")
+    # cap radius 32 (half the wall length): at 60 deg its height is 16 = 4 delta, so
+    # the contact-angle fit still has an arc clear of the 2-delta wall layer
+    R = 32.0
+    return Case("c2", m, LATTICE_D2Q9, x0=(64.0, -R * cb), R=R, seed=2, steps=10000,
+                wall_geom=dict(kind="plane", point=(0.0, 0.0), normal=(0.0, -1.0)),
+                theta_deg=theta_deg)
+
+
+def c3(theta_deg: float = 90.0, n_az: int = 128, n_rad: int = 16, N: int = 8) -> Case:
+    """D2Q9 droplet on a cylinder (R=40) in a 256^2 box: O-grid of 2048 curved quads, N=8."""
+    Rc = 40.0
+    R = 40.0
+    cc = math.cos(math.radians(theta_deg))
+    m = meshes.ogrid2d(n_az, n_rad, N, center=(128.0, 128.0), Rc=Rc, half_width=128.0,
+                       grading=4.0, jitter=0.1, seed=3, cos_cyl=cc, cos_box=0.0, name="c3")
+    d = young_center_distance(Rc, R, theta_deg)
+    return Case("c3", m, LATTICE_D2Q9, x0=(128.0, 128.0 + d), R=R, seed=3, steps=20000,
+                wall_geom=dict(kind="circle", center=(128.0, 128.0), radius=Rc),
+                theta_deg=theta_deg)
+
+
+def c4(n_t: int = 20, n_rad: int = 10, N: int = 5, theta_deg: float = 90.0) -> Case:
+    """D3Q19 droplet (R=20) on a sphere (R=30): cubed-sphere shell in a 128^3 box, N=5."""
+    Rs, R = 30.0, 20.0
+    cs = math.cos(math.radians(theta_deg))
+    m = meshes.cubed_sphere3d(n_t, n_rad, N, center=(64.0, 64.0, 64.0), Rs=Rs,
+                              half_width=64.0, grading=3.0, jitter=0.1, seed=4,
+                              cos_sphere=cs, cos_box=0.0, name="c4")
+    d = young_center_distance(Rs, R, theta_deg)
+    return Case("c4", m, LATTICE_D3Q19, x0=(64.0, 64.0, 64.0 + d), R=R, seed=4, steps=5000,
+                wall_geom=dict(kind="sphere", center=(64.0, 64.0, 64.0), radius=Rs),
+                theta_deg=theta_deg)
+
+
+# ---------------------------------------------------------------------------
+# small variants for CPU-speed checks (same structure, fewer nodes)
+# ---------------------------------------------------------------------------
+
+def small_flat(theta_deg: float = 60.0, nx: int = 8, ny: int = 4, N: int = 4,
+               jitter: float = 0.2, seed: int = 12, Lx: float = 64.0, Ly: float = 32.0,
+               R: float = 12.0) -> Case:
+    """Flat-wall sessile cap on a jittered walled box (default 64x32)."""
+    cb = math.cos(math.radians(theta_deg))
+    m = meshes.box2d(nx, ny, N, Lx, Ly, periodic=(False, False), jitter=jitter, seed=seed,
+                     cos_theta={"bottom": cb}, name="small_flat")
+    return Case("small_flat", m, LATTICE_D2Q9, x0=(0.5 * Lx, -R * cb), R=R, seed=seed,
+                steps=200, wall_geom=dict(kind="plane", point=(0.0, 0.0), normal=(0.0, -1.0)),
+                theta_deg=theta_deg)
+
+
+def small_cyl(theta_deg: float = 90.0, n_az: int = 16, n_rad: int = 4, N: int = 5) -> Case:
+    """Cylinder O-grid (R=12) in a 80x80 box with a Young cap."""
+    Rc, R = 12.0, 12.0
+    cc = math.cos(math.radians(theta_deg))
+    m = meshes.ogrid2d(n_az, n_rad, N, center=(40.0, 40.0), Rc=Rc, half_width=40.0,
+                       grading=2.0, jitter=0.1, seed=13, cos_cyl=cc, cos_box=0.0,
+                       name="small_cyl")
+    d = young_center_distance(Rc, R, theta_deg)
+    return Case("small_cyl", m, LATTICE_D2Q9, x0=(40.0, 40.0 + d), R=R, seed=13, steps=100,
+                wall_geom=dict(kind="circle", center=(40.0, 40.0), radius=Rc),
+                theta_deg=theta_deg)
+
+
+def small_sphere(theta_deg: float = 90.0, n_t: int = 2, n_rad: int = 2, N: int = 4) -> Case:
+    """Cubed-sphere shell (R=10) in a 48^3 box with a Young cap, D3Q19."""
+    Rs, R = 10.0, 8.0
+    cs = math.cos(math.radians(theta_deg))
+    m = meshes.cubed_sphere3d(n_t, n_rad, N, center=(24.0, 24.0, 24.0), Rs=Rs,
+                              half_width=24.0, grading=2.0, jitter=0.1, seed=14,
+                              cos_sphere=cs, cos_box=0.0, name="small_sphere")
+    d = young_center_distance(Rs, R, theta_deg)
+    return Case("small_sphere", m, LATTICE_D3Q19, x0=(24.0, 24.0, 24.0 + d), R=R, seed=14,
+                steps=20, wall_geom=dict(kind="sphere", center=(24.0, 24.0, 24.0), radius=Rs),
+                theta_deg=theta_deg)
+
+
+def small_box3d(N: int = 3, n: int = 3, periodic=(True, True, True), jitter: float = 0.0) -> Case:
+    """Periodic (or walled) cube of side 24 with a centred droplet, D3Q19."""
+    m = meshes.box3d(n, n, n, N, (24.0, 24.0, 24.0), periodic=periodic, jitter=jitter, seed=15,
+                     name="small_box3d")
+    return Case("small_box3d", m, LATTICE_D3Q19, x0=(12.0, 12.0, 12.0), R=7.0, noise=1e-4,
+                seed=15, steps=20)
+
+
+CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}
+
+
+def sizes(case: Case) -> dict:
+    m = case.mesh
+    return dict(E=m.E, N=m.N, n_local=m.n_local, n_global=m.n_global, Q=case.lattice,
+                walls=int(m.wall_face.shape[0]))
+
+
+def request_stream(n_req: int = 256, seed: int = 5):
+    """Serving workload: seeded list of 2-D droplet requests.
+
+    Each entry: geometry 'flat' or 'cyl' (p = 1/2), element counts from the
+    allowed list, N in {4,6,8}, theta ~ U[30,150] deg, R ~ U[10,30] clipped so
+    the cap stays clear of the other walls, and a Poisson arrival time at unit
+    mean rate (scale it to the wanted rate).
+    """
+    rng = np.random.default_rng(seed)
+    sizes_ = [(8, 8), (16, 8), (16, 16), (32, 16), (32, 32), (64, 32)]
+    out = []
+    t = 0.0
+    for k in range(n_req):
+        t += rng.exponential(1.0)
+        geom = "flat" if rng.random() < 0.5 else "cyl"
+        nx, ny = sizes_[rng.integers(len(sizes_))]
+        N = int(rng.choice([4, 6, 8]))
+        theta = float(rng.uniform(30.0, 150.0))
+        R = float(rng.uniform(10.0, 30.0))
+        out.append(dict(id=k, t_arrive=t, geom=geom, nx=nx, ny=ny, N=N, theta_deg=theta, R=R))
+    return out
+
+
+def request_case(req: dict, delta: float = 4.0) -> Case:
+    """Build the Case of one serving request (see :func:`request_stream`)."""
+    theta = req["theta_deg"]
+    c = math.cos(math.radians(theta))
+    R = req["R"]
+    N = req["N"]
+    nx, ny = req["nx"], req["ny"]
+    if req["geom"] == "flat":
+        h = 8.0
+        Lx, Ly = nx * h, ny * h
+        # keep the cap clear of the side and top walls by 2 delta
+        Rmax_x = (0.5 * Lx - 2.0 * delta)
+        top = Ly - 2.0 * delta
+        Rmax_y = top / (1.0 - c) if c < 1.0 else top
+        R = min(R, Rmax_x, Rmax_y)
+        m = meshes.box2d(nx, ny, N, Lx, Ly, periodic=(False, False), jitter=0.0,
+                         cos_theta={"bottom": c}, name="req_flat")
+        return Case(f"req{req['id']}", m, LATTICE_D2Q9, delta=delta, x0=(0.5 * Lx, -R * c),
+                    R=R, seed=1000 + req["id"], steps=50000,
+                    wall_geom=dict(kind="plane", point=(0.0, 0.0), normal=(0.0, -1.0)),
+                    theta_deg=theta)
+    Rc = R
+    half = Rc + 2.0 * R + 3.0 * delta
+    n_az = 4 * max(1, nx // 2)
+    n_rad = max(1, ny // 2)
+    m = meshes.ogrid2d(n_az, n_rad, N, center=(half, half), Rc=Rc, half_width=half,
+                       grading=2.0, jitter=0.0, cos_cyl=c, cos_box=0.0, name="req_cyl")
+    d = young_center_distance(Rc, R, theta)
+    return Case(f"req{req['id']}", m, LATTICE_D2Q9, delta=delta, x0=(half, half + d), R=R,
+                seed=1000 + req["id"], steps=50000,
+                wall_geom=dict(kind="circle", center=(half, half), radius=Rc), theta_deg=theta)

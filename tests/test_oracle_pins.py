@@ -1,0 +1,438 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed-form
+values, exactness of polynomial operations, conservation laws, exact
+continuum equilibria, convergence rates, or the published SplitMix64 vector.
+They are chosen so that a plausible mistake (a dropped factor, a flipped sign,
+a transposed operand, a wrong coefficient) fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, load
+from oracle.contact import contact_angle, fit_circle, interface_points
+from synth import cases, meshes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _case(mesh, lattice=None, **kw):
+    lattice = lattice or (9 if mesh.dim == 2 else 19)
+    return cases.Case("t", mesh, lattice, **kw)
+
+
+# ---------------------------------------------------------------------------
+# GLL tables (Deville, Fischer & Mund ch. 2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 8, 11, 16])
+def test_gll_differentiation_exact_on_polynomials(N):
+    o = Oracle(_case(meshes.box2d(1, 1, N, 2.0, 2.0)))
+    x, w, D = o.gll()
+    for k in range(1, N + 1):
+        exact = k * x ** (k - 1)
+        assert np.abs(D @ x ** k - exact).max() <= 1e-12 * max(1.0, np.abs(exact).max()) * N * N
+    # quadrature exact to degree 2N-1
+    for k in range(2 * N):
+        exact = 2.0 / (k + 1) if k % 2 == 0 else 0.0
+        assert abs(np.dot(w, x ** k) - exact) < 1e-14 * (N + 1)
+    # summation-by-parts: W D + D^T W = diag(-1, 0, ..., 0, 1)
+    B = np.diag(w) @ D + D.T @ np.diag(w)
+    E = np.zeros_like(B)
+    E[0, 0], E[N, N] = -1.0, 1.0
+    assert np.abs(B - E).max() < 1e-13 * N
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 6, 9, 12])
+def test_gll_nodes_are_legendre_derivative_roots(N):
+    from numpy.polynomial import legendre as L
+    o = Oracle(_case(meshes.box2d(1, 1, N, 2.0, 2.0)))
+    x, w, _ = o.gll()
+    c = np.zeros(N + 1)
+    c[N] = 1.0
+    r = np.sort(np.real(L.legroots(L.legder(c))))
+    assert np.abs(x[1:-1] - r).max() < 1e-14
+    assert x[0] == -1.0 and x[-1] == 1.0
+
+
+def test_gll_closed_forms():
+    g = json.load(open(os.path.join(GOLDEN, "gll_closed_forms.json")))
+    for Ns, ref in g.items():
+        N = int(Ns)
+        o = Oracle(_case(meshes.box2d(1, 1, N, 2.0, 2.0)))
+        x, w, _ = o.gll()
+        assert np.abs(x - np.array(ref["x"])).max() < 2e-16
+        assert np.abs(w - np.array(ref["w"])).max() < 4e-16
+
+
+# ---------------------------------------------------------------------------
+# lattices and free-energy parameters
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("Q", [9, 19])
+def test_lattice_moments(Q):
+    mk = cases.c1 if Q == 9 else cases.small_box3d
+    o = Oracle(mk())
+    ev, tw, opp = o.lattice()
+    d = 2 if Q == 9 else 3
+    e = ev[:, :d]
+    cs2 = 1.0 / 3.0
+    from fractions import Fraction
+    assert sum(Fraction(t) for t in tw) == 1          # exact in FP64 (no mass bleed)
+    assert np.abs(tw @ e).max() == 0.0
+    assert np.abs(np.einsum("a,ai,aj->ij", tw, e, e) - cs2 * np.eye(d)).max() < 3e-16
+    assert np.abs(np.einsum("a,ai,aj,ak->ijk", tw, e, e, e)).max() < 1e-17
+    I = np.eye(d)
+    iso4 = cs2 ** 2 * (np.einsum("ij,kl->ijkl", I, I) + np.einsum("ik,jl->ijkl", I, I)
+                        + np.einsum("il,jk->ijkl", I, I))
+    assert np.abs(np.einsum("a,ai,aj,ak,al->ijkl", tw, e, e, e, e) - iso4).max() < 3e-16
+    assert np.all(e[opp] == -e)
+    # paper's weights (Sec. 2.1 for D2Q9): rest 4/9, axes 1/9, diagonals 1/36
+    if Q == 9:
+        assert abs(tw[0] - 4 / 9) < 1e-16 and np.all(tw[1:5] == 1 / 9) and np.all(tw[5:] == 1 / 36)
+    else:
+        assert abs(tw[0] - 1 / 3) < 1e-16 and np.all(tw[1:7] == 1 / 18) and np.all(tw[7:] == 1 / 36)
+
+
+def test_parameters_reproduce_surface_tension():
+    """kappa, beta of (A.4) with gamma of (A.5): gamma = sigma; config-1 values."""
+    for (sigma, delta, rl, rv) in [(0.01, 4.0, 1.0, 0.1), (0.003, 3.0, 1.0, 0.001), (0.05, 5.0, 2.0, 0.5)]:
+        c = cases.c1()
+        c.sigma, c.delta, c.rho_l, c.rho_v = sigma, delta, rl, rv
+        o = Oracle(c)
+        dr = rl - rv
+        assert abs(o.kappa - o.beta * delta ** 2 * dr ** 2 / 8.0) < 1e-15 * o.kappa
+        gamma = dr ** 3 / 6.0 * math.sqrt(2.0 * o.kappa * o.beta)
+        assert abs(gamma - sigma) < 1e-15 * sigma
+    o = Oracle(cases.c1())
+    assert abs(o.beta - 0.0457247370827618) < 1e-15
+    assert abs(o.kappa - 2.0 / 27.0) < 1e-16
+    # dt = CFL h_min, h_min of an 8-wide N=4 element: 8 (1 - sqrt(3/7)) / 2
+    assert abs(o.hmin - 4.0 * (1.0 - math.sqrt(3.0 / 7.0))) < 1e-13
+    assert abs(o.dt - 0.4 * o.hmin) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# collision (Eq. 4, A.2, A.6-A.7)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mk", [cases.c1, cases.small_box3d])
+def test_collision_conserves_mass_and_momentum(mk):
+    c = mk()
+    o = Oracle(c)
+    rng = np.random.default_rng(3)
+    ev, tw, _ = o.lattice()
+    d = c.dim
+    e = ev[:, :d]
+    rho = 0.1 + 0.9 * rng.random(o.Ng)
+    u = 0.05 * rng.standard_normal((d, o.Ng))
+    eu = e @ u
+    f = rho * tw[:, None] * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (u * u).sum(0))
+    f += 1e-3 * rng.standard_normal(f.shape) * tw[:, None]
+    rho = f.sum(0)
+    grho = 0.1 * rng.standard_normal((d, o.Ng))
+    gmu = 0.1 * rng.standard_normal((d, o.Ng))
+    fs = o.collide(f, rho, grho, gmu)
+    assert np.abs(fs.sum(0) - f.sum(0)).max() < 1e-15
+    assert np.abs(e.T @ fs - e.T @ f).max() < 1e-15
+    # the higher-order force F** carries no mass and no momentum but changes the stress
+    # by dt (u F + F u) at tau = 1/2 (full relaxation): Pi(f*) = Pi_eq + dt/2 (uF + Fu)
+    F = grho / 3.0 - rho * gmu
+    uu = (e.T @ f) / rho
+    Pi = np.einsum("ai,aj,ag->ijg", e, e, fs)
+    Pi_eq = rho * (np.eye(d)[:, :, None] / 3.0 + uu[:, None, :] * uu[None, :, :])
+    corr = 0.5 * o.dt * (uu[:, None, :] * F[None, :, :] + F[:, None, :] * uu[None, :, :])
+    assert abs(o.omega - 1.0) < 1e-16
+    assert np.abs(Pi - Pi_eq - corr).max() < 1e-14
+
+
+def test_collision_rest_state_is_fixed_point():
+    o = Oracle(cases.c1())
+    ev, tw, _ = o.lattice()
+    rho = 0.3 + np.linspace(0, 0.5, o.Ng)
+    f = tw[:, None] * rho
+    z = np.zeros((2, o.Ng))
+    fs = o.collide(f, rho, np.ones((2, o.Ng)), np.ones((2, o.Ng)))  # u = 0 => F** = 0
+    assert np.abs(fs - f).max() < 1e-16
+
+
+# ---------------------------------------------------------------------------
+# chemical potential and weak Laplacian (Eq. 2, Eq. 8)
+# ---------------------------------------------------------------------------
+
+def test_weak_laplacian_exact_for_quadratics():
+    """lap(x^2 + y^2) = 4 at every node off the walls (natural BC only enters at walls)."""
+    m = meshes.box2d(4, 3, 5, 32.0, 24.0, periodic=(False, False))
+    o = Oracle(_case(m))
+    X = m.first_copy_coords()
+    lap = o.lap(X[:, 0] ** 2 + 0.5 * X[:, 1] ** 2 - 3 * X[:, 0] * X[:, 1], with_wall=False)
+    off = (X[:, 0] > 1e-9) & (X[:, 0] < 32 - 1e-9) & (X[:, 1] > 1e-9) & (X[:, 1] < 24 - 1e-9)
+    assert np.abs(lap[off] - 3.0).max() < 1e-10
+
+
+def test_weak_laplacian_3d_trilinear_exact_and_curved_convergent():
+    """Jittered trilinear hexes: lap(x^2 + y z) = 2 off the walls to rounding.  Curved
+    (cubed-sphere) hexes with curl-form metrics: lap of a linear field -> 0 spectrally."""
+    c = cases.small_box3d(periodic=(False, False, False), jitter=0.2)
+    o = Oracle(c)
+    X = c.mesh.first_copy_coords()
+    lap = o.lap(X[:, 0] ** 2 + X[:, 1] * X[:, 2], with_wall=False)
+    off = np.all((X > 1e-9) & (X < 24 - 1e-9), axis=1)
+    assert np.abs(lap[off] - 2.0).max() < 1e-10
+    errs = []
+    for N in [3, 5, 7]:
+        cs = cases.small_sphere(N=N)
+        o = Oracle(cs)
+        X = cs.mesh.first_copy_coords()
+        lap = o.lap(2.0 * X[:, 0] - X[:, 1] + 0.5 * X[:, 2], with_wall=False)
+        wl, _, _ = o.wall_entries()
+        onwall = np.zeros(o.Ng, bool)
+        onwall[cs.mesh.gid.reshape(-1)[wl]] = True
+        errs.append(np.abs(lap[~onwall]).max())
+    assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 8 and errs[2] < 1e-3
+
+
+def test_weak_laplacian_periodic_spectral():
+    """lap(sin(kx) cos(2ky)) = -5k^2 (...) on a jittered periodic mesh, spectrally in N."""
+    L = 32.0
+    errs = []
+    for N in [4, 6, 8, 10]:
+        m = meshes.box2d(4, 4, N, L, L, periodic=(True, True), jitter=0.15, seed=5)
+        o = Oracle(_case(m))
+        X = m.first_copy_coords()
+        k = 2 * np.pi / L
+        phi = np.sin(k * X[:, 0]) * np.cos(2 * k * X[:, 1])
+        errs.append(np.abs(o.lap(phi) + 5 * k * k * phi).max() / (5 * k * k))
+    assert all(b < a / 5 for a, b in zip(errs, errs[1:])) and errs[-1] < 1e-5
+
+
+def test_mu_vanishes_on_flat_tanh_interface():
+    """(A.1) with (A.4) is an exact continuum equilibrium: mu -> 0 spectrally.  With the
+    factor 1 of Eq. (2) as printed, mu would stay at -mu0/2 = O(beta drho^3)."""
+    errs = []
+    for N in [4, 6, 8, 10]:
+        m = meshes.box2d(8, 2, N, 64.0, 16.0, periodic=(True, True))
+        o = Oracle(_case(m))
+        X = m.first_copy_coords()
+        rho = 0.55 - 0.45 * np.tanh(2 * (np.abs(X[:, 0] - 32.0) - 16.0) / 4.0)
+        errs.append(np.abs(o.mu(rho)).max())
+    scale = o.beta * 0.9 ** 3
+    assert all(b < a / 3 for a, b in zip(errs, errs[1:]))
+    assert errs[2] < 1.5e-3 * scale and errs[3] < 5e-4 * scale
+
+
+@pytest.mark.parametrize("theta", [45.0, 60.0, 120.0])
+def test_wetting_inclined_interface_equilibrium(theta):
+    """A planar tanh interface meeting the wall at theta (through the liquid) is an exact
+    equilibrium under n.grad(rho) = cos(theta) sqrt(2 e0/kappa) with n the outward
+    normal: discrete mu at wall nodes stays at the interior level.  The opposite sign
+    convention gives wall values O(0.1)."""
+    th = math.radians(theta)
+    ni = np.array([math.sin(th), math.cos(th)])
+
+    def run(sign):
+        cb = sign * math.cos(th)
+        m = meshes.box2d(32, 8, 6, 128.0, 32.0, periodic=(False, False),
+                         cos_theta={"bottom": cb, "top": -cb})
+        o = Oracle(_case(m))
+        X = m.first_copy_coords()
+        d = (X[:, 0] - 64.0) * ni[0] + X[:, 1] * ni[1]
+        mu = o.mu(0.55 - 0.45 * np.tanh(2 * d / 4.0))
+        wall = (X[:, 1] < 1e-9) | (X[:, 1] > 32 - 1e-9)
+        return np.abs(mu[wall]).max(), np.abs(mu[~wall]).max()
+
+    w, i = run(+1)
+    assert w < 2.0 * i and w < 5e-5
+    w_bad, _ = run(-1)
+    assert w_bad > 1e3 * w
+
+
+# ---------------------------------------------------------------------------
+# streaming operator and SSP-RK3 (Eqs. 5-6, Sec. 2.1), pure advection mode
+# ---------------------------------------------------------------------------
+
+def _advect(N, nsteps, L=16.0, ne=4, jitter=0.2):
+    m = meshes.box2d(ne, ne, N, L, L, periodic=(True, True), jitter=jitter, seed=7)
+    o = Oracle(_case(m, dt=L / nsteps), mode=1)
+    X = m.first_copy_coords()
+    phi = 2.0 + np.sin(2 * np.pi * X[:, 0] / L) * np.cos(2 * np.pi * X[:, 1] / L) \
+        + 0.3 * np.cos(4 * np.pi * (X[:, 0] + X[:, 1]) / L)
+    f0 = np.tile(phi, (9, 1))
+    o.set_f(f0)
+    o.step(nsteps)
+    return np.abs(o.get_f() - f0).max()
+
+
+@pytest.mark.slow
+def test_advection_spectral_in_N_and_third_order_in_time():
+    """Every population returns after one period T = L (integer lattice speeds)."""
+    e4, e6, e8 = _advect(4, 2000), _advect(6, 2000), _advect(8, 2000)
+    assert e6 < e4 / 20 and e8 < e6 / 20 and e8 < 2e-4
+    a, b = _advect(10, 400), _advect(10, 800)
+    assert 6.0 < a / b < 10.0  # 2^3 = 8
+
+
+def test_stream_op_of_rest_state_vanishes_with_walls():
+    """Well-balanced form: at u = 0 and uniform mu, e.grad(f - t rho) = 0 and the flux
+    bounce-back terms cancel exactly (f_a = f_b, u_b = 0)."""
+    c = cases.small_flat()
+    o = Oracle(c)
+    ev, tw, _ = o.lattice()
+    X = c.mesh.first_copy_coords()
+    rho = 0.55 - 0.45 * np.tanh((X[:, 0] - 30) / 7.0)
+    g = tw[:, None] * rho
+    L = o.stream_op(g, rho, np.full(o.Ng, 0.123))
+    assert np.abs(L).max() < 1e-15
+
+
+def test_flux_bounce_back_moving_wall_momentum_input():
+    """Eq. (9) with a moving wall: the penalty's momentum input along the wall equals
+    -2 sum_in t_a (n.e_a)(e_a.u_b) e_a rho s / cs^2 summed over wall nodes."""
+    m = meshes.box2d(4, 2, 4, 16.0, 8.0, periodic=(True, False),
+                     ub={"top": (0.01, 0.0)})
+    o = Oracle(_case(m))
+    ev, tw, opp = o.lattice()
+    g = tw[:, None] * np.ones(o.Ng)
+    L = o.stream_op(g, np.ones(o.Ng), np.zeros(o.Ng))
+    MA = o.mass_matrix()
+    P = (MA * (ev[:, :2].T @ L)).sum(1)
+    # top wall length 16, outward normal +y: incoming are e_y = -1 (a = 4, 7, 8)
+    expected = 0.0
+    for a in (4, 7, 8):
+        expected += -2.0 * 3.0 * tw[a] * (-1.0) * (ev[a, 0] * 0.01) * ev[a, 0] * 16.0
+    assert abs(P[0] - expected) < 1e-14 and abs(P[1]) < 1e-14
+    assert abs((MA * L.sum(0)).sum()) < 1e-14  # tangential wall motion adds no mass
+
+
+# ---------------------------------------------------------------------------
+# full step: conservation, rest state, Laplace law, Young caps
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mk,n", [(cases.c1, 200), (cases.small_flat, 200),
+                                  (cases.small_cyl, 40), (cases.small_sphere, 6)])
+def test_mass_conserved_to_machine_precision(mk, n):
+    c = mk()
+    o = Oracle(c)
+    o.init_tanh()
+    _, m0 = o.diag()
+    o.step(n)
+    _, m1 = o.diag()
+    assert abs(m1 - m0) / m0 < 1e-13
+
+
+def test_rest_state_stationary_in_walled_jittered_box():
+    c = cases.small_flat(theta_deg=90.0)
+    o = Oracle(c)
+    o.set_rho(np.full(o.Ng, c.rho_l))
+    f0 = o.get_f()
+    o.step(50)
+    assert np.abs(o.get_f() - f0).max() < 1e-15
+
+
+def test_mass_matrix_sums_to_area_and_wall_weights_to_perimeter():
+    """sum M_A = fluid area/volume and sum of wall weights s = wall length/area, to
+    the accuracy of the isoparametric geometry."""
+    c = cases.small_cyl()
+    o = Oracle(c)
+    Rc, H = 12.0, 40.0
+    area = (2 * H) ** 2 - math.pi * Rc ** 2
+    assert abs(o.mass_matrix().sum() - area) / area < 1e-9
+    _, _, ws = o.wall_entries()
+    per_face = ws.reshape(-1, c.N + 1).sum(1)
+    cyl = c.mesh.wall_face[:, 1] == meshes.FACE_XI_M
+    assert abs(per_face[cyl].sum() - 2 * math.pi * Rc) / (2 * math.pi * Rc) < 1e-9
+    assert abs(per_face[~cyl].sum() - 8 * H) < 1e-11
+    s = cases.small_sphere()
+    o = Oracle(s)
+    vol = 48.0 ** 3 - 4.0 / 3.0 * math.pi * 10.0 ** 3
+    assert abs(o.mass_matrix().sum() - vol) / vol < 1e-7
+    _, _, ws = o.wall_entries()
+    per_face = ws.reshape(-1, (s.N + 1) ** 2).sum(1)
+    sph = s.mesh.wall_face[:, 1] == meshes.FACE_ZETA_M
+    assert abs(per_face[sph].sum() - 400 * math.pi) / (400 * math.pi) < 1e-4
+    assert abs(per_face[~sph].sum() - 6 * 48.0 ** 2) < 1e-9
+
+
+@pytest.mark.slow
+def test_laplace_pressure_jump():
+    """Isolated droplet at equilibrium: p_in - p_out = gamma / R (2-D), with
+    p = rho mu0 - e0, R the fitted radius of the mid-density contour."""
+    m = meshes.box2d(8, 8, 4, 64.0, 64.0, periodic=(False, False))
+    c = _case(m, x0=(32.0, 32.0), R=16.0, delta=6.0)
+    o = Oracle(c)
+    o.init_tanh()
+    o.step(3000)
+    ke, _ = o.diag()
+    assert ke < 1e-8
+    rho = o.rho()
+    X = m.first_copy_coords()
+    r = np.hypot(X[:, 0] - 32, X[:, 1] - 32)
+    b = o.beta
+    mu0 = 2 * b * (rho - 1) * (rho - 0.1) * (2 * rho - 1.1)
+    p = rho * mu0 - b * (rho - 1) ** 2 * (rho - 0.1) ** 2
+    dp = p[r < 4].mean() - p[r > 28].mean()
+    _, Rf = fit_circle(interface_points(m.xyz, m.gid, m.N, rho, 0.55))
+    assert abs(dp / (c.sigma / Rf) - 1.0) < 0.05
+    mu = o.mu(rho)
+    assert mu.max() - mu.min() < 0.02 * abs(mu.mean())  # uniform chemical potential
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_young_cap_keeps_its_angle(theta):
+    c = cases.small_flat(theta_deg=theta, nx=16, ny=8, N=6, jitter=0.15, Lx=128.0, Ly=64.0,
+                         R=32.0)
+    o = Oracle(c)
+    o.init_tanh()
+    a0, _, _ = contact_angle(c.mesh, o.rho(), c.rho_l, c.rho_v, c.delta, c.wall_geom)
+    o.step(1500)
+    a1, _, _ = contact_angle(c.mesh, o.rho(), c.rho_l, c.rho_v, c.delta, c.wall_geom)
+    assert abs(a0 - theta) < 1.0
+    assert abs(a1 - theta) < 2.0
+
+
+# ---------------------------------------------------------------------------
+# contact-angle measurement and initial condition
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("theta", [30.0, 60.0, 90.0, 135.0])
+def test_contact_angle_exact_on_synthetic_caps(theta):
+    if theta >= 60.0:  # flat-wall caps thinner than ~3 delta leave no arc to fit
+        c = cases.c2(theta_deg=theta)
+        X = c.mesh.first_copy_coords()
+        r = np.hypot(X[:, 0] - c.x0[0], X[:, 1] - c.x0[1])
+        rho = 0.55 - 0.45 * np.tanh(2 * (r - c.R) / c.delta)
+        a, cc, R = contact_angle(c.mesh, rho, c.rho_l, c.rho_v, c.delta, c.wall_geom)
+        assert abs(a - theta) < 0.5 and abs(R - c.R) < 0.1
+    cy = cases.c3(theta_deg=theta)
+    X = cy.mesh.first_copy_coords()
+    r = np.hypot(X[:, 0] - cy.x0[0], X[:, 1] - cy.x0[1])
+    rho = 0.55 - 0.45 * np.tanh(2 * (r - cy.R) / cy.delta)
+    a, _, R = contact_angle(cy.mesh, rho, cy.rho_l, cy.rho_v, cy.delta, cy.wall_geom)
+    assert abs(a - theta) < 0.1 and abs(R - cy.R) < 0.01
+
+
+def test_splitmix64_reference_vector_and_noise():
+    ref = json.load(open(os.path.join(GOLDEN, "splitmix64.json")))["state0_outputs_hex"]
+    lib = load()
+    gamma = 0x9E3779B97F4A7C15
+    got = [lib.orc_splitmix64((k * gamma) % 2 ** 64) for k in range(3)]
+    assert got == [int(h, 16) for h in ref]
+    c = cases.c1()
+    o = Oracle(c)
+    o.init_tanh(noise=0.0)
+    r0 = o.rho()
+    o.init_tanh(noise=1e-4)
+    dn = o.rho() - r0
+    assert np.abs(dn).max() <= 1e-4 and abs(dn.mean()) < 1e-5 and dn.std() > 5e-5
+    # noise is a function of the global id only: reversing element order changes nothing
+    m = c.mesh
+    m2 = meshes.Mesh(2, m.N, m.xyz[::-1].copy(), m.gid[::-1].copy(), m.n_global,
+                     m.wall_face, m.wall_cos, m.wall_ub)
+    o2 = Oracle(cases.Case("rev", m2, 9, x0=c.x0, R=c.R, noise=1e-4, seed=c.seed))
+    o2.init_tanh()
+    assert np.array_equal(o2.rho(), o.rho())
