@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-phase SEM-LBM time step on one MI355X.
+
+Metric: FP64 node-updates/s.  One node-update advances one unique global GLL node by
+one full time step (collision + three SSP-RK3 streaming stages, all populations).
+Default workload: config 2 (D2Q9 sessile droplet on a 60-degree wetting wall, 128x64
+domain, 32x16 jittered quads, N=6).  All inputs are seeded and synthetic and resident
+in device memory before the timed region.
+
+Prints one JSON line (see the "value", "roofline" and "cpu_baseline" keys).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def algorithmic_bytes(kind: str, Q: int, d: int, Ng: int, Nl: int) -> float:
+    """Minimum bytes one launch of a kernel kind must move (FP64 values, assembled
+    sizes: the per-local-copy residual buffers are implementation overhead)."""
+    ng = d * (d + 1) // 2
+    per = {
+        # reads rho (Ng), metric G (ng*Nl); writes the Laplacian residual (Ng)
+        "lap": 2 * Ng + ng * Nl,
+        # reads residual, rho, 1/M; writes mu
+        "mu": 4 * Ng,
+        # reads rho, mu, metric Ja; writes 2d gradient components
+        "grad": 2 * Ng + d * d * Nl + 2 * d * Ng,
+        # reads f (Q), rho, 2d averaged gradients, 1/M; writes f* (Q)
+        "collide": Q * Ng + Ng + 2 * d * Ng + Ng + Q * Ng,
+        # reads Q-1 populations, rho, mu, metric Ja; writes Q-1 residuals
+        "stream": (Q - 1) * Ng + 2 * Ng + d * d * Nl + (Q - 1) * Ng,
+        # reads Q-1 residuals, g (Q), g0 (Q), 1/M; writes Q populations and rho
+        "rk": (Q - 1) * Ng + Q * Ng + Q * Ng + Ng + Q * Ng + Ng,
+    }[kind]
+    return 8.0 * per
+
+
+def step_model_bytes(Q: int, d: int, Ng: int, Nl: int) -> float:
+    """Whole-step model: 9Q population doubles per node plus three stages of geometry
+    (8 doubles per local node in 2-D, 16 in 3-D) and 4 scalars per node."""
+    Gd = 8 if d == 2 else 16
+    return 8.0 * (9 * Q * Ng + 3 * (Gd * Nl + 4 * Ng))
+
+
+def make_case(name: str):
+    from synth import cases
+    return cases.CASES[name]()
+
+
+def cpu_baseline(case, steps: int):
+    from oracle import Oracle
+    o = Oracle(case)
+    o.init_tanh()
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=case.mesh.n_global * steps / dt, unit="node-updates/s", cores=1,
+                kind="oracle",
+                sample=f"{case.name}: {steps} full time steps of the single-threaded C oracle "
+                       f"({dt:.1f} s wall)")
+
+
+def traffic_from_profiles(workload: str, kind: str):
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary, if it
+    was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2609_00535_amd", "csrc", "kernels.hip"), "rb").read()
+    if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    v = rec.get("bytes_per_launch", {}).get(kind)
+    return float(v) if v is not None else None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--profile-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 "
+                                   "(multi-GPU element partitioning is design-only)"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2609_00535_amd as P
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    case = make_case(args.workload)
+    m = case.mesh
+    Q, d, Ng, Nl = case.lattice, m.dim, m.n_global, m.n_local
+    stream = torch.cuda.Stream()  # default priority; capturable (not the null stream)
+    with torch.cuda.stream(stream):
+        s = P.Solve(case, stream=stream)
+        s.init_tanh()
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        s.step(args.steps)
+        end.record(stream)
+        end.synchronize()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        ke, mass = s.kinetic_energy()
+        # per-kernel durations: HIP events around every launch of the same step sequence
+        prof = s.step_profile(args.profile_steps)
+    ms_per_step = ms / args.steps
+    value = Ng * args.steps / (ms / 1e3)
+    dom = max(prof, key=lambda k: prof[k][0])
+    tot, nl = prof[dom]
+    avg_ms = tot / max(nl, 1)
+    alg = algorithmic_bytes(dom, Q, d, Ng, Nl)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(args.workload, dom)
+    out = {
+        "metric": "FP64 node-updates/s per step",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{case.name}: " + (case.mesh.name or ""),
+                   "lattice": f"D{d}Q{Q}", "N": m.N, "elements": m.E, "n_global": Ng,
+                   "n_local": Nl, "local_node_updates_per_s": Nl * args.steps / (ms / 1e3),
+                   "model_bytes_per_step": step_model_bytes(Q, d, Ng, Nl),
+                   "model_GBps": step_model_bytes(Q, d, Ng, Nl) / (ms_per_step * 1e-3) / 1e9,
+                   "ke_max_end": ke, "mass_end": mass, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_launch_us": avg_ms * 1e3,
+                     "algorithmic_bytes_per_launch": alg,
+                     "kernel_ms_per_step": {k: v[0] / args.profile_steps for k, v in prof.items()}},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -117,6 +117,13 @@ slbm_status slbm_set_state(slbm_ctx *c, const double *f, int64_t step);
  * and returns SLBM_EDIVERGED on a non-finite or too-large kinetic energy. */
 slbm_status slbm_step(slbm_ctx *c, int64_t n);
 
+/* Tracing: advance n steps like slbm_step with a HIP event pair around every kernel
+ * launch; ms[k] accumulates the elapsed milliseconds and launches[k] the launch count of
+ * kernel kind k (0 Laplacian, 1 chemical potential, 2 gradients, 3 collision, 4 streaming
+ * residual, 5 DSS + Runge-Kutta combine).  Synchronises after every step. */
+#define SLBM_NUM_KERNEL_KINDS 6
+slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int64_t *launches);
+
 /* Queries (synchronising).  rho [n_global] by Eq. (10); u [d][n_global] by Eq. (11);
  * ke_max = max over nodes of rho |u|^2 / 2; mass = sum of lumped mass times rho. */
 slbm_status slbm_get_rho(slbm_ctx *c, double *rho);
@@ -135,6 +142,13 @@ typedef struct slbm_wall_geom {
 slbm_status slbm_contact_angle(slbm_ctx *c, const slbm_wall_geom *w, double *theta_deg);
 
 slbm_status slbm_get_info(const slbm_ctx *c, slbm_info *info);
+
+/* Host-side tables derived by slbm_create / slbm_set_mesh (no device work):
+ * GLL nodes x[N+1], weights w[N+1] and differentiation matrix D[(N+1)^2] (row-major,
+ * D[i][m] = l_m'(x_i)), Deville, Fischer & Mund ch. 2; and the assembled GLL-lumped mass
+ * matrix MA[n_global] (caller's ids), the M of Eqs. (6) and (8). */
+slbm_status slbm_get_gll(const slbm_ctx *c, double *x, double *w, double *D);
+slbm_status slbm_get_mass(const slbm_ctx *c, double *MA);
 const char *slbm_last_error(const slbm_ctx *c);
 void slbm_destroy(slbm_ctx *c);
 

@@ -1,0 +1,67 @@
+// Host-side context of one solve (the opaque slbm_ctx of the C ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/semlbm.h"
+#include "internal.hpp"
+
+namespace slbm {
+// enqueue n full time steps for one (d, N) group of solves
+int enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &np, int64_t n, void *stream);
+// capture 'steps' calls of fn(stream) into an instantiated graph (hipGraphExec_t)
+int capture_graph(void *stream, void **exec, int (*fn)(void *, void *), void *arg);
+int launch_graph(void *exec, void *stream);
+void destroy_graph(void *exec);
+}  // namespace slbm
+
+struct slbm_ctx {
+    slbm_params prm{};
+    int dim = 0, Q = 0, N = 0, Np = 0, nloc = 0;
+    double beta = 0, kappa = 0, omega = 0, dt = 0, hmin = 0;
+    double ev[slbm::kMaxQ][3] = {};
+    double tw[slbm::kMaxQ] = {}, tc[slbm::kMaxQ] = {};
+    int opp[slbm::kMaxQ] = {};
+    std::vector<double> xi, wq, Dm, wn;
+    // mesh (host copies)
+    bool has_mesh = false;
+    int64_t E = 0, Nl = 0, Ng = 0, nw = 0;
+    std::vector<double> xyz;
+    std::vector<int32_t> lgid, ig2ug, csr_ptr, csr_idx, wel_ptr, w_node;
+    std::vector<double> Ja, Gm, MA, Minv, w_lap, w_cn, w_eub;
+    // device
+    struct Offsets {
+        size_t desc, eplan, nplan, lgid, csr_ptr, csr_idx, wel_ptr, w_node, Ja, G, Minv, Dm, wn, w_lap,
+            w_cn, w_eub, f, g0, gA, rho, mu, rl, gl, rs, aux, diag, red;
+    } off{};
+    size_t ws_bytes = 0;
+    int n_eblocks = 0, n_nblocks = 0;
+    bool bound = false, has_state = false;
+    void *dev = nullptr;
+    void *stream = nullptr;
+    slbm::SolveDesc desc{};
+    slbm::LaunchPlan eplan{}, nplan{};
+    int64_t step = 0;
+    std::string err;
+    // HIP graphs of 1 and kGraphSteps time steps (captured lazily on a non-null stream)
+    static constexpr int kGraphSteps = 10;
+    void *graph[2] = {nullptr, nullptr};  // hipGraphExec_t
+    bool use_graph = true;
+
+    ~slbm_ctx();
+    slbm_status enqueue(int64_t n);
+
+    slbm_status fail(slbm_status s, const char *fmt, ...);
+    slbm_status hip_check(int e, const char *what);
+    int stride(int a) const;
+    int along(int n, int a) const;
+    double dline(const double *h, int n, int a) const;
+    void layout();
+    slbm_status require_bound(bool need_state);
+    slbm_status upload_f_and_density(const std::vector<double> &f_int);
+    slbm_status read_diag(double *ke, double *mass);
+    slbm_status put(double *dst, const double *src_user, int fields);
+    slbm_status get(const double *src, double *dst_user, int fields);
+    slbm_status restore_density();
+};

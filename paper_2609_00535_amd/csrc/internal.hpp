@@ -1,0 +1,74 @@
+// Internal interface between the host runtime (semlbm.cpp, serve.cpp) and the HIP
+// kernels (kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace slbm {
+
+constexpr int kMaxQ = 19;
+
+// Everything one solve's kernels need, resident in device memory (one entry per batch
+// member).  Index arrays are int32: a solve holds < 2^31 local nodes.
+struct SolveDesc {
+    int E, Nl, Ng, pad0;
+    // mesh tables (device)
+    const int *lgid;      // [Nl] local node -> internal global node
+    const double *Ja;     // [d*d][Nl] J * d xi_a / d x_c, index (a*d + c)
+    const double *G;      // [d(d+1)/2][Nl] w (Ja_a . Ja_b) / J, upper triangle row-major
+    const double *Minv;   // [Ng] inverse assembled lumped mass
+    const int *csr_ptr;   // [Ng+1] local copies of each global node
+    const int *csr_idx;   // [Nl]   ascending local indices
+    const int *wel_ptr;   // [E+1] wall entries of each element
+    const int *w_node;    // [nw] element-local node of the entry
+    const double *w_lap;  // [nw] s cos(theta) sqrt(2 beta / kappa)
+    const double *w_cn;   // [nw][Q] (s n) . e_a (only negative values act)
+    const double *w_eub;  // [nw][Q] e_a . u_b
+    const double *Dm;     // [(N+1)^2] GLL differentiation matrix, Dm[i*(N+1)+m]
+    const double *wn;     // [(N+1)^d] tensor GLL weights
+    // state and work buffers (device)
+    double *f;    // [Q][Ng] f-bar (state)
+    double *g0;   // [Q][Ng] post-collision f*
+    double *gA;   // [Q][Ng] Runge-Kutta stage
+    double *rho;  // [Ng]
+    double *mu;   // [Ng]
+    double *rl;   // [Nl] Laplacian residual of each local copy
+    double *gl;   // [2d][Nl] lumped-mass weighted element gradients of rho and mu
+    double *rs;   // [Q-1][Nl] streaming residual of each local copy
+    double *aux;  // [2d][Ng] averaged gradients (operator entry points)
+    double *diag; // [4] KE_max, mass, -, -
+    double *red;  // [2 * max blocks] reduction partials
+    // physics
+    double rho_l, rho_v, beta, kappa, omega, dt;
+    double t[kMaxQ], tc[kMaxQ];
+};
+
+// Launch-shape bookkeeping shared by host and device.
+struct LaunchPlan {
+    const SolveDesc *desc;   // device array of descriptors
+    const int *blk_solve;    // device: block -> batch member index
+    const int *blk_local;    // device: block -> block index within its member
+    int nblocks;
+};
+
+// Element-kernel shape for order N in d dimensions (must match kernels.hip).
+inline int nloc_of(int d, int N) { int p = N + 1; return d == 2 ? p * p : p * p * p; }
+inline int epb_of(int d, int N) { int n = nloc_of(d, N); return n <= 256 ? 256 / n : 1; }
+constexpr int kNodeThreads = 256;
+
+// Kernel launchers (kernels.hip).  'stage' is 1..3 for the RK stages.  All launch on
+// 'stream' and return the hipError_t of the launch as int.
+int launch_lap(int d, int N, const LaunchPlan &p, void *stream);
+int launch_mu(int d, int N, const LaunchPlan &p, void *stream);
+int launch_grad(int d, int N, const LaunchPlan &p, void *stream);
+int launch_gavg(int d, int N, const LaunchPlan &p, void *stream);
+int launch_collide(int d, int N, const LaunchPlan &p, int use_aux, void *stream);
+int launch_stream(int d, int N, const LaunchPlan &p, int stage, void *stream);
+int launch_rk(int d, int N, const LaunchPlan &p, int stage, void *stream);
+int launch_density(int d, int N, const LaunchPlan &p, int which, void *stream);
+int launch_diag(int d, int N, const LaunchPlan &p, void *stream);
+int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream);
+bool supported_order(int d, int N);
+
+}  // namespace slbm

@@ -1,0 +1,612 @@
+// HIP kernels (gfx950) of the two-phase spectral-element LBM time step.
+//
+// Two kernel families alternate inside a step:
+//   * element kernels: one thread per element node, several elements per 256-thread block,
+//     element fields staged in LDS; tensor-product GLL derivatives are contractions of an
+//     LDS line with a row (or column) of the differentiation matrix;
+//   * node kernels: one thread per global node; they finish the direct stiffness summation
+//     (DSS) by gathering the node's local copies in ascending order (deterministic, no
+//     atomics) and apply the pointwise physics.
+// Every kernel serves a whole batch: block b works on member blk_solve[b], block
+// blk_local[b] of it, with the member's tables and state in its SolveDesc.  A single solve
+// is a batch of one.
+//
+// Floating point: the build disables contraction; the GLL contractions use fma explicitly
+// and every other expression is written with the operand order of the CPU oracle, so the
+// two implementations round identically.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace slbm {
+
+// ------------------------------------------------------------------------------------------
+// lattice tables
+// ------------------------------------------------------------------------------------------
+template <int Q> struct Lat;
+template <> struct Lat<9> {
+    static constexpr int D = 2;
+    static constexpr int e[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+                                    {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+};
+template <> struct Lat<19> {
+    static constexpr int D = 3;
+    static constexpr int e[19][3] = {
+        {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
+        {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+        {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+};
+template <int D> struct QOf;
+template <> struct QOf<2> { static constexpr int Q = 9; };
+template <> struct QOf<3> { static constexpr int Q = 19; };
+
+// v . e_q summed in ascending component order from 0 (components of e are -1, 0, 1, so
+// the sum equals the plain dot product bit for bit)
+template <int Q, int D>
+__device__ __forceinline__ double dot_e(const double *v, int q) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        const int ec = Lat<Q>::e[q][c];
+        if (ec == 1) s = s + v[c];
+        else if (ec == -1) s = s - v[c];
+    }
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// element shapes
+// ------------------------------------------------------------------------------------------
+template <int D, int N> struct Shape {
+    static constexpr int NP = N + 1;
+    static constexpr int NLOC = D == 2 ? NP * NP : NP * NP * NP;
+    static constexpr int EPB = NLOC <= 256 ? 256 / NLOC : 1;
+    static constexpr int NB = EPB * NLOC;  // nodes of one block
+    static constexpr int NT = NLOC <= 256 ? 256 : ((NLOC + 63) / 64) * 64;
+    static constexpr int NG = D * (D + 1) / 2;
+};
+
+template <int NP, int A> struct Stride { static constexpr int v = A == 0 ? 1 : (A == 1 ? NP : NP * NP); };
+
+// d/dxi_A at element node n of an LDS field s (element base): sum_m D[i][m] s[.. m ..]
+template <int NP, int A>
+__device__ __forceinline__ double dref(const double *__restrict__ sD, const double *__restrict__ s, int n) {
+    constexpr int st = Stride<NP, A>::v;
+    const int i = (n / st) % NP;
+    const double *row = sD + i * NP;
+    const double *line = s + (n - i * st);
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) acc = fma(row[m], line[m * st], acc);
+    return acc;
+}
+
+// transpose: sum_m D[m][i] v[.. m ..]
+template <int NP, int A>
+__device__ __forceinline__ double drefT(const double *__restrict__ sD, const double *__restrict__ v, int n) {
+    constexpr int st = Stride<NP, A>::v;
+    const int i = (n / st) % NP;
+    const double *line = v + (n - i * st);
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) acc = fma(sD[m * NP + i], line[m * st], acc);
+    return acc;
+}
+
+template <int D, int NP>
+__device__ __forceinline__ void grad_ref(const double *sD, const double *s, int n, double *out) {
+    out[0] = dref<NP, 0>(sD, s, n);
+    out[1] = dref<NP, 1>(sD, s, n);
+    if constexpr (D == 3) out[2] = dref<NP, 2>(sD, s, n);
+}
+
+template <int D, int NP>
+__device__ __forceinline__ double div_refT(const double *sD, const double *v, int stride_field, int n) {
+    double s = 0.0;
+    s += drefT<NP, 0>(sD, v, n);
+    s += drefT<NP, 1>(sD, v + stride_field, n);
+    if constexpr (D == 3) s += drefT<NP, 2>(sD, v + 2 * stride_field, n);
+    return s;
+}
+
+// block -> (member descriptor, first element of the block)
+struct BlockSlot {
+    const SolveDesc *sd;
+    int local;
+};
+__device__ __forceinline__ BlockSlot block_slot(const LaunchPlan &p) {
+    BlockSlot b;
+    b.sd = p.desc + p.blk_solve[blockIdx.x];
+    b.local = p.blk_local[blockIdx.x];
+    return b;
+}
+
+// wall entries of element e that sit on node n (at most d faces meet at a node), in
+// list order
+template <int D>
+__device__ __forceinline__ int wall_entries_of(const SolveDesc &sd, int e, int n, int *wk) {
+    int cnt = 0;
+    const int k0 = sd.wel_ptr[e], k1 = sd.wel_ptr[e + 1];
+    for (int k = k0; k < k1; ++k)
+        if (sd.w_node[k] == n && cnt < D) wk[cnt++] = k;
+    return cnt;
+}
+
+// ------------------------------------------------------------------------------------------
+// Eq. (8): element part of the weak Laplacian, r = -sum_a D_a^T (G^{ab} D_b rho), plus the
+// wetting boundary integral s n.grad(rho) = s cos(theta) sqrt(2 beta/kappa) |(rho-rl)(rho-rv)|
+// ------------------------------------------------------------------------------------------
+template <int D, int N>
+__global__ __launch_bounds__((Shape<D, N>::NT)) void k_lap(LaunchPlan p) {
+    using S = Shape<D, N>;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    __shared__ double sD[NP * NP];
+    __shared__ double srho[NB];
+    __shared__ double sv[D * NB];
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const int es = tid / NLOC, n = tid - es * NLOC;
+    const int e = bs.local * S::EPB + es;
+    const bool act = tid < NB && e < sd.E;
+    const int l = e * NLOC + n;
+    double rh = 0.0;
+    if (act) {
+        rh = sd.rho[sd.lgid[l]];
+        srho[tid] = rh;
+    }
+    __syncthreads();
+    if (act) {
+        double d[D];
+        grad_ref<D, NP>(sD, srho + es * NLOC, n, d);
+        double g[S::NG];
+#pragma unroll
+        for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * sd.Nl + l];
+        // v_a = sum_b G_ab d_b (ascending b from 0)
+        if constexpr (D == 2) {
+            double v0 = 0.0, v1 = 0.0;
+            v0 += g[0] * d[0]; v0 += g[1] * d[1];
+            v1 += g[1] * d[0]; v1 += g[2] * d[1];
+            sv[tid] = v0; sv[NB + tid] = v1;
+        } else {
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+            v0 += g[0] * d[0]; v0 += g[1] * d[1]; v0 += g[2] * d[2];
+            v1 += g[1] * d[0]; v1 += g[3] * d[1]; v1 += g[4] * d[2];
+            v2 += g[2] * d[0]; v2 += g[4] * d[1]; v2 += g[5] * d[2];
+            sv[tid] = v0; sv[NB + tid] = v1; sv[2 * NB + tid] = v2;
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
+    int wk[3];
+    const int nw = wall_entries_of<D>(sd, e, n, wk);
+    for (int j = 0; j < nw; ++j) r += sd.w_lap[wk[j]] * fabs((rh - sd.rho_l) * (rh - sd.rho_v));
+    sd.rl[l] = r;
+}
+
+// Eq. (2): mu = mu0(rho) - kappa lap, lap = DSS(r) / M (reading: mu0 = 2 beta (rho-rl)(rho-rv)(2rho-rl-rv))
+template <int D, int N>
+__global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int G = bs.local * kNodeThreads + threadIdx.x;
+    if (G >= sd.Ng) return;
+    double s = 0.0;
+    for (int k = sd.csr_ptr[G]; k < sd.csr_ptr[G + 1]; ++k) s += sd.rl[sd.csr_idx[k]];
+    const double lap = s * sd.Minv[G];
+    const double pr = sd.rho[G], rl = sd.rho_l, rv = sd.rho_v;
+    const double mu0 = 2.0 * sd.beta * (pr - rl) * (pr - rv) * (2.0 * pr - rl - rv);
+    sd.mu[G] = mu0 - sd.kappa * lap;
+}
+
+// lumped-mass weighted element gradients w Ja^T grad_ref of rho and mu (for the collision)
+template <int D, int N>
+__global__ __launch_bounds__((Shape<D, N>::NT)) void k_grad(LaunchPlan p) {
+    using S = Shape<D, N>;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    __shared__ double sD[NP * NP];
+    __shared__ double sf[2 * NB];
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const int es = tid / NLOC, n = tid - es * NLOC;
+    const int e = bs.local * S::EPB + es;
+    const bool act = tid < NB && e < sd.E;
+    const int l = e * NLOC + n;
+    if (act) {
+        const int G = sd.lgid[l];
+        sf[tid] = sd.rho[G];
+        sf[NB + tid] = sd.mu[G];
+    }
+    __syncthreads();
+    if (!act) return;
+    const double w = sd.wn[n];
+    double J[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        double d[D];
+        grad_ref<D, NP>(sD, sf + f * NB + es * NLOC, n, d);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) s += J[a][c] * d[a];
+            sd.gl[(size_t)(f * D + c) * sd.Nl + l] = w * s;
+        }
+    }
+}
+
+// averaged gradients DSS(gl) / M into aux [2d][Ng] (operator entry point)
+template <int D, int N>
+__global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int G = bs.local * kNodeThreads + threadIdx.x;
+    if (G >= sd.Ng) return;
+    const int k0 = sd.csr_ptr[G], k1 = sd.csr_ptr[G + 1];
+    const double mi = sd.Minv[G];
+#pragma unroll
+    for (int c = 0; c < 2 * D; ++c) {
+        double s = 0.0;
+        for (int k = k0; k < k1; ++k) s += sd.gl[(size_t)c * sd.Nl + sd.csr_idx[k]];
+        sd.aux[(size_t)c * sd.Ng + G] = s * mi;
+    }
+}
+
+// Eq. (4) with (A.2), (A.6)-(A.7) and F** of Sec. 2.1: f* = f - omega (f - (feq - dt/2 F**)) + dt F**,
+// F = cs^2 grad(rho) - rho grad(mu) from the lumped-mass averaged element gradients
+template <int D, int N>
+__global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_aux) {
+    constexpr int Q = QOf<D>::Q;
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int G = bs.local * kNodeThreads + threadIdx.x;
+    if (G >= sd.Ng) return;
+    const size_t Ng = sd.Ng;
+    double gr[D], gm[D];
+    if (use_aux) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            gr[c] = sd.aux[c * Ng + G];
+            gm[c] = sd.aux[(D + c) * Ng + G];
+        }
+    } else {
+        const int k0 = sd.csr_ptr[G], k1 = sd.csr_ptr[G + 1];
+        const double mi = sd.Minv[G];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double s = 0.0, t = 0.0;
+            for (int k = k0; k < k1; ++k) {
+                const int li = sd.csr_idx[k];
+                s += sd.gl[(size_t)c * sd.Nl + li];
+                t += sd.gl[(size_t)(D + c) * sd.Nl + li];
+            }
+            gr[c] = s * mi;
+            gm[c] = t * mi;
+        }
+    }
+    double f[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
+    const double pr = sd.rho[G];
+    const double cs2 = 1.0 / 3.0, dt = sd.dt, om = sd.omega;
+    double u[D], F[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        double m = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int ec = Lat<Q>::e[q][c];
+            if (ec == 1) m = m + f[q];
+            else if (ec == -1) m = m - f[q];
+        }
+        u[c] = m / pr;
+        F[c] = cs2 * gr[c] - pr * gm[c];
+    }
+    double uF = 0.0, uu = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        uF += u[c] * F[c];
+        uu += u[c] * u[c];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const double eu = dot_e<Q, D>(u, q), eF = dot_e<Q, D>(F, q);
+        const double tq = sd.t[q], tc = sd.tc[q];
+        const double Fss = tc * (eu * eF * 3.0 - uF);
+        const double feq = pr * tq * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        const double fbeq = feq - 0.5 * dt * Fss;
+        sd.g0[q * Ng + G] = f[q] - om * (f[q] - fbeq) + dt * Fss;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Eqs. (5)-(6), (12), (9): element residual of the force-split weak streaming,
+//   r_a = -w [ (Ja e_a) . D(g_a - t_a rho) + (t_a/cs^2) rho (Ja e_a) . D mu ]
+// plus, on wall faces with (s n).e_a < 0, (s n . e_a) [g_a - g_opp - 2 (t_a/cs^2) rho e_a.u_b]
+// stage 1 streams g0, stages 2-3 stream gA
+// ------------------------------------------------------------------------------------------
+template <int D, int N>
+__global__ __launch_bounds__((Shape<D, N>::NT)) void k_stream(LaunchPlan p, int stage) {
+    using S = Shape<D, N>;
+    constexpr int Q = QOf<D>::Q;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    __shared__ double sD[NP * NP];
+    __shared__ double smu[NB];
+    __shared__ double sh[(Q - 1) * NB];
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const double *__restrict__ g = stage == 1 ? sd.g0 : sd.gA;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const int es = tid / NLOC, n = tid - es * NLOC;
+    const int e = bs.local * S::EPB + es;
+    const bool act = tid < NB && e < sd.E;
+    const int l = e * NLOC + n;
+    const size_t Ng = sd.Ng;
+    int G = 0;
+    double pr = 0.0;
+    if (act) {
+        G = sd.lgid[l];
+        pr = sd.rho[G];
+        smu[tid] = sd.mu[G];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = g[q * Ng + G] - sd.t[q] * pr;
+    }
+    __syncthreads();
+    if (!act) return;
+    double dmu[D];
+    grad_ref<D, NP>(sD, smu + es * NLOC, n, dmu);
+    double J[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+    const double w = sd.wn[n];
+    int wk[3];
+    const int nw = wall_entries_of<D>(sd, e, n, wk);
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        double dh[D];
+        grad_ref<D, NP>(sD, sh + (q - 1) * NB + es * NLOC, n, dh);
+        double adv = 0.0, frc = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double ca = dot_e<Q, D>(J[a], q);
+            adv += ca * dh[a];
+            frc += ca * dmu[a];
+        }
+        const double tc = sd.tc[q];
+        double r = -(w * (adv + tc * pr * frc));
+        for (int j = 0; j < nw; ++j) {
+            const int k = wk[j];
+            const double cn = sd.w_cn[k * Q + q];
+            if (cn < 0.0) {
+                const double ga = g[q * Ng + G], gb = g[Lat<Q>::opp[q] * Ng + G];
+                const double bc = ga - gb - 2.0 * tc * pr * sd.w_eub[k * Q + q];
+                r += cn * bc;
+            }
+        }
+        sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
+    }
+}
+
+// SSP-RK3 stage combination after DSS(r)/M, and the new stage's density (Eq. (10))
+//   stage 0 (operator entry point only): gA = L(gA)
+//   stage 1: gA = g0 + dt L(g0); stage 2: gA = 3/4 g0 + 1/4 (gA + dt L(gA));
+//   stage 3: f = (g0 + 2 (gA + dt L(gA))) / 3
+template <int D, int N>
+__global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
+    constexpr int Q = QOf<D>::Q;
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int G = bs.local * kNodeThreads + threadIdx.x;
+    if (G >= sd.Ng) return;
+    const size_t Ng = sd.Ng, Nl = sd.Nl;
+    const double *gin = stage == 1 ? sd.g0 : sd.gA;
+    double *gout = stage == 3 ? sd.f : sd.gA;
+    const int k0 = sd.csr_ptr[G], k1 = sd.csr_ptr[G + 1];
+    const double mi = sd.Minv[G], dt = sd.dt;
+    double rho = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double L = 0.0;
+        if (q > 0) {
+            double s = 0.0;
+            for (int k = k0; k < k1; ++k) s += sd.rs[(size_t)(q - 1) * Nl + sd.csr_idx[k]];
+            L = s * mi;
+        }
+        const double x = gin[q * Ng + G] + dt * L;
+        double out;
+        if (stage == 0) out = L;  // operator entry point: the assembled right-hand side
+        else if (stage == 1) out = x;
+        else if (stage == 2) out = 0.75 * sd.g0[q * Ng + G] + 0.25 * x;
+        else out = (sd.g0[q * Ng + G] + 2.0 * x) / 3.0;
+        gout[q * Ng + G] = out;
+        rho += out;
+    }
+    sd.rho[G] = rho;
+}
+
+// rho = sum_a f_a (Eq. (10)) of the state (which = 0) or of gA (which = 1)
+template <int D, int N>
+__global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int which) {
+    constexpr int Q = QOf<D>::Q;
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int G = bs.local * kNodeThreads + threadIdx.x;
+    if (G >= sd.Ng) return;
+    const double *src = which == 0 ? sd.f : sd.gA;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += src[(size_t)q * sd.Ng + G];
+    sd.rho[G] = s;
+}
+
+// KE_max = max 1/2 rho |u|^2 and mass = sum M rho; per-block partials in red[]
+template <int D, int N>
+__global__ __launch_bounds__(kNodeThreads) void k_diag(LaunchPlan p) {
+    constexpr int Q = QOf<D>::Q;
+    __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int tid = threadIdx.x;
+    const int G = bs.local * kNodeThreads + tid;
+    double ke = 0.0, ms = 0.0;
+    if (G < sd.Ng) {
+        const size_t Ng = sd.Ng;
+        double f[Q];
+        double pr = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            f[q] = sd.f[q * Ng + G];
+            pr += f[q];
+        }
+        double uu = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double m = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int ec = Lat<Q>::e[q][c];
+                if (ec == 1) m = m + f[q];
+                else if (ec == -1) m = m - f[q];
+            }
+            const double u = m / pr;
+            uu += u * u;
+        }
+        ke = 0.5 * pr * uu;
+        ms = (1.0 / sd.Minv[G]) * pr;
+    }
+    smax[tid] = ke;
+    ssum[tid] = ms;
+    __syncthreads();
+    for (int s = kNodeThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            const double a = smax[tid], b = smax[tid + s];
+            smax[tid] = (a >= b || a != a) ? a : b;  // NaN propagates
+            ssum[tid] += ssum[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        sd.red[2 * bs.local] = smax[0];
+        sd.red[2 * bs.local + 1] = ssum[0];
+    }
+}
+
+__global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *desc) {
+    __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
+    const SolveDesc &sd = desc[blockIdx.x];
+    const int nb = (sd.Ng + kNodeThreads - 1) / kNodeThreads;
+    const int tid = threadIdx.x;
+    double km = 0.0, ms = 0.0;
+    for (int b = tid; b < nb; b += kNodeThreads) {
+        const double a = sd.red[2 * b];
+        km = (km >= a || km != km) ? km : a;
+        ms += sd.red[2 * b + 1];
+    }
+    smax[tid] = km;
+    ssum[tid] = ms;
+    __syncthreads();
+    for (int s = kNodeThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            const double a = smax[tid], b = smax[tid + s];
+            smax[tid] = (a >= b || a != a) ? a : b;
+            ssum[tid] += ssum[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        sd.diag[0] = smax[0];
+        sd.diag[1] = ssum[0];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers: dispatch (d, N) to template instances
+// ------------------------------------------------------------------------------------------
+#define SLBM_FOR_ORDERS(X)                                                                     \
+    X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(2, 7) X(2, 8) X(2, 9) X(2, 10) X(2, 11) X(2, 12) \
+    X(2, 14) X(2, 16) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6)
+
+bool supported_order(int d, int N) {
+#define X(DD, NN) if (d == DD && N == NN) return true;
+    SLBM_FOR_ORDERS(X)
+#undef X
+    return false;
+}
+
+#define SLBM_DISPATCH(KERNEL, THREADS, ...)                                                  \
+    do {                                                                                     \
+        if (p.nblocks <= 0) return 0;                                                        \
+        hipStream_t st = (hipStream_t)stream;                                                \
+        bool done = false;                                                                   \
+        SLBM_FOR_ORDERS(SLBM_CASE_##KERNEL)                                                  \
+        if (!done) return (int)hipErrorInvalidValue;                                         \
+        return (int)hipGetLastError();                                                       \
+    } while (0)
+
+#define SLBM_ELEM_CASE(KERNEL, DD, NN, ...)                                                  \
+    if (!done && d == DD && N == NN) {                                                       \
+        KERNEL<DD, NN><<<p.nblocks, Shape<DD, NN>::NT, 0, st>>>(p, ##__VA_ARGS__);           \
+        done = true;                                                                         \
+    }
+#define SLBM_NODE_CASE(KERNEL, DD, NN, ...)                                                  \
+    if (!done && d == DD && N == NN) {                                                       \
+        KERNEL<DD, NN><<<p.nblocks, kNodeThreads, 0, st>>>(p, ##__VA_ARGS__);                \
+        done = true;                                                                         \
+    }
+
+int launch_lap(int d, int N, const LaunchPlan &p, void *stream) {
+#define SLBM_CASE_lap(DD, NN) SLBM_ELEM_CASE(k_lap, DD, NN)
+    SLBM_DISPATCH(lap, 0);
+}
+int launch_mu(int d, int N, const LaunchPlan &p, void *stream) {
+#define SLBM_CASE_mu(DD, NN) SLBM_NODE_CASE(k_mu, DD, NN)
+    SLBM_DISPATCH(mu, 0);
+}
+int launch_grad(int d, int N, const LaunchPlan &p, void *stream) {
+#define SLBM_CASE_grad(DD, NN) SLBM_ELEM_CASE(k_grad, DD, NN)
+    SLBM_DISPATCH(grad, 0);
+}
+int launch_gavg(int d, int N, const LaunchPlan &p, void *stream) {
+#define SLBM_CASE_gavg(DD, NN) SLBM_NODE_CASE(k_gavg, DD, NN)
+    SLBM_DISPATCH(gavg, 0);
+}
+int launch_collide(int d, int N, const LaunchPlan &p, int use_aux, void *stream) {
+#define SLBM_CASE_collide(DD, NN) SLBM_NODE_CASE(k_collide, DD, NN, use_aux)
+    SLBM_DISPATCH(collide, 0);
+}
+int launch_stream(int d, int N, const LaunchPlan &p, int stage, void *stream) {
+#define SLBM_CASE_stream(DD, NN) SLBM_ELEM_CASE(k_stream, DD, NN, stage)
+    SLBM_DISPATCH(stream, 0);
+}
+int launch_rk(int d, int N, const LaunchPlan &p, int stage, void *stream) {
+#define SLBM_CASE_rk(DD, NN) SLBM_NODE_CASE(k_rk, DD, NN, stage)
+    SLBM_DISPATCH(rk, 0);
+}
+int launch_density(int d, int N, const LaunchPlan &p, int which, void *stream) {
+#define SLBM_CASE_density(DD, NN) SLBM_NODE_CASE(k_density, DD, NN, which)
+    SLBM_DISPATCH(density, 0);
+}
+int launch_diag(int d, int N, const LaunchPlan &p, void *stream) {
+#define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)
+    SLBM_DISPATCH(diag, 0);
+}
+int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream) {
+    if (nsolves <= 0) return 0;
+    k_diag_final<<<nsolves, kNodeThreads, 0, (hipStream_t)stream>>>(desc);
+    return (int)hipGetLastError();
+}
+
+}  // namespace slbm

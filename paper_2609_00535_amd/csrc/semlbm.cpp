@@ -1,0 +1,970 @@
+// Host runtime of the C ABI in include/semlbm.h: parameter set-up (Appendix A), mesh
+// processing (GLL tables, isoparametric metric terms, lumped mass, wall tables, DSS
+// gather lists), workspace layout, and the launch sequence of one time step.
+//
+// Geometry is computed once on the host in FP64 with the same expression trees as the
+// time step needs on the device: GLL contractions by fma, everything else plain IEEE
+// operations (this file is compiled without floating-point contraction).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/semlbm.h"
+#include "ctx.hpp"
+
+using namespace slbm;
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// GLL points, weights and differentiation matrix (Deville, Fischer & Mund, ch. 2)
+// ------------------------------------------------------------------------------------------
+void legendre_pair(int N, double x, double &P, double &dP) {
+    // Bonnet: (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1};  P'_{k+1} = P'_{k-1} + (2k+1) P_k
+    double pm = 1.0, pc = x, dm = 0.0, dc = 1.0;
+    if (N == 0) { P = 1.0; dP = 0.0; return; }
+    for (int k = 1; k < N; ++k) {
+        const double pn = ((2.0 * k + 1.0) * x * pc - k * pm) / (k + 1.0);
+        const double dn = dm + (2.0 * k + 1.0) * pc;
+        pm = pc; pc = pn; dm = dc; dc = dn;
+    }
+    P = pc;
+    dP = dc;
+}
+
+void gll_tables(int N, std::vector<double> &x, std::vector<double> &w, std::vector<double> &D) {
+    const int Np = N + 1;
+    x.assign(Np, 0.0);
+    w.assign(Np, 0.0);
+    D.assign(Np * Np, 0.0);
+    x[0] = -1.0;
+    x[N] = 1.0;
+    // interior nodes: roots of P_N', Newton with P_N'' from the Legendre equation,
+    // started from the Chebyshev-Gauss-Lobatto points
+    for (int i = 1; i < N; ++i) {
+        double t = -std::cos(M_PI * i / N);
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre_pair(N, t, P, dP);
+            const double d2P = (2.0 * t * dP - N * (N + 1.0) * P) / (1.0 - t * t);
+            const double step = dP / d2P;
+            t -= step;
+            if (std::fabs(step) < 1e-16) break;
+        }
+        x[i] = t;
+    }
+    for (int i = 0; i < Np / 2; ++i) {
+        const double h = 0.5 * (x[N - i] - x[i]);
+        x[N - i] = h;
+        x[i] = -h;
+    }
+    if (N % 2 == 0) x[N / 2] = 0.0;
+    std::vector<double> PN(Np);
+    for (int i = 0; i < Np; ++i) {
+        double dP;
+        legendre_pair(N, x[i], PN[i], dP);
+        w[i] = 2.0 / (N * (N + 1.0) * PN[i] * PN[i]);
+    }
+    for (int i = 0; i < Np; ++i)
+        for (int j = 0; j < Np; ++j) {
+            double v = 0.0;
+            if (i != j) v = PN[i] / (PN[j] * (x[i] - x[j]));
+            else if (i == 0) v = -N * (N + 1.0) / 4.0;
+            else if (i == N) v = N * (N + 1.0) / 4.0;
+            D[i * Np + j] = v;
+        }
+}
+
+// lattice tables (population order of the header); rest weight closes the sum exactly
+void lattice_tables(int Q, double e[][3], double *t, int *opp) {
+    static const int e9[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+                                 {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    static const int e19[19][3] = {
+        {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
+        {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+        {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    for (int q = 0; q < Q; ++q) {
+        for (int c = 0; c < 3; ++c) e[q][c] = Q == 9 ? e9[q][c] : e19[q][c];
+        const int nz = std::abs((int)e[q][0]) + std::abs((int)e[q][1]) + std::abs((int)e[q][2]);
+        if (Q == 9) t[q] = nz == 0 ? 4.0 / 9.0 : (nz == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+        else t[q] = nz == 0 ? 1.0 / 3.0 : (nz == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+    // exact sum of the moving weights by Knuth's TwoSum, then 1 - sum (representable)
+    double hi = 0.0, lo = 0.0;
+    for (int q = 1; q < Q; ++q) {
+        const double s = hi + t[q];
+        const double bb = s - hi;
+        lo += (hi - (s - bb)) + (t[q] - bb);
+        hi = s;
+    }
+    t[0] = (1.0 - hi) - lo;
+    for (int q = 0; q < Q; ++q) {
+        opp[q] = -1;
+        for (int r = 0; r < Q; ++r)
+            if (e[r][0] == -e[q][0] && e[r][1] == -e[q][1] && e[r][2] == -e[q][2]) opp[q] = r;
+    }
+}
+
+uint64_t splitmix64(uint64_t x) {  // Steele, Lea & Flood (2014), one output from state x
+    uint64_t z = x + 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// error handling
+// ------------------------------------------------------------------------------------------
+slbm_status slbm_ctx::fail(slbm_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return s;
+}
+
+slbm_status slbm_ctx::hip_check(int e, const char *what) {
+    if (e == 0) return SLBM_OK;
+    return fail(SLBM_EDEVICE, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+// ------------------------------------------------------------------------------------------
+// element-line helpers (host)
+// ------------------------------------------------------------------------------------------
+int slbm_ctx::stride(int a) const { return a == 0 ? 1 : (a == 1 ? Np : Np * Np); }
+int slbm_ctx::along(int n, int a) const { return (n / stride(a)) % Np; }
+
+double slbm_ctx::dline(const double *h, int n, int a) const {
+    const int s = stride(a), i = along(n, a), base = n - i * s;
+    double acc = 0.0;
+    for (int m = 0; m < Np; ++m) acc = std::fma(Dm[i * Np + m], h[base + m * s], acc);
+    return acc;
+}
+
+// ------------------------------------------------------------------------------------------
+// create / mesh
+// ------------------------------------------------------------------------------------------
+extern "C" slbm_status slbm_create(const slbm_params *p, slbm_ctx **out) {
+    if (!out) return SLBM_EINVAL;
+    *out = nullptr;
+    if (!p) return SLBM_EINVAL;
+    slbm_ctx *c = new (std::nothrow) slbm_ctx();
+    if (!c) return SLBM_ENOMEM;
+    c->prm = *p;
+    if (p->lattice != 9 && p->lattice != 19) {
+        c->fail(SLBM_EINVAL, "lattice must be 9 (D2Q9) or 19 (D3Q19)");
+        delete c;
+        return SLBM_EINVAL;
+    }
+    c->Q = p->lattice;
+    c->dim = c->Q == 9 ? 2 : 3;
+    c->N = p->N;
+    if (!supported_order(c->dim, c->N)) {
+        delete c;
+        return SLBM_EINVAL;
+    }
+    const double dr = p->rho_l - p->rho_v;
+    if (!(dr > 0.0) || !(p->delta > 0.0) || !(p->sigma > 0.0) || !(p->tau > 0.0) ||
+        !(p->dt > 0.0 || p->cfl > 0.0)) {
+        delete c;
+        return SLBM_EINVAL;
+    }
+    c->Np = c->N + 1;
+    c->nloc = nloc_of(c->dim, c->N);
+    // (A.4)-(A.5) solved for beta and kappa with gamma = sigma
+    c->beta = 12.0 * p->sigma / (p->delta * dr * dr * dr * dr);
+    c->kappa = 3.0 * p->sigma * p->delta / (2.0 * dr * dr);
+    c->omega = 1.0 / (p->tau + 0.5);
+    lattice_tables(c->Q, c->ev, c->tw, c->opp);
+    for (int q = 0; q < c->Q; ++q) c->tc[q] = 3.0 * c->tw[q];
+    gll_tables(c->N, c->xi, c->wq, c->Dm);
+    c->wn.resize(c->nloc);
+    for (int n = 0; n < c->nloc; ++n) {
+        double pw = c->wq[c->along(n, 0)] * c->wq[c->along(n, 1)];
+        if (c->dim == 3) pw = pw * c->wq[c->along(n, 2)];
+        c->wn[n] = pw;
+    }
+    *out = c;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, const int32_t *gid,
+                                     int64_t n_global, int64_t n_wall_faces,
+                                     const int32_t *wall_face, const double *wall_cos,
+                                     const double *wall_ub) {
+    if (!c) return SLBM_EINVAL;
+    if (c->bound) return c->fail(SLBM_ESTATE, "set_mesh after bind");
+    const int dim = c->dim, nloc = c->nloc, Q = c->Q, N = c->N;
+    if (E <= 0 || !xyz || !gid || n_global <= 0 || n_wall_faces < 0 ||
+        (n_wall_faces > 0 && (!wall_face || !wall_cos)))
+        return c->fail(SLBM_EINVAL, "bad mesh arguments");
+    if (E * (int64_t)nloc >= (int64_t)1 << 31 || n_global >= (int64_t)1 << 31)
+        return c->fail(SLBM_EINVAL, "mesh too large for 32-bit indices");
+    const int64_t Nl = E * nloc;
+    // --- ids: internal numbering by first appearance in local order ---
+    std::vector<int32_t> ug2ig(n_global, -1);
+    c->ig2ug.clear();
+    c->lgid.assign(Nl, 0);
+    for (int64_t l = 0; l < Nl; ++l) {
+        const int32_t g = gid[l];
+        if (g < 0 || g >= n_global) return c->fail(SLBM_EINVAL, "global id %d out of range", g);
+        if (ug2ig[g] < 0) {
+            ug2ig[g] = (int32_t)c->ig2ug.size();
+            c->ig2ug.push_back(g);
+        }
+        c->lgid[l] = ug2ig[g];
+    }
+    if ((int64_t)c->ig2ug.size() != n_global)
+        return c->fail(SLBM_EINVAL, "global ids are not contiguous (%zu of %lld used)",
+                       c->ig2ug.size(), (long long)n_global);
+    c->E = E;
+    c->Nl = Nl;
+    c->Ng = n_global;
+    // DSS gather lists: local copies of each global node in ascending local order
+    c->csr_ptr.assign(n_global + 1, 0);
+    for (int64_t l = 0; l < Nl; ++l) c->csr_ptr[c->lgid[l] + 1]++;
+    for (int64_t g = 0; g < n_global; ++g) c->csr_ptr[g + 1] += c->csr_ptr[g];
+    c->csr_idx.assign(Nl, 0);
+    {
+        std::vector<int32_t> fill(c->csr_ptr.begin(), c->csr_ptr.end() - 1);
+        for (int64_t l = 0; l < Nl; ++l) c->csr_idx[fill[c->lgid[l]]++] = (int32_t)l;
+    }
+    c->xyz.assign(xyz, xyz + Nl * dim);
+    // --- metric terms, Jacobian, G, lumped mass ---
+    const int ng = dim * (dim + 1) / 2;
+    c->Ja.assign((size_t)dim * dim * Nl, 0.0);
+    c->Gm.assign((size_t)ng * Nl, 0.0);
+    std::vector<double> MA(n_global, 0.0);
+    std::vector<double> X(3 * nloc), dX(9 * nloc), V(3 * nloc), J(nloc);
+    double hmin = INFINITY;
+    std::vector<double> Jloc(9 * nloc);
+    for (int64_t e = 0; e < E; ++e) {
+        for (int n = 0; n < nloc; ++n)
+            for (int cc = 0; cc < dim; ++cc) X[cc * nloc + n] = xyz[(e * nloc + n) * dim + cc];
+        for (int cc = 0; cc < dim; ++cc)
+            for (int a = 0; a < dim; ++a)
+                for (int n = 0; n < nloc; ++n) dX[(cc * 3 + a) * nloc + n] = c->dline(&X[cc * nloc], n, a);
+        if (dim == 2) {
+            for (int n = 0; n < nloc; ++n) {
+                const double xa = dX[0 * nloc + n], xb = dX[1 * nloc + n];
+                const double ya = dX[3 * nloc + n], yb = dX[4 * nloc + n];
+                double *Jn = &Jloc[9 * n];
+                Jn[0] = yb; Jn[1] = -xb;   // J grad(xi)
+                Jn[3] = -ya; Jn[4] = xa;   // J grad(eta)
+                J[n] = xa * yb - xb * ya;
+            }
+        } else {
+            // conservative curl form (Kopriva 2006): J grad(xi_i)_c = -[curl_xi(x_l grad_xi x_m)]_i
+            for (int cn = 0; cn < 3; ++cn) {
+                const int cm = (cn + 1) % 3, cl = (cn + 2) % 3;
+                for (int k = 0; k < 3; ++k)
+                    for (int n = 0; n < nloc; ++n)
+                        V[k * nloc + n] = X[cl * nloc + n] * dX[(cm * 3 + k) * nloc + n];
+                for (int n = 0; n < nloc; ++n) {
+                    const double c0 = c->dline(&V[2 * nloc], n, 1) - c->dline(&V[1 * nloc], n, 2);
+                    const double c1 = c->dline(&V[0 * nloc], n, 2) - c->dline(&V[2 * nloc], n, 0);
+                    const double c2 = c->dline(&V[1 * nloc], n, 0) - c->dline(&V[0 * nloc], n, 1);
+                    Jloc[9 * n + 0 * 3 + cn] = -c0;
+                    Jloc[9 * n + 1 * 3 + cn] = -c1;
+                    Jloc[9 * n + 2 * 3 + cn] = -c2;
+                }
+            }
+            for (int n = 0; n < nloc; ++n) {
+                const double a0 = dX[0 * nloc + n], a1 = dX[3 * nloc + n], a2 = dX[6 * nloc + n];
+                const double b0 = dX[1 * nloc + n], b1 = dX[4 * nloc + n], b2 = dX[7 * nloc + n];
+                const double d0 = dX[2 * nloc + n], d1 = dX[5 * nloc + n], d2 = dX[8 * nloc + n];
+                const double cx = b1 * d2 - b2 * d1, cy = b2 * d0 - b0 * d2, cz = b0 * d1 - b1 * d0;
+                J[n] = a0 * cx + a1 * cy + a2 * cz;
+            }
+        }
+        for (int n = 0; n < nloc; ++n) {
+            const int64_t l = e * nloc + n;
+            if (!(J[n] > 0.0))
+                return c->fail(SLBM_EINVAL, "non-positive Jacobian %g in element %lld node %d", J[n],
+                               (long long)e, n);
+            for (int a = 0; a < dim; ++a)
+                for (int cc = 0; cc < dim; ++cc) c->Ja[(size_t)(a * dim + cc) * Nl + l] = Jloc[9 * n + a * 3 + cc];
+            int k = 0;
+            for (int a = 0; a < dim; ++a)
+                for (int b = a; b < dim; ++b) {
+                    double s = 0.0;
+                    for (int cc = 0; cc < dim; ++cc) s += Jloc[9 * n + a * 3 + cc] * Jloc[9 * n + b * 3 + cc];
+                    c->Gm[(size_t)k * Nl + l] = c->wn[n] * s / J[n];
+                    ++k;
+                }
+            MA[c->lgid[l]] += c->wn[n] * J[n];
+        }
+        for (int a = 0; a < dim; ++a) {
+            const int s = c->stride(a);
+            for (int n = 0; n < nloc; ++n) {
+                if (c->along(n, a) == N) continue;
+                double d2 = 0.0;
+                for (int cc = 0; cc < dim; ++cc) {
+                    const double dd = X[cc * nloc + n + s] - X[cc * nloc + n];
+                    d2 += dd * dd;
+                }
+                const double d = std::sqrt(d2);
+                if (d < hmin) hmin = d;
+            }
+        }
+        // keep the element's metric for the wall tables below
+        if (n_wall_faces > 0) {
+            // (nothing: wall tables read c->Ja directly)
+        }
+    }
+    // MA accumulated in local order over the internal numbering equals the caller-order sum
+    c->Minv.resize(n_global);
+    c->MA = MA;
+    for (int64_t g = 0; g < n_global; ++g) c->Minv[g] = 1.0 / MA[g];
+    c->hmin = hmin;
+    c->dt = c->prm.dt > 0.0 ? c->prm.dt : c->prm.cfl * hmin;
+    if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return c->fail(SLBM_EINVAL, "invalid time step");
+    // --- wall tables: one entry per (face, face node), grouped by element in face order ---
+    const double sq = std::sqrt(2.0 * c->beta / c->kappa);
+    struct WE { int64_t e; int64_t order; int node; double lap; double cn[kMaxQ]; double eub[kMaxQ]; };
+    std::vector<WE> ents;
+    int64_t order = 0;
+    for (int64_t fidx = 0; fidx < n_wall_faces; ++fidx) {
+        const int64_t e = wall_face[2 * fidx];
+        const int face = wall_face[2 * fidx + 1];
+        if (e < 0 || e >= E || face < 0 || face >= 2 * dim)
+            return c->fail(SLBM_EINVAL, "wall face %lld: bad element or face", (long long)fidx);
+        const int a = face / 2, side = face % 2;
+        const double sign = side ? 1.0 : -1.0;
+        double ub[3] = {0.0, 0.0, 0.0};
+        if (wall_ub)
+            for (int cc = 0; cc < dim; ++cc) ub[cc] = wall_ub[fidx * dim + cc];
+        for (int n = 0; n < nloc; ++n) {
+            if (c->along(n, a) != (side ? N : 0)) continue;
+            double wf = 1.0;
+            for (int b = 0; b < dim; ++b)
+                if (b != a) wf = wf * c->wq[c->along(n, b)];
+            const int64_t l = e * nloc + n;
+            double Jv[3], sn[3] = {0.0, 0.0, 0.0};
+            double nrm2 = 0.0;
+            for (int cc = 0; cc < dim; ++cc) {
+                Jv[cc] = c->Ja[(size_t)(a * dim + cc) * Nl + l];
+                nrm2 += Jv[cc] * Jv[cc];
+            }
+            for (int cc = 0; cc < dim; ++cc) sn[cc] = sign * wf * Jv[cc];
+            const double s = wf * std::sqrt(nrm2);
+            WE w;
+            w.e = e;
+            w.order = order++;
+            w.node = n;
+            w.lap = s * wall_cos[fidx] * sq;
+            for (int q = 0; q < Q; ++q) {
+                double cn = 0.0, eu = 0.0;
+                for (int cc = 0; cc < dim; ++cc) cn += sn[cc] * c->ev[q][cc];
+                for (int cc = 0; cc < dim; ++cc) eu += c->ev[q][cc] * ub[cc];
+                w.cn[q] = cn;
+                w.eub[q] = eu;
+            }
+            ents.push_back(w);
+        }
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const WE &x, const WE &y) { return x.e < y.e; });
+    c->nw = (int64_t)ents.size();
+    c->wel_ptr.assign(E + 1, 0);
+    c->w_node.resize(c->nw);
+    c->w_lap.resize(c->nw);
+    c->w_cn.resize((size_t)c->nw * Q);
+    c->w_eub.resize((size_t)c->nw * Q);
+    for (int64_t k = 0; k < c->nw; ++k) {
+        c->wel_ptr[ents[k].e + 1]++;
+        c->w_node[k] = ents[k].node;
+        c->w_lap[k] = ents[k].lap;
+        for (int q = 0; q < Q; ++q) {
+            c->w_cn[k * Q + q] = ents[k].cn[q];
+            c->w_eub[k * Q + q] = ents[k].eub[q];
+        }
+    }
+    for (int64_t e = 0; e < E; ++e) c->wel_ptr[e + 1] += c->wel_ptr[e];
+    c->has_mesh = true;
+    c->layout();
+    return SLBM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// workspace
+// ------------------------------------------------------------------------------------------
+void slbm_ctx::layout() {
+    const int dim_ = dim, Q_ = Q;
+    const size_t ng = (size_t)dim_ * (dim_ + 1) / 2;
+    off = Offsets();
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    n_eblocks = (int)((E + epb_of(dim_, N) - 1) / epb_of(dim_, N));
+    n_nblocks = (int)((Ng + kNodeThreads - 1) / kNodeThreads);
+    off.desc = take(sizeof(SolveDesc));
+    off.eplan = take(sizeof(int) * 2 * (size_t)n_eblocks);
+    off.nplan = take(sizeof(int) * 2 * (size_t)n_nblocks);
+    off.lgid = take(sizeof(int) * Nl);
+    off.csr_ptr = take(sizeof(int) * (Ng + 1));
+    off.csr_idx = take(sizeof(int) * Nl);
+    off.wel_ptr = take(sizeof(int) * (E + 1));
+    off.w_node = take(sizeof(int) * std::max<int64_t>(nw, 1));
+    off.Ja = take(sizeof(double) * dim_ * dim_ * Nl);
+    off.G = take(sizeof(double) * ng * Nl);
+    off.Minv = take(sizeof(double) * Ng);
+    off.Dm = take(sizeof(double) * Np * Np);
+    off.wn = take(sizeof(double) * nloc);
+    off.w_lap = take(sizeof(double) * std::max<int64_t>(nw, 1));
+    off.w_cn = take(sizeof(double) * Q_ * std::max<int64_t>(nw, 1));
+    off.w_eub = take(sizeof(double) * Q_ * std::max<int64_t>(nw, 1));
+    off.f = take(sizeof(double) * Q_ * Ng);
+    off.g0 = take(sizeof(double) * Q_ * Ng);
+    off.gA = take(sizeof(double) * Q_ * Ng);
+    off.rho = take(sizeof(double) * Ng);
+    off.mu = take(sizeof(double) * Ng);
+    off.rl = take(sizeof(double) * Nl);
+    off.gl = take(sizeof(double) * 2 * dim_ * Nl);
+    off.rs = take(sizeof(double) * (Q_ - 1) * Nl);
+    off.aux = take(sizeof(double) * 2 * dim_ * Ng);
+    off.diag = take(sizeof(double) * 4);
+    off.red = take(sizeof(double) * 2 * (size_t)n_nblocks);
+    ws_bytes = o;
+}
+
+extern "C" size_t slbm_workspace_bytes(const slbm_ctx *c) { return (c && c->has_mesh) ? c->ws_bytes : 0; }
+
+template <class T> static T *at(void *base, size_t off) { return reinterpret_cast<T *>((char *)base + off); }
+
+extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
+    if (!c) return SLBM_EINVAL;
+    if (!c->has_mesh) return c->fail(SLBM_ESTATE, "bind before set_mesh");
+    if (c->bound) return c->fail(SLBM_ESTATE, "already bound");
+    if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return c->fail(SLBM_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < c->ws_bytes)
+        return c->fail(SLBM_ENOMEM, "workspace %zu bytes < required %zu", bytes, c->ws_bytes);
+    c->dev = dev_ptr;
+    c->stream = hip_stream;
+    hipStream_t st = (hipStream_t)hip_stream;
+    void *b = dev_ptr;
+    SolveDesc &d = c->desc;
+    std::memset(&d, 0, sizeof d);
+    d.E = (int)c->E;
+    d.Nl = (int)c->Nl;
+    d.Ng = (int)c->Ng;
+    d.lgid = at<int>(b, c->off.lgid);
+    d.Ja = at<double>(b, c->off.Ja);
+    d.G = at<double>(b, c->off.G);
+    d.Minv = at<double>(b, c->off.Minv);
+    d.csr_ptr = at<int>(b, c->off.csr_ptr);
+    d.csr_idx = at<int>(b, c->off.csr_idx);
+    d.wel_ptr = at<int>(b, c->off.wel_ptr);
+    d.w_node = at<int>(b, c->off.w_node);
+    d.w_lap = at<double>(b, c->off.w_lap);
+    d.w_cn = at<double>(b, c->off.w_cn);
+    d.w_eub = at<double>(b, c->off.w_eub);
+    d.Dm = at<double>(b, c->off.Dm);
+    d.wn = at<double>(b, c->off.wn);
+    d.f = at<double>(b, c->off.f);
+    d.g0 = at<double>(b, c->off.g0);
+    d.gA = at<double>(b, c->off.gA);
+    d.rho = at<double>(b, c->off.rho);
+    d.mu = at<double>(b, c->off.mu);
+    d.rl = at<double>(b, c->off.rl);
+    d.gl = at<double>(b, c->off.gl);
+    d.rs = at<double>(b, c->off.rs);
+    d.aux = at<double>(b, c->off.aux);
+    d.diag = at<double>(b, c->off.diag);
+    d.red = at<double>(b, c->off.red);
+    d.rho_l = c->prm.rho_l;
+    d.rho_v = c->prm.rho_v;
+    d.beta = c->beta;
+    d.kappa = c->kappa;
+    d.omega = c->omega;
+    d.dt = c->dt;
+    for (int q = 0; q < c->Q; ++q) {
+        d.t[q] = c->tw[q];
+        d.tc[q] = c->tc[q];
+    }
+    // block tables of the single-member plans
+    std::vector<int> ep(2 * (size_t)c->n_eblocks), np_(2 * (size_t)c->n_nblocks);
+    for (int i = 0; i < c->n_eblocks; ++i) { ep[i] = 0; ep[c->n_eblocks + i] = i; }
+    for (int i = 0; i < c->n_nblocks; ++i) { np_[i] = 0; np_[c->n_nblocks + i] = i; }
+    c->eplan.desc = at<SolveDesc>(b, c->off.desc);
+    c->eplan.blk_solve = at<int>(b, c->off.eplan);
+    c->eplan.blk_local = at<int>(b, c->off.eplan) + c->n_eblocks;
+    c->eplan.nblocks = c->n_eblocks;
+    c->nplan.desc = at<SolveDesc>(b, c->off.desc);
+    c->nplan.blk_solve = at<int>(b, c->off.nplan);
+    c->nplan.blk_local = at<int>(b, c->off.nplan) + c->n_nblocks;
+    c->nplan.nblocks = c->n_nblocks;
+    const int Q = c->Q, dim = c->dim;
+    const size_t ng = (size_t)dim * (dim + 1) / 2;
+    int e = 0;
+    auto up = [&](size_t off, const void *src, size_t n) {
+        if (e == 0 && n) e = (int)hipMemcpyAsync((char *)b + off, src, n, hipMemcpyHostToDevice, st);
+    };
+    up(c->off.desc, &d, sizeof d);
+    up(c->off.eplan, ep.data(), sizeof(int) * ep.size());
+    up(c->off.nplan, np_.data(), sizeof(int) * np_.size());
+    up(c->off.lgid, c->lgid.data(), sizeof(int) * c->Nl);
+    up(c->off.csr_ptr, c->csr_ptr.data(), sizeof(int) * (c->Ng + 1));
+    up(c->off.csr_idx, c->csr_idx.data(), sizeof(int) * c->Nl);
+    up(c->off.wel_ptr, c->wel_ptr.data(), sizeof(int) * (c->E + 1));
+    up(c->off.w_node, c->w_node.data(), sizeof(int) * c->nw);
+    up(c->off.Ja, c->Ja.data(), sizeof(double) * dim * dim * c->Nl);
+    up(c->off.G, c->Gm.data(), sizeof(double) * ng * c->Nl);
+    up(c->off.Minv, c->Minv.data(), sizeof(double) * c->Ng);
+    up(c->off.Dm, c->Dm.data(), sizeof(double) * c->Np * c->Np);
+    up(c->off.wn, c->wn.data(), sizeof(double) * c->nloc);
+    up(c->off.w_lap, c->w_lap.data(), sizeof(double) * c->nw);
+    up(c->off.w_cn, c->w_cn.data(), sizeof(double) * Q * c->nw);
+    up(c->off.w_eub, c->w_eub.data(), sizeof(double) * Q * c->nw);
+    if (e == 0) e = (int)hipMemsetAsync((char *)b + c->off.f, 0, c->off.diag - c->off.f, st);
+    if (e == 0) e = (int)hipStreamSynchronize(st);
+    if (e) return c->hip_check(e, "bind upload");
+    c->bound = true;
+    c->has_state = false;
+    c->step = 0;
+    const char *nog = std::getenv("SLBM_NO_GRAPH");
+    c->use_graph = !(nog && nog[0] == '1');
+    return SLBM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// state
+// ------------------------------------------------------------------------------------------
+slbm_status slbm_ctx::upload_f_and_density(const std::vector<double> &f_int) {
+    hipStream_t st = (hipStream_t)stream;
+    int e = (int)hipMemcpyAsync(desc.f, f_int.data(), sizeof(double) * Q * Ng, hipMemcpyHostToDevice, st);
+    if (e == 0) e = launch_density(dim, N, nplan, 0, stream);
+    if (e == 0) e = (int)hipStreamSynchronize(st);
+    if (e) return hip_check(e, "upload state");
+    has_state = true;
+    return SLBM_OK;
+}
+
+slbm_status slbm_ctx::require_bound(bool need_state) {
+    if (!bound) return fail(SLBM_ESTATE, "context is not bound");
+    if (need_state && !has_state) return fail(SLBM_ESTATE, "no state: call init_tanh, set_rho or set_state");
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_set_rho(slbm_ctx *c, const double *rho) {
+    if (!c || !rho) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(false)) return s;
+    std::vector<double> f((size_t)c->Q * c->Ng);
+    for (int64_t g = 0; g < c->Ng; ++g) {
+        const double r = rho[c->ig2ug[g]];
+        for (int q = 0; q < c->Q; ++q) f[(size_t)q * c->Ng + g] = c->tw[q] * r;
+    }
+    c->step = 0;
+    return c->upload_f_and_density(f);
+}
+
+extern "C" slbm_status slbm_init_tanh(slbm_ctx *c, const double *x0, double R, double noise_amp,
+                                      uint64_t seed) {
+    if (!c || !x0) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(false)) return s;
+    const int dim = c->dim;
+    const double rl = c->prm.rho_l, rv = c->prm.rho_v, dl = c->prm.delta;
+    std::vector<double> rho_user(c->Ng);
+    for (int64_t g = 0; g < c->Ng; ++g) {
+        const int64_t l = c->csr_idx[c->csr_ptr[g]];  // lowest local copy
+        double r2 = 0.0;
+        for (int cc = 0; cc < dim; ++cc) {
+            const double d = c->xyz[l * dim + cc] - x0[cc];
+            r2 += d * d;
+        }
+        const double x = std::sqrt(r2) - R;
+        double p = 0.5 * (rl + rv) - 0.5 * (rl - rv) * std::tanh(2.0 * x / dl);
+        const uint64_t ug = (uint64_t)c->ig2ug[g];
+        if (noise_amp != 0.0) {
+            const uint64_t h = splitmix64(seed ^ ug);
+            const double U = (double)(h >> 11) * 0x1.0p-53;
+            p += noise_amp * (2.0 * U - 1.0);
+        }
+        rho_user[ug] = p;
+    }
+    return slbm_set_rho(c, rho_user.data());
+}
+
+extern "C" slbm_status slbm_get_state(slbm_ctx *c, double *f, int64_t *step) {
+    if (!c || !f) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(true)) return s;
+    std::vector<double> fi((size_t)c->Q * c->Ng);
+    int e = (int)hipMemcpyAsync(fi.data(), c->desc.f, sizeof(double) * fi.size(), hipMemcpyDeviceToHost,
+                                (hipStream_t)c->stream);
+    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+    if (e) return c->hip_check(e, "get_state");
+    for (int q = 0; q < c->Q; ++q)
+        for (int64_t g = 0; g < c->Ng; ++g) f[(size_t)q * c->Ng + c->ig2ug[g]] = fi[(size_t)q * c->Ng + g];
+    if (step) *step = c->step;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_set_state(slbm_ctx *c, const double *f, int64_t step) {
+    if (!c || !f) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(false)) return s;
+    std::vector<double> fi((size_t)c->Q * c->Ng);
+    for (int q = 0; q < c->Q; ++q)
+        for (int64_t g = 0; g < c->Ng; ++g) fi[(size_t)q * c->Ng + g] = f[(size_t)q * c->Ng + c->ig2ug[g]];
+    c->step = step;
+    return c->upload_f_and_density(fi);
+}
+
+// ------------------------------------------------------------------------------------------
+// time step
+// ------------------------------------------------------------------------------------------
+int slbm::enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &np, int64_t n,
+                        void *stream) {
+    int e = 0;
+    for (int64_t s = 0; s < n && e == 0; ++s) {
+        // chemical potential of the state's density (also stage 1's, R10)
+        e = launch_lap(d, N, ep, stream);
+        if (!e) e = launch_mu(d, N, np, stream);
+        // collision with averaged gradients
+        if (!e) e = launch_grad(d, N, ep, stream);
+        if (!e) e = launch_collide(d, N, np, 0, stream);
+        // three SSP-RK3 streaming stages
+        for (int stage = 1; stage <= 3 && !e; ++stage) {
+            if (stage > 1) {
+                e = launch_lap(d, N, ep, stream);
+                if (!e) e = launch_mu(d, N, np, stream);
+            }
+            if (!e) e = launch_stream(d, N, ep, stage, stream);
+            if (!e) e = launch_rk(d, N, np, stage, stream);
+        }
+    }
+    return e;
+}
+
+slbm_status slbm_ctx::read_diag(double *ke, double *mass) {
+    hipStream_t st = (hipStream_t)stream;
+    int e = launch_diag(dim, N, nplan, stream);
+    if (e == 0) e = launch_diag_final(eplan.desc, 1, stream);
+    double h[2] = {0.0, 0.0};
+    if (e == 0) e = (int)hipMemcpyAsync(h, desc.diag, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == 0) e = (int)hipStreamSynchronize(st);
+    if (e) return hip_check(e, "kinetic energy");
+    if (ke) *ke = h[0];
+    if (mass) *mass = h[1];
+    return SLBM_OK;
+}
+
+int slbm::capture_graph(void *stream, void **exec, int (*fn)(void *, void *), void *arg) {
+    hipStream_t st = (hipStream_t)stream;
+    hipGraph_t g = nullptr;
+    int e = (int)hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e) return e;
+    const int e1 = fn(stream, arg);
+    e = (int)hipStreamEndCapture(st, &g);
+    if (e1) e = e1;
+    if (e == 0) {
+        hipGraphExec_t x = nullptr;
+        e = (int)hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e == 0) *exec = (void *)x;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+int slbm::launch_graph(void *exec, void *stream) {
+    return (int)hipGraphLaunch((hipGraphExec_t)exec, (hipStream_t)stream);
+}
+
+void slbm::destroy_graph(void *exec) {
+    if (exec) (void)hipGraphExecDestroy((hipGraphExec_t)exec);
+}
+
+slbm_ctx::~slbm_ctx() {
+    destroy_graph(graph[0]);
+    destroy_graph(graph[1]);
+}
+
+// n steps: replay captured graphs when the stream can be captured, plain launches otherwise
+slbm_status slbm_ctx::enqueue(int64_t n) {
+    if (use_graph && stream != nullptr && n > 0) {
+        const int sizes[2] = {1, kGraphSteps};
+        for (int k = 0; k < 2; ++k)
+            if (!graph[k]) {
+                struct A { slbm_ctx *c; int steps; } a{this, sizes[k]};
+                auto fn = [](void *st, void *p) -> int {
+                    A *x = (A *)p;
+                    return enqueue_steps(x->c->dim, x->c->N, x->c->eplan, x->c->nplan, x->steps, st);
+                };
+                const int e = capture_graph(stream, &graph[k], fn, &a);
+                if (e) {  // capture unsupported here: fall back to plain launches for good
+                    (void)hipGetLastError();
+                    use_graph = false;
+                    destroy_graph(graph[0]);
+                    destroy_graph(graph[1]);
+                    graph[0] = graph[1] = nullptr;
+                    break;
+                }
+            }
+        if (use_graph) {
+            int64_t left = n;
+            int e = 0;
+            while (left >= kGraphSteps && !e) { e = launch_graph(graph[1], stream); left -= kGraphSteps; }
+            while (left > 0 && !e) { e = launch_graph(graph[0], stream); left -= 1; }
+            return hip_check(e, "graph launch");
+        }
+    }
+    return hip_check(enqueue_steps(dim, N, eplan, nplan, n, stream), "step launch");
+}
+
+extern "C" slbm_status slbm_step(slbm_ctx *c, int64_t n) {
+    if (!c || n < 0) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(true)) return s;
+    const int every = c->prm.ke_every;
+    const double lim = c->prm.ke_limit > 0.0 ? c->prm.ke_limit : 1.0;
+    int64_t done = 0;
+    while (done < n) {
+        int64_t chunk = n - done;
+        if (every > 0) chunk = std::min<int64_t>(chunk, every - (c->step % every));
+        if (slbm_status s = c->enqueue(chunk)) return s;
+        done += chunk;
+        c->step += chunk;
+        if (every > 0 && c->step % every == 0) {
+            double ke = 0.0;
+            if (slbm_status s = c->read_diag(&ke, nullptr)) return s;
+            if (!(ke <= lim)) return c->fail(SLBM_EDIVERGED, "KE_max = %g at step %lld", ke, (long long)c->step);
+        }
+    }
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
+    if (!c || n < 0 || !ms || !launches) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(true)) return s;
+    hipStream_t st = (hipStream_t)c->stream;
+    constexpr int kPerStep = 14;
+    hipEvent_t ev[2 * kPerStep];
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return c->fail(SLBM_EDEVICE, "event create");
+    for (int k = 0; k < SLBM_NUM_KERNEL_KINDS; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    const int d = c->dim, N = c->N;
+    int kinds[kPerStep];
+    int e = 0;
+    for (int64_t s = 0; s < n && e == 0; ++s) {
+        int i = 0;
+        auto rec = [&](int kind, auto &&fn) {
+            if (e) return;
+            e = (int)hipEventRecord(ev[2 * i], st);
+            if (!e) e = fn();
+            if (!e) e = (int)hipEventRecord(ev[2 * i + 1], st);
+            kinds[i++] = kind;
+        };
+        rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
+        rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
+        rec(2, [&] { return launch_grad(d, N, c->eplan, c->stream); });
+        rec(3, [&] { return launch_collide(d, N, c->nplan, 0, c->stream); });
+        for (int stage = 1; stage <= 3; ++stage) {
+            if (stage > 1) {
+                rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
+                rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
+            }
+            rec(4, [&] { return launch_stream(d, N, c->eplan, stage, c->stream); });
+            rec(5, [&] { return launch_rk(d, N, c->nplan, stage, c->stream); });
+        }
+        if (!e) e = (int)hipEventSynchronize(ev[2 * i - 1]);
+        for (int j = 0; j < i && !e; ++j) {
+            float t = 0.0f;
+            e = (int)hipEventElapsedTime(&t, ev[2 * j], ev[2 * j + 1]);
+            ms[kinds[j]] += t;
+            launches[kinds[j]] += 1;
+        }
+        c->step += 1;
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    return c->hip_check(e, "step_profile");
+}
+
+// ------------------------------------------------------------------------------------------
+// queries
+// ------------------------------------------------------------------------------------------
+extern "C" slbm_status slbm_get_rho(slbm_ctx *c, double *rho) {
+    if (!c || !rho) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(true)) return s;
+    std::vector<double> r(c->Ng);
+    int e = (int)hipMemcpyAsync(r.data(), c->desc.rho, sizeof(double) * c->Ng, hipMemcpyDeviceToHost,
+                                (hipStream_t)c->stream);
+    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+    if (e) return c->hip_check(e, "get_rho");
+    for (int64_t g = 0; g < c->Ng; ++g) rho[c->ig2ug[g]] = r[g];
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_get_u(slbm_ctx *c, double *u) {
+    if (!c || !u) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(true)) return s;
+    std::vector<double> f((size_t)c->Q * c->Ng);
+    int e = (int)hipMemcpyAsync(f.data(), c->desc.f, sizeof(double) * f.size(), hipMemcpyDeviceToHost,
+                                (hipStream_t)c->stream);
+    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+    if (e) return c->hip_check(e, "get_u");
+    // Eq. (11) on the host from the downloaded state (a query, not part of the step)
+    for (int64_t g = 0; g < c->Ng; ++g) {
+        double p = 0.0;
+        for (int q = 0; q < c->Q; ++q) p += f[(size_t)q * c->Ng + g];
+        for (int cc = 0; cc < c->dim; ++cc) {
+            double m = 0.0;
+            for (int q = 0; q < c->Q; ++q) m += f[(size_t)q * c->Ng + g] * c->ev[q][cc];
+            u[(size_t)cc * c->Ng + c->ig2ug[g]] = m / p;
+        }
+    }
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_kinetic_energy(slbm_ctx *c, double *ke_max, double *mass) {
+    if (!c) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(true)) return s;
+    return c->read_diag(ke_max, mass);
+}
+
+extern "C" slbm_status slbm_get_info(const slbm_ctx *c, slbm_info *info) {
+    if (!c || !info) return SLBM_EINVAL;
+    std::memset(info, 0, sizeof *info);
+    info->dt = c->dt;
+    info->beta = c->beta;
+    info->kappa = c->kappa;
+    info->omega = c->omega;
+    info->h_min = c->hmin;
+    info->n_elements = c->E;
+    info->n_local = c->Nl;
+    info->n_global = c->Ng;
+    info->n_wall_nodes = c->nw;
+    info->step = c->step;
+    info->workspace_bytes = c->has_mesh ? c->ws_bytes : 0;
+    info->dim = c->dim;
+    info->Q = c->Q;
+    info->N = c->N;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_get_gll(const slbm_ctx *c, double *x, double *w, double *D) {
+    if (!c || !x || !w || !D) return SLBM_EINVAL;
+    std::memcpy(x, c->xi.data(), sizeof(double) * c->Np);
+    std::memcpy(w, c->wq.data(), sizeof(double) * c->Np);
+    std::memcpy(D, c->Dm.data(), sizeof(double) * c->Np * c->Np);
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_get_mass(const slbm_ctx *c, double *MA) {
+    if (!c || !MA) return SLBM_EINVAL;
+    if (!c->has_mesh) return SLBM_ESTATE;
+    for (int64_t g = 0; g < c->Ng; ++g) MA[c->ig2ug[g]] = c->MA[g];
+    return SLBM_OK;
+}
+
+extern "C" const char *slbm_last_error(const slbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" void slbm_destroy(slbm_ctx *c) { delete c; }
+
+// ------------------------------------------------------------------------------------------
+// operator entry points
+// ------------------------------------------------------------------------------------------
+slbm_status slbm_ctx::put(double *dst, const double *src_user, int fields) {
+    std::vector<double> v((size_t)fields * Ng);
+    for (int k = 0; k < fields; ++k)
+        for (int64_t g = 0; g < Ng; ++g) v[(size_t)k * Ng + g] = src_user[(size_t)k * Ng + ig2ug[g]];
+    int e = (int)hipMemcpyAsync(dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice,
+                                (hipStream_t)stream);
+    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)stream);
+    return hip_check(e, "upload");
+}
+
+slbm_status slbm_ctx::get(const double *src, double *dst_user, int fields) {
+    std::vector<double> v((size_t)fields * Ng);
+    int e = (int)hipMemcpyAsync(v.data(), src, sizeof(double) * v.size(), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream);
+    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)stream);
+    if (e) return hip_check(e, "download");
+    for (int k = 0; k < fields; ++k)
+        for (int64_t g = 0; g < Ng; ++g) dst_user[(size_t)k * Ng + ig2ug[g]] = v[(size_t)k * Ng + g];
+    return SLBM_OK;
+}
+
+// the operators overwrite rho/mu/g0/gA scratch; the state's density is restored afterwards
+slbm_status slbm_ctx::restore_density() {
+    if (!has_state) return SLBM_OK;
+    int e = launch_density(dim, N, nplan, 0, stream);
+    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)stream);
+    return hip_check(e, "restore density");
+}
+
+extern "C" slbm_status slbm_op_mu(slbm_ctx *c, const double *rho, double *mu) {
+    if (!c || !rho || !mu) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(false)) return s;
+    if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
+    int e = launch_lap(c->dim, c->N, c->eplan, c->stream);
+    if (e == 0) e = launch_mu(c->dim, c->N, c->nplan, c->stream);
+    if (e) return c->hip_check(e, "op_mu");
+    if (slbm_status s = c->get(c->desc.mu, mu, 1)) return s;
+    return c->restore_density();
+}
+
+extern "C" slbm_status slbm_op_grad(slbm_ctx *c, const double *phi, double *grad) {
+    if (!c || !phi || !grad) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(false)) return s;
+    if (slbm_status s = c->put(c->desc.rho, phi, 1)) return s;
+    int e = launch_grad(c->dim, c->N, c->eplan, c->stream);
+    if (e == 0) e = launch_gavg(c->dim, c->N, c->nplan, c->stream);
+    if (e) return c->hip_check(e, "op_grad");
+    if (slbm_status s = c->get(c->desc.aux, grad, c->dim)) return s;
+    return c->restore_density();
+}
+
+extern "C" slbm_status slbm_op_stream(slbm_ctx *c, const double *g, const double *rho,
+                                      const double *mu, double *L) {
+    if (!c || !g || !rho || !mu || !L) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(false)) return s;
+    if (slbm_status s = c->put(c->desc.gA, g, c->Q)) return s;
+    if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
+    if (slbm_status s = c->put(c->desc.mu, mu, 1)) return s;
+    int e = launch_stream(c->dim, c->N, c->eplan, 2, c->stream);
+    if (e == 0) e = launch_rk(c->dim, c->N, c->nplan, 0, c->stream);  // stage 0: L into gA
+    if (e) return c->hip_check(e, "op_stream");
+    if (slbm_status s = c->get(c->desc.gA, L, c->Q)) return s;
+    return c->restore_density();
+}
+
+extern "C" slbm_status slbm_op_collide(slbm_ctx *c, const double *f, const double *rho,
+                                       const double *grho, const double *gmu, double *fstar) {
+    if (!c || !f || !rho || !grho || !gmu || !fstar) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(false)) return s;
+    // the collision kernel reads the state buffer: save it, run, restore
+    std::vector<double> saved;
+    if (c->has_state) {
+        saved.resize((size_t)c->Q * c->Ng);
+        int e = (int)hipMemcpyAsync(saved.data(), c->desc.f, sizeof(double) * saved.size(),
+                                    hipMemcpyDeviceToHost, (hipStream_t)c->stream);
+        if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+        if (e) return c->hip_check(e, "op_collide save");
+    }
+    std::vector<double> gg((size_t)2 * c->dim * c->Ng);
+    std::memcpy(gg.data(), grho, sizeof(double) * c->dim * c->Ng);
+    std::memcpy(gg.data() + (size_t)c->dim * c->Ng, gmu, sizeof(double) * c->dim * c->Ng);
+    if (slbm_status s = c->put(c->desc.f, f, c->Q)) return s;
+    if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
+    if (slbm_status s = c->put(c->desc.aux, gg.data(), 2 * c->dim)) return s;
+    int e = launch_collide(c->dim, c->N, c->nplan, 1, c->stream);
+    if (e) return c->hip_check(e, "op_collide");
+    if (slbm_status s = c->get(c->desc.g0, fstar, c->Q)) return s;
+    if (c->has_state) {
+        int e2 = (int)hipMemcpyAsync(c->desc.f, saved.data(), sizeof(double) * saved.size(),
+                                     hipMemcpyHostToDevice, (hipStream_t)c->stream);
+        if (e2 == 0) e2 = (int)hipStreamSynchronize((hipStream_t)c->stream);
+        if (e2) return c->hip_check(e2, "op_collide restore");
+    }
+    return c->restore_density();
+}

@@ -1,0 +1,556 @@
+// Batching, serving and the contact-angle query of the C ABI (include/semlbm.h).
+//
+// A batch groups its bound members by (dimension, N); every kernel of the time step runs
+// once per group and covers all of the group's members (block tables map each block to a
+// member and to a block of that member).  The server keeps a queue of requests, admits
+// them while slots and arena bytes are free, advances all active solves as one batch in
+// rounds of check_every steps, and retires each solve when its kinetic energy has dropped
+// below the threshold (Sec. 3: KE_max is the paper's equilibrium measure) or its step
+// budget is spent.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/semlbm.h"
+#include "ctx.hpp"
+
+using namespace slbm;
+
+// ------------------------------------------------------------------------------------------
+// batch
+// ------------------------------------------------------------------------------------------
+struct slbm_batch {
+    void *stream = nullptr;
+    std::vector<slbm_ctx *> members;
+    bool dirty = true;
+    struct Group {
+        int d = 0, N = 0;
+        std::vector<int> idx;  // member indices
+        LaunchPlan ep{}, np{};
+        SolveDesc *desc = nullptr;  // device
+        double *diag_out = nullptr; // device [2 * members]
+    };
+    std::vector<Group> groups;
+    void *dmem = nullptr;
+    size_t dcap = 0;
+    slbm_status status = SLBM_OK;
+
+    ~slbm_batch() {
+        if (dmem) {
+            (void)hipStreamSynchronize((hipStream_t)stream);
+            (void)hipFree(dmem);
+        }
+    }
+
+    slbm_status rebuild() {
+        groups.clear();
+        for (int i = 0; i < (int)members.size(); ++i) {
+            slbm_ctx *c = members[i];
+            Group *g = nullptr;
+            for (auto &x : groups)
+                if (x.d == c->dim && x.N == c->N) g = &x;
+            if (!g) {
+                groups.emplace_back();
+                g = &groups.back();
+                g->d = c->dim;
+                g->N = c->N;
+            }
+            g->idx.push_back(i);
+        }
+        // one device block: per group [descs][e tables][n tables][diag out]
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        size_t total = 0;
+        std::vector<size_t> goff;
+        for (auto &g : groups) {
+            goff.push_back(total);
+            int ne = 0, nn = 0;
+            for (int i : g.idx) {
+                ne += members[i]->n_eblocks;
+                nn += members[i]->n_nblocks;
+            }
+            total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(int) * 2 * ne) +
+                     al(sizeof(int) * 2 * nn) + al(sizeof(double) * 2 * g.idx.size());
+        }
+        hipStream_t st = (hipStream_t)stream;
+        if (total > dcap) {
+            if (dmem) {
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(dmem);
+                dmem = nullptr;
+            }
+            size_t cap = std::max(total, (size_t)1 << 16);
+            if (hipMalloc(&dmem, cap) != hipSuccess) {
+                dcap = 0;
+                return SLBM_ENOMEM;
+            }
+            dcap = cap;
+        }
+        std::vector<char> host(total, 0);
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            Group &g = groups[gi];
+            size_t o = goff[gi];
+            const size_t o_desc = o;
+            o += al(sizeof(SolveDesc) * g.idx.size());
+            int ne = 0, nn = 0;
+            for (int i : g.idx) {
+                ne += members[i]->n_eblocks;
+                nn += members[i]->n_nblocks;
+            }
+            const size_t o_e = o;
+            o += al(sizeof(int) * 2 * ne);
+            const size_t o_n = o;
+            o += al(sizeof(int) * 2 * nn);
+            const size_t o_d = o;
+            SolveDesc *dh = reinterpret_cast<SolveDesc *>(host.data() + o_desc);
+            int *eh = reinterpret_cast<int *>(host.data() + o_e);
+            int *nh = reinterpret_cast<int *>(host.data() + o_n);
+            int be = 0, bn = 0;
+            for (int k = 0; k < (int)g.idx.size(); ++k) {
+                slbm_ctx *c = members[g.idx[k]];
+                dh[k] = c->desc;
+                for (int b = 0; b < c->n_eblocks; ++b, ++be) {
+                    eh[be] = k;
+                    eh[ne + be] = b;
+                }
+                for (int b = 0; b < c->n_nblocks; ++b, ++bn) {
+                    nh[bn] = k;
+                    nh[nn + bn] = b;
+                }
+            }
+            char *base = (char *)dmem;
+            g.desc = reinterpret_cast<SolveDesc *>(base + o_desc);
+            g.ep = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_e), reinterpret_cast<int *>(base + o_e) + ne, ne};
+            g.np = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_n), reinterpret_cast<int *>(base + o_n) + nn, nn};
+            g.diag_out = reinterpret_cast<double *>(base + o_d);
+        }
+        if (total) {
+            if (hipMemcpyAsync(dmem, host.data(), total, hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return SLBM_EDEVICE;
+        }
+        dirty = false;
+        return SLBM_OK;
+    }
+};
+
+extern "C" slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out) {
+    if (!out) return SLBM_EINVAL;
+    *out = new (std::nothrow) slbm_batch();
+    if (!*out) return SLBM_ENOMEM;
+    (*out)->stream = hip_stream;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_batch_add(slbm_batch *b, slbm_ctx *c) {
+    if (!b || !c) return SLBM_EINVAL;
+    if (!c->bound || !c->has_state) return SLBM_ESTATE;
+    if (c->stream != b->stream) return SLBM_EINVAL;
+    if (std::find(b->members.begin(), b->members.end(), c) != b->members.end()) return SLBM_EINVAL;
+    b->members.push_back(c);
+    b->dirty = true;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_batch_remove(slbm_batch *b, slbm_ctx *c) {
+    if (!b || !c) return SLBM_EINVAL;
+    auto it = std::find(b->members.begin(), b->members.end(), c);
+    if (it == b->members.end()) return SLBM_EINVAL;
+    b->members.erase(it);
+    b->dirty = true;
+    return SLBM_OK;
+}
+
+extern "C" int slbm_batch_size(const slbm_batch *b) { return b ? (int)b->members.size() : 0; }
+
+extern "C" slbm_status slbm_batch_step(slbm_batch *b, int64_t n) {
+    if (!b || n < 0) return SLBM_EINVAL;
+    if (b->members.empty() || n == 0) return SLBM_OK;
+    if (b->dirty)
+        if (slbm_status s = b->rebuild()) return s;
+    for (int64_t s = 0; s < n; ++s)
+        for (auto &g : b->groups) {
+            const int e = enqueue_steps(g.d, g.N, g.ep, g.np, 1, b->stream);
+            if (e) return SLBM_EDEVICE;
+        }
+    for (slbm_ctx *c : b->members) c->step += n;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_batch_kinetic_energy(slbm_batch *b, double *ke, double *mass) {
+    if (!b) return SLBM_EINVAL;
+    if (b->members.empty()) return SLBM_OK;
+    if (b->dirty)
+        if (slbm_status s = b->rebuild()) return s;
+    hipStream_t st = (hipStream_t)b->stream;
+    std::vector<std::vector<double>> outs(b->groups.size());
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        auto &g = b->groups[gi];
+        int e = launch_diag(g.d, g.N, g.np, b->stream);
+        if (e == 0) e = launch_diag_final(g.desc, (int)g.idx.size(), b->stream);
+        if (e) return SLBM_EDEVICE;
+        outs[gi].resize(2 * g.idx.size());
+        // diag_final writes each member's own diag slot; gather them
+        for (size_t k = 0; k < g.idx.size(); ++k)
+            if (hipMemcpyAsync(&outs[gi][2 * k], b->members[g.idx[k]]->desc.diag, 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, st) != hipSuccess)
+                return SLBM_EDEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return SLBM_EDEVICE;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi)
+        for (size_t k = 0; k < b->groups[gi].idx.size(); ++k) {
+            const int m = b->groups[gi].idx[k];
+            if (ke) ke[m] = outs[gi][2 * k];
+            if (mass) mass[m] = outs[gi][2 * k + 1];
+        }
+    return SLBM_OK;
+}
+
+extern "C" void slbm_batch_destroy(slbm_batch *b) { delete b; }
+
+// ------------------------------------------------------------------------------------------
+// contact angle (host): mid-density crossings, Kasa circle/sphere fit, wall intersection
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// solve the small dense system A x = r (n <= 4) by Gaussian elimination with pivoting
+bool solve_small(int n, double A[4][4], double *r, double *x) {
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(A[i][k]) > std::fabs(A[piv][k])) piv = i;
+        if (A[piv][k] == 0.0) return false;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) std::swap(A[k][j], A[piv][j]);
+            std::swap(r[k], r[piv]);
+        }
+        for (int i = k + 1; i < n; ++i) {
+            const double m = A[i][k] / A[k][k];
+            for (int j = k; j < n; ++j) A[i][j] -= m * A[k][j];
+            r[i] -= m * r[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = r[k];
+        for (int j = k + 1; j < n; ++j) s -= A[k][j] * x[j];
+        x[k] = s / A[k][k];
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" slbm_status slbm_contact_angle(slbm_ctx *c, const slbm_wall_geom *w, double *theta_deg) {
+    if (!c || !w || !theta_deg) return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(true)) return s;
+    const int dim = c->dim, Np = c->Np, nloc = c->nloc;
+    std::vector<double> rho(c->Ng);
+    int e = (int)hipMemcpyAsync(rho.data(), c->desc.rho, sizeof(double) * c->Ng, hipMemcpyDeviceToHost,
+                                (hipStream_t)c->stream);
+    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+    if (e) return c->hip_check(e, "contact_angle");
+    const double level = 0.5 * (c->prm.rho_l + c->prm.rho_v);
+    const double excl = 2.0 * c->prm.delta;
+    std::unordered_set<uint64_t> seen;
+    std::vector<double> pts;
+    for (int64_t el = 0; el < c->E; ++el)
+        for (int a = 0; a < dim; ++a) {
+            const int s = c->stride(a);
+            for (int n = 0; n < nloc; ++n) {
+                if (c->along(n, a) == Np - 1) continue;
+                const int64_t l1 = el * nloc + n, l2 = l1 + s;
+                const uint32_t g1 = (uint32_t)c->lgid[l1], g2 = (uint32_t)c->lgid[l2];
+                const uint64_t key = ((uint64_t)std::min(g1, g2) << 32) | std::max(g1, g2);
+                const double r1 = rho[g1] - level, r2 = rho[g2] - level;
+                if ((r1 == 0.0 && r2 == 0.0) || r1 * r2 > 0.0) continue;
+                if (!seen.insert(key).second) continue;
+                const double t = r1 / (r1 - r2);
+                double p[3] = {0, 0, 0};
+                for (int k = 0; k < dim; ++k) {
+                    const double x1 = c->xyz[l1 * dim + k], x2 = c->xyz[l2 * dim + k];
+                    p[k] = x1 + t * (x2 - x1);
+                }
+                double dist;
+                if (w->kind == 0) {
+                    double dd = 0.0;
+                    for (int k = 0; k < dim; ++k) dd += (p[k] - w->point[k]) * w->normal[k];
+                    dist = std::fabs(dd);
+                } else {
+                    double r2s = 0.0;
+                    for (int k = 0; k < dim; ++k) r2s += (p[k] - w->point[k]) * (p[k] - w->point[k]);
+                    dist = std::sqrt(r2s) - w->radius;
+                }
+                if (dist < excl) continue;
+                for (int k = 0; k < dim; ++k) pts.push_back(p[k]);
+            }
+        }
+    const int64_t np = (int64_t)pts.size() / dim;
+    if (np < dim + 2) return c->fail(SLBM_EINVAL, "contact angle: too few interface points (%lld)", (long long)np);
+    // Kasa fit about the centroid: |y|^2 + b.y + k = 0 with y = p - m
+    double m[3] = {0, 0, 0};
+    for (int64_t i = 0; i < np; ++i)
+        for (int k = 0; k < dim; ++k) m[k] += pts[i * dim + k];
+    for (int k = 0; k < dim; ++k) m[k] /= (double)np;
+    const int nu = dim + 1;
+    double A[4][4] = {}, rhs[4] = {}, x[4] = {};
+    for (int64_t i = 0; i < np; ++i) {
+        double row[4], y2 = 0.0;
+        for (int k = 0; k < dim; ++k) {
+            row[k] = pts[i * dim + k] - m[k];
+            y2 += row[k] * row[k];
+        }
+        row[dim] = 1.0;
+        for (int r = 0; r < nu; ++r) {
+            for (int q = 0; q < nu; ++q) A[r][q] += row[r] * row[q];
+            rhs[r] -= row[r] * y2;
+        }
+    }
+    if (!solve_small(nu, A, rhs, x)) return c->fail(SLBM_EINVAL, "contact angle: singular fit");
+    double cen[3] = {0, 0, 0}, c2 = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        cen[k] = -0.5 * x[k];
+        c2 += cen[k] * cen[k];
+        cen[k] += m[k];
+    }
+    const double R = std::sqrt(c2 - x[dim]);
+    double cth;
+    if (w->kind == 0) {
+        double dd = 0.0;
+        for (int k = 0; k < dim; ++k) dd += (cen[k] - w->point[k]) * w->normal[k];
+        cth = dd / R;
+    } else {
+        double d2 = 0.0;
+        for (int k = 0; k < dim; ++k) d2 += (cen[k] - w->point[k]) * (cen[k] - w->point[k]);
+        const double Rw = w->radius;
+        cth = (Rw * Rw + R * R - d2) / (2.0 * R * Rw);
+    }
+    cth = std::max(-1.0, std::min(1.0, cth));
+    *theta_deg = std::acos(cth) * 180.0 / M_PI;
+    return SLBM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// server
+// ------------------------------------------------------------------------------------------
+namespace {
+struct Request {
+    uint64_t id = 0;
+    slbm_request r{};
+    std::vector<double> xyz, wcos, wub;
+    std::vector<int32_t> gid, wface;
+    slbm_result res{};
+    slbm_ctx *ctx = nullptr;
+    size_t off = 0, bytes = 0;
+    int64_t steps = 0;
+};
+
+// first-fit allocator over the arena (offsets 256-byte aligned)
+struct Arena {
+    std::map<size_t, size_t> free_;  // offset -> size
+    void init(size_t bytes) { free_.clear(); if (bytes) free_[0] = bytes; }
+    bool alloc(size_t n, size_t &off) {
+        n = (n + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                off = it->first;
+                const size_t rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = (n + 255) & ~(size_t)255;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+}  // namespace
+
+struct slbm_server {
+    slbm_server_cfg cfg{};
+    std::chrono::steady_clock::time_point t0;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;
+    std::map<uint64_t, Request *> all;
+    uint64_t next_id = 1;
+    Arena arena;
+    slbm_batch *batch = nullptr;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    ~slbm_server() {
+        for (auto *r : active) slbm_destroy(r->ctx);
+        for (auto &kv : all) delete kv.second;
+        slbm_batch_destroy(batch);
+    }
+
+    void finish(Request *r, slbm_status st) {
+        r->res.status = st;
+        r->res.steps = r->steps;
+        r->res.t_done = now();
+        if (r->ctx) {
+            slbm_destroy(r->ctx);
+            r->ctx = nullptr;
+        }
+        if (r->bytes) {
+            arena.release(r->off, r->bytes);
+            r->bytes = 0;
+        }
+        // inputs are no longer needed
+        r->xyz.clear(); r->xyz.shrink_to_fit();
+        r->gid.clear(); r->gid.shrink_to_fit();
+    }
+
+    // try to admit the head of the queue; returns false if it does not fit now
+    bool admit(Request *r) {
+        slbm_ctx *c = nullptr;
+        slbm_params p = r->r.params;
+        if (slbm_create(&p, &c) != SLBM_OK) { finish(r, SLBM_EINVAL); return true; }
+        if (slbm_set_mesh(c, r->r.E, r->xyz.data(), r->gid.data(), r->r.n_global, r->r.n_wall_faces,
+                          r->wface.empty() ? nullptr : r->wface.data(),
+                          r->wcos.empty() ? nullptr : r->wcos.data(),
+                          r->wub.empty() ? nullptr : r->wub.data()) != SLBM_OK) {
+            slbm_destroy(c);
+            finish(r, SLBM_EINVAL);
+            return true;
+        }
+        const size_t need = slbm_workspace_bytes(c);
+        size_t off = 0;
+        if (need > cfg.arena_bytes) { slbm_destroy(c); finish(r, SLBM_ENOMEM); return true; }
+        if (!arena.alloc(need, off)) { slbm_destroy(c); return false; }
+        r->off = off;
+        r->bytes = need;
+        r->ctx = c;
+        slbm_status s = slbm_bind(c, (char *)cfg.arena + off, need, cfg.hip_stream);
+        if (s == SLBM_OK) s = slbm_init_tanh(c, r->r.x0, r->r.R, r->r.noise_amp, p.seed);
+        if (s == SLBM_OK) s = slbm_batch_add(batch, c);
+        if (s != SLBM_OK) { finish(r, s); return true; }
+        r->res.t_admit = now();
+        active.push_back(r);
+        return true;
+    }
+};
+
+extern "C" slbm_status slbm_server_create(const slbm_server_cfg *cfg, slbm_server **out) {
+    if (!cfg || !out || !cfg->arena || cfg->max_slots <= 0 || cfg->check_every <= 0) return SLBM_EINVAL;
+    slbm_server *s = new (std::nothrow) slbm_server();
+    if (!s) return SLBM_ENOMEM;
+    s->cfg = *cfg;
+    s->t0 = std::chrono::steady_clock::now();
+    s->arena.init(cfg->arena_bytes);
+    if (slbm_batch_create(cfg->hip_stream, &s->batch) != SLBM_OK) { delete s; return SLBM_ENOMEM; }
+    *out = s;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_server_submit(slbm_server *s, const slbm_request *r, uint64_t *id) {
+    if (!s || !r || !r->xyz || !r->gid || r->E <= 0) return SLBM_EINVAL;
+    const int dim = r->params.lattice == 19 ? 3 : 2;
+    const int64_t nloc = nloc_of(dim, r->params.N);
+    Request *q = new (std::nothrow) Request();
+    if (!q) return SLBM_ENOMEM;
+    q->id = s->next_id++;
+    q->r = *r;
+    q->xyz.assign(r->xyz, r->xyz + r->E * nloc * dim);
+    q->gid.assign(r->gid, r->gid + r->E * nloc);
+    if (r->n_wall_faces > 0) {
+        q->wface.assign(r->wall_face, r->wall_face + 2 * r->n_wall_faces);
+        q->wcos.assign(r->wall_cos, r->wall_cos + r->n_wall_faces);
+        if (r->wall_ub) q->wub.assign(r->wall_ub, r->wall_ub + dim * r->n_wall_faces);
+    }
+    q->r.xyz = nullptr;
+    q->r.gid = nullptr;
+    q->r.wall_face = nullptr;
+    q->r.wall_cos = nullptr;
+    q->r.wall_ub = nullptr;
+    q->res.status = 1;
+    q->res.t_arrive = s->now();
+    s->all[q->id] = q;
+    s->queue.push_back(q);
+    if (id) *id = q->id;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_server_tick(slbm_server *s, int *pending) {
+    if (!s) return SLBM_EINVAL;
+    // admission: FIFO while slots and arena bytes allow
+    while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_slots) {
+        Request *r = s->queue.front();
+        if (!s->admit(r)) break;
+        s->queue.pop_front();
+    }
+    if (!s->active.empty()) {
+        if (slbm_status st = slbm_batch_step(s->batch, s->cfg.check_every)) return st;
+        std::vector<double> ke(s->active.size()), mass(s->active.size());
+        if (slbm_status st = slbm_batch_kinetic_energy(s->batch, ke.data(), mass.data())) return st;
+        std::vector<Request *> keep;
+        for (size_t i = 0; i < s->active.size(); ++i) {
+            Request *r = s->active[i];
+            r->steps += s->cfg.check_every;
+            r->res.ke_max = ke[i];
+            const double lim = r->r.params.ke_limit > 0.0 ? r->r.params.ke_limit : 1.0;
+            const bool bad = !(ke[i] <= lim);
+            const bool done = ke[i] < s->cfg.ke_stop || r->steps >= s->cfg.max_steps;
+            if (bad || done) {
+                slbm_batch_remove(s->batch, r->ctx);
+                slbm_status st = bad ? SLBM_EDIVERGED : SLBM_OK;
+                if (!bad) {
+                    double th = NAN;
+                    if (slbm_contact_angle(r->ctx, &r->r.wall, &th) == SLBM_OK) r->res.theta_deg = th;
+                    else r->res.theta_deg = NAN;
+                }
+                s->finish(r, st);
+            } else {
+                keep.push_back(r);
+            }
+        }
+        s->active.swap(keep);
+    }
+    if (pending) *pending = (int)(s->active.size() + s->queue.size());
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_server_poll(slbm_server *s, uint64_t id, slbm_result *out) {
+    if (!s || !out) return SLBM_EINVAL;
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return SLBM_EINVAL;
+    *out = it->second->res;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_server_drain(slbm_server *s) {
+    if (!s) return SLBM_EINVAL;
+    int pending = 1;
+    while (pending > 0) {
+        const size_t before_q = s->queue.size(), before_a = s->active.size();
+        if (slbm_status st = slbm_server_tick(s, &pending)) return st;
+        if (pending > 0 && s->active.empty() && s->queue.size() == before_q && before_a == 0)
+            return SLBM_ENOMEM;  // head of the queue can never be admitted
+    }
+    return SLBM_OK;
+}
+
+extern "C" double slbm_server_clock(const slbm_server *s) { return s ? s->now() : 0.0; }
+
+extern "C" void slbm_server_destroy(slbm_server *s) { delete s; }

@@ -1,0 +1,143 @@
+"""Host-side tests of the C ABI (no GPU): symbols, argument checks, call order, and the
+host tables (GLL, lumped mass, time step) compared with the oracle bit for bit."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synth import cases, meshes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "semlbm.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2609_00535_amd as P
+    try:
+        return P.lib()
+    except RuntimeError as e:  # library not built in this checkout
+        pytest.skip(str(e))
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    import paper_2609_00535_amd as P
+    names = declared_functions()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(P.SIGNATURES), set(names) ^ set(P.SIGNATURES)
+
+
+def _create(L, case):
+    import paper_2609_00535_amd as P
+    p = P.make_params(case)
+    h = C.c_void_p()
+    assert L.slbm_create(C.byref(p), C.byref(h)) == 0
+    return h
+
+
+def _set_mesh(L, h, m):
+    xyz = np.ascontiguousarray(m.xyz)
+    gid = np.ascontiguousarray(m.gid, dtype=np.int32)
+    wf = np.ascontiguousarray(m.wall_face, dtype=np.int32)
+    wc = np.ascontiguousarray(m.wall_cos)
+    wu = np.ascontiguousarray(m.wall_ub)
+    nwf = wf.shape[0]
+    return L.slbm_set_mesh(h, m.E, xyz.ctypes.data, gid.ctypes.data, m.n_global, nwf,
+                           wf.ctypes.data if nwf else None, wc.ctypes.data if nwf else None,
+                           wu.ctypes.data if nwf else None)
+
+
+def test_argument_and_order_errors(L):
+    import paper_2609_00535_amd as P
+    c = cases.c1()
+    p = P.make_params(c)
+    h = C.c_void_p()
+    bad = P.make_params(c)
+    bad.lattice = 7
+    assert L.slbm_create(C.byref(bad), C.byref(h)) == P.binding.SLBM_EINVAL and not h.value
+    bad = P.make_params(c)
+    bad.N = 40
+    assert L.slbm_create(C.byref(bad), C.byref(h)) == P.binding.SLBM_EINVAL
+    bad = P.make_params(c)
+    bad.rho_v = 2.0
+    assert L.slbm_create(C.byref(bad), C.byref(h)) == P.binding.SLBM_EINVAL
+    assert L.slbm_create(C.byref(p), C.byref(h)) == 0
+    assert L.slbm_workspace_bytes(h) == 0
+    assert L.slbm_step(h, 1) == P.binding.SLBM_ESTATE
+    m = c.mesh
+    gid = np.ascontiguousarray(m.gid, dtype=np.int32).copy()
+    gid[3] = m.n_global + 5
+    xyz = np.ascontiguousarray(m.xyz)
+    assert L.slbm_set_mesh(h, m.E, xyz.ctypes.data, gid.ctypes.data, m.n_global, 0, None, None,
+                           None) == P.binding.SLBM_EINVAL
+    assert b"out of range" in L.slbm_last_error(h)
+    # inverted element -> non-positive Jacobian
+    xyz2 = xyz.copy()
+    xyz2[0, :, 0] = -xyz2[0, :, 0]
+    gid = np.ascontiguousarray(m.gid, dtype=np.int32)
+    assert L.slbm_set_mesh(h, m.E, xyz2.ctypes.data, gid.ctypes.data, m.n_global, 0, None, None,
+                           None) == P.binding.SLBM_EINVAL
+    assert b"Jacobian" in L.slbm_last_error(h)
+    assert _set_mesh(L, h, m) == 0
+    assert L.slbm_workspace_bytes(h) > 0
+    # misaligned / too small workspace
+    assert L.slbm_bind(h, 8, 10 ** 9, None) == P.binding.SLBM_EINVAL
+    assert L.slbm_bind(h, 4096, 16, None) == P.binding.SLBM_ENOMEM
+    assert L.slbm_step(h, 1) == P.binding.SLBM_ESTATE
+    assert L.slbm_get_rho(h, np.zeros(m.n_global).ctypes.data_as(C.POINTER(C.c_double))) == \
+        P.binding.SLBM_ESTATE
+    L.slbm_destroy(h)
+
+
+@pytest.mark.parametrize("mk", [cases.c1, cases.c2, cases.small_cyl, cases.small_sphere,
+                                cases.small_box3d])
+def test_host_tables_match_oracle_bitwise(L, mk):
+    """GLL tables, lumped mass, h_min and dt of the library equal the oracle's exactly:
+    parity of the time step to 1e-11 needs identical inputs to every kernel."""
+    import paper_2609_00535_amd as P
+    from oracle import Oracle
+    c = mk()
+    h = _create(L, c)
+    assert _set_mesh(L, h, c.mesh) == 0
+    Np = c.N + 1
+    x, w, D = np.zeros(Np), np.zeros(Np), np.zeros(Np * Np)
+    dp = C.POINTER(C.c_double)
+    assert L.slbm_get_gll(h, x.ctypes.data_as(dp), w.ctypes.data_as(dp), D.ctypes.data_as(dp)) == 0
+    o = Oracle(c)
+    xo, wo, Do = o.gll()
+    assert np.array_equal(x, xo) and np.array_equal(w, wo) and np.array_equal(D, Do.reshape(-1))
+    MA = np.zeros(c.mesh.n_global)
+    assert L.slbm_get_mass(h, MA.ctypes.data_as(dp)) == 0
+    assert np.array_equal(MA, o.mass_matrix())
+    inf = P.binding.Info()
+    assert L.slbm_get_info(h, C.byref(inf)) == 0
+    assert inf.dt == o.dt and inf.h_min == o.hmin and inf.beta == o.beta and inf.kappa == o.kappa
+    assert inf.n_wall_nodes == o.nw
+    L.slbm_destroy(h)
+
+
+def test_mesh_generators_structure():
+    """Inputs: shared nodes bitwise equal (no periodic wrap), Jacobians positive."""
+    for m in [cases.c2().mesh, cases.small_cyl().mesh, cases.small_sphere().mesh]:
+        X = m.xyz.reshape(-1, m.dim)
+        g = m.gid.reshape(-1)
+        first = m.first_copy_coords()
+        assert np.array_equal(X, first[g])
+    m = cases.c3().mesh
+    X = m.xyz.reshape(-1, 2)
+    r = np.hypot(X[:, 0] - 128, X[:, 1] - 128)
+    wall_e = m.wall_face[m.wall_face[:, 1] == meshes.FACE_XI_M, 0]
+    Np = m.N + 1
+    on = m.xyz[wall_e][:, ::Np, :]  # i = 0 nodes of cylinder elements
+    assert np.abs(np.hypot(on[..., 0] - 128, on[..., 1] - 128) - 40.0).max() < 1e-12
+    assert r.min() > 40.0 - 1e-12

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+The bar is the relative infinity-norm difference ||gpu - oracle|| / ||oracle|| on rho
+and u.  Both implementations follow the same expression trees (GLL contractions by fma,
+no other contraction), so they usually agree bit for bit; the asserted tolerance is the
+1e-11 of the method's parity target, far above the 1e-14 (rho) / 2e-11 (u) spread that
+FMA contraction alone produces after 1000 steps of config 1.
+"""
+import numpy as np
+import pytest
+
+from synth import cases, meshes
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def rel(a, b):
+    d = np.abs(np.asarray(a) - np.asarray(b)).max()
+    s = np.abs(np.asarray(b)).max()
+    return d / s if s > 0 else d
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_00535_amd as P
+    P.lib()
+    return P
+
+
+def _pair(case, P, mode=0):
+    from oracle import Oracle
+    print(f"[parity] case={case.name} E={case.mesh.E} N={case.N} Q={case.lattice}", flush=True)
+    return P.Solve(case), Oracle(case)
+
+
+SMALL = [cases.c1, cases.small_flat, cases.small_cyl, cases.small_sphere, cases.small_box3d]
+
+
+@pytest.mark.parametrize("mk", SMALL)
+def test_operator_parity(P, mk):
+    """Each kernel pass alone: mu (a2), averaged gradients (a3), collision (a4),
+    streaming right-hand side with walls (a5-a6)."""
+    c = mk()
+    s, o = _pair(c, P)
+    rng = np.random.default_rng(11)
+    X = c.mesh.first_copy_coords()
+    r = np.linalg.norm(X - np.asarray(c.x0)[None, : c.dim], axis=1)
+    rho = 0.55 - 0.45 * np.tanh(2 * (r - c.R) / c.delta) + 1e-3 * rng.standard_normal(o.Ng)
+    mu_o, mu_g = o.mu(rho), s.op_mu(rho)
+    assert rel(mu_g, mu_o) <= 1e-13, rel(mu_g, mu_o)
+    gr_o, gr_g = o.avg_grad(rho), s.op_grad(rho)
+    assert rel(gr_g, gr_o) <= 1e-13
+    ev, tw, _ = o.lattice()
+    e = ev[:, : c.dim]
+    u = 0.01 * rng.standard_normal((c.dim, o.Ng))
+    eu = e @ u
+    f = rho * tw[:, None] * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (u * u).sum(0))
+    f += 1e-4 * rng.standard_normal(f.shape) * tw[:, None]
+    gm = o.avg_grad(mu_o)
+    fs_o = o.collide(f, rho, gr_o, gm)
+    fs_g = s.op_collide(f, rho, gr_o, gm)
+    assert rel(fs_g, fs_o) <= 1e-14
+    L_o = o.stream_op(f, rho, mu_o)
+    L_g = s.op_stream(f, rho, mu_o)
+    assert rel(L_g, L_o) <= 1e-13, rel(L_g, L_o)
+
+
+def _run_pair(c, P, steps):
+    s, o = _pair(c, P)
+    s.init_tanh()
+    o.init_tanh()
+    f0g, _ = s.get_state()
+    assert np.array_equal(f0g, o.get_f())  # identical initial state (same tanh, same hash)
+    s.step(steps)
+    o.step(steps)
+    return s, o
+
+
+def test_config1_1000_steps(P):
+    """c1: D2Q9 isolated droplet, periodic, N=4, 1e-4 noise: 1000 steps, 1e-11 on rho, u."""
+    c = cases.c1()
+    s, o = _run_pair(c, P, 1000)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] c1 1000 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+    keg, mg = s.kinetic_energy()
+    keo, mo = o.diag()
+    assert abs(keg - keo) <= 1e-9 * keo and abs(mg - mo) <= 1e-13 * mo
+
+
+@pytest.mark.parametrize("mk,steps", [(cases.small_flat, 300), (cases.small_cyl, 100),
+                                      (cases.small_sphere, 20), (cases.small_box3d, 30)])
+def test_walls_and_3d_parity(P, mk, steps):
+    c = mk()
+    s, o = _run_pair(c, P, steps)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] {c.name} {steps} steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+
+
+def test_config2_full_size(P):
+    """c2 at full size (32x16 jittered quads, N=6, 60 deg wetting wall), 200 steps."""
+    c = cases.c2()
+    s, o = _run_pair(c, P, 200)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] c2 200 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+
+
+def test_mass_conservation_gpu(P):
+    c = cases.small_flat()
+    s = P.Solve(c)
+    s.init_tanh()
+    _, m0 = s.kinetic_energy()
+    s.step(2000)
+    _, m1 = s.kinetic_energy()
+    assert abs(m1 - m0) / m0 < 1e-13
+
+
+def test_checkpoint_resume_bitwise(P):
+    c = cases.small_flat()
+    a = P.Solve(c)
+    a.init_tanh()
+    a.step(50)
+    f, st = a.get_state()
+    assert st == 50
+    a.step(50)
+    b = P.Solve(c)
+    b.set_state(f, st)
+    b.step(50)
+    fa, _ = a.get_state()
+    fb, sb = b.get_state()
+    assert sb == 100 and np.array_equal(fa, fb)
+
+
+def test_diverged_is_reported(P):
+    """A time step far above the advective limit blows up and the step reports it."""
+    c = cases.small_flat()
+    c.dt = 10.0
+    s = P.Solve(c, ke_every=10, ke_limit=1.0)
+    s.init_tanh()
+    with pytest.raises(P.SLBMError) as ei:
+        s.step(200)
+    assert ei.value.status == -5
+
+
+def test_batch_equals_alone(P):
+    """Members of a batch (different N, lattices and meshes) evolve exactly as alone."""
+    import torch
+    mk = [lambda: cases.small_flat(), lambda: cases.small_cyl(), lambda: cases.c1(),
+          lambda: cases.small_sphere(), lambda: cases.small_flat(theta_deg=120.0, N=6)]
+    stream = torch.cuda.current_stream()
+    alone, inbatch = [], []
+    b = P.Batch(stream)
+    for f in mk:
+        c = f()
+        a = P.Solve(c)
+        a.init_tanh()
+        a.step(40)
+        alone.append(a.get_state()[0])
+        m = P.Solve(c)
+        m.init_tanh()
+        b.add(m)
+        inbatch.append(m)
+    b.step(40)
+    for a, m in zip(alone, inbatch):
+        assert np.array_equal(a, m.get_state()[0])
+    ke, ms = b.kinetic_energy()
+    for k, m in enumerate(inbatch):
+        kk, mm = m.kinetic_energy()
+        assert kk == ke[k] and mm == ms[k]
+
+
+def test_contact_angle_gpu_matches_oracle(P):
+    from oracle import contact_angle
+    for th in (60.0, 120.0):
+        c = cases.c2(theta_deg=th)
+        s = P.Solve(c)
+        s.init_tanh()
+        a_g = s.contact_angle()
+        a_o, _, _ = contact_angle(c.mesh, s.rho(), c.rho_l, c.rho_v, c.delta, c.wall_geom)
+        assert abs(a_g - a_o) < 1e-9 and abs(a_g - th) < 0.5
+    c = cases.c3(theta_deg=135.0)
+    s = P.Solve(c)
+    s.init_tanh()
+    assert abs(s.contact_angle() - 135.0) < 0.1
+
+
+def test_server_results_equal_alone(P):
+    """Continuous batching: each request's result equals the same solve run alone."""
+    reqs = [cases.small_flat(theta_deg=t, nx=8, ny=4, N=n, Lx=128.0, Ly=64.0, R=32.0)
+            for t, n in ((60.0, 4), (90.0, 6), (120.0, 4), (75.0, 6), (100.0, 4))]
+    srv = P.Server(arena_bytes=64 << 20, max_slots=3, check_every=50, ke_stop=1e-30,
+                   max_steps=200)
+    ids = [srv.submit(c) for c in reqs]
+    srv.drain()
+    for rid, c in zip(ids, reqs):
+        res = srv.poll(rid)
+        assert res.status == 0 and res.steps == 200
+        a = P.Solve(c)
+        a.init_tanh()
+        a.step(200)
+        ke, _ = a.kinetic_energy()
+        assert res.ke_max == ke
+        assert abs(res.theta_deg - a.contact_angle()) < 1e-12
+        assert res.t_arrive <= res.t_admit <= res.t_done
