@@ -41,6 +41,16 @@ def algorithmic_bytes(kind: str, Q: int, d: int, Ng: int, Nl: int) -> float:
         "stream": (Q - 1) * Ng + 2 * Ng + d * d * Nl + (Q - 1) * Ng,
         # reads Q-1 residuals, g (Q), g0 (Q), 1/M; writes Q populations and rho
         "rk": (Q - 1) * Ng + Q * Ng + Q * Ng + Ng + Q * Ng + Ng,
+        # fused path: each kernel finishes the previous pass's summation itself
+        # A: Laplacian sum, rho, 1/M -> mu; metric Ja -> 2d gradient sums
+        "f_mu_grad": 4 * Ng + d * d * Nl + 2 * d * Ng,
+        # B: 2d gradient sums, 1/M, f (Q), rho, mu -> f* (Q); Ja -> Q-1 residual sums
+        "f_collide_stream": (2 * d + 1 + Q + 2 + Q + (Q - 1)) * Ng + d * d * Nl,
+        # C: Q-1 residual sums, 1/M, g (Q), g0 (2Q/3 on average over the three stages)
+        #    -> g' (Q), rho; metric G -> Laplacian sum
+        "f_rk_lap": ((Q - 1) + 1 + Q + (2 * Q) / 3.0 + Q + 2) * Ng + ng * Nl,
+        # D: Laplacian sum, rho, 1/M, g (Q), Ja -> Q-1 residual sums
+        "f_mu_stream": (3 + Q + (Q - 1)) * Ng + d * d * Nl,
     }[kind]
     return 8.0 * per
 

@@ -56,7 +56,8 @@ typedef struct slbm_params {
     double sigma;     /* surface tension gamma; beta = 12 sigma/(delta drho^4),
                          kappa = 3 sigma delta/(2 drho^2) solve Eqs. (A.4)-(A.5) */
     double tau;       /* dimensionless relaxation time of Eq. (4) (0.5 in Sec. 3.3) */
-    double dt;        /* > 0: time step; otherwise dt = cfl * h_min */
+    double dt;        /* > 0: time step; otherwise dt = min(cfl h_min,
+                         0.25 h_min^2 / sqrt(kappa rho_l)) (advective and capillary bounds) */
     double cfl;       /* h_min = smallest distance of neighbouring GLL nodes on element lines */
     int ke_every;     /* slbm_step checks finiteness and KE_max every ke_every steps (0: never) */
     double ke_limit;  /* KE_max above this (or non-finite) -> SLBM_EDIVERGED; <= 0: 1.0 */
@@ -119,9 +120,12 @@ slbm_status slbm_step(slbm_ctx *c, int64_t n);
 
 /* Tracing: advance n steps like slbm_step with a HIP event pair around every kernel
  * launch; ms[k] accumulates the elapsed milliseconds and launches[k] the launch count of
- * kernel kind k (0 Laplacian, 1 chemical potential, 2 gradients, 3 collision, 4 streaming
- * residual, 5 DSS + Runge-Kutta combine).  Synchronises after every step. */
-#define SLBM_NUM_KERNEL_KINDS 6
+ * kernel kind k.  Unfused path (separate element and node kernels): 0 Laplacian, 1 chemical
+ * potential, 2 gradients, 3 collision, 4 streaming residual, 5 DSS + Runge-Kutta combine.
+ * Fused path (element kernels that finish the previous pass's summation): 6 chemical
+ * potential + gradients, 7 collision + stage-1 residual, 8 summation + Runge-Kutta +
+ * Laplacian, 9 chemical potential + residual.  Synchronises after every step. */
+#define SLBM_NUM_KERNEL_KINDS 10
 slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int64_t *launches);
 
 /* Queries (synchronising).  rho [n_global] by Eq. (10); u [d][n_global] by Eq. (11);

@@ -246,7 +246,8 @@ class Solve:
     def step(self, n=1):
         self._check(lib().slbm_step(self._h, int(n)))
 
-    KERNEL_KINDS = ("lap", "mu", "grad", "collide", "stream", "rk")
+    KERNEL_KINDS = ("lap", "mu", "grad", "collide", "stream", "rk",
+                    "f_mu_grad", "f_collide_stream", "f_rk_lap", "f_mu_stream")
 
     def step_profile(self, n=1):
         """n steps with per-kernel HIP event timing: {kind: (total_ms, launches)}."""
@@ -254,7 +255,7 @@ class Solve:
         cnt = np.zeros(len(self.KERNEL_KINDS), dtype=np.int64)
         self._check(lib().slbm_step_profile(self._h, int(n), _d(ms),
                                             cnt.ctypes.data_as(C.POINTER(C.c_int64))))
-        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNEL_KINDS)}
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNEL_KINDS) if cnt[i]}
 
     def rho(self):
         out = np.zeros(self.Ng)

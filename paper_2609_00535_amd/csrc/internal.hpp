@@ -20,6 +20,9 @@ struct SolveDesc {
     const double *Minv;   // [Ng] inverse assembled lumped mass
     const int *csr_ptr;   // [Ng+1] local copies of each global node
     const int *csr_idx;   // [Nl]   ascending local indices
+    const int *lcp;       // [vmax][Nl] local copies of the global node of each local node,
+                          // ascending, -1 padded (fused path)
+    int vmax, pad1;
     const int *wel_ptr;   // [E+1] wall entries of each element
     const int *w_node;    // [nw] element-local node of the entry
     const double *w_lap;  // [nw] s cos(theta) sqrt(2 beta / kappa)
@@ -30,7 +33,8 @@ struct SolveDesc {
     // state and work buffers (device)
     double *f;    // [Q][Ng] f-bar (state)
     double *g0;   // [Q][Ng] post-collision f*
-    double *gA;   // [Q][Ng] Runge-Kutta stage
+    double *g1;   // [Q][Ng] Runge-Kutta stage 1 (the unfused path keeps every stage here)
+    double *g2;   // [Q][Ng] Runge-Kutta stage 2 (fused path)
     double *rho;  // [Ng]
     double *mu;   // [Ng]
     double *rl;   // [Nl] Laplacian residual of each local copy
@@ -69,6 +73,13 @@ int launch_rk(int d, int N, const LaunchPlan &p, int stage, void *stream);
 int launch_density(int d, int N, const LaunchPlan &p, int which, void *stream);
 int launch_diag(int d, int N, const LaunchPlan &p, void *stream);
 int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream);
+// fused path: four element kernels per stage sequence (A: mu + gradients, B: collision +
+// stage-1 residual, C: DSS + Runge-Kutta combine + Laplacian residual, D: mu + residual)
+constexpr int kMaxCopies = 8;
+int launch_fA(int d, int N, const LaunchPlan &p, void *stream);
+int launch_fB(int d, int N, const LaunchPlan &p, void *stream);
+int launch_fC(int d, int N, const LaunchPlan &p, int stage, void *stream);
+int launch_fD(int d, int N, const LaunchPlan &p, int stage, void *stream);
 bool supported_order(int d, int N);
 
 }  // namespace slbm

@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_
 // Eqs. (5)-(6), (12), (9): element residual of the force-split weak streaming,
 //   r_a = -w [ (Ja e_a) . D(g_a - t_a rho) + (t_a/cs^2) rho (Ja e_a) . D mu ]
 // plus, on wall faces with (s n).e_a < 0, (s n . e_a) [g_a - g_opp - 2 (t_a/cs^2) rho e_a.u_b]
-// stage 1 streams g0, stages 2-3 stream gA
+// stage 1 streams g0, stages 2-3 stream g1
 // ------------------------------------------------------------------------------------------
 template <int D, int N>
 __global__ __launch_bounds__((Shape<D, N>::NT)) void k_stream(LaunchPlan p, int stage) {
@@ -345,7 +345,7 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_stream(LaunchPlan p, int 
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
     const SolveDesc &sd = *bs.sd;
-    const double *__restrict__ g = stage == 1 ? sd.g0 : sd.gA;
+    const double *__restrict__ g = stage == 1 ? sd.g0 : sd.g1;
     const int tid = threadIdx.x;
     for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
     const int es = tid / NLOC, n = tid - es * NLOC;
@@ -401,9 +401,9 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_stream(LaunchPlan p, int 
 }
 
 // SSP-RK3 stage combination after DSS(r)/M, and the new stage's density (Eq. (10))
-//   stage 0 (operator entry point only): gA = L(gA)
-//   stage 1: gA = g0 + dt L(g0); stage 2: gA = 3/4 g0 + 1/4 (gA + dt L(gA));
-//   stage 3: f = (g0 + 2 (gA + dt L(gA))) / 3
+//   stage 0 (operator entry point only): g1 = L(g1)
+//   stage 1: g1 = g0 + dt L(g0); stage 2: g1 = 3/4 g0 + 1/4 (g1 + dt L(g1));
+//   stage 3: f = (g0 + 2 (g1 + dt L(g1))) / 3
 template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     constexpr int Q = QOf<D>::Q;
@@ -412,8 +412,8 @@ __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
     const size_t Ng = sd.Ng, Nl = sd.Nl;
-    const double *gin = stage == 1 ? sd.g0 : sd.gA;
-    double *gout = stage == 3 ? sd.f : sd.gA;
+    const double *gin = stage == 1 ? sd.g0 : sd.g1;
+    double *gout = stage == 3 ? sd.f : sd.g1;
     const int k0 = sd.csr_ptr[G], k1 = sd.csr_ptr[G + 1];
     const double mi = sd.Minv[G], dt = sd.dt;
     double rho = 0.0;
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     sd.rho[G] = rho;
 }
 
-// rho = sum_a f_a (Eq. (10)) of the state (which = 0) or of gA (which = 1)
+// rho = sum_a f_a (Eq. (10)) of the state (which = 0) or of g1 (which = 1)
 template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int which) {
     constexpr int Q = QOf<D>::Q;
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int whic
     const SolveDesc &sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
-    const double *src = which == 0 ? sd.f : sd.gA;
+    const double *src = which == 0 ? sd.f : sd.g1;
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) s += src[(size_t)q * sd.Ng + G];
@@ -533,6 +533,339 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *de
 }
 
 // ------------------------------------------------------------------------------------------
+// Fused path.  Each element kernel finishes the previous pass's direct stiffness summation
+// itself: every thread gathers the per-copy partial sums of all local copies of its node
+// (ascending local order, the same sum as the node kernels) and applies the pointwise
+// update; the lowest local copy ("owner") stores the node's global value.  Shared nodes
+// are thus updated redundantly and identically by each element that holds them, which
+// halves the number of grid-wide dependencies of a step (7 kernels instead of 14).
+// ------------------------------------------------------------------------------------------
+
+// copy list of local node l into registers; returns the number of copies
+__device__ __forceinline__ int load_copies(const SolveDesc &sd, int l, int *cp) {
+    int nc = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxCopies; ++k) {
+        cp[k] = -1;
+        if (k < sd.vmax) {
+            const int v = sd.lcp[(size_t)k * sd.Nl + l];
+            cp[k] = v;
+            if (v >= 0) nc = k + 1;
+        }
+    }
+    return nc;
+}
+
+__device__ __forceinline__ double gather1(const double *__restrict__ v, const int *cp, int nc) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxCopies; ++k)
+        if (k < nc) s += v[cp[k]];
+    return s;
+}
+
+__device__ __forceinline__ double mu_of(const SolveDesc &sd, double pr, double lap) {
+    const double rl = sd.rho_l, rv = sd.rho_v;
+    const double mu0 = 2.0 * sd.beta * (pr - rl) * (pr - rv) * (2.0 * pr - rl - rv);
+    return mu0 - sd.kappa * lap;
+}
+
+// element residual of the streaming (Eqs. (5)-(6), (12)) and flux bounce-back (Eq. (9)) at
+// node n, from LDS h_q = g_q - t_q rho, LDS mu, register g (for the flux) ; writes rs
+template <int D, int N>
+__device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
+                                                const double *smu_e, int es, int n, int e, int l,
+                                                double pr, const double *gq) {
+    using S = Shape<D, N>;
+    constexpr int Q = QOf<D>::Q;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    double dmu[D];
+    grad_ref<D, NP>(sD, smu_e, n, dmu);
+    double J[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+    const double w = sd.wn[n];
+    int wk[3];
+    const int nw = wall_entries_of<D>(sd, e, n, wk);
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        double dh[D];
+        grad_ref<D, NP>(sD, sh + (q - 1) * NB + es * NLOC, n, dh);
+        double adv = 0.0, frc = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double ca = dot_e<Q, D>(J[a], q);
+            adv += ca * dh[a];
+            frc += ca * dmu[a];
+        }
+        const double tc = sd.tc[q];
+        double r = -(w * (adv + tc * pr * frc));
+        for (int j = 0; j < nw; ++j) {
+            const int k = wk[j];
+            const double cn = sd.w_cn[k * Q + q];
+            if (cn < 0.0) {
+                const double bc = gq[q] - gq[Lat<Q>::opp[q]] - 2.0 * tc * pr * sd.w_eub[k * Q + q];
+                r += cn * bc;
+            }
+        }
+        sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
+    }
+}
+
+// A: mu of the state's density (DSS of the Laplacian partials) and the lumped-mass
+// weighted element gradients of rho and mu for the collision
+template <int D, int N>
+__global__ __launch_bounds__((Shape<D, N>::NT)) void k_fA(LaunchPlan p) {
+    using S = Shape<D, N>;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    __shared__ double sD[NP * NP];
+    __shared__ double sf[2 * NB];
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const int es = tid / NLOC, n = tid - es * NLOC;
+    const int e = bs.local * S::EPB + es;
+    const bool act = tid < NB && e < sd.E;
+    const int l = e * NLOC + n;
+    if (act) {
+        int cp[kMaxCopies];
+        const int nc = load_copies(sd, l, cp);
+        const int G = sd.lgid[l];
+        const double pr = sd.rho[G];
+        const double mu = mu_of(sd, pr, gather1(sd.rl, cp, nc) * sd.Minv[G]);
+        if (cp[0] == l) sd.mu[G] = mu;
+        sf[tid] = pr;
+        sf[NB + tid] = mu;
+    }
+    __syncthreads();
+    if (!act) return;
+    const double w = sd.wn[n];
+    double J[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        double d[D];
+        grad_ref<D, NP>(sD, sf + f * NB + es * NLOC, n, d);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) s += J[a][c] * d[a];
+            sd.gl[(size_t)(f * D + c) * sd.Nl + l] = w * s;
+        }
+    }
+}
+
+// B: averaged gradients (DSS), collision (Eq. (4)) at every element node, owners store f*
+// in g0, then the stage-1 streaming residual of f*
+template <int D, int N>
+__global__ __launch_bounds__((Shape<D, N>::NT)) void k_fB(LaunchPlan p) {
+    using S = Shape<D, N>;
+    constexpr int Q = QOf<D>::Q;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    __shared__ double sD[NP * NP];
+    __shared__ double smu[NB];
+    __shared__ double sh[(Q - 1) * NB];
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const int es = tid / NLOC, n = tid - es * NLOC;
+    const int e = bs.local * S::EPB + es;
+    const bool act = tid < NB && e < sd.E;
+    const int l = e * NLOC + n;
+    const size_t Ng = sd.Ng;
+    double fs[Q];
+    double pr = 0.0;
+    if (act) {
+        int cp[kMaxCopies];
+        const int nc = load_copies(sd, l, cp);
+        const int G = sd.lgid[l];
+        const double mi = sd.Minv[G];
+        double gr[D], gm[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double s = 0.0, t = 0.0;
+#pragma unroll
+            for (int k = 0; k < kMaxCopies; ++k)
+                if (k < nc) {
+                    s += sd.gl[(size_t)c * sd.Nl + cp[k]];
+                    t += sd.gl[(size_t)(D + c) * sd.Nl + cp[k]];
+                }
+            gr[c] = s * mi;
+            gm[c] = t * mi;
+        }
+        double f[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
+        pr = sd.rho[G];
+        const double cs2 = 1.0 / 3.0, dt = sd.dt, om = sd.omega;
+        double u[D], F[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double m = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int ec = Lat<Q>::e[q][c];
+                if (ec == 1) m = m + f[q];
+                else if (ec == -1) m = m - f[q];
+            }
+            u[c] = m / pr;
+            F[c] = cs2 * gr[c] - pr * gm[c];
+        }
+        double uF = 0.0, uu = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            uF += u[c] * F[c];
+            uu += u[c] * u[c];
+        }
+        const bool owner = cp[0] == l;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double eu = dot_e<Q, D>(u, q), eF = dot_e<Q, D>(F, q);
+            const double tq = sd.t[q], tc = sd.tc[q];
+            const double Fss = tc * (eu * eF * 3.0 - uF);
+            const double feq = pr * tq * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+            const double fbeq = feq - 0.5 * dt * Fss;
+            fs[q] = f[q] - om * (f[q] - fbeq) + dt * Fss;
+            if (owner) sd.g0[q * Ng + G] = fs[q];
+        }
+        smu[tid] = sd.mu[G];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = fs[q] - sd.t[q] * pr;
+    }
+    __syncthreads();
+    if (!act) return;
+    stream_residual<D, N>(sd, sD, sh, smu + es * NLOC, es, n, e, l, pr, fs);
+}
+
+// C: DSS of the streaming residual, SSP-RK3 combination and the stage density at every
+// element node (owners store them), then the Laplacian partials of the new density
+//   stage 1: g1 = g0 + dt L;  stage 2: g2 = 3/4 g0 + 1/4 (g1 + dt L);
+//   stage 3: f = (g0 + 2 (g2 + dt L)) / 3
+template <int D, int N>
+__global__ __launch_bounds__((Shape<D, N>::NT)) void k_fC(LaunchPlan p, int stage) {
+    using S = Shape<D, N>;
+    constexpr int Q = QOf<D>::Q;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    __shared__ double sD[NP * NP];
+    __shared__ double srho[NB];
+    __shared__ double sv[D * NB];
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const int es = tid / NLOC, n = tid - es * NLOC;
+    const int e = bs.local * S::EPB + es;
+    const bool act = tid < NB && e < sd.E;
+    const int l = e * NLOC + n;
+    const size_t Ng = sd.Ng, Nl = sd.Nl;
+    double rho = 0.0;
+    if (act) {
+        int cp[kMaxCopies];
+        const int nc = load_copies(sd, l, cp);
+        const int G = sd.lgid[l];
+        double R[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) R[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMaxCopies; ++k)
+            if (k < nc) {
+#pragma unroll
+                for (int q = 1; q < Q; ++q) R[q] += sd.rs[(size_t)(q - 1) * Nl + cp[k]];
+            }
+        const double *gin = stage == 1 ? sd.g0 : (stage == 2 ? sd.g1 : sd.g2);
+        double *gout = stage == 1 ? sd.g1 : (stage == 2 ? sd.g2 : sd.f);
+        const double mi = sd.Minv[G], dt = sd.dt;
+        const bool owner = cp[0] == l;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double L = q > 0 ? R[q] * mi : 0.0;
+            const double x = gin[q * Ng + G] + dt * L;
+            double out;
+            if (stage == 1) out = x;
+            else if (stage == 2) out = 0.75 * sd.g0[q * Ng + G] + 0.25 * x;
+            else out = (sd.g0[q * Ng + G] + 2.0 * x) / 3.0;
+            rho += out;
+            if (owner) gout[q * Ng + G] = out;
+        }
+        if (owner) sd.rho[G] = rho;
+        srho[tid] = rho;
+    }
+    __syncthreads();
+    if (act) {
+        double d[D];
+        grad_ref<D, NP>(sD, srho + es * NLOC, n, d);
+        double g[S::NG];
+#pragma unroll
+        for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * Nl + l];
+        if constexpr (D == 2) {
+            double v0 = 0.0, v1 = 0.0;
+            v0 += g[0] * d[0]; v0 += g[1] * d[1];
+            v1 += g[1] * d[0]; v1 += g[2] * d[1];
+            sv[tid] = v0; sv[NB + tid] = v1;
+        } else {
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+            v0 += g[0] * d[0]; v0 += g[1] * d[1]; v0 += g[2] * d[2];
+            v1 += g[1] * d[0]; v1 += g[3] * d[1]; v1 += g[4] * d[2];
+            v2 += g[2] * d[0]; v2 += g[4] * d[1]; v2 += g[5] * d[2];
+            sv[tid] = v0; sv[NB + tid] = v1; sv[2 * NB + tid] = v2;
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
+    int wk[3];
+    const int nw = wall_entries_of<D>(sd, e, n, wk);
+    for (int j = 0; j < nw; ++j) r += sd.w_lap[wk[j]] * fabs((rho - sd.rho_l) * (rho - sd.rho_v));
+    sd.rl[l] = r;
+}
+
+// D: mu of the stage density (DSS of the Laplacian partials) and the streaming residual of
+// stage 2 (g1) or 3 (g2)
+template <int D, int N>
+__global__ __launch_bounds__((Shape<D, N>::NT)) void k_fD(LaunchPlan p, int stage) {
+    using S = Shape<D, N>;
+    constexpr int Q = QOf<D>::Q;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    __shared__ double sD[NP * NP];
+    __shared__ double smu[NB];
+    __shared__ double sh[(Q - 1) * NB];
+    const BlockSlot bs = block_slot(p);
+    const SolveDesc &sd = *bs.sd;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const int es = tid / NLOC, n = tid - es * NLOC;
+    const int e = bs.local * S::EPB + es;
+    const bool act = tid < NB && e < sd.E;
+    const int l = e * NLOC + n;
+    const size_t Ng = sd.Ng;
+    const double *__restrict__ g = stage == 2 ? sd.g1 : sd.g2;
+    double gq[Q];
+    double pr = 0.0;
+    if (act) {
+        int cp[kMaxCopies];
+        const int nc = load_copies(sd, l, cp);
+        const int G = sd.lgid[l];
+        pr = sd.rho[G];
+        smu[tid] = mu_of(sd, pr, gather1(sd.rl, cp, nc) * sd.Minv[G]);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) gq[q] = g[q * Ng + G];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = gq[q] - sd.t[q] * pr;
+    }
+    __syncthreads();
+    if (!act) return;
+    stream_residual<D, N>(sd, sD, sh, smu + es * NLOC, es, n, e, l, pr, gq);
+}
+
+// ------------------------------------------------------------------------------------------
 // launchers: dispatch (d, N) to template instances
 // ------------------------------------------------------------------------------------------
 #define SLBM_FOR_ORDERS(X)                                                                     \
@@ -602,6 +935,22 @@ int launch_density(int d, int N, const LaunchPlan &p, int which, void *stream) {
 int launch_diag(int d, int N, const LaunchPlan &p, void *stream) {
 #define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)
     SLBM_DISPATCH(diag, 0);
+}
+int launch_fA(int d, int N, const LaunchPlan &p, void *stream) {
+#define SLBM_CASE_fA(DD, NN) SLBM_ELEM_CASE(k_fA, DD, NN)
+    SLBM_DISPATCH(fA, 0);
+}
+int launch_fB(int d, int N, const LaunchPlan &p, void *stream) {
+#define SLBM_CASE_fB(DD, NN) SLBM_ELEM_CASE(k_fB, DD, NN)
+    SLBM_DISPATCH(fB, 0);
+}
+int launch_fC(int d, int N, const LaunchPlan &p, int stage, void *stream) {
+#define SLBM_CASE_fC(DD, NN) SLBM_ELEM_CASE(k_fC, DD, NN, stage)
+    SLBM_DISPATCH(fC, 0);
+}
+int launch_fD(int d, int N, const LaunchPlan &p, int stage, void *stream) {
+#define SLBM_CASE_fD(DD, NN) SLBM_ELEM_CASE(k_fD, DD, NN, stage)
+    SLBM_DISPATCH(fD, 0);
 }
 int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream) {
     if (nsolves <= 0) return 0;

@@ -243,6 +243,22 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         std::vector<int32_t> fill(c->csr_ptr.begin(), c->csr_ptr.end() - 1);
         for (int64_t l = 0; l < Nl; ++l) c->csr_idx[fill[c->lgid[l]]++] = (int32_t)l;
     }
+    // per-local-node copy lists (fused path): the ascending local copies of its global node
+    c->vmax = 0;
+    for (int64_t g = 0; g < n_global; ++g) c->vmax = std::max<int>(c->vmax, c->csr_ptr[g + 1] - c->csr_ptr[g]);
+    c->lcp.clear();
+    if (c->vmax <= kMaxCopies) {
+        c->lcp.assign((size_t)c->vmax * Nl, -1);
+        for (int64_t l = 0; l < Nl; ++l) {
+            const int g = c->lgid[l];
+            for (int k = c->csr_ptr[g]; k < c->csr_ptr[g + 1]; ++k)
+                c->lcp[(size_t)(k - c->csr_ptr[g]) * Nl + l] = c->csr_idx[k];
+        }
+    }
+    {
+        const char *nf = std::getenv("SLBM_UNFUSED");
+        c->fused = c->vmax <= kMaxCopies && !(nf && nf[0] == '1');
+    }
     c->xyz.assign(xyz, xyz + Nl * dim);
     // --- metric terms, Jacobian, G, lumped mass ---
     const int ng = dim * (dim + 1) / 2;
@@ -331,7 +347,15 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
     c->MA = MA;
     for (int64_t g = 0; g < n_global; ++g) c->Minv[g] = 1.0 / MA[g];
     c->hmin = hmin;
-    c->dt = c->prm.dt > 0.0 ? c->prm.dt : c->prm.cfl * hmin;
+    if (c->prm.dt > 0.0) {
+        c->dt = c->prm.dt;
+    } else {
+        // advective CFL bound, and the capillary bound: the kappa lap(rho) part of the
+        // streaming force has a discrete spectrum growing like h^-2
+        const double dt_adv = c->prm.cfl * hmin;
+        const double dt_cap = 0.25 * hmin * hmin / std::sqrt(c->kappa * c->prm.rho_l);
+        c->dt = dt_adv < dt_cap ? dt_adv : dt_cap;
+    }
     if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return c->fail(SLBM_EINVAL, "invalid time step");
     // --- wall tables: one entry per (face, face node), grouped by element in face order ---
     const double sq = std::sqrt(2.0 * c->beta / c->kappa);
@@ -416,6 +440,7 @@ void slbm_ctx::layout() {
     off.lgid = take(sizeof(int) * Nl);
     off.csr_ptr = take(sizeof(int) * (Ng + 1));
     off.csr_idx = take(sizeof(int) * Nl);
+    off.lcp = take(sizeof(int) * std::max<size_t>(lcp.size(), 1));
     off.wel_ptr = take(sizeof(int) * (E + 1));
     off.w_node = take(sizeof(int) * std::max<int64_t>(nw, 1));
     off.Ja = take(sizeof(double) * dim_ * dim_ * Nl);
@@ -428,7 +453,8 @@ void slbm_ctx::layout() {
     off.w_eub = take(sizeof(double) * Q_ * std::max<int64_t>(nw, 1));
     off.f = take(sizeof(double) * Q_ * Ng);
     off.g0 = take(sizeof(double) * Q_ * Ng);
-    off.gA = take(sizeof(double) * Q_ * Ng);
+    off.g1 = take(sizeof(double) * Q_ * Ng);
+    off.g2 = take(sizeof(double) * Q_ * Ng);
     off.rho = take(sizeof(double) * Ng);
     off.mu = take(sizeof(double) * Ng);
     off.rl = take(sizeof(double) * Nl);
@@ -466,6 +492,8 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     d.Minv = at<double>(b, c->off.Minv);
     d.csr_ptr = at<int>(b, c->off.csr_ptr);
     d.csr_idx = at<int>(b, c->off.csr_idx);
+    d.lcp = at<int>(b, c->off.lcp);
+    d.vmax = c->vmax;
     d.wel_ptr = at<int>(b, c->off.wel_ptr);
     d.w_node = at<int>(b, c->off.w_node);
     d.w_lap = at<double>(b, c->off.w_lap);
@@ -475,7 +503,8 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     d.wn = at<double>(b, c->off.wn);
     d.f = at<double>(b, c->off.f);
     d.g0 = at<double>(b, c->off.g0);
-    d.gA = at<double>(b, c->off.gA);
+    d.g1 = at<double>(b, c->off.g1);
+    d.g2 = at<double>(b, c->off.g2);
     d.rho = at<double>(b, c->off.rho);
     d.mu = at<double>(b, c->off.mu);
     d.rl = at<double>(b, c->off.rl);
@@ -518,6 +547,7 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     up(c->off.lgid, c->lgid.data(), sizeof(int) * c->Nl);
     up(c->off.csr_ptr, c->csr_ptr.data(), sizeof(int) * (c->Ng + 1));
     up(c->off.csr_idx, c->csr_idx.data(), sizeof(int) * c->Nl);
+    up(c->off.lcp, c->lcp.data(), sizeof(int) * c->lcp.size());
     up(c->off.wel_ptr, c->wel_ptr.data(), sizeof(int) * (c->E + 1));
     up(c->off.w_node, c->w_node.data(), sizeof(int) * c->nw);
     up(c->off.Ja, c->Ja.data(), sizeof(double) * dim * dim * c->Nl);
@@ -546,6 +576,7 @@ slbm_status slbm_ctx::upload_f_and_density(const std::vector<double> &f_int) {
     hipStream_t st = (hipStream_t)stream;
     int e = (int)hipMemcpyAsync(desc.f, f_int.data(), sizeof(double) * Q * Ng, hipMemcpyHostToDevice, st);
     if (e == 0) e = launch_density(dim, N, nplan, 0, stream);
+    if (e == 0) e = launch_lap(dim, N, eplan, stream);  // Laplacian partials the fused step starts from
     if (e == 0) e = (int)hipStreamSynchronize(st);
     if (e) return hip_check(e, "upload state");
     has_state = true;
@@ -625,8 +656,22 @@ extern "C" slbm_status slbm_set_state(slbm_ctx *c, const double *f, int64_t step
 // time step
 // ------------------------------------------------------------------------------------------
 int slbm::enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &np, int64_t n,
-                        void *stream) {
+                        void *stream, bool fused) {
     int e = 0;
+    if (fused) {
+        // A (mu, gradients) B (collision, stage-1 residual) then C/D pairs; the state's
+        // Laplacian partials come from the previous step's last C (or the state upload)
+        for (int64_t s = 0; s < n && e == 0; ++s) {
+            e = launch_fA(d, N, ep, stream);
+            if (!e) e = launch_fB(d, N, ep, stream);
+            if (!e) e = launch_fC(d, N, ep, 1, stream);
+            if (!e) e = launch_fD(d, N, ep, 2, stream);
+            if (!e) e = launch_fC(d, N, ep, 2, stream);
+            if (!e) e = launch_fD(d, N, ep, 3, stream);
+            if (!e) e = launch_fC(d, N, ep, 3, stream);
+        }
+        return e;
+    }
     for (int64_t s = 0; s < n && e == 0; ++s) {
         // chemical potential of the state's density (also stage 1's, R10)
         e = launch_lap(d, N, ep, stream);
@@ -699,7 +744,8 @@ slbm_status slbm_ctx::enqueue(int64_t n) {
                 struct A { slbm_ctx *c; int steps; } a{this, sizes[k]};
                 auto fn = [](void *st, void *p) -> int {
                     A *x = (A *)p;
-                    return enqueue_steps(x->c->dim, x->c->N, x->c->eplan, x->c->nplan, x->steps, st);
+                    return enqueue_steps(x->c->dim, x->c->N, x->c->eplan, x->c->nplan, x->steps, st,
+                                         x->c->fused);
                 };
                 const int e = capture_graph(stream, &graph[k], fn, &a);
                 if (e) {  // capture unsupported here: fall back to plain launches for good
@@ -719,7 +765,7 @@ slbm_status slbm_ctx::enqueue(int64_t n) {
             return hip_check(e, "graph launch");
         }
     }
-    return hip_check(enqueue_steps(dim, N, eplan, nplan, n, stream), "step launch");
+    return hip_check(enqueue_steps(dim, N, eplan, nplan, n, stream, fused), "step launch");
 }
 
 extern "C" slbm_status slbm_step(slbm_ctx *c, int64_t n) {
@@ -764,11 +810,20 @@ extern "C" slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int
             if (!e) e = (int)hipEventRecord(ev[2 * i + 1], st);
             kinds[i++] = kind;
         };
-        rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
-        rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
-        rec(2, [&] { return launch_grad(d, N, c->eplan, c->stream); });
-        rec(3, [&] { return launch_collide(d, N, c->nplan, 0, c->stream); });
-        for (int stage = 1; stage <= 3; ++stage) {
+        if (c->fused) {
+            rec(6, [&] { return launch_fA(d, N, c->eplan, c->stream); });
+            rec(7, [&] { return launch_fB(d, N, c->eplan, c->stream); });
+            rec(8, [&] { return launch_fC(d, N, c->eplan, 1, c->stream); });
+            rec(9, [&] { return launch_fD(d, N, c->eplan, 2, c->stream); });
+            rec(8, [&] { return launch_fC(d, N, c->eplan, 2, c->stream); });
+            rec(9, [&] { return launch_fD(d, N, c->eplan, 3, c->stream); });
+            rec(8, [&] { return launch_fC(d, N, c->eplan, 3, c->stream); });
+        }
+        if (!c->fused) rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
+        if (!c->fused) rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
+        if (!c->fused) rec(2, [&] { return launch_grad(d, N, c->eplan, c->stream); });
+        if (!c->fused) rec(3, [&] { return launch_collide(d, N, c->nplan, 0, c->stream); });
+        for (int stage = 1; stage <= 3 && !c->fused; ++stage) {
             if (stage > 1) {
                 rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
                 rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
@@ -894,10 +949,11 @@ slbm_status slbm_ctx::get(const double *src, double *dst_user, int fields) {
     return SLBM_OK;
 }
 
-// the operators overwrite rho/mu/g0/gA scratch; the state's density is restored afterwards
+// the operators overwrite rho/mu/g0/g1 scratch; the state's density is restored afterwards
 slbm_status slbm_ctx::restore_density() {
     if (!has_state) return SLBM_OK;
     int e = launch_density(dim, N, nplan, 0, stream);
+    if (e == 0) e = launch_lap(dim, N, eplan, stream);
     if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)stream);
     return hip_check(e, "restore density");
 }
@@ -928,13 +984,13 @@ extern "C" slbm_status slbm_op_stream(slbm_ctx *c, const double *g, const double
                                       const double *mu, double *L) {
     if (!c || !g || !rho || !mu || !L) return SLBM_EINVAL;
     if (slbm_status s = c->require_bound(false)) return s;
-    if (slbm_status s = c->put(c->desc.gA, g, c->Q)) return s;
+    if (slbm_status s = c->put(c->desc.g1, g, c->Q)) return s;
     if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
     if (slbm_status s = c->put(c->desc.mu, mu, 1)) return s;
     int e = launch_stream(c->dim, c->N, c->eplan, 2, c->stream);
-    if (e == 0) e = launch_rk(c->dim, c->N, c->nplan, 0, c->stream);  // stage 0: L into gA
+    if (e == 0) e = launch_rk(c->dim, c->N, c->nplan, 0, c->stream);  // stage 0: L into g1
     if (e) return c->hip_check(e, "op_stream");
-    if (slbm_status s = c->get(c->desc.gA, L, c->Q)) return s;
+    if (slbm_status s = c->get(c->desc.g1, L, c->Q)) return s;
     return c->restore_density();
 }
 

@@ -33,6 +33,7 @@ struct slbm_batch {
     bool dirty = true;
     struct Group {
         int d = 0, N = 0;
+        bool fused = true;     // every member can take the fused path
         std::vector<int> idx;  // member indices
         LaunchPlan ep{}, np{};
         SolveDesc *desc = nullptr;  // device
@@ -64,6 +65,7 @@ struct slbm_batch {
                 g->N = c->N;
             }
             g->idx.push_back(i);
+            g->fused = g->fused && c->fused;
         }
         // one device block: per group [descs][e tables][n tables][diag out]
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -177,7 +179,7 @@ extern "C" slbm_status slbm_batch_step(slbm_batch *b, int64_t n) {
         if (slbm_status s = b->rebuild()) return s;
     for (int64_t s = 0; s < n; ++s)
         for (auto &g : b->groups) {
-            const int e = enqueue_steps(g.d, g.N, g.ep, g.np, 1, b->stream);
+            const int e = enqueue_steps(g.d, g.N, g.ep, g.np, 1, b->stream, g.fused);
             if (e) return SLBM_EDEVICE;
         }
     for (slbm_ctx *c : b->members) c->step += n;

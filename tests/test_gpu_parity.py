@@ -209,3 +209,21 @@ def test_server_results_equal_alone(P):
         assert res.ke_max == ke
         assert abs(res.theta_deg - a.contact_angle()) < 1e-12
         assert res.t_arrive <= res.t_admit <= res.t_done
+
+
+def test_unfused_path_matches(P, monkeypatch):
+    """The unfused path (separate node kernels for every summation) gives the same bits."""
+    monkeypatch.setenv("SLBM_UNFUSED", "1")
+    c = cases.small_flat()
+    s, o = _run_pair(c, P, 100)
+    assert np.array_equal(s.rho(), o.rho()) or rel(s.rho(), o.rho()) <= TOL
+    assert rel(s.u(), o.u()) <= TOL
+    prof = s.step_profile(2)
+    assert "rk" in prof and "f_rk_lap" not in prof
+    monkeypatch.delenv("SLBM_UNFUSED")
+    f = P.Solve(c)
+    f.init_tanh()
+    f.step(102)
+    assert "f_rk_lap" in f.step_profile(1)
+    s.step(1)
+    assert np.array_equal(f.get_state()[0], s.get_state()[0])
