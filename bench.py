@@ -95,12 +95,103 @@ def traffic_from_profiles(workload: str, kind: str):
     return float(v) if v is not None else None
 
 
+def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
+                  ke_stop: float = 1e-20, max_slots: int = 64, seed: int = 5):
+    """Config 5 (reduced): n_req droplet requests (flat or cylinder wall, N in {4,6,8},
+    theta ~ U[30,150], R ~ U[10,30]) run to KE_max < ke_stop or max_steps.
+
+    Three runs of the same request list: (1) the plain stepper, one solve at a time with
+    the same KE check cadence; (2) the continuous-batching server with every request
+    submitted at once (throughput); (3) the server under Poisson arrivals at 0.7x the
+    measured batched capacity (latency p50/p99 from arrival to retirement)."""
+    import numpy as np
+
+    from synth import cases
+    reqs = cases.request_stream(n_req, seed=seed)
+    cs = []
+    for r in reqs:
+        c = cases.request_case(r)
+        c.steps = max_steps
+        cs.append(c)
+    stream = torch.cuda.Stream()
+    # (1) plain stepper
+    t0 = time.perf_counter()
+    plain_steps = []
+    with torch.cuda.stream(stream):
+        for c in cs:
+            s = P.Solve(c, stream=stream)
+            s.init_tanh()
+            n = 0
+            while n < max_steps:
+                s.step(check_every)
+                n += check_every
+                ke, _ = s.kinetic_energy()
+                if not (ke <= 1.0) or ke < ke_stop:
+                    break
+            plain_steps.append(n)
+            del s
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+
+    def run_server(arrivals):
+        srv = P.Server(arena_bytes=8 << 30, max_slots=max_slots, check_every=check_every,
+                       ke_stop=ke_stop, max_steps=max_steps, stream=stream)
+        ids = [None] * len(cs)
+        order = np.argsort(arrivals)
+        k = 0
+        t_start = srv.clock()
+        pending = 1
+        while k < len(cs) or pending > 0:
+            now = srv.clock() - t_start
+            while k < len(cs) and arrivals[order[k]] <= now:
+                ids[order[k]] = srv.submit(cs[order[k]])
+                k += 1
+            pending = srv.tick()
+            if pending == 0 and k < len(cs):
+                time.sleep(max(0.0, arrivals[order[k]] - (srv.clock() - t_start)))
+        t_total = srv.clock() - t_start
+        res = [srv.poll(i) for i in ids]
+        lat = np.array([r.t_done - r.t_arrive for r in res])
+        ok = sum(1 for r in res if r.status == 0)
+        steps = [r.steps for r in res]
+        theta = [r.theta_deg for r in res]
+        del srv
+        return t_total, lat, ok, steps, theta
+
+    with torch.cuda.stream(stream):
+        t_batch, lat_b, ok_b, steps_b, theta_b = run_server(np.zeros(len(cs)))
+        cap = len(cs) / t_batch
+        arr = np.array([r["t_arrive"] for r in reqs]) / (0.7 * cap)
+        t_pois, lat_p, ok_p, _, _ = run_server(arr - arr.min())
+    stopped_ke = sum(1 for s_ in steps_b if s_ < max_steps)
+    return {
+        "metric": "batched sweep solves/s",
+        "requests": len(cs), "max_steps": max_steps, "check_every": check_every,
+        "ke_stop": ke_stop, "max_slots": max_slots,
+        "batched_solves_per_s": len(cs) / t_batch,
+        "plain_solves_per_s": len(cs) / t_plain,
+        "batched_over_plain": t_plain / t_batch,
+        "saturated_latency_s": {"p50": float(np.percentile(lat_b, 50)),
+                                "p99": float(np.percentile(lat_b, 99))},
+        "poisson_0p7": {"rate_per_s": 0.7 * cap, "makespan_s": t_pois,
+                        "latency_p50_s": float(np.percentile(lat_p, 50)),
+                        "latency_p99_s": float(np.percentile(lat_p, 99)), "ok": ok_p},
+        "ok": ok_b, "retired_by_ke": stopped_ke,
+        "plain_total_steps": int(sum(plain_steps)), "batched_total_steps": int(sum(steps_b)),
+        "theta_err_deg_median": float(np.nanmedian(np.abs(np.array(theta_b) -
+                                                           np.array([c.theta_deg for c in cs])))),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-max-steps", type=int, default=2000)
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -117,6 +208,13 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
+    if args.workload == "c5":
+        out = serving_bench(P, torch, args.serve_requests, args.serve_max_steps)
+        out.update({"value": out["batched_solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+                    "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                    "config": {"workload": "c5 (reduced request count and step cap)"}})
+        print(json.dumps(out))
+        return
     case = make_case(args.workload)
     m = case.mesh
     Q, d, Ng, Nl = case.lattice, m.dim, m.n_global, m.n_local
@@ -169,6 +267,8 @@ def main():
                      "algorithmic_bytes_per_launch": alg,
                      "kernel_ms_per_step": {k: v[0] / args.profile_steps for k, v in prof.items()}},
     }
+    if not args.no_serving and args.workload == "c2":
+        out["serving"] = serving_bench(P, torch, args.serve_requests, args.serve_max_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_steps)
     print(json.dumps(out))

@@ -39,7 +39,7 @@ struct slbm_ctx {
             w_cn, w_eub, f, g0, g1, g2, rho, mu, rl, gl, rs, aux, diag, red;
     } off{};
     size_t ws_bytes = 0;
-    int n_eblocks = 0, n_nblocks = 0;
+    int n_eblocks = 0, n_nblocks = 0, epb = 1;
     bool bound = false, has_state = false;
     void *dev = nullptr;
     void *stream = nullptr;

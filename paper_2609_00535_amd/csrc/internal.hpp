@@ -54,11 +54,19 @@ struct LaunchPlan {
     const int *blk_solve;    // device: block -> batch member index
     const int *blk_local;    // device: block -> block index within its member
     int nblocks;
+    int single;              // one member: block b is block b of desc[0] (no table lookup)
+    int epb;                 // elements per block of element kernels (wide or 1)
 };
 
-// Element-kernel shape for order N in d dimensions (must match kernels.hip).
+// Element-kernel shape for order N in d dimensions (must match kernels.hip): "wide" blocks
+// hold as many elements as fit in 256 threads; small meshes use one element per block so
+// that every compute unit gets work.
 inline int nloc_of(int d, int N) { int p = N + 1; return d == 2 ? p * p : p * p * p; }
-inline int epb_of(int d, int N) { int n = nloc_of(d, N); return n <= 256 ? 256 / n : 1; }
+inline int epb_wide(int d, int N) { int n = nloc_of(d, N); return n <= 256 ? 256 / n : 1; }
+inline int epb_for(int d, int N, int64_t E) {
+    const int w = epb_wide(d, N);
+    return (E + w - 1) / w < 256 ? 1 : w;
+}
 constexpr int kNodeThreads = 256;
 
 // Kernel launchers (kernels.hip).  'stage' is 1..3 for the RK stages.  All launch on

@@ -59,12 +59,12 @@ __device__ __forceinline__ double dot_e(const double *v, int q) {
 // ------------------------------------------------------------------------------------------
 // element shapes
 // ------------------------------------------------------------------------------------------
-template <int D, int N> struct Shape {
+template <int D, int N, bool WIDE = true> struct Shape {
     static constexpr int NP = N + 1;
     static constexpr int NLOC = D == 2 ? NP * NP : NP * NP * NP;
-    static constexpr int EPB = NLOC <= 256 ? 256 / NLOC : 1;
+    static constexpr int EPB = WIDE && NLOC <= 256 ? 256 / NLOC : 1;
     static constexpr int NB = EPB * NLOC;  // nodes of one block
-    static constexpr int NT = NLOC <= 256 ? 256 : ((NLOC + 63) / 64) * 64;
+    static constexpr int NT = ((NB + 63) / 64) * 64;
     static constexpr int NG = D * (D + 1) / 2;
 };
 
@@ -118,19 +118,35 @@ struct BlockSlot {
 };
 __device__ __forceinline__ BlockSlot block_slot(const LaunchPlan &p) {
     BlockSlot b;
-    b.sd = p.desc + p.blk_solve[blockIdx.x];
-    b.local = p.blk_local[blockIdx.x];
+    if (p.single) {
+        b.sd = p.desc;
+        b.local = blockIdx.x;
+    } else {
+        b.sd = p.desc + p.blk_solve[blockIdx.x];
+        b.local = p.blk_local[blockIdx.x];
+    }
     return b;
 }
 
 // wall entries of element e that sit on node n (at most d faces meet at a node), in
 // list order
+// (fixed-size, constant-indexed register array: a dynamically indexed one would live in
+// scratch memory)
+struct WallIdx {
+    int k[3];
+};
 template <int D>
-__device__ __forceinline__ int wall_entries_of(const SolveDesc &sd, int e, int n, int *wk) {
+__device__ __forceinline__ int wall_entries_of(const SolveDesc &sd, int e, int n, WallIdx &wi) {
     int cnt = 0;
+    wi.k[0] = wi.k[1] = wi.k[2] = 0;
     const int k0 = sd.wel_ptr[e], k1 = sd.wel_ptr[e + 1];
     for (int k = k0; k < k1; ++k)
-        if (sd.w_node[k] == n && cnt < D) wk[cnt++] = k;
+        if (sd.w_node[k] == n) {
+            if (cnt == 0) wi.k[0] = k;
+            else if (cnt == 1) wi.k[1] = k;
+            else if (D == 3 && cnt == 2) wi.k[2] = k;
+            cnt = cnt < D ? cnt + 1 : cnt;
+        }
     return cnt;
 }
 
@@ -138,9 +154,9 @@ __device__ __forceinline__ int wall_entries_of(const SolveDesc &sd, int e, int n
 // Eq. (8): element part of the weak Laplacian, r = -sum_a D_a^T (G^{ab} D_b rho), plus the
 // wetting boundary integral s n.grad(rho) = s cos(theta) sqrt(2 beta/kappa) |(rho-rl)(rho-rv)|
 // ------------------------------------------------------------------------------------------
-template <int D, int N>
-__global__ __launch_bounds__((Shape<D, N>::NT)) void k_lap(LaunchPlan p) {
-    using S = Shape<D, N>;
+template <int D, int N, bool WIDE>
+__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
+    using S = Shape<D, N, WIDE>;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
     __shared__ double srho[NB];
@@ -182,9 +198,11 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_lap(LaunchPlan p) {
     __syncthreads();
     if (!act) return;
     double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
-    int wk[3];
-    const int nw = wall_entries_of<D>(sd, e, n, wk);
-    for (int j = 0; j < nw; ++j) r += sd.w_lap[wk[j]] * fabs((rh - sd.rho_l) * (rh - sd.rho_v));
+    WallIdx wi;
+    const int nw = wall_entries_of<D>(sd, e, n, wi);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        if (j < nw) r += sd.w_lap[wi.k[j]] * fabs((rh - sd.rho_l) * (rh - sd.rho_v));
     sd.rl[l] = r;
 }
 
@@ -204,9 +222,9 @@ __global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
 }
 
 // lumped-mass weighted element gradients w Ja^T grad_ref of rho and mu (for the collision)
-template <int D, int N>
-__global__ __launch_bounds__((Shape<D, N>::NT)) void k_grad(LaunchPlan p) {
-    using S = Shape<D, N>;
+template <int D, int N, bool WIDE>
+__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_grad(LaunchPlan p) {
+    using S = Shape<D, N, WIDE>;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
     __shared__ double sf[2 * NB];
@@ -335,9 +353,9 @@ __global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_
 // plus, on wall faces with (s n).e_a < 0, (s n . e_a) [g_a - g_opp - 2 (t_a/cs^2) rho e_a.u_b]
 // stage 1 streams g0, stages 2-3 stream g1
 // ------------------------------------------------------------------------------------------
-template <int D, int N>
-__global__ __launch_bounds__((Shape<D, N>::NT)) void k_stream(LaunchPlan p, int stage) {
-    using S = Shape<D, N>;
+template <int D, int N, bool WIDE>
+__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_stream(LaunchPlan p, int stage) {
+    using S = Shape<D, N, WIDE>;
     constexpr int Q = QOf<D>::Q;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
@@ -372,8 +390,8 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_stream(LaunchPlan p, int 
 #pragma unroll
         for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
     const double w = sd.wn[n];
-    int wk[3];
-    const int nw = wall_entries_of<D>(sd, e, n, wk);
+    WallIdx wi;
+    const int nw = wall_entries_of<D>(sd, e, n, wi);
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
         double dh[D];
@@ -387,8 +405,10 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_stream(LaunchPlan p, int 
         }
         const double tc = sd.tc[q];
         double r = -(w * (adv + tc * pr * frc));
-        for (int j = 0; j < nw; ++j) {
-            const int k = wk[j];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j >= nw) break;
+            const int k = wi.k[j];
             const double cn = sd.w_cn[k * Q + q];
             if (cn < 0.0) {
                 const double ga = g[q * Ng + G], gb = g[Lat<Q>::opp[q] * Ng + G];
@@ -572,23 +592,35 @@ __device__ __forceinline__ double mu_of(const SolveDesc &sd, double pr, double l
 
 // element residual of the streaming (Eqs. (5)-(6), (12)) and flux bounce-back (Eq. (9)) at
 // node n, from LDS h_q = g_q - t_q rho, LDS mu, register g (for the flux) ; writes rs
-template <int D, int N>
+// per-node metric and wall data, loaded before the block's first barrier so that their
+// latency overlaps the gathers
+template <int D> struct NodeGeo {
+    double J[D][D];
+    double w;
+    int nw;
+    WallIdx wi;
+};
+template <int D>
+__device__ __forceinline__ void load_geo(const SolveDesc &sd, int e, int n, int l, NodeGeo<D> &g) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) g.J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+    g.w = sd.wn[n];
+    g.nw = wall_entries_of<D>(sd, e, n, g.wi);
+}
+
+template <int D, int N, bool WIDE>
 __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
-                                                const double *smu_e, int es, int n, int e, int l,
-                                                double pr, const double *gq) {
-    using S = Shape<D, N>;
+                                                const double *smu_e, int es, int n, int l,
+                                                double pr, const double *gq, const NodeGeo<D> &geo) {
+    using S = Shape<D, N, WIDE>;
     constexpr int Q = QOf<D>::Q;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     double dmu[D];
     grad_ref<D, NP>(sD, smu_e, n, dmu);
-    double J[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
-    const double w = sd.wn[n];
-    int wk[3];
-    const int nw = wall_entries_of<D>(sd, e, n, wk);
+    const double w = geo.w;
+    const int nw = geo.nw;
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
         double dh[D];
@@ -596,14 +628,16 @@ __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const doubl
         double adv = 0.0, frc = 0.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const double ca = dot_e<Q, D>(J[a], q);
+            const double ca = dot_e<Q, D>(geo.J[a], q);
             adv += ca * dh[a];
             frc += ca * dmu[a];
         }
         const double tc = sd.tc[q];
         double r = -(w * (adv + tc * pr * frc));
-        for (int j = 0; j < nw; ++j) {
-            const int k = wk[j];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j >= nw) break;
+            const int k = geo.wi.k[j];
             const double cn = sd.w_cn[k * Q + q];
             if (cn < 0.0) {
                 const double bc = gq[q] - gq[Lat<Q>::opp[q]] - 2.0 * tc * pr * sd.w_eub[k * Q + q];
@@ -616,9 +650,9 @@ __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const doubl
 
 // A: mu of the state's density (DSS of the Laplacian partials) and the lumped-mass
 // weighted element gradients of rho and mu for the collision
-template <int D, int N>
-__global__ __launch_bounds__((Shape<D, N>::NT)) void k_fA(LaunchPlan p) {
-    using S = Shape<D, N>;
+template <int D, int N, bool WIDE>
+__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
+    using S = Shape<D, N, WIDE>;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
     __shared__ double sf[2 * NB];
@@ -664,9 +698,9 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_fA(LaunchPlan p) {
 
 // B: averaged gradients (DSS), collision (Eq. (4)) at every element node, owners store f*
 // in g0, then the stage-1 streaming residual of f*
-template <int D, int N>
-__global__ __launch_bounds__((Shape<D, N>::NT)) void k_fB(LaunchPlan p) {
-    using S = Shape<D, N>;
+template <int D, int N, bool WIDE>
+__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
+    using S = Shape<D, N, WIDE>;
     constexpr int Q = QOf<D>::Q;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
@@ -683,10 +717,12 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_fB(LaunchPlan p) {
     const size_t Ng = sd.Ng;
     double fs[Q];
     double pr = 0.0;
+    NodeGeo<D> geo;
     if (act) {
         int cp[kMaxCopies];
         const int nc = load_copies(sd, l, cp);
         const int G = sd.lgid[l];
+        load_geo<D>(sd, e, n, l, geo);
         const double mi = sd.Minv[G];
         double gr[D], gm[D];
 #pragma unroll
@@ -742,16 +778,16 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_fB(LaunchPlan p) {
     }
     __syncthreads();
     if (!act) return;
-    stream_residual<D, N>(sd, sD, sh, smu + es * NLOC, es, n, e, l, pr, fs);
+    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, fs, geo);
 }
 
 // C: DSS of the streaming residual, SSP-RK3 combination and the stage density at every
 // element node (owners store them), then the Laplacian partials of the new density
 //   stage 1: g1 = g0 + dt L;  stage 2: g2 = 3/4 g0 + 1/4 (g1 + dt L);
 //   stage 3: f = (g0 + 2 (g2 + dt L)) / 3
-template <int D, int N>
-__global__ __launch_bounds__((Shape<D, N>::NT)) void k_fC(LaunchPlan p, int stage) {
-    using S = Shape<D, N>;
+template <int D, int N, bool WIDE>
+__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, int stage) {
+    using S = Shape<D, N, WIDE>;
     constexpr int Q = QOf<D>::Q;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
@@ -767,10 +803,16 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_fC(LaunchPlan p, int stag
     const int l = e * NLOC + n;
     const size_t Ng = sd.Ng, Nl = sd.Nl;
     double rho = 0.0;
+    double gm[S::NG];
+    WallIdx wi;
+    int nw = 0;
     if (act) {
         int cp[kMaxCopies];
         const int nc = load_copies(sd, l, cp);
         const int G = sd.lgid[l];
+#pragma unroll
+        for (int k = 0; k < S::NG; ++k) gm[k] = sd.G[(size_t)k * Nl + l];
+        nw = wall_entries_of<D>(sd, e, n, wi);
         double R[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) R[q] = 0.0;
@@ -802,9 +844,7 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_fC(LaunchPlan p, int stag
     if (act) {
         double d[D];
         grad_ref<D, NP>(sD, srho + es * NLOC, n, d);
-        double g[S::NG];
-#pragma unroll
-        for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * Nl + l];
+        const double *g = gm;
         if constexpr (D == 2) {
             double v0 = 0.0, v1 = 0.0;
             v0 += g[0] * d[0]; v0 += g[1] * d[1];
@@ -821,17 +861,17 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_fC(LaunchPlan p, int stag
     __syncthreads();
     if (!act) return;
     double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
-    int wk[3];
-    const int nw = wall_entries_of<D>(sd, e, n, wk);
-    for (int j = 0; j < nw; ++j) r += sd.w_lap[wk[j]] * fabs((rho - sd.rho_l) * (rho - sd.rho_v));
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        if (j < nw) r += sd.w_lap[wi.k[j]] * fabs((rho - sd.rho_l) * (rho - sd.rho_v));
     sd.rl[l] = r;
 }
 
 // D: mu of the stage density (DSS of the Laplacian partials) and the streaming residual of
 // stage 2 (g1) or 3 (g2)
-template <int D, int N>
-__global__ __launch_bounds__((Shape<D, N>::NT)) void k_fD(LaunchPlan p, int stage) {
-    using S = Shape<D, N>;
+template <int D, int N, bool WIDE>
+__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, int stage) {
+    using S = Shape<D, N, WIDE>;
     constexpr int Q = QOf<D>::Q;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
@@ -849,10 +889,12 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_fD(LaunchPlan p, int stag
     const double *__restrict__ g = stage == 2 ? sd.g1 : sd.g2;
     double gq[Q];
     double pr = 0.0;
+    NodeGeo<D> geo;
     if (act) {
         int cp[kMaxCopies];
         const int nc = load_copies(sd, l, cp);
         const int G = sd.lgid[l];
+        load_geo<D>(sd, e, n, l, geo);
         pr = sd.rho[G];
         smu[tid] = mu_of(sd, pr, gather1(sd.rl, cp, nc) * sd.Minv[G]);
 #pragma unroll
@@ -862,7 +904,7 @@ __global__ __launch_bounds__((Shape<D, N>::NT)) void k_fD(LaunchPlan p, int stag
     }
     __syncthreads();
     if (!act) return;
-    stream_residual<D, N>(sd, sD, sh, smu + es * NLOC, es, n, e, l, pr, gq);
+    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -891,7 +933,10 @@ bool supported_order(int d, int N) {
 
 #define SLBM_ELEM_CASE(KERNEL, DD, NN, ...)                                                  \
     if (!done && d == DD && N == NN) {                                                       \
-        KERNEL<DD, NN><<<p.nblocks, Shape<DD, NN>::NT, 0, st>>>(p, ##__VA_ARGS__);           \
+        if (p.epb == Shape<DD, NN, true>::EPB)                                               \
+            KERNEL<DD, NN, true><<<p.nblocks, Shape<DD, NN, true>::NT, 0, st>>>(p, ##__VA_ARGS__); \
+        else                                                                                 \
+            KERNEL<DD, NN, false><<<p.nblocks, Shape<DD, NN, false>::NT, 0, st>>>(p, ##__VA_ARGS__); \
         done = true;                                                                         \
     }
 #define SLBM_NODE_CASE(KERNEL, DD, NN, ...)                                                  \

@@ -256,8 +256,15 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         }
     }
     {
+        // fused kernels finish each summation by gathering all copies at every copy: the
+        // right trade for latency-bound meshes; large 3-D meshes (up to 8 copies per node,
+        // 18 moving populations) move less data through the separate node kernels
         const char *nf = std::getenv("SLBM_UNFUSED");
-        c->fused = c->vmax <= kMaxCopies && !(nf && nf[0] == '1');
+        const char *ff = std::getenv("SLBM_FUSED");
+        const bool large3d = dim == 3 && Nl > (int64_t)1 << 20;
+        c->fused = c->vmax <= kMaxCopies && !large3d;
+        if (nf && nf[0] == '1') c->fused = false;
+        if (ff && ff[0] == '1' && c->vmax <= kMaxCopies) c->fused = true;
     }
     c->xyz.assign(xyz, xyz + Nl * dim);
     // --- metric terms, Jacobian, G, lumped mass ---
@@ -432,7 +439,8 @@ void slbm_ctx::layout() {
     off = Offsets();
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    n_eblocks = (int)((E + epb_of(dim_, N) - 1) / epb_of(dim_, N));
+    epb = epb_for(dim_, N, E);
+    n_eblocks = (int)((E + epb - 1) / epb);
     n_nblocks = (int)((Ng + kNodeThreads - 1) / kNodeThreads);
     off.desc = take(sizeof(SolveDesc));
     off.eplan = take(sizeof(int) * 2 * (size_t)n_eblocks);
@@ -531,10 +539,14 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     c->eplan.blk_solve = at<int>(b, c->off.eplan);
     c->eplan.blk_local = at<int>(b, c->off.eplan) + c->n_eblocks;
     c->eplan.nblocks = c->n_eblocks;
+    c->eplan.single = 1;
+    c->eplan.epb = c->epb;
     c->nplan.desc = at<SolveDesc>(b, c->off.desc);
     c->nplan.blk_solve = at<int>(b, c->off.nplan);
     c->nplan.blk_local = at<int>(b, c->off.nplan) + c->n_nblocks;
     c->nplan.nblocks = c->n_nblocks;
+    c->nplan.single = 1;
+    c->nplan.epb = 0;
     const int Q = c->Q, dim = c->dim;
     const size_t ng = (size_t)dim * (dim + 1) / 2;
     int e = 0;

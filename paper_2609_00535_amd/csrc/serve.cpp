@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -32,7 +33,7 @@ struct slbm_batch {
     std::vector<slbm_ctx *> members;
     bool dirty = true;
     struct Group {
-        int d = 0, N = 0;
+        int d = 0, N = 0, epb = 1;
         bool fused = true;     // every member can take the fused path
         std::vector<int> idx;  // member indices
         LaunchPlan ep{}, np{};
@@ -43,8 +44,54 @@ struct slbm_batch {
     void *dmem = nullptr;
     size_t dcap = 0;
     slbm_status status = SLBM_OK;
+    // graphs of 1 and 10 batched steps for the current membership (captured lazily)
+    void *graph[2] = {nullptr, nullptr};
+    bool use_graph = true;
+
+    void drop_graphs() {
+        destroy_graph(graph[0]);
+        destroy_graph(graph[1]);
+        graph[0] = graph[1] = nullptr;
+    }
+
+    int enqueue(int64_t n) {
+        for (int64_t s = 0; s < n; ++s)
+            for (auto &g : groups) {
+                const int e = enqueue_steps(g.d, g.N, g.ep, g.np, 1, stream, g.fused);
+                if (e) return e;
+            }
+        return 0;
+    }
+
+    int run(int64_t n) {
+        if (use_graph && stream != nullptr) {
+            const int sizes[2] = {1, 10};
+            for (int k = 0; k < 2 && use_graph; ++k)
+                if (!graph[k]) {
+                    struct A { slbm_batch *b; int steps; } a{this, sizes[k]};
+                    auto fn = [](void *, void *p) -> int {
+                        A *x = (A *)p;
+                        return x->b->enqueue(x->steps);
+                    };
+                    if (capture_graph(stream, &graph[k], fn, &a)) {
+                        (void)hipGetLastError();
+                        use_graph = false;
+                        drop_graphs();
+                    }
+                }
+            if (use_graph) {
+                int e = 0;
+                int64_t left = n;
+                while (left >= 10 && !e) { e = launch_graph(graph[1], stream); left -= 10; }
+                while (left > 0 && !e) { e = launch_graph(graph[0], stream); left -= 1; }
+                return e;
+            }
+        }
+        return enqueue(n);
+    }
 
     ~slbm_batch() {
+        drop_graphs();
         if (dmem) {
             (void)hipStreamSynchronize((hipStream_t)stream);
             (void)hipFree(dmem);
@@ -52,17 +99,19 @@ struct slbm_batch {
     }
 
     slbm_status rebuild() {
+        drop_graphs();
         groups.clear();
         for (int i = 0; i < (int)members.size(); ++i) {
             slbm_ctx *c = members[i];
             Group *g = nullptr;
             for (auto &x : groups)
-                if (x.d == c->dim && x.N == c->N) g = &x;
+                if (x.d == c->dim && x.N == c->N && x.epb == c->epb) g = &x;
             if (!g) {
                 groups.emplace_back();
                 g = &groups.back();
                 g->d = c->dim;
                 g->N = c->N;
+                g->epb = c->epb;
             }
             g->idx.push_back(i);
             g->fused = g->fused && c->fused;
@@ -129,8 +178,11 @@ struct slbm_batch {
             }
             char *base = (char *)dmem;
             g.desc = reinterpret_cast<SolveDesc *>(base + o_desc);
-            g.ep = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_e), reinterpret_cast<int *>(base + o_e) + ne, ne};
-            g.np = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_n), reinterpret_cast<int *>(base + o_n) + nn, nn};
+            const int single = g.idx.size() == 1;
+            g.ep = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_e), reinterpret_cast<int *>(base + o_e) + ne, ne,
+                              single, g.epb};
+            g.np = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_n), reinterpret_cast<int *>(base + o_n) + nn, nn,
+                              single, 0};
             g.diag_out = reinterpret_cast<double *>(base + o_d);
         }
         if (total) {
@@ -148,6 +200,8 @@ extern "C" slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out) {
     *out = new (std::nothrow) slbm_batch();
     if (!*out) return SLBM_ENOMEM;
     (*out)->stream = hip_stream;
+    const char *ng = std::getenv("SLBM_NO_GRAPH");
+    (*out)->use_graph = !(ng && ng[0] == '1');
     return SLBM_OK;
 }
 
@@ -177,11 +231,7 @@ extern "C" slbm_status slbm_batch_step(slbm_batch *b, int64_t n) {
     if (b->members.empty() || n == 0) return SLBM_OK;
     if (b->dirty)
         if (slbm_status s = b->rebuild()) return s;
-    for (int64_t s = 0; s < n; ++s)
-        for (auto &g : b->groups) {
-            const int e = enqueue_steps(g.d, g.N, g.ep, g.np, 1, b->stream, g.fused);
-            if (e) return SLBM_EDEVICE;
-        }
+    if (b->run(n)) return SLBM_EDEVICE;
     for (slbm_ctx *c : b->members) c->step += n;
     return SLBM_OK;
 }

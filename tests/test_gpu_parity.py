@@ -112,6 +112,28 @@ def test_config2_full_size(P):
     assert er <= TOL and eu <= TOL
 
 
+def test_config3_full_size(P):
+    """c3 at full size (O-grid of 2048 curved quads, N=8, cylinder wall), 10 steps."""
+    c = cases.c3()
+    s, o = _run_pair(c, P, 10)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] c3 10 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+
+
+def test_config4_full_size(P):
+    """c4 at full size (24000 curved hexes, N=5, D3Q19, sphere wall): the launch
+    configuration the benchmark times, 2 steps against the oracle (~1 min of CPU)."""
+    c = cases.c4()
+    s, o = _run_pair(c, P, 2)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] c4 2 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+    _, mg = s.kinetic_energy()
+    _, mo = o.diag()
+    assert abs(mg - mo) <= 1e-13 * mo
+
+
 def test_mass_conservation_gpu(P):
     c = cases.small_flat()
     s = P.Solve(c)
