@@ -5,6 +5,16 @@
 #include <cstddef>
 #include <cstdint>
 
+// Pointers into device memory are qualified as global-address-space when compiled for the
+// GPU (the host sees plain pointers; both are 64-bit, so the layouts agree).  Pointers read
+// from a descriptor would otherwise be generic and compile to FLAT instructions, which share
+// the LDS wait counter and serialise memory with LDS traffic.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SLBM_GLOBAL __attribute__((address_space(1)))
+#else
+#define SLBM_GLOBAL
+#endif
+
 namespace slbm {
 
 constexpr int kMaxQ = 19;
@@ -14,35 +24,35 @@ constexpr int kMaxQ = 19;
 struct SolveDesc {
     int E, Nl, Ng, pad0;
     // mesh tables (device)
-    const int *lgid;      // [Nl] local node -> internal global node
-    const double *Ja;     // [d*d][Nl] J * d xi_a / d x_c, index (a*d + c)
-    const double *G;      // [d(d+1)/2][Nl] w (Ja_a . Ja_b) / J, upper triangle row-major
-    const double *Minv;   // [Ng] inverse assembled lumped mass
-    const int *csr_ptr;   // [Ng+1] local copies of each global node
-    const int *csr_idx;   // [Nl]   ascending local indices
-    const int *lcp;       // [vmax][Nl] local copies of the global node of each local node,
+    const int SLBM_GLOBAL *lgid;      // [Nl] local node -> internal global node
+    const double SLBM_GLOBAL *Ja;     // [d*d][Nl] J * d xi_a / d x_c, index (a*d + c)
+    const double SLBM_GLOBAL *G;      // [d(d+1)/2][Nl] w (Ja_a . Ja_b) / J, upper triangle row-major
+    const double SLBM_GLOBAL *Minv;   // [Ng] inverse assembled lumped mass
+    const int SLBM_GLOBAL *csr_ptr;   // [Ng+1] local copies of each global node
+    const int SLBM_GLOBAL *csr_idx;   // [Nl]   ascending local indices
+    const int SLBM_GLOBAL *lcp;       // [vmax][Nl] local copies of the global node of each local node,
                           // ascending, -1 padded (fused path)
     int vmax, pad1;
-    const int *wel_ptr;   // [E+1] wall entries of each element
-    const int *w_node;    // [nw] element-local node of the entry
-    const double *w_lap;  // [nw] s cos(theta) sqrt(2 beta / kappa)
-    const double *w_cn;   // [nw][Q] (s n) . e_a (only negative values act)
-    const double *w_eub;  // [nw][Q] e_a . u_b
-    const double *Dm;     // [(N+1)^2] GLL differentiation matrix, Dm[i*(N+1)+m]
-    const double *wn;     // [(N+1)^d] tensor GLL weights
+    const int SLBM_GLOBAL *wel_ptr;   // [E+1] wall entries of each element
+    const int SLBM_GLOBAL *w_node;    // [nw] element-local node of the entry
+    const double SLBM_GLOBAL *w_lap;  // [nw] s cos(theta) sqrt(2 beta / kappa)
+    const double SLBM_GLOBAL *w_cn;   // [nw][Q] (s n) . e_a (only negative values act)
+    const double SLBM_GLOBAL *w_eub;  // [nw][Q] e_a . u_b
+    const double SLBM_GLOBAL *Dm;     // [(N+1)^2] GLL differentiation matrix, Dm[i*(N+1)+m]
+    const double SLBM_GLOBAL *wn;     // [(N+1)^d] tensor GLL weights
     // state and work buffers (device)
-    double *f;    // [Q][Ng] f-bar (state)
-    double *g0;   // [Q][Ng] post-collision f*
-    double *g1;   // [Q][Ng] Runge-Kutta stage 1 (the unfused path keeps every stage here)
-    double *g2;   // [Q][Ng] Runge-Kutta stage 2 (fused path)
-    double *rho;  // [Ng]
-    double *mu;   // [Ng]
-    double *rl;   // [Nl] Laplacian residual of each local copy
-    double *gl;   // [2d][Nl] lumped-mass weighted element gradients of rho and mu
-    double *rs;   // [Q-1][Nl] streaming residual of each local copy
-    double *aux;  // [2d][Ng] averaged gradients (operator entry points)
-    double *diag; // [4] KE_max, mass, -, -
-    double *red;  // [2 * max blocks] reduction partials
+    double SLBM_GLOBAL *f;    // [Q][Ng] f-bar (state)
+    double SLBM_GLOBAL *g0;   // [Q][Ng] post-collision f*
+    double SLBM_GLOBAL *g1;   // [Q][Ng] Runge-Kutta stage 1 (the unfused path keeps every stage here)
+    double SLBM_GLOBAL *g2;   // [Q][Ng] Runge-Kutta stage 2 (fused path)
+    double SLBM_GLOBAL *rho;  // [Ng]
+    double SLBM_GLOBAL *mu;   // [Ng]
+    double SLBM_GLOBAL *rl;   // [Nl] Laplacian residual of each local copy
+    double SLBM_GLOBAL *gl;   // [2d][Nl] lumped-mass weighted element gradients of rho and mu
+    double SLBM_GLOBAL *rs;   // [Q-1][Nl] streaming residual of each local copy
+    double SLBM_GLOBAL *aux;  // [2d][Ng] averaged gradients (operator entry points)
+    double SLBM_GLOBAL *diag; // [4] KE_max, mass, -, -
+    double SLBM_GLOBAL *red;  // [2 * max blocks] reduction partials
     // physics
     double rho_l, rho_v, beta, kappa, omega, dt;
     double t[kMaxQ], tc[kMaxQ];
@@ -50,9 +60,9 @@ struct SolveDesc {
 
 // Launch-shape bookkeeping shared by host and device.
 struct LaunchPlan {
-    const SolveDesc *desc;   // device array of descriptors
-    const int *blk_solve;    // device: block -> batch member index
-    const int *blk_local;    // device: block -> block index within its member
+    const SolveDesc SLBM_GLOBAL *desc;   // device array of descriptors
+    const int SLBM_GLOBAL *blk_solve;    // device: block -> batch member index
+    const int SLBM_GLOBAL *blk_local;    // device: block -> block index within its member
     int nblocks;
     int single;              // one member: block b is block b of desc[0] (no table lookup)
     int epb;                 // elements per block of element kernels (wide or 1)
@@ -84,6 +94,7 @@ int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream);
 // fused path: four element kernels per stage sequence (A: mu + gradients, B: collision +
 // stage-1 residual, C: DSS + Runge-Kutta combine + Laplacian residual, D: mu + residual)
 constexpr int kMaxCopies = 8;
+constexpr int kCopySlots[2] = {4, 8};  // register copy slots of the fused kernels (2-D, 3-D)
 int launch_fA(int d, int N, const LaunchPlan &p, void *stream);
 int launch_fB(int d, int N, const LaunchPlan &p, void *stream);
 int launch_fC(int d, int N, const LaunchPlan &p, int stage, void *stream);

@@ -437,14 +437,21 @@ __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     const int k0 = sd.csr_ptr[G], k1 = sd.csr_ptr[G + 1];
     const double mi = sd.Minv[G], dt = sd.dt;
     double rho = 0.0;
+    // copies outer, populations inner: all Q-1 loads of a copy are in flight together
+    double R[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) R[q] = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const int li = sd.csr_idx[k];
+        double x[Q];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + li];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) R[q] += x[q];
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        double L = 0.0;
-        if (q > 0) {
-            double s = 0.0;
-            for (int k = k0; k < k1; ++k) s += sd.rs[(size_t)(q - 1) * Nl + sd.csr_idx[k]];
-            L = s * mi;
-        }
+        const double L = q > 0 ? R[q] * mi : 0.0;
         const double x = gin[q * Ng + G] + dt * L;
         double out;
         if (stage == 0) out = L;  // operator entry point: the assembled right-hand side
@@ -561,26 +568,38 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *de
 // halves the number of grid-wide dependencies of a step (7 kernels instead of 14).
 // ------------------------------------------------------------------------------------------
 
-// copy list of local node l into registers; returns the number of copies
-__device__ __forceinline__ int load_copies(const SolveDesc &sd, int l, int *cp) {
-    int nc = 0;
+// Copy list of local node l in registers (K slots: 4 in 2-D, 8 in 3-D).  Unused slots
+// repeat the first copy so every slot can be loaded without a branch; sums mask them out,
+// adding +0.0 after the real terms, which leaves the ascending-order sum unchanged.  All
+// loads of a gather are thus in flight together.
+template <int D> struct CopyList {
+    static constexpr int K = kCopySlots[D - 2];
+    int cp[K];
+    int nc;
+};
+template <int D>
+__device__ __forceinline__ void load_copies(const SolveDesc &sd, int l, CopyList<D> &c) {
+    c.nc = 0;
 #pragma unroll
-    for (int k = 0; k < kMaxCopies; ++k) {
-        cp[k] = -1;
-        if (k < sd.vmax) {
-            const int v = sd.lcp[(size_t)k * sd.Nl + l];
-            cp[k] = v;
-            if (v >= 0) nc = k + 1;
-        }
+    for (int k = 0; k < CopyList<D>::K; ++k) {
+        int v = -1;
+        if (k < sd.vmax) v = sd.lcp[(size_t)k * sd.Nl + l];  // uniform branch
+        c.cp[k] = v;
+        if (v >= 0) c.nc = k + 1;
     }
-    return nc;
+#pragma unroll
+    for (int k = 1; k < CopyList<D>::K; ++k)
+        if (k >= c.nc) c.cp[k] = c.cp[0];
 }
 
-__device__ __forceinline__ double gather1(const double *__restrict__ v, const int *cp, int nc) {
+template <int D, class P>
+__device__ __forceinline__ double gather1(P v, const CopyList<D> &c) {
+    double x[CopyList<D>::K];
+#pragma unroll
+    for (int k = 0; k < CopyList<D>::K; ++k) x[k] = v[c.cp[k]];
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < kMaxCopies; ++k)
-        if (k < nc) s += v[cp[k]];
+    for (int k = 0; k < CopyList<D>::K; ++k) s += k < c.nc ? x[k] : 0.0;
     return s;
 }
 
@@ -665,12 +684,12 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
     const bool act = tid < NB && e < sd.E;
     const int l = e * NLOC + n;
     if (act) {
-        int cp[kMaxCopies];
-        const int nc = load_copies(sd, l, cp);
+        CopyList<D> cl;
+        load_copies<D>(sd, l, cl);
         const int G = sd.lgid[l];
         const double pr = sd.rho[G];
-        const double mu = mu_of(sd, pr, gather1(sd.rl, cp, nc) * sd.Minv[G]);
-        if (cp[0] == l) sd.mu[G] = mu;
+        const double mu = mu_of(sd, pr, gather1<D>(sd.rl, cl) * sd.Minv[G]);
+        if (cl.cp[0] == l) sd.mu[G] = mu;
         sf[tid] = pr;
         sf[NB + tid] = mu;
     }
@@ -719,23 +738,16 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
     double pr = 0.0;
     NodeGeo<D> geo;
     if (act) {
-        int cp[kMaxCopies];
-        const int nc = load_copies(sd, l, cp);
+        CopyList<D> cl;
+        load_copies<D>(sd, l, cl);
         const int G = sd.lgid[l];
         load_geo<D>(sd, e, n, l, geo);
         const double mi = sd.Minv[G];
         double gr[D], gm[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            double s = 0.0, t = 0.0;
-#pragma unroll
-            for (int k = 0; k < kMaxCopies; ++k)
-                if (k < nc) {
-                    s += sd.gl[(size_t)c * sd.Nl + cp[k]];
-                    t += sd.gl[(size_t)(D + c) * sd.Nl + cp[k]];
-                }
-            gr[c] = s * mi;
-            gm[c] = t * mi;
+            gr[c] = gather1<D>(sd.gl + (size_t)c * sd.Nl, cl) * mi;
+            gm[c] = gather1<D>(sd.gl + (size_t)(D + c) * sd.Nl, cl) * mi;
         }
         double f[Q];
 #pragma unroll
@@ -761,7 +773,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
             uF += u[c] * F[c];
             uu += u[c] * u[c];
         }
-        const bool owner = cp[0] == l;
+        const bool owner = cl.cp[0] == l;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const double eu = dot_e<Q, D>(u, q), eF = dot_e<Q, D>(F, q);
@@ -807,8 +819,8 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
     WallIdx wi;
     int nw = 0;
     if (act) {
-        int cp[kMaxCopies];
-        const int nc = load_copies(sd, l, cp);
+        CopyList<D> cl;
+        load_copies<D>(sd, l, cl);
         const int G = sd.lgid[l];
 #pragma unroll
         for (int k = 0; k < S::NG; ++k) gm[k] = sd.G[(size_t)k * Nl + l];
@@ -817,15 +829,18 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
 #pragma unroll
         for (int q = 0; q < Q; ++q) R[q] = 0.0;
 #pragma unroll
-        for (int k = 0; k < kMaxCopies; ++k)
-            if (k < nc) {
+        for (int k = 0; k < CopyList<D>::K; ++k) {
+            double x[Q];
 #pragma unroll
-                for (int q = 1; q < Q; ++q) R[q] += sd.rs[(size_t)(q - 1) * Nl + cp[k]];
-            }
+            for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + cl.cp[k]];
+            const bool valid = k < cl.nc;
+#pragma unroll
+            for (int q = 1; q < Q; ++q) R[q] += valid ? x[q] : 0.0;
+        }
         const double *gin = stage == 1 ? sd.g0 : (stage == 2 ? sd.g1 : sd.g2);
         double *gout = stage == 1 ? sd.g1 : (stage == 2 ? sd.g2 : sd.f);
         const double mi = sd.Minv[G], dt = sd.dt;
-        const bool owner = cp[0] == l;
+        const bool owner = cl.cp[0] == l;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const double L = q > 0 ? R[q] * mi : 0.0;
@@ -891,12 +906,12 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
     double pr = 0.0;
     NodeGeo<D> geo;
     if (act) {
-        int cp[kMaxCopies];
-        const int nc = load_copies(sd, l, cp);
+        CopyList<D> cl;
+        load_copies<D>(sd, l, cl);
         const int G = sd.lgid[l];
         load_geo<D>(sd, e, n, l, geo);
         pr = sd.rho[G];
-        smu[tid] = mu_of(sd, pr, gather1(sd.rl, cp, nc) * sd.Minv[G]);
+        smu[tid] = mu_of(sd, pr, gather1<D>(sd.rl, cl) * sd.Minv[G]);
 #pragma unroll
         for (int q = 0; q < Q; ++q) gq[q] = g[q * Ng + G];
 #pragma unroll

@@ -262,9 +262,10 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         const char *nf = std::getenv("SLBM_UNFUSED");
         const char *ff = std::getenv("SLBM_FUSED");
         const bool large3d = dim == 3 && Nl > (int64_t)1 << 20;
-        c->fused = c->vmax <= kMaxCopies && !large3d;
+        const bool fits = c->vmax <= kCopySlots[dim - 2];
+        c->fused = fits && !large3d;
         if (nf && nf[0] == '1') c->fused = false;
-        if (ff && ff[0] == '1' && c->vmax <= kMaxCopies) c->fused = true;
+        if (ff && ff[0] == '1' && fits) c->fused = true;
     }
     c->xyz.assign(xyz, xyz + Nl * dim);
     // --- metric terms, Jacobian, G, lumped mass ---
