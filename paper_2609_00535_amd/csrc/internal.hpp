@@ -63,10 +63,19 @@ struct LaunchPlan {
     const SolveDesc SLBM_GLOBAL *desc;   // device array of descriptors
     const int SLBM_GLOBAL *blk_solve;    // device: block -> batch member index
     const int SLBM_GLOBAL *blk_local;    // device: block -> block index within its member
-    int nblocks;
-    int single;              // one member: block b is block b of desc[0] (no table lookup)
+    int nblocks;             // logical blocks (single member) or table length
+    int single;              // one member: no table lookup, XCD-aware block mapping
     int epb;                 // elements per block of element kernels (wide or 1)
+    int grid;                // launched blocks (multiple of kXcds)
 };
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 accelerator dies (XCDs),
+// each with its own L2.  Logical block j is run by hardware block b with
+// j = (b % 8) * ceil(n / 8) + b / 8, so each die works on one contiguous range of
+// elements or nodes and neighbours share that die's L2.
+constexpr int kXcds = 8;
+inline int xcd_grid(int n) { return ((n + kXcds - 1) / kXcds) * kXcds; }
+inline int xcd_logical(int b, int n) { const int per = (n + kXcds - 1) / kXcds; return (b % kXcds) * per + b / kXcds; }
 
 // Element-kernel shape for order N in d dimensions (must match kernels.hip): "wide" blocks
 // hold as many elements as fit in 256 threads; small meshes use one element per block so

@@ -115,15 +115,20 @@ __device__ __forceinline__ double div_refT(const double *sD, const double *v, in
 struct BlockSlot {
     const SolveDesc *sd;
     int local;
+    bool valid;  // padding blocks of the XCD-aware grid do nothing
 };
 __device__ __forceinline__ BlockSlot block_slot(const LaunchPlan &p) {
     BlockSlot b;
     if (p.single) {
         b.sd = p.desc;
-        b.local = blockIdx.x;
+        const int per = (p.nblocks + kXcds - 1) / kXcds;
+        b.local = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+        b.valid = b.local < p.nblocks;
     } else {
-        b.sd = p.desc + p.blk_solve[blockIdx.x];
-        b.local = p.blk_local[blockIdx.x];
+        const int j = blockIdx.x < (unsigned)p.nblocks ? (int)blockIdx.x : 0;
+        b.local = p.blk_local[j];
+        b.valid = blockIdx.x < (unsigned)p.nblocks && b.local >= 0;
+        b.sd = p.desc + (b.valid ? p.blk_solve[j] : 0);
     }
     return b;
 }
@@ -162,6 +167,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
     __shared__ double srho[NB];
     __shared__ double sv[D * NB];
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int tid = threadIdx.x;
     for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
@@ -210,6 +216,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
 template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
@@ -229,6 +236,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_grad(LaunchPlan p) 
     __shared__ double sD[NP * NP];
     __shared__ double sf[2 * NB];
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int tid = threadIdx.x;
     for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
@@ -267,6 +275,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_grad(LaunchPlan p) 
 template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
@@ -286,6 +295,7 @@ template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_aux) {
     constexpr int Q = QOf<D>::Q;
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
@@ -362,6 +372,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_stream(LaunchPlan p
     __shared__ double smu[NB];
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const double *__restrict__ g = stage == 1 ? sd.g0 : sd.g1;
     const int tid = threadIdx.x;
@@ -428,6 +439,7 @@ template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     constexpr int Q = QOf<D>::Q;
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
@@ -469,6 +481,7 @@ template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int which) {
     constexpr int Q = QOf<D>::Q;
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
@@ -485,6 +498,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag(LaunchPlan p) {
     constexpr int Q = QOf<D>::Q;
     __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int tid = threadIdx.x;
     const int G = bs.local * kNodeThreads + tid;
@@ -676,6 +690,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
     __shared__ double sD[NP * NP];
     __shared__ double sf[2 * NB];
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int tid = threadIdx.x;
     for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
@@ -726,6 +741,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
     __shared__ double smu[NB];
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int tid = threadIdx.x;
     for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
@@ -806,6 +822,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
     __shared__ double srho[NB];
     __shared__ double sv[D * NB];
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int tid = threadIdx.x;
     for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
@@ -893,6 +910,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
     __shared__ double smu[NB];
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
     const SolveDesc &sd = *bs.sd;
     const int tid = threadIdx.x;
     for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
@@ -938,7 +956,7 @@ bool supported_order(int d, int N) {
 
 #define SLBM_DISPATCH(KERNEL, THREADS, ...)                                                  \
     do {                                                                                     \
-        if (p.nblocks <= 0) return 0;                                                        \
+        if (p.nblocks <= 0 || p.grid <= 0) return 0;                                         \
         hipStream_t st = (hipStream_t)stream;                                                \
         bool done = false;                                                                   \
         SLBM_FOR_ORDERS(SLBM_CASE_##KERNEL)                                                  \
@@ -949,14 +967,14 @@ bool supported_order(int d, int N) {
 #define SLBM_ELEM_CASE(KERNEL, DD, NN, ...)                                                  \
     if (!done && d == DD && N == NN) {                                                       \
         if (p.epb == Shape<DD, NN, true>::EPB)                                               \
-            KERNEL<DD, NN, true><<<p.nblocks, Shape<DD, NN, true>::NT, 0, st>>>(p, ##__VA_ARGS__); \
+            KERNEL<DD, NN, true><<<p.grid, Shape<DD, NN, true>::NT, 0, st>>>(p, ##__VA_ARGS__); \
         else                                                                                 \
-            KERNEL<DD, NN, false><<<p.nblocks, Shape<DD, NN, false>::NT, 0, st>>>(p, ##__VA_ARGS__); \
+            KERNEL<DD, NN, false><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p, ##__VA_ARGS__); \
         done = true;                                                                         \
     }
 #define SLBM_NODE_CASE(KERNEL, DD, NN, ...)                                                  \
     if (!done && d == DD && N == NN) {                                                       \
-        KERNEL<DD, NN><<<p.nblocks, kNodeThreads, 0, st>>>(p, ##__VA_ARGS__);                \
+        KERNEL<DD, NN><<<p.grid, kNodeThreads, 0, st>>>(p, ##__VA_ARGS__);                   \
         done = true;                                                                         \
     }
 

@@ -127,8 +127,8 @@ struct slbm_batch {
                 ne += members[i]->n_eblocks;
                 nn += members[i]->n_nblocks;
             }
-            total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(int) * 2 * ne) +
-                     al(sizeof(int) * 2 * nn) + al(sizeof(double) * 2 * g.idx.size());
+            total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(int) * 2 * xcd_grid(ne)) +
+                     al(sizeof(int) * 2 * xcd_grid(nn)) + al(sizeof(double) * 2 * g.idx.size());
         }
         hipStream_t st = (hipStream_t)stream;
         if (total > dcap) {
@@ -155,34 +155,40 @@ struct slbm_batch {
                 ne += members[i]->n_eblocks;
                 nn += members[i]->n_nblocks;
             }
+            // tables in XCD-aware order: hardware block b runs logical block
+            // xcd_logical(b, n) (contiguous logical ranges per die), padded with -1
+            const int te = xcd_grid(ne), tn = xcd_grid(nn);
             const size_t o_e = o;
-            o += al(sizeof(int) * 2 * ne);
+            o += al(sizeof(int) * 2 * te);
             const size_t o_n = o;
-            o += al(sizeof(int) * 2 * nn);
+            o += al(sizeof(int) * 2 * tn);
             const size_t o_d = o;
             SolveDesc *dh = reinterpret_cast<SolveDesc *>(host.data() + o_desc);
             int *eh = reinterpret_cast<int *>(host.data() + o_e);
             int *nh = reinterpret_cast<int *>(host.data() + o_n);
-            int be = 0, bn = 0;
+            std::vector<int> le_s, le_l, ln_s, ln_l;  // logical order
             for (int k = 0; k < (int)g.idx.size(); ++k) {
                 slbm_ctx *c = members[g.idx[k]];
                 dh[k] = c->desc;
-                for (int b = 0; b < c->n_eblocks; ++b, ++be) {
-                    eh[be] = k;
-                    eh[ne + be] = b;
-                }
-                for (int b = 0; b < c->n_nblocks; ++b, ++bn) {
-                    nh[bn] = k;
-                    nh[nn + bn] = b;
-                }
+                for (int b = 0; b < c->n_eblocks; ++b) { le_s.push_back(k); le_l.push_back(b); }
+                for (int b = 0; b < c->n_nblocks; ++b) { ln_s.push_back(k); ln_l.push_back(b); }
+            }
+            for (int b = 0; b < te; ++b) {
+                const int j = xcd_logical(b, ne);
+                eh[b] = j < ne ? le_s[j] : 0;
+                eh[te + b] = j < ne ? le_l[j] : -1;
+            }
+            for (int b = 0; b < tn; ++b) {
+                const int j = xcd_logical(b, nn);
+                nh[b] = j < nn ? ln_s[j] : 0;
+                nh[tn + b] = j < nn ? ln_l[j] : -1;
             }
             char *base = (char *)dmem;
             g.desc = reinterpret_cast<SolveDesc *>(base + o_desc);
-            const int single = g.idx.size() == 1;
-            g.ep = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_e), reinterpret_cast<int *>(base + o_e) + ne, ne,
-                              single, g.epb};
-            g.np = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_n), reinterpret_cast<int *>(base + o_n) + nn, nn,
-                              single, 0};
+            g.ep = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_e), reinterpret_cast<int *>(base + o_e) + te, te,
+                              0, g.epb, te};
+            g.np = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_n), reinterpret_cast<int *>(base + o_n) + tn, tn,
+                              0, 0, tn};
             g.diag_out = reinterpret_cast<double *>(base + o_d);
         }
         if (total) {
