@@ -96,7 +96,7 @@ def traffic_from_profiles(workload: str, kind: str):
 
 
 def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
-                  ke_stop: float = 1e-20, max_slots: int = 64, seed: int = 5):
+                  ke_stop: float = 1e-20, max_slots: int = 256, seed: int = 5):
     """Config 5 (reduced): n_req droplet requests (flat or cylinder wall, N in {4,6,8},
     theta ~ U[30,150], R ~ U[10,30]) run to KE_max < ke_stop or max_steps.
 

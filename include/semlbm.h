@@ -230,9 +230,10 @@ typedef struct slbm_server slbm_server;
 slbm_status slbm_server_create(const slbm_server_cfg *cfg, slbm_server **out);
 /* Queue a request (inputs are copied); returns its id.  t_arrive is stamped now. */
 slbm_status slbm_server_submit(slbm_server *s, const slbm_request *r, uint64_t *id);
-/* Advance the server by one scheduling round: admit queued requests that fit (slots and
+/* Advance the server by one scheduling round: admit prepared requests that fit (slots and
  * arena bytes), run check_every steps of all active solves as one batch, retire finished
- * ones.  Returns the number of active + queued requests in *pending. */
+ * ones.  Submitted requests are prepared (context creation, mesh processing) by host worker
+ * threads while the device runs.  Returns the number of unfinished requests in *pending. */
 slbm_status slbm_server_tick(slbm_server *s, int *pending);
 /* Result of a request (status 1 while pending). */
 slbm_status slbm_server_poll(slbm_server *s, uint64_t id, slbm_result *out);

@@ -11,12 +11,15 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <unordered_set>
 #include <vector>
 
@@ -400,6 +403,7 @@ extern "C" slbm_status slbm_contact_angle(slbm_ctx *c, const slbm_wall_geom *w, 
 namespace {
 struct Request {
     uint64_t id = 0;
+    slbm_status prep_status = SLBM_OK;
     slbm_request r{};
     std::vector<double> xyz, wcos, wub;
     std::vector<int32_t> gid, wface;
@@ -447,18 +451,68 @@ struct Arena {
 struct slbm_server {
     slbm_server_cfg cfg{};
     std::chrono::steady_clock::time_point t0;
-    std::deque<Request *> queue;
-    std::vector<Request *> active;
     std::map<uint64_t, Request *> all;
+    std::vector<Request *> active;
     uint64_t next_id = 1;
     Arena arena;
     slbm_batch *batch = nullptr;
+    // host-side preparation (context creation and mesh processing) runs on worker threads
+    // while the device advances the active solves
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> to_prepare;          // submitted, not yet prepared
+    std::map<uint64_t, Request *> prepared;    // ready for admission, by id
+    int preparing = 0;
+    bool stopping = false;
+    std::vector<std::thread> workers;
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
+
+    void worker() {
+        for (;;) {
+            Request *r = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stopping || !to_prepare.empty(); });
+                if (stopping && to_prepare.empty()) return;
+                r = to_prepare.front();
+                to_prepare.pop_front();
+                ++preparing;
+            }
+            slbm_ctx *c = nullptr;
+            slbm_params p = r->r.params;
+            slbm_status st = slbm_create(&p, &c);
+            if (st == SLBM_OK)
+                st = slbm_set_mesh(c, r->r.E, r->xyz.data(), r->gid.data(), r->r.n_global,
+                                   r->r.n_wall_faces, r->wface.empty() ? nullptr : r->wface.data(),
+                                   r->wcos.empty() ? nullptr : r->wcos.data(),
+                                   r->wub.empty() ? nullptr : r->wub.data());
+            if (st != SLBM_OK && c) {
+                slbm_destroy(c);
+                c = nullptr;
+            }
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                r->ctx = c;
+                r->prep_status = st;
+                prepared[r->id] = r;
+                --preparing;
+            }
+            cv.notify_all();
+        }
+    }
+
     ~slbm_server() {
-        for (auto *r : active) slbm_destroy(r->ctx);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stopping = true;
+        }
+        cv.notify_all();
+        for (auto &t : workers) t.join();
+        for (auto &kv : all)
+            if (kv.second->ctx) slbm_destroy(kv.second->ctx);
         for (auto &kv : all) delete kv.second;
         slbm_batch_destroy(batch);
     }
@@ -475,38 +529,36 @@ struct slbm_server {
             arena.release(r->off, r->bytes);
             r->bytes = 0;
         }
-        // inputs are no longer needed
         r->xyz.clear(); r->xyz.shrink_to_fit();
         r->gid.clear(); r->gid.shrink_to_fit();
     }
 
-    // try to admit the head of the queue; returns false if it does not fit now
+    // admit a prepared request if a slot and arena bytes are free; false if it must wait
     bool admit(Request *r) {
-        slbm_ctx *c = nullptr;
-        slbm_params p = r->r.params;
-        if (slbm_create(&p, &c) != SLBM_OK) { finish(r, SLBM_EINVAL); return true; }
-        if (slbm_set_mesh(c, r->r.E, r->xyz.data(), r->gid.data(), r->r.n_global, r->r.n_wall_faces,
-                          r->wface.empty() ? nullptr : r->wface.data(),
-                          r->wcos.empty() ? nullptr : r->wcos.data(),
-                          r->wub.empty() ? nullptr : r->wub.data()) != SLBM_OK) {
-            slbm_destroy(c);
-            finish(r, SLBM_EINVAL);
-            return true;
-        }
+        if (r->prep_status != SLBM_OK || !r->ctx) { finish(r, r->prep_status ? r->prep_status : SLBM_EINVAL); return true; }
+        slbm_ctx *c = r->ctx;
         const size_t need = slbm_workspace_bytes(c);
         size_t off = 0;
-        if (need > cfg.arena_bytes) { slbm_destroy(c); finish(r, SLBM_ENOMEM); return true; }
-        if (!arena.alloc(need, off)) { slbm_destroy(c); return false; }
+        if (need > cfg.arena_bytes) { finish(r, SLBM_ENOMEM); return true; }
+        if (!arena.alloc(need, off)) {
+            // with no active solve the arena is entirely free: this request can never fit
+            if (active.empty()) { finish(r, SLBM_ENOMEM); return true; }
+            return false;
+        }
         r->off = off;
         r->bytes = need;
-        r->ctx = c;
         slbm_status s = slbm_bind(c, (char *)cfg.arena + off, need, cfg.hip_stream);
-        if (s == SLBM_OK) s = slbm_init_tanh(c, r->r.x0, r->r.R, r->r.noise_amp, p.seed);
+        if (s == SLBM_OK) s = slbm_init_tanh(c, r->r.x0, r->r.R, r->r.noise_amp, r->r.params.seed);
         if (s == SLBM_OK) s = slbm_batch_add(batch, c);
         if (s != SLBM_OK) { finish(r, s); return true; }
         r->res.t_admit = now();
         active.push_back(r);
         return true;
+    }
+
+    int pending() {
+        std::lock_guard<std::mutex> lk(mu);
+        return (int)(active.size() + to_prepare.size() + prepared.size()) + preparing;
     }
 };
 
@@ -518,6 +570,9 @@ extern "C" slbm_status slbm_server_create(const slbm_server_cfg *cfg, slbm_serve
     s->t0 = std::chrono::steady_clock::now();
     s->arena.init(cfg->arena_bytes);
     if (slbm_batch_create(cfg->hip_stream, &s->batch) != SLBM_OK) { delete s; return SLBM_ENOMEM; }
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned nw = std::min(8u, std::max(1u, hw / 2));
+    for (unsigned k = 0; k < nw; ++k) s->workers.emplace_back([s] { s->worker(); });
     *out = s;
     return SLBM_OK;
 }
@@ -544,21 +599,33 @@ extern "C" slbm_status slbm_server_submit(slbm_server *s, const slbm_request *r,
     q->r.wall_ub = nullptr;
     q->res.status = 1;
     q->res.t_arrive = s->now();
-    s->all[q->id] = q;
-    s->queue.push_back(q);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->all[q->id] = q;
+        s->to_prepare.push_back(q);
+    }
+    s->cv.notify_one();
     if (id) *id = q->id;
     return SLBM_OK;
 }
 
 extern "C" slbm_status slbm_server_tick(slbm_server *s, int *pending) {
     if (!s) return SLBM_EINVAL;
-    // admission: FIFO while slots and arena bytes allow
-    while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_slots) {
-        Request *r = s->queue.front();
+    // admission: prepared requests in submission order while slots and arena bytes allow
+    for (;;) {
+        if ((int)s->active.size() >= s->cfg.max_slots) break;
+        Request *r = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (s->prepared.empty()) break;
+            r = s->prepared.begin()->second;
+        }
         if (!s->admit(r)) break;
-        s->queue.pop_front();
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->prepared.erase(r->id);
     }
     if (!s->active.empty()) {
+        // the device advances every active solve while the workers prepare new requests
         if (slbm_status st = slbm_batch_step(s->batch, s->cfg.check_every)) return st;
         std::vector<double> ke(s->active.size()), mass(s->active.size());
         if (slbm_status st = slbm_batch_kinetic_energy(s->batch, ke.data(), mass.data())) return st;
@@ -584,8 +651,13 @@ extern "C" slbm_status slbm_server_tick(slbm_server *s, int *pending) {
             }
         }
         s->active.swap(keep);
+    } else {
+        // nothing to run: wait for a worker to finish a preparation
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->prepared.empty() && (s->preparing > 0 || !s->to_prepare.empty()))
+            s->cv.wait_for(lk, std::chrono::milliseconds(5));
     }
-    if (pending) *pending = (int)(s->active.size() + s->queue.size());
+    if (pending) *pending = s->pending();
     return SLBM_OK;
 }
 
@@ -600,12 +672,8 @@ extern "C" slbm_status slbm_server_poll(slbm_server *s, uint64_t id, slbm_result
 extern "C" slbm_status slbm_server_drain(slbm_server *s) {
     if (!s) return SLBM_EINVAL;
     int pending = 1;
-    while (pending > 0) {
-        const size_t before_q = s->queue.size(), before_a = s->active.size();
+    while (pending > 0)
         if (slbm_status st = slbm_server_tick(s, &pending)) return st;
-        if (pending > 0 && s->active.empty() && s->queue.size() == before_q && before_a == 0)
-            return SLBM_ENOMEM;  // head of the queue can never be admitted
-    }
     return SLBM_OK;
 }
 
