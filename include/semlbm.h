@@ -128,6 +128,16 @@ slbm_status slbm_step(slbm_ctx *c, int64_t n);
 #define SLBM_NUM_KERNEL_KINDS 10
 slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int64_t *launches);
 
+/* Tracing: average duration of one kernel kind (numbering as for slbm_step_profile) when
+ * reps (1..4096) launches of it run back to back from one HIP graph on the bound stream
+ * (plain launches where the stream cannot be captured), timed by a HIP event pair around
+ * the replay (after one untimed replay).  Kinds with
+ * stages cycle through them (streaming and Runge-Kutta 1,2,3; fused kinds 8: 1,2,3 and 9:
+ * 2,3).  Only the kinds of the context's path (unfused 0-5, fused 6-9) are accepted.  The
+ * state and the step counter are restored afterwards (f-bar is saved to the host and
+ * uploaded again); synchronising. */
+slbm_status slbm_time_kernel(slbm_ctx *c, int kind, int64_t reps, double *ms_per_launch);
+
 /* Queries (synchronising).  rho [n_global] by Eq. (10); u [d][n_global] by Eq. (11);
  * ke_max = max over nodes of rho |u|^2 / 2; mass = sum of lumped mass times rho. */
 slbm_status slbm_get_rho(slbm_ctx *c, double *rho);

@@ -77,6 +77,7 @@ SIGNATURES = {
     "slbm_set_state": (C.c_int, [_vp, _dp, _i64]),
     "slbm_step": (C.c_int, [_vp, _i64]),
     "slbm_step_profile": (C.c_int, [_vp, _i64, _dp, C.POINTER(C.c_int64)]),
+    "slbm_time_kernel": (C.c_int, [_vp, C.c_int, _i64, _dp]),
     "slbm_get_rho": (C.c_int, [_vp, _dp]),
     "slbm_get_u": (C.c_int, [_vp, _dp]),
     "slbm_kinetic_energy": (C.c_int, [_vp, _dp, _dp]),
@@ -256,6 +257,13 @@ class Solve:
         self._check(lib().slbm_step_profile(self._h, int(n), _d(ms),
                                             cnt.ctypes.data_as(C.POINTER(C.c_int64))))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNEL_KINDS) if cnt[i]}
+
+    def time_kernel(self, kind, reps=300):
+        """Average ms of one launch of kernel `kind` over reps back-to-back graph launches."""
+        ms = C.c_double(0.0)
+        self._check(lib().slbm_time_kernel(self._h, self.KERNEL_KINDS.index(kind), int(reps),
+                                           C.byref(ms)))
+        return ms.value
 
     def rho(self):
         out = np.zeros(self.Ng)

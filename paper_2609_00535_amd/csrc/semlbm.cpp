@@ -859,6 +859,75 @@ extern "C" slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int
     return c->hip_check(e, "step_profile");
 }
 
+namespace {
+// One launch of kernel kind `kind`; kinds with stages cycle through them so that every
+// launch reads what a launch of the step sequence reads.
+int launch_kind(const slbm_ctx *c, int kind, int64_t i) {
+    const int d = c->dim, N = c->N;
+    void *st = c->stream;
+    switch (kind) {
+    case 0: return launch_lap(d, N, c->eplan, st);
+    case 1: return launch_mu(d, N, c->nplan, st);
+    case 2: return launch_grad(d, N, c->eplan, st);
+    case 3: return launch_collide(d, N, c->nplan, 0, st);
+    case 4: return launch_stream(d, N, c->eplan, 1 + (int)(i % 3), st);
+    case 5: return launch_rk(d, N, c->nplan, 1 + (int)(i % 3), st);
+    case 6: return launch_fA(d, N, c->eplan, st);
+    case 7: return launch_fB(d, N, c->eplan, st);
+    case 8: return launch_fC(d, N, c->eplan, 1 + (int)(i % 3), st);
+    default: return launch_fD(d, N, c->eplan, 2 + (int)(i % 2), st);
+    }
+}
+
+struct KindLaunches {
+    const slbm_ctx *c;
+    int kind;
+    int64_t reps;
+};
+}  // namespace
+
+extern "C" slbm_status slbm_time_kernel(slbm_ctx *c, int kind, int64_t reps, double *ms_per_launch) {
+    if (!c || !ms_per_launch || kind < 0 || kind >= SLBM_NUM_KERNEL_KINDS || reps < 1 || reps > 4096)
+        return SLBM_EINVAL;
+    if (slbm_status s = c->require_bound(true)) return s;
+    if ((kind >= 6) != c->fused) return c->fail(SLBM_EINVAL, "kernel kind is not on this context's path");
+    hipStream_t st = (hipStream_t)c->stream;
+    // the launches overwrite stage buffers and the state's density: keep f-bar to restore
+    std::vector<double> f((size_t)c->Q * c->Ng);
+    int e = (int)hipMemcpyAsync(f.data(), c->desc.f, sizeof(double) * f.size(), hipMemcpyDeviceToHost, st);
+    if (e == 0) e = (int)hipStreamSynchronize(st);
+    if (e) return c->hip_check(e, "time_kernel save");
+    KindLaunches a{c, kind, reps};
+    auto fn = +[](void *, void *arg) -> int {
+        const KindLaunches *x = (const KindLaunches *)arg;
+        int r = 0;
+        for (int64_t i = 0; i < x->reps && r == 0; ++i) r = launch_kind(x->c, x->kind, i);
+        return r;
+    };
+    void *exec = nullptr;
+    if (c->use_graph && capture_graph(c->stream, &exec, fn, &a) != 0) {
+        (void)hipGetLastError();  // stream not capturable (the null stream): plain launches
+        exec = nullptr;
+    }
+    auto replay = [&]() { return exec ? launch_graph(exec, c->stream) : fn(c->stream, &a); };
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (e == 0) e = (int)hipEventCreate(&ev[0]);
+    if (e == 0) e = (int)hipEventCreate(&ev[1]);
+    if (e == 0) e = replay();  // warm-up
+    if (e == 0) e = (int)hipEventRecord(ev[0], st);
+    if (e == 0) e = replay();
+    if (e == 0) e = (int)hipEventRecord(ev[1], st);
+    if (e == 0) e = (int)hipEventSynchronize(ev[1]);
+    float t = 0.0f;
+    if (e == 0) e = (int)hipEventElapsedTime(&t, ev[0], ev[1]);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (exec) destroy_graph(exec);
+    if (e) return c->hip_check(e, "time_kernel");
+    *ms_per_launch = (double)t / (double)reps;
+    return c->upload_f_and_density(f);
+}
+
 // ------------------------------------------------------------------------------------------
 // queries
 // ------------------------------------------------------------------------------------------

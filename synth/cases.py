@@ -156,6 +156,15 @@ def small_box3d(N: int = 3, n: int = 3, periodic=(True, True, True), jitter: flo
                 seed=15, steps=20)
 
 
+def walled_droplet(nx: int = 8, N: int = 4, L: float = 64.0, R: float = 16.0,
+                   delta: float = 6.0) -> Case:
+    """Isolated droplet in a closed square box (non-wetting outer walls): the
+    equilibration run whose kinetic energy decays to the residual floor."""
+    m = meshes.box2d(nx, nx, N, L, L, periodic=(False, False), name="walled_droplet")
+    return Case("walled_droplet", m, LATTICE_D2Q9, x0=(0.5 * L, 0.5 * L), R=R, delta=delta,
+                steps=10500)
+
+
 CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}
 
 

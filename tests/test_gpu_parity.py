@@ -134,6 +134,24 @@ def test_config4_full_size(P):
     assert abs(mg - mo) <= 1e-13 * mo
 
 
+def test_kinetic_energy_floor(P):
+    """Equilibration of a walled droplet to the residual floor (Sec. 3.3): log10 of the
+    GPU's KE_max within 0.5 decades of the oracle's at every checkpoint, ending below
+    1e-20 after 10500 steps (~30 s of oracle time)."""
+    c = cases.walled_droplet()
+    s, o = _pair(c, P)
+    s.init_tanh()
+    o.init_tanh()
+    for k in range(7):
+        s.step(1500)
+        o.step(1500)
+        kg, _ = s.kinetic_energy()
+        ko, _ = o.diag()
+        print(f"[parity] floor step {1500 * (k + 1)}: KE gpu {kg:.3e} oracle {ko:.3e}", flush=True)
+        assert abs(np.log10(kg) - np.log10(ko)) <= 0.5
+    assert kg < 1e-20 and ko < 1e-20
+
+
 def test_mass_conservation_gpu(P):
     c = cases.small_flat()
     s = P.Solve(c)
@@ -231,6 +249,28 @@ def test_server_results_equal_alone(P):
         assert res.ke_max == ke
         assert abs(res.theta_deg - a.contact_angle()) < 1e-12
         assert res.t_arrive <= res.t_admit <= res.t_done
+
+
+@pytest.mark.parametrize("unfused", [False, True])
+def test_time_kernel_restores_state(P, monkeypatch, unfused):
+    """Back-to-back kernel timing leaves the trajectory untouched."""
+    if unfused:
+        monkeypatch.setenv("SLBM_UNFUSED", "1")
+    c = cases.small_flat()
+    a, b = P.Solve(c), P.Solve(c)
+    for s in (a, b):
+        s.init_tanh()
+        s.step(10)
+    kinds = P.Solve.KERNEL_KINDS[:6] if unfused else P.Solve.KERNEL_KINDS[6:]
+    for k in kinds:
+        assert b.time_kernel(k, 12) > 0.0
+    with pytest.raises(P.SLBMError):
+        b.time_kernel(P.Solve.KERNEL_KINDS[0 if not unfused else 6], 3)
+    a.step(10)
+    b.step(10)
+    fa, sa = a.get_state()
+    fb, sb = b.get_state()
+    assert sa == sb == 20 and np.array_equal(fa, fb)
 
 
 def test_unfused_path_matches(P, monkeypatch):
