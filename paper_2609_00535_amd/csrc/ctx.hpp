@@ -29,14 +29,14 @@ struct slbm_ctx {
     bool has_mesh = false;
     int64_t E = 0, Nl = 0, Ng = 0, nw = 0;
     std::vector<double> xyz;
-    std::vector<int32_t> lgid, ig2ug, csr_ptr, csr_idx, wel_ptr, w_node, lcp;
+    std::vector<int32_t> lgid, ig2ug, csr_ptr, csr_idx, gcopy, lwall, lcp;
     int vmax = 0;
     bool fused = true;  // fused element-kernel path (needs vmax <= kMaxCopies)
-    std::vector<double> Ja, Gm, MA, Minv, w_lap, w_cn, w_eub;
+    std::vector<double> Ja, Gm, MA, Minv, w_dat;
     // device
     struct Offsets {
-        size_t desc, eplan, nplan, lgid, csr_ptr, csr_idx, lcp, wel_ptr, w_node, Ja, G, Minv, Dm, wn, w_lap,
-            w_cn, w_eub, f, g0, g1, g2, rho, mu, rl, gl, rs, aux, diag, red;
+        size_t desc, eplan, nplan, lgid, gcopy, csr_idx, lcp, lwall, w_dat, Ja, G, Minv, Dm, wn, f, g0, g1,
+            g2, rho, mu, rl, gl, rs, aux, diag, red;
     } off{};
     size_t ws_bytes = 0;
     int n_eblocks = 0, n_nblocks = 0, epb = 1;

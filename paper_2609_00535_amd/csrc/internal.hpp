@@ -19,25 +19,29 @@ namespace slbm {
 
 constexpr int kMaxQ = 19;
 
+// First DSS copies of a global node: csr position k0 of its local copies, their count nc
+// and the first two local indices (i1 repeats i0 for a single copy), read with one 16-byte
+// load; copies beyond the second are read through csr_idx.
+struct alignas(16) NodeCopies {
+    int k0, nc, i0, i1;
+};
+
 // Everything one solve's kernels need, resident in device memory (one entry per batch
 // member).  Index arrays are int32: a solve holds < 2^31 local nodes.
 struct SolveDesc {
-    int E, Nl, Ng, pad0;
+    int E, Nl, Ng, vmax;
     // mesh tables (device)
     const int SLBM_GLOBAL *lgid;      // [Nl] local node -> internal global node
     const double SLBM_GLOBAL *Ja;     // [d*d][Nl] J * d xi_a / d x_c, index (a*d + c)
     const double SLBM_GLOBAL *G;      // [d(d+1)/2][Nl] w (Ja_a . Ja_b) / J, upper triangle row-major
     const double SLBM_GLOBAL *Minv;   // [Ng] inverse assembled lumped mass
-    const int SLBM_GLOBAL *csr_ptr;   // [Ng+1] local copies of each global node
-    const int SLBM_GLOBAL *csr_idx;   // [Nl]   ascending local indices
+    const NodeCopies SLBM_GLOBAL *gcopy;  // [Ng] first copies of each global node
+    const int SLBM_GLOBAL *csr_idx;   // [Nl]   local copies of the global nodes, ascending per node
     const int SLBM_GLOBAL *lcp;       // [vmax][Nl] local copies of the global node of each local node,
-                          // ascending, -1 padded (fused path)
-    int vmax, pad1;
-    const int SLBM_GLOBAL *wel_ptr;   // [E+1] wall entries of each element
-    const int SLBM_GLOBAL *w_node;    // [nw] element-local node of the entry
-    const double SLBM_GLOBAL *w_lap;  // [nw] s cos(theta) sqrt(2 beta / kappa)
-    const double SLBM_GLOBAL *w_cn;   // [nw][Q] (s n) . e_a (only negative values act)
-    const double SLBM_GLOBAL *w_eub;  // [nw][Q] e_a . u_b
+                                      // ascending, -1 padded (fused path)
+    const int SLBM_GLOBAL *lwall;     // [Nl] (first wall entry << 2) | number of entries of the node
+    const double SLBM_GLOBAL *w_dat;  // [nw][2d+1] per wall entry: s n (d), u_b (d),
+                                      // s cos(theta) sqrt(2 beta / kappa); a node's entries adjacent
     const double SLBM_GLOBAL *Dm;     // [(N+1)^2] GLL differentiation matrix, Dm[i*(N+1)+m]
     const double SLBM_GLOBAL *wn;     // [(N+1)^d] tensor GLL weights
     // state and work buffers (device)
@@ -55,7 +59,8 @@ struct SolveDesc {
     double SLBM_GLOBAL *red;  // [2 * max blocks] reduction partials
     // physics
     double rho_l, rho_v, beta, kappa, omega, dt;
-    double t[kMaxQ], tc[kMaxQ];
+    // lattice weights t and t / cs^2 by class |e|^2 = 0 (rest), 1 (axis), 2 (diagonal)
+    double tw[3], twc[3];
 };
 
 // Launch-shape bookkeeping shared by host and device.

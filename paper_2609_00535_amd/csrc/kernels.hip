@@ -11,6 +11,13 @@
 // blk_local[b] of it, with the member's tables and state in its SolveDesc.  A single solve
 // is a batch of one.
 //
+// Memory-level parallelism: each kernel issues all of its global loads (index tables
+// first, then the data they address) before its first global store, and reads the
+// descriptor into registers at entry.  A store through a state pointer may alias any
+// later load as far as the compiler knows, so loads placed after a store are issued only
+// after it and their latencies add up; this ordering keeps every wave to two dependent
+// memory round trips (index, data) plus its barriers.
+//
 // Floating point: the build disables contraction; the GLL contractions use fma explicitly
 // and every other expression is written with the operand order of the CPU oracle, so the
 // two implementations round identically.
@@ -42,6 +49,13 @@ template <int D> struct QOf;
 template <> struct QOf<2> { static constexpr int Q = 9; };
 template <> struct QOf<3> { static constexpr int Q = 19; };
 
+// weight class |e_q|^2 (0 rest, 1 axis, 2 diagonal): t_q = tw[class], t_q / cs^2 = twc[class]
+template <int Q>
+__device__ __forceinline__ constexpr int wcls(int q) {
+    return Lat<Q>::e[q][0] * Lat<Q>::e[q][0] + Lat<Q>::e[q][1] * Lat<Q>::e[q][1] +
+           Lat<Q>::e[q][2] * Lat<Q>::e[q][2];
+}
+
 // v . e_q summed in ascending component order from 0 (components of e are -1, 0, 1, so
 // the sum equals the plain dot product bit for bit)
 template <int Q, int D>
@@ -66,6 +80,7 @@ template <int D, int N, bool WIDE = true> struct Shape {
     static constexpr int NB = EPB * NLOC;  // nodes of one block
     static constexpr int NT = ((NB + 63) / 64) * 64;
     static constexpr int NG = D * (D + 1) / 2;
+    static_assert(NT >= NP * NP, "one differentiation-matrix entry per thread");
 };
 
 template <int NP, int A> struct Stride { static constexpr int v = A == 0 ? 1 : (A == 1 ? NP : NP * NP); };
@@ -111,9 +126,20 @@ __device__ __forceinline__ double div_refT(const double *sD, const double *v, in
     return s;
 }
 
+// The differentiation matrix is fetched into a register with the block's first loads and
+// written to LDS just before the first barrier, so its latency overlaps theirs.
+template <int NP>
+__device__ __forceinline__ double dm_fetch(const SolveDesc &sd, int tid) {
+    return sd.Dm[tid < NP * NP ? tid : 0];
+}
+template <int NP>
+__device__ __forceinline__ void dm_store(double *sD, int tid, double v) {
+    if (tid < NP * NP) sD[tid] = v;
+}
+
 // block -> (member descriptor, first element of the block)
 struct BlockSlot {
-    const SolveDesc *sd;
+    const SolveDesc SLBM_GLOBAL *sd;
     int local;
     bool valid;  // padding blocks of the XCD-aware grid do nothing
 };
@@ -133,32 +159,103 @@ __device__ __forceinline__ BlockSlot block_slot(const LaunchPlan &p) {
     return b;
 }
 
-// wall entries of element e that sit on node n (at most d faces meet at a node), in
-// list order
-// (fixed-size, constant-indexed register array: a dynamically indexed one would live in
-// scratch memory)
-struct WallIdx {
-    int k[3];
+// ------------------------------------------------------------------------------------------
+// wall entries of a local node (at most d faces of its element): the first entry and the
+// count come from lwall; entries beyond the count repeat the last one so every slot can be
+// loaded without a branch (only nodes with walls load anything)
+// ------------------------------------------------------------------------------------------
+template <int D> struct WallLap {
+    int cnt;
+    double lap[D];  // s cos(theta) sqrt(2 beta / kappa) of each face through the node
 };
 template <int D>
-__device__ __forceinline__ int wall_entries_of(const SolveDesc &sd, int e, int n, WallIdx &wi) {
-    int cnt = 0;
-    wi.k[0] = wi.k[1] = wi.k[2] = 0;
-    const int k0 = sd.wel_ptr[e], k1 = sd.wel_ptr[e + 1];
-    for (int k = k0; k < k1; ++k)
-        if (sd.w_node[k] == n) {
-            if (cnt == 0) wi.k[0] = k;
-            else if (cnt == 1) wi.k[1] = k;
-            else if (D == 3 && cnt == 2) wi.k[2] = k;
-            cnt = cnt < D ? cnt + 1 : cnt;
+__device__ __forceinline__ void load_wall_lap(const SolveDesc &sd, int l, WallLap<D> &w) {
+    const int v = sd.lwall[l];
+    const int k0 = v >> 2;
+    w.cnt = v & 3;
+#pragma unroll
+    for (int j = 0; j < D; ++j) w.lap[j] = 0.0;
+    if (w.cnt > 0) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int k = k0 + (j < w.cnt ? j : w.cnt - 1);
+            w.lap[j] = sd.w_dat[(size_t)k * (2 * D + 1) + 2 * D];
         }
-    return cnt;
+    }
+}
+template <int D> struct WallFlux {
+    int cnt;
+    double sn[D][D];  // s n of each face through the node
+    double ub[D][D];  // wall velocity of that face
+};
+template <int D>
+__device__ __forceinline__ void load_wall_flux(const SolveDesc &sd, int l, WallFlux<D> &w) {
+    const int v = sd.lwall[l];
+    const int k0 = v >> 2;
+    w.cnt = v & 3;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int c = 0; c < D; ++c) w.sn[j][c] = w.ub[j][c] = 0.0;
+    if (w.cnt > 0) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int k = k0 + (j < w.cnt ? j : w.cnt - 1);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                w.sn[j][c] = sd.w_dat[(size_t)k * (2 * D + 1) + c];
+                w.ub[j][c] = sd.w_dat[(size_t)k * (2 * D + 1) + D + c];
+            }
+        }
+    }
+}
+
+// wetting term of Eq. (8) at a wall node: s n.grad(rho) = s cos(theta) sqrt(2 beta/kappa)
+// |(rho-rl)(rho-rv)| for every face through the node, in the caller's face order
+template <int D>
+__device__ __forceinline__ double wall_lap_term(const SolveDesc &sd, const WallLap<D> &w, double rh, double r) {
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        if (j < w.cnt) r += w.lap[j] * fabs((rh - sd.rho_l) * (rh - sd.rho_v));
+    return r;
+}
+
+// ------------------------------------------------------------------------------------------
+// DSS through the CSR copy lists: the first two copies come from the node's NodeCopies
+// entry (one load); further copies, on nodes shared by more than two elements, through
+// csr_idx.  Ascending local order, from +0.0, as the oracle sums.
+// ------------------------------------------------------------------------------------------
+template <class P>
+__device__ __forceinline__ double dss_sum(P v, const NodeCopies &c, const int SLBM_GLOBAL *csr_idx) {
+    const double x0 = v[c.i0], x1 = v[c.i1];
+    double s = 0.0;
+    s += x0;
+    s += c.nc > 1 ? x1 : 0.0;
+    for (int k = 2; k < c.nc; ++k) s += v[csr_idx[c.k0 + k]];
+    return s;
 }
 
 // ------------------------------------------------------------------------------------------
 // Eq. (8): element part of the weak Laplacian, r = -sum_a D_a^T (G^{ab} D_b rho), plus the
 // wetting boundary integral s n.grad(rho) = s cos(theta) sqrt(2 beta/kappa) |(rho-rl)(rho-rv)|
 // ------------------------------------------------------------------------------------------
+template <int D, int NB, int NG>
+__device__ __forceinline__ void metric_times_grad(const double *g, const double *d, double *sv, int tid) {
+    // v_a = sum_b G_ab d_b (ascending b from 0)
+    if constexpr (D == 2) {
+        double v0 = 0.0, v1 = 0.0;
+        v0 += g[0] * d[0]; v0 += g[1] * d[1];
+        v1 += g[1] * d[0]; v1 += g[2] * d[1];
+        sv[tid] = v0; sv[NB + tid] = v1;
+    } else {
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        v0 += g[0] * d[0]; v0 += g[1] * d[1]; v0 += g[2] * d[2];
+        v1 += g[1] * d[0]; v1 += g[3] * d[1]; v1 += g[4] * d[2];
+        v2 += g[2] * d[0]; v2 += g[4] * d[1]; v2 += g[5] * d[2];
+        sv[tid] = v0; sv[NB + tid] = v1; sv[2 * NB + tid] = v2;
+    }
+}
+
 template <int D, int N, bool WIDE>
 __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
     using S = Shape<D, N, WIDE>;
@@ -168,64 +265,55 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
     __shared__ double sv[D * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int tid = threadIdx.x;
-    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
     const int l = e * NLOC + n;
     double rh = 0.0;
+    double g[S::NG];
+    WallLap<D> wl;
     if (act) {
-        rh = sd.rho[sd.lgid[l]];
+        const int G = sd.lgid[l];
+#pragma unroll
+        for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * sd.Nl + l];
+        load_wall_lap<D>(sd, l, wl);
+        rh = sd.rho[G];
         srho[tid] = rh;
     }
+    dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (act) {
         double d[D];
         grad_ref<D, NP>(sD, srho + es * NLOC, n, d);
-        double g[S::NG];
-#pragma unroll
-        for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * sd.Nl + l];
-        // v_a = sum_b G_ab d_b (ascending b from 0)
-        if constexpr (D == 2) {
-            double v0 = 0.0, v1 = 0.0;
-            v0 += g[0] * d[0]; v0 += g[1] * d[1];
-            v1 += g[1] * d[0]; v1 += g[2] * d[1];
-            sv[tid] = v0; sv[NB + tid] = v1;
-        } else {
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-            v0 += g[0] * d[0]; v0 += g[1] * d[1]; v0 += g[2] * d[2];
-            v1 += g[1] * d[0]; v1 += g[3] * d[1]; v1 += g[4] * d[2];
-            v2 += g[2] * d[0]; v2 += g[4] * d[1]; v2 += g[5] * d[2];
-            sv[tid] = v0; sv[NB + tid] = v1; sv[2 * NB + tid] = v2;
-        }
+        metric_times_grad<D, NB, S::NG>(g, d, sv, tid);
     }
     __syncthreads();
     if (!act) return;
-    double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
-    WallIdx wi;
-    const int nw = wall_entries_of<D>(sd, e, n, wi);
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-        if (j < nw) r += sd.w_lap[wi.k[j]] * fabs((rh - sd.rho_l) * (rh - sd.rho_v));
-    sd.rl[l] = r;
+    const double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
+    sd.rl[l] = wall_lap_term<D>(sd, wl, rh, r);
 }
 
 // Eq. (2): mu = mu0(rho) - kappa lap, lap = DSS(r) / M (reading: mu0 = 2 beta (rho-rl)(rho-rv)(2rho-rl-rv))
+__device__ __forceinline__ double mu_of(const SolveDesc &sd, double pr, double lap) {
+    const double rl = sd.rho_l, rv = sd.rho_v;
+    const double mu0 = 2.0 * sd.beta * (pr - rl) * (pr - rv) * (2.0 * pr - rl - rv);
+    return mu0 - sd.kappa * lap;
+}
+
 template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
-    double s = 0.0;
-    for (int k = sd.csr_ptr[G]; k < sd.csr_ptr[G + 1]; ++k) s += sd.rl[sd.csr_idx[k]];
-    const double lap = s * sd.Minv[G];
-    const double pr = sd.rho[G], rl = sd.rho_l, rv = sd.rho_v;
-    const double mu0 = 2.0 * sd.beta * (pr - rl) * (pr - rv) * (2.0 * pr - rl - rv);
-    sd.mu[G] = mu0 - sd.kappa * lap;
+    const NodeCopies c = sd.gcopy[G];
+    const double mi = sd.Minv[G], pr = sd.rho[G];
+    const double lap = dss_sum(sd.rl, c, sd.csr_idx) * mi;
+    sd.mu[G] = mu_of(sd, pr, lap);
 }
 
 // lumped-mass weighted element gradients w Ja^T grad_ref of rho and mu (for the collision)
@@ -237,26 +325,28 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_grad(LaunchPlan p) 
     __shared__ double sf[2 * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int tid = threadIdx.x;
-    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
     const int l = e * NLOC + n;
+    double J[D][D];
+    double w = 0.0;
     if (act) {
         const int G = sd.lgid[l];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+        w = sd.wn[n];
         sf[tid] = sd.rho[G];
         sf[NB + tid] = sd.mu[G];
     }
+    dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
-    const double w = sd.wn[n];
-    double J[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
         double d[D];
@@ -276,56 +366,23 @@ template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
-    const int k0 = sd.csr_ptr[G], k1 = sd.csr_ptr[G + 1];
+    const NodeCopies cp = sd.gcopy[G];
     const double mi = sd.Minv[G];
+    double s[2 * D];
 #pragma unroll
-    for (int c = 0; c < 2 * D; ++c) {
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k) s += sd.gl[(size_t)c * sd.Nl + sd.csr_idx[k]];
-        sd.aux[(size_t)c * sd.Ng + G] = s * mi;
-    }
+    for (int c = 0; c < 2 * D; ++c) s[c] = dss_sum(sd.gl + (size_t)c * sd.Nl, cp, sd.csr_idx);
+#pragma unroll
+    for (int c = 0; c < 2 * D; ++c) sd.aux[(size_t)c * sd.Ng + G] = s[c] * mi;
 }
 
-// Eq. (4) with (A.2), (A.6)-(A.7) and F** of Sec. 2.1: f* = f - omega (f - (feq - dt/2 F**)) + dt F**,
-// F = cs^2 grad(rho) - rho grad(mu) from the lumped-mass averaged element gradients
-template <int D, int N>
-__global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_aux) {
-    constexpr int Q = QOf<D>::Q;
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
-    const int G = bs.local * kNodeThreads + threadIdx.x;
-    if (G >= sd.Ng) return;
-    const size_t Ng = sd.Ng;
-    double gr[D], gm[D];
-    if (use_aux) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            gr[c] = sd.aux[c * Ng + G];
-            gm[c] = sd.aux[(D + c) * Ng + G];
-        }
-    } else {
-        const int k0 = sd.csr_ptr[G], k1 = sd.csr_ptr[G + 1];
-        const double mi = sd.Minv[G];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            double s = 0.0, t = 0.0;
-            for (int k = k0; k < k1; ++k) {
-                const int li = sd.csr_idx[k];
-                s += sd.gl[(size_t)c * sd.Nl + li];
-                t += sd.gl[(size_t)(D + c) * sd.Nl + li];
-            }
-            gr[c] = s * mi;
-            gm[c] = t * mi;
-        }
-    }
-    double f[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
-    const double pr = sd.rho[G];
+// Eq. (4) with (A.2), (A.6)-(A.7) and F** of Sec. 2.1 at one node:
+// f* = f - omega (f - (feq - dt/2 F**)) + dt F**, F = cs^2 grad(rho) - rho grad(mu)
+template <int Q, int D>
+__device__ __forceinline__ void collide_node(const SolveDesc &sd, const double *f, double pr,
+                                             const double *gr, const double *gm, double *fs) {
     const double cs2 = 1.0 / 3.0, dt = sd.dt, om = sd.omega;
     double u[D], F[D];
 #pragma unroll
@@ -349,20 +406,112 @@ __global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const double eu = dot_e<Q, D>(u, q), eF = dot_e<Q, D>(F, q);
-        const double tq = sd.t[q], tc = sd.tc[q];
+        const double tq = sd.tw[wcls<Q>(q)], tc = sd.twc[wcls<Q>(q)];
         const double Fss = tc * (eu * eF * 3.0 - uF);
         const double feq = pr * tq * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
         const double fbeq = feq - 0.5 * dt * Fss;
-        sd.g0[q * Ng + G] = f[q] - om * (f[q] - fbeq) + dt * Fss;
+        fs[q] = f[q] - om * (f[q] - fbeq) + dt * Fss;
     }
+}
+
+template <int D, int N>
+__global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_aux) {
+    constexpr int Q = QOf<D>::Q;
+    const BlockSlot bs = block_slot(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = *bs.sd;
+    const int G = bs.local * kNodeThreads + threadIdx.x;
+    if (G >= sd.Ng) return;
+    const size_t Ng = sd.Ng;
+    double gr[D], gm[D];
+    double f[Q];
+    if (use_aux) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            gr[c] = sd.aux[c * Ng + G];
+            gm[c] = sd.aux[(D + c) * Ng + G];
+        }
+    } else {
+        const NodeCopies cp = sd.gcopy[G];
+        const double mi = sd.Minv[G];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            gr[c] = dss_sum(sd.gl + (size_t)c * sd.Nl, cp, sd.csr_idx) * mi;
+            gm[c] = dss_sum(sd.gl + (size_t)(D + c) * sd.Nl, cp, sd.csr_idx) * mi;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
+    const double pr = sd.rho[G];
+    double fs[Q];
+    collide_node<Q, D>(sd, f, pr, gr, gm, fs);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sd.g0[q * Ng + G] = fs[q];
 }
 
 // ------------------------------------------------------------------------------------------
 // Eqs. (5)-(6), (12), (9): element residual of the force-split weak streaming,
 //   r_a = -w [ (Ja e_a) . D(g_a - t_a rho) + (t_a/cs^2) rho (Ja e_a) . D mu ]
 // plus, on wall faces with (s n).e_a < 0, (s n . e_a) [g_a - g_opp - 2 (t_a/cs^2) rho e_a.u_b]
-// stage 1 streams g0, stages 2-3 stream g1
 // ------------------------------------------------------------------------------------------
+// per-node metric and wall data of the streaming, loaded with the block's first loads
+template <int D> struct NodeGeo {
+    double J[D][D];
+    double w;
+    WallFlux<D> wf;
+};
+template <int D>
+__device__ __forceinline__ void load_geo(const SolveDesc &sd, int n, int l, NodeGeo<D> &g) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) g.J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+    g.w = sd.wn[n];
+    load_wall_flux<D>(sd, l, g.wf);
+}
+
+// residual at node n from LDS h_q = g_q - t_q rho (fields of stride NB, element base es),
+// LDS mu, register g (for the flux); the loop reads only LDS and registers, so its stores
+// delay no load
+template <int D, int N, bool WIDE>
+__device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
+                                                const double *smu_e, int es, int n, int l,
+                                                double pr, const double *gq, const NodeGeo<D> &geo) {
+    using S = Shape<D, N, WIDE>;
+    constexpr int Q = QOf<D>::Q;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    double dmu[D];
+    grad_ref<D, NP>(sD, smu_e, n, dmu);
+    const double w = geo.w;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        double dh[D];
+        grad_ref<D, NP>(sD, sh + (q - 1) * NB + es * NLOC, n, dh);
+        double adv = 0.0, frc = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double ca = dot_e<Q, D>(geo.J[a], q);
+            adv += ca * dh[a];
+            frc += ca * dmu[a];
+        }
+        const double tc = sd.twc[wcls<Q>(q)];
+        double r = -(w * (adv + tc * pr * frc));
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j < geo.wf.cnt) {
+                const double cn = dot_e<Q, D>(geo.wf.sn[j], q);
+                if (cn < 0.0) {
+                    const double eub = dot_e<Q, D>(geo.wf.ub[j], q);
+                    const double bc = gq[q] - gq[Lat<Q>::opp[q]] - 2.0 * tc * pr * eub;
+                    r += cn * bc;
+                }
+            }
+        }
+        sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
+    }
+}
+
+// stage 1 streams g0, stages 2-3 stream g1
 template <int D, int N, bool WIDE>
 __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_stream(LaunchPlan p, int stage) {
     using S = Shape<D, N, WIDE>;
@@ -373,103 +522,98 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_stream(LaunchPlan p
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
-    const double *__restrict__ g = stage == 1 ? sd.g0 : sd.g1;
+    const SolveDesc sd = *bs.sd;
+    const double SLBM_GLOBAL *g = stage == 1 ? sd.g0 : sd.g1;
     const int tid = threadIdx.x;
-    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
     const int l = e * NLOC + n;
     const size_t Ng = sd.Ng;
-    int G = 0;
     double pr = 0.0;
+    double gq[Q];
+    NodeGeo<D> geo;
     if (act) {
-        G = sd.lgid[l];
+        const int G = sd.lgid[l];
+        load_geo<D>(sd, n, l, geo);
         pr = sd.rho[G];
         smu[tid] = sd.mu[G];
 #pragma unroll
-        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = g[q * Ng + G] - sd.t[q] * pr;
+        for (int q = 1; q < Q; ++q) gq[q] = g[q * Ng + G];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = gq[q] - sd.tw[wcls<Q>(q)] * pr;
     }
+    dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
-    double dmu[D];
-    grad_ref<D, NP>(sD, smu + es * NLOC, n, dmu);
-    double J[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
-    const double w = sd.wn[n];
-    WallIdx wi;
-    const int nw = wall_entries_of<D>(sd, e, n, wi);
-#pragma unroll
-    for (int q = 1; q < Q; ++q) {
-        double dh[D];
-        grad_ref<D, NP>(sD, sh + (q - 1) * NB + es * NLOC, n, dh);
-        double adv = 0.0, frc = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const double ca = dot_e<Q, D>(J[a], q);
-            adv += ca * dh[a];
-            frc += ca * dmu[a];
-        }
-        const double tc = sd.tc[q];
-        double r = -(w * (adv + tc * pr * frc));
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j >= nw) break;
-            const int k = wi.k[j];
-            const double cn = sd.w_cn[k * Q + q];
-            if (cn < 0.0) {
-                const double ga = g[q * Ng + G], gb = g[Lat<Q>::opp[q] * Ng + G];
-                const double bc = ga - gb - 2.0 * tc * pr * sd.w_eub[k * Q + q];
-                r += cn * bc;
-            }
-        }
-        sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
-    }
+    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
 }
 
 // SSP-RK3 stage combination after DSS(r)/M, and the new stage's density (Eq. (10))
 //   stage 0 (operator entry point only): g1 = L(g1)
 //   stage 1: g1 = g0 + dt L(g0); stage 2: g1 = 3/4 g0 + 1/4 (g1 + dt L(g1));
 //   stage 3: f = (g0 + 2 (g1 + dt L(g1))) / 3
+template <int Q>
+__device__ __forceinline__ double rk_combine(int stage, double L, double gin, double g0, double dt) {
+    const double x = gin + dt * L;
+    if (stage == 0) return L;  // operator entry point: the assembled right-hand side
+    if (stage == 1) return x;
+    if (stage == 2) return 0.75 * g0 + 0.25 * x;
+    return (g0 + 2.0 * x) / 3.0;
+}
+
 template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     constexpr int Q = QOf<D>::Q;
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
     const size_t Ng = sd.Ng, Nl = sd.Nl;
-    const double *gin = stage == 1 ? sd.g0 : sd.g1;
-    double *gout = stage == 3 ? sd.f : sd.g1;
-    const int k0 = sd.csr_ptr[G], k1 = sd.csr_ptr[G + 1];
+    const double SLBM_GLOBAL *gin = stage == 1 ? sd.g0 : sd.g1;
+    double SLBM_GLOBAL *gout = stage == 3 ? sd.f : sd.g1;
+    const NodeCopies cp = sd.gcopy[G];
     const double mi = sd.Minv[G], dt = sd.dt;
-    double rho = 0.0;
-    // copies outer, populations inner: all Q-1 loads of a copy are in flight together
+    // every load is issued before the first store: residuals of the first two copies,
+    // the stage input and g0
+    double x0[Q], x1[Q], gi[Q], g0v[Q];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        x0[q] = sd.rs[(size_t)(q - 1) * Nl + cp.i0];
+        x1[q] = sd.rs[(size_t)(q - 1) * Nl + cp.i1];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) gi[q] = gin[q * Ng + G];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g0v[q] = 0.0;
+    if (stage >= 2) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) g0v[q] = sd.g0[q * Ng + G];
+    }
     double R[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) R[q] = 0.0;
-    for (int k = k0; k < k1; ++k) {
-        const int li = sd.csr_idx[k];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        R[q] += x0[q];
+        R[q] += cp.nc > 1 ? x1[q] : 0.0;
+    }
+    // copies beyond the second (edges and corners): copies outer, populations inner
+    for (int k = 2; k < cp.nc; ++k) {
+        const int li = sd.csr_idx[cp.k0 + k];
         double x[Q];
 #pragma unroll
         for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + li];
 #pragma unroll
         for (int q = 1; q < Q; ++q) R[q] += x[q];
     }
+    double rho = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const double L = q > 0 ? R[q] * mi : 0.0;
-        const double x = gin[q * Ng + G] + dt * L;
-        double out;
-        if (stage == 0) out = L;  // operator entry point: the assembled right-hand side
-        else if (stage == 1) out = x;
-        else if (stage == 2) out = 0.75 * sd.g0[q * Ng + G] + 0.25 * x;
-        else out = (sd.g0[q * Ng + G] + 2.0 * x) / 3.0;
+        const double out = rk_combine<Q>(stage, L, gi[q], g0v[q], dt);
         gout[q * Ng + G] = out;
         rho += out;
     }
@@ -482,10 +626,10 @@ __global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int whic
     constexpr int Q = QOf<D>::Q;
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
-    const double *src = which == 0 ? sd.f : sd.g1;
+    const double SLBM_GLOBAL *src = which == 0 ? sd.f : sd.g1;
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) s += src[(size_t)q * sd.Ng + G];
@@ -499,7 +643,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag(LaunchPlan p) {
     __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int tid = threadIdx.x;
     const int G = bs.local * kNodeThreads + tid;
     double ke = 0.0, ms = 0.0;
@@ -617,70 +761,6 @@ __device__ __forceinline__ double gather1(P v, const CopyList<D> &c) {
     return s;
 }
 
-__device__ __forceinline__ double mu_of(const SolveDesc &sd, double pr, double lap) {
-    const double rl = sd.rho_l, rv = sd.rho_v;
-    const double mu0 = 2.0 * sd.beta * (pr - rl) * (pr - rv) * (2.0 * pr - rl - rv);
-    return mu0 - sd.kappa * lap;
-}
-
-// element residual of the streaming (Eqs. (5)-(6), (12)) and flux bounce-back (Eq. (9)) at
-// node n, from LDS h_q = g_q - t_q rho, LDS mu, register g (for the flux) ; writes rs
-// per-node metric and wall data, loaded before the block's first barrier so that their
-// latency overlaps the gathers
-template <int D> struct NodeGeo {
-    double J[D][D];
-    double w;
-    int nw;
-    WallIdx wi;
-};
-template <int D>
-__device__ __forceinline__ void load_geo(const SolveDesc &sd, int e, int n, int l, NodeGeo<D> &g) {
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) g.J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
-    g.w = sd.wn[n];
-    g.nw = wall_entries_of<D>(sd, e, n, g.wi);
-}
-
-template <int D, int N, bool WIDE>
-__device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
-                                                const double *smu_e, int es, int n, int l,
-                                                double pr, const double *gq, const NodeGeo<D> &geo) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    double dmu[D];
-    grad_ref<D, NP>(sD, smu_e, n, dmu);
-    const double w = geo.w;
-    const int nw = geo.nw;
-#pragma unroll
-    for (int q = 1; q < Q; ++q) {
-        double dh[D];
-        grad_ref<D, NP>(sD, sh + (q - 1) * NB + es * NLOC, n, dh);
-        double adv = 0.0, frc = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const double ca = dot_e<Q, D>(geo.J[a], q);
-            adv += ca * dh[a];
-            frc += ca * dmu[a];
-        }
-        const double tc = sd.tc[q];
-        double r = -(w * (adv + tc * pr * frc));
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j >= nw) break;
-            const int k = geo.wi.k[j];
-            const double cn = sd.w_cn[k * Q + q];
-            if (cn < 0.0) {
-                const double bc = gq[q] - gq[Lat<Q>::opp[q]] - 2.0 * tc * pr * sd.w_eub[k * Q + q];
-                r += cn * bc;
-            }
-        }
-        sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
-    }
-}
-
 // A: mu of the state's density (DSS of the Laplacian partials) and the lumped-mass
 // weighted element gradients of rho and mu for the collision
 template <int D, int N, bool WIDE>
@@ -691,31 +771,33 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
     __shared__ double sf[2 * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int tid = threadIdx.x;
-    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
     const int l = e * NLOC + n;
+    double J[D][D];
+    double w = 0.0;
     if (act) {
         CopyList<D> cl;
         load_copies<D>(sd, l, cl);
         const int G = sd.lgid[l];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+        w = sd.wn[n];
         const double pr = sd.rho[G];
         const double mu = mu_of(sd, pr, gather1<D>(sd.rl, cl) * sd.Minv[G]);
         if (cl.cp[0] == l) sd.mu[G] = mu;
         sf[tid] = pr;
         sf[NB + tid] = mu;
     }
+    dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
-    const double w = sd.wn[n];
-    double J[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
         double d[D];
@@ -742,9 +824,9 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int tid = threadIdx.x;
-    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
@@ -757,7 +839,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
         CopyList<D> cl;
         load_copies<D>(sd, l, cl);
         const int G = sd.lgid[l];
-        load_geo<D>(sd, e, n, l, geo);
+        load_geo<D>(sd, n, l, geo);
         const double mi = sd.Minv[G];
         double gr[D], gm[D];
 #pragma unroll
@@ -769,41 +851,17 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
         pr = sd.rho[G];
-        const double cs2 = 1.0 / 3.0, dt = sd.dt, om = sd.omega;
-        double u[D], F[D];
+        const double mu = sd.mu[G];
+        collide_node<Q, D>(sd, f, pr, gr, gm, fs);
+        if (cl.cp[0] == l) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            double m = 0.0;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int ec = Lat<Q>::e[q][c];
-                if (ec == 1) m = m + f[q];
-                else if (ec == -1) m = m - f[q];
-            }
-            u[c] = m / pr;
-            F[c] = cs2 * gr[c] - pr * gm[c];
+            for (int q = 0; q < Q; ++q) sd.g0[q * Ng + G] = fs[q];
         }
-        double uF = 0.0, uu = 0.0;
+        smu[tid] = mu;
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            uF += u[c] * F[c];
-            uu += u[c] * u[c];
-        }
-        const bool owner = cl.cp[0] == l;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const double eu = dot_e<Q, D>(u, q), eF = dot_e<Q, D>(F, q);
-            const double tq = sd.t[q], tc = sd.tc[q];
-            const double Fss = tc * (eu * eF * 3.0 - uF);
-            const double feq = pr * tq * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-            const double fbeq = feq - 0.5 * dt * Fss;
-            fs[q] = f[q] - om * (f[q] - fbeq) + dt * Fss;
-            if (owner) sd.g0[q * Ng + G] = fs[q];
-        }
-        smu[tid] = sd.mu[G];
-#pragma unroll
-        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = fs[q] - sd.t[q] * pr;
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = fs[q] - sd.tw[wcls<Q>(q)] * pr;
     }
+    dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
     stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, fs, geo);
@@ -818,35 +876,42 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
     using S = Shape<D, N, WIDE>;
     constexpr int Q = QOf<D>::Q;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    constexpr int K = CopyList<D>::K;
     __shared__ double sD[NP * NP];
     __shared__ double srho[NB];
     __shared__ double sv[D * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int tid = threadIdx.x;
-    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
     const int l = e * NLOC + n;
     const size_t Ng = sd.Ng, Nl = sd.Nl;
+    const double SLBM_GLOBAL *gin = stage == 1 ? sd.g0 : (stage == 2 ? sd.g1 : sd.g2);
+    double SLBM_GLOBAL *gout = stage == 1 ? sd.g1 : (stage == 2 ? sd.g2 : sd.f);
     double rho = 0.0;
     double gm[S::NG];
-    WallIdx wi;
-    int nw = 0;
+    WallLap<D> wl;
     if (act) {
         CopyList<D> cl;
         load_copies<D>(sd, l, cl);
         const int G = sd.lgid[l];
 #pragma unroll
         for (int k = 0; k < S::NG; ++k) gm[k] = sd.G[(size_t)k * Nl + l];
-        nw = wall_entries_of<D>(sd, e, n, wi);
+        load_wall_lap<D>(sd, l, wl);
+        // every load before the first store: residual partials of all copies, the stage
+        // input and g0
+        // (3-D: the first two slots; copies of edge and corner nodes beyond them in a loop,
+        // which keeps the register footprint of 8 slots x 18 populations away)
+        constexpr int KU = D == 2 ? K : 2;
         double R[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) R[q] = 0.0;
 #pragma unroll
-        for (int k = 0; k < CopyList<D>::K; ++k) {
+        for (int k = 0; k < KU; ++k) {
             double x[Q];
 #pragma unroll
             for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + cl.cp[k]];
@@ -854,49 +919,49 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
 #pragma unroll
             for (int q = 1; q < Q; ++q) R[q] += valid ? x[q] : 0.0;
         }
-        const double *gin = stage == 1 ? sd.g0 : (stage == 2 ? sd.g1 : sd.g2);
-        double *gout = stage == 1 ? sd.g1 : (stage == 2 ? sd.g2 : sd.f);
+        if constexpr (KU < K) {
+            for (int k = KU; k < cl.nc; ++k) {
+                double x[Q];
+                const int c = k == 2 ? cl.cp[2] : (k == 3 ? cl.cp[3] : (k == 4 ? cl.cp[4] :
+                              (k == 5 ? cl.cp[5] : (k == 6 ? cl.cp[6] : cl.cp[7]))));
+#pragma unroll
+                for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + c];
+#pragma unroll
+                for (int q = 1; q < Q; ++q) R[q] += x[q];
+            }
+        }
+        double gi[Q], g0v[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) gi[q] = gin[q * Ng + G];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) g0v[q] = 0.0;
+        if (stage != 1) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) g0v[q] = sd.g0[q * Ng + G];
+        }
         const double mi = sd.Minv[G], dt = sd.dt;
         const bool owner = cl.cp[0] == l;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const double L = q > 0 ? R[q] * mi : 0.0;
-            const double x = gin[q * Ng + G] + dt * L;
-            double out;
-            if (stage == 1) out = x;
-            else if (stage == 2) out = 0.75 * sd.g0[q * Ng + G] + 0.25 * x;
-            else out = (sd.g0[q * Ng + G] + 2.0 * x) / 3.0;
+            const double out = rk_combine<Q>(stage, L, gi[q], g0v[q], dt);
             rho += out;
             if (owner) gout[q * Ng + G] = out;
         }
         if (owner) sd.rho[G] = rho;
         srho[tid] = rho;
     }
+    dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (act) {
         double d[D];
         grad_ref<D, NP>(sD, srho + es * NLOC, n, d);
-        const double *g = gm;
-        if constexpr (D == 2) {
-            double v0 = 0.0, v1 = 0.0;
-            v0 += g[0] * d[0]; v0 += g[1] * d[1];
-            v1 += g[1] * d[0]; v1 += g[2] * d[1];
-            sv[tid] = v0; sv[NB + tid] = v1;
-        } else {
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-            v0 += g[0] * d[0]; v0 += g[1] * d[1]; v0 += g[2] * d[2];
-            v1 += g[1] * d[0]; v1 += g[3] * d[1]; v1 += g[4] * d[2];
-            v2 += g[2] * d[0]; v2 += g[4] * d[1]; v2 += g[5] * d[2];
-            sv[tid] = v0; sv[NB + tid] = v1; sv[2 * NB + tid] = v2;
-        }
+        metric_times_grad<D, NB, S::NG>(gm, d, sv, tid);
     }
     __syncthreads();
     if (!act) return;
-    double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-        if (j < nw) r += sd.w_lap[wi.k[j]] * fabs((rho - sd.rho_l) * (rho - sd.rho_v));
-    sd.rl[l] = r;
+    const double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
+    sd.rl[l] = wall_lap_term<D>(sd, wl, rho, r);
 }
 
 // D: mu of the stage density (DSS of the Laplacian partials) and the streaming residual of
@@ -911,15 +976,15 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc &sd = *bs.sd;
+    const SolveDesc sd = *bs.sd;
     const int tid = threadIdx.x;
-    for (int k = tid; k < NP * NP; k += blockDim.x) sD[k] = sd.Dm[k];
+    const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
     const int l = e * NLOC + n;
     const size_t Ng = sd.Ng;
-    const double *__restrict__ g = stage == 2 ? sd.g1 : sd.g2;
+    const double SLBM_GLOBAL *g = stage == 2 ? sd.g1 : sd.g2;
     double gq[Q];
     double pr = 0.0;
     NodeGeo<D> geo;
@@ -927,14 +992,15 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
         CopyList<D> cl;
         load_copies<D>(sd, l, cl);
         const int G = sd.lgid[l];
-        load_geo<D>(sd, e, n, l, geo);
+        load_geo<D>(sd, n, l, geo);
         pr = sd.rho[G];
         smu[tid] = mu_of(sd, pr, gather1<D>(sd.rl, cl) * sd.Minv[G]);
 #pragma unroll
         for (int q = 0; q < Q; ++q) gq[q] = g[q * Ng + G];
 #pragma unroll
-        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = gq[q] - sd.t[q] * pr;
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = gq[q] - sd.tw[wcls<Q>(q)] * pr;
     }
+    dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
     stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);

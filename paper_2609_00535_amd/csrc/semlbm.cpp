@@ -208,7 +208,7 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
                                      const double *wall_ub) {
     if (!c) return SLBM_EINVAL;
     if (c->bound) return c->fail(SLBM_ESTATE, "set_mesh after bind");
-    const int dim = c->dim, nloc = c->nloc, Q = c->Q, N = c->N;
+    const int dim = c->dim, nloc = c->nloc, N = c->N;
     if (E <= 0 || !xyz || !gid || n_global <= 0 || n_wall_faces < 0 ||
         (n_wall_faces > 0 && (!wall_face || !wall_cos)))
         return c->fail(SLBM_EINVAL, "bad mesh arguments");
@@ -242,6 +242,15 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
     {
         std::vector<int32_t> fill(c->csr_ptr.begin(), c->csr_ptr.end() - 1);
         for (int64_t l = 0; l < Nl; ++l) c->csr_idx[fill[c->lgid[l]]++] = (int32_t)l;
+    }
+    // first two copies of every global node, read by the node kernels in one load
+    c->gcopy.assign((size_t)4 * n_global, 0);
+    for (int64_t g = 0; g < n_global; ++g) {
+        const int k0 = c->csr_ptr[g], nc = c->csr_ptr[g + 1] - k0;
+        c->gcopy[4 * g] = k0;
+        c->gcopy[4 * g + 1] = nc;
+        c->gcopy[4 * g + 2] = c->csr_idx[k0];
+        c->gcopy[4 * g + 3] = c->csr_idx[nc > 1 ? k0 + 1 : k0];
     }
     // per-local-node copy lists (fused path): the ascending local copies of its global node
     c->vmax = 0;
@@ -365,11 +374,11 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         c->dt = dt_adv < dt_cap ? dt_adv : dt_cap;
     }
     if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return c->fail(SLBM_EINVAL, "invalid time step");
-    // --- wall tables: one entry per (face, face node), grouped by element in face order ---
+    // --- wall tables: one entry per (face, face node); the entries of a local node are
+    // adjacent, in the order of the caller's face list ---
     const double sq = std::sqrt(2.0 * c->beta / c->kappa);
-    struct WE { int64_t e; int64_t order; int node; double lap; double cn[kMaxQ]; double eub[kMaxQ]; };
+    struct WE { int64_t l; double sn[3]; double ub[3]; double lap; };
     std::vector<WE> ents;
-    int64_t order = 0;
     for (int64_t fidx = 0; fidx < n_wall_faces; ++fidx) {
         const int64_t e = wall_face[2 * fidx];
         const int face = wall_face[2 * fidx + 1];
@@ -386,46 +395,42 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
             for (int b = 0; b < dim; ++b)
                 if (b != a) wf = wf * c->wq[c->along(n, b)];
             const int64_t l = e * nloc + n;
-            double Jv[3], sn[3] = {0.0, 0.0, 0.0};
+            double Jv[3];
             double nrm2 = 0.0;
             for (int cc = 0; cc < dim; ++cc) {
                 Jv[cc] = c->Ja[(size_t)(a * dim + cc) * Nl + l];
                 nrm2 += Jv[cc] * Jv[cc];
             }
-            for (int cc = 0; cc < dim; ++cc) sn[cc] = sign * wf * Jv[cc];
-            const double s = wf * std::sqrt(nrm2);
             WE w;
-            w.e = e;
-            w.order = order++;
-            w.node = n;
-            w.lap = s * wall_cos[fidx] * sq;
-            for (int q = 0; q < Q; ++q) {
-                double cn = 0.0, eu = 0.0;
-                for (int cc = 0; cc < dim; ++cc) cn += sn[cc] * c->ev[q][cc];
-                for (int cc = 0; cc < dim; ++cc) eu += c->ev[q][cc] * ub[cc];
-                w.cn[q] = cn;
-                w.eub[q] = eu;
+            w.l = l;
+            for (int cc = 0; cc < 3; ++cc) {
+                w.sn[cc] = cc < dim ? sign * wf * Jv[cc] : 0.0;
+                w.ub[cc] = ub[cc];
             }
+            // s cos(theta) sqrt(2 beta / kappa), s = w_face |J_s|
+            w.lap = wf * std::sqrt(nrm2) * wall_cos[fidx] * sq;
             ents.push_back(w);
         }
     }
-    std::stable_sort(ents.begin(), ents.end(), [](const WE &x, const WE &y) { return x.e < y.e; });
+    std::stable_sort(ents.begin(), ents.end(), [](const WE &x, const WE &y) { return x.l < y.l; });
     c->nw = (int64_t)ents.size();
-    c->wel_ptr.assign(E + 1, 0);
-    c->w_node.resize(c->nw);
-    c->w_lap.resize(c->nw);
-    c->w_cn.resize((size_t)c->nw * Q);
-    c->w_eub.resize((size_t)c->nw * Q);
+    const int W = 2 * dim + 1;
+    c->lwall.assign(Nl, 0);
+    c->w_dat.assign((size_t)W * std::max<int64_t>(c->nw, 1), 0.0);
     for (int64_t k = 0; k < c->nw; ++k) {
-        c->wel_ptr[ents[k].e + 1]++;
-        c->w_node[k] = ents[k].node;
-        c->w_lap[k] = ents[k].lap;
-        for (int q = 0; q < Q; ++q) {
-            c->w_cn[k * Q + q] = ents[k].cn[q];
-            c->w_eub[k * Q + q] = ents[k].eub[q];
+        const int64_t l = ents[k].l;
+        const int cnt = (c->lwall[l] & 3) + 1;
+        if (cnt > dim)
+            return c->fail(SLBM_EINVAL, "element %lld: a node lies on more than %d listed wall faces "
+                           "(duplicate face?)", (long long)(l / nloc), dim);
+        c->lwall[l] = cnt == 1 ? (int32_t)((k << 2) | 1) : (c->lwall[l] & ~3) | cnt;
+        for (int cc = 0; cc < dim; ++cc) {
+            c->w_dat[(size_t)k * W + cc] = ents[k].sn[cc];
+            c->w_dat[(size_t)k * W + dim + cc] = ents[k].ub[cc];
         }
+        c->w_dat[(size_t)k * W + 2 * dim] = ents[k].lap;
     }
-    for (int64_t e = 0; e < E; ++e) c->wel_ptr[e + 1] += c->wel_ptr[e];
+    if (c->nw >= (int64_t)1 << 29) return c->fail(SLBM_EINVAL, "too many wall nodes");
     c->has_mesh = true;
     c->layout();
     return SLBM_OK;
@@ -447,19 +452,16 @@ void slbm_ctx::layout() {
     off.eplan = take(sizeof(int) * 2 * (size_t)n_eblocks);
     off.nplan = take(sizeof(int) * 2 * (size_t)n_nblocks);
     off.lgid = take(sizeof(int) * Nl);
-    off.csr_ptr = take(sizeof(int) * (Ng + 1));
+    off.gcopy = take(sizeof(int) * 4 * Ng);
     off.csr_idx = take(sizeof(int) * Nl);
     off.lcp = take(sizeof(int) * std::max<size_t>(lcp.size(), 1));
-    off.wel_ptr = take(sizeof(int) * (E + 1));
-    off.w_node = take(sizeof(int) * std::max<int64_t>(nw, 1));
+    off.lwall = take(sizeof(int) * Nl);
+    off.w_dat = take(sizeof(double) * w_dat.size());
     off.Ja = take(sizeof(double) * dim_ * dim_ * Nl);
     off.G = take(sizeof(double) * ng * Nl);
     off.Minv = take(sizeof(double) * Ng);
     off.Dm = take(sizeof(double) * Np * Np);
     off.wn = take(sizeof(double) * nloc);
-    off.w_lap = take(sizeof(double) * std::max<int64_t>(nw, 1));
-    off.w_cn = take(sizeof(double) * Q_ * std::max<int64_t>(nw, 1));
-    off.w_eub = take(sizeof(double) * Q_ * std::max<int64_t>(nw, 1));
     off.f = take(sizeof(double) * Q_ * Ng);
     off.g0 = take(sizeof(double) * Q_ * Ng);
     off.g1 = take(sizeof(double) * Q_ * Ng);
@@ -499,15 +501,12 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     d.Ja = at<double>(b, c->off.Ja);
     d.G = at<double>(b, c->off.G);
     d.Minv = at<double>(b, c->off.Minv);
-    d.csr_ptr = at<int>(b, c->off.csr_ptr);
+    d.gcopy = at<NodeCopies>(b, c->off.gcopy);
     d.csr_idx = at<int>(b, c->off.csr_idx);
     d.lcp = at<int>(b, c->off.lcp);
     d.vmax = c->vmax;
-    d.wel_ptr = at<int>(b, c->off.wel_ptr);
-    d.w_node = at<int>(b, c->off.w_node);
-    d.w_lap = at<double>(b, c->off.w_lap);
-    d.w_cn = at<double>(b, c->off.w_cn);
-    d.w_eub = at<double>(b, c->off.w_eub);
+    d.lwall = at<int>(b, c->off.lwall);
+    d.w_dat = at<double>(b, c->off.w_dat);
     d.Dm = at<double>(b, c->off.Dm);
     d.wn = at<double>(b, c->off.wn);
     d.f = at<double>(b, c->off.f);
@@ -529,8 +528,9 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     d.omega = c->omega;
     d.dt = c->dt;
     for (int q = 0; q < c->Q; ++q) {
-        d.t[q] = c->tw[q];
-        d.tc[q] = c->tc[q];
+        const int cls = (int)(std::fabs(c->ev[q][0]) + std::fabs(c->ev[q][1]) + std::fabs(c->ev[q][2]));
+        d.tw[cls] = c->tw[q];
+        d.twc[cls] = c->tc[q];
     }
     // block tables of the single-member plans
     std::vector<int> ep(2 * (size_t)c->n_eblocks), np_(2 * (size_t)c->n_nblocks);
@@ -550,7 +550,7 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     c->nplan.single = 1;
     c->nplan.epb = 0;
     c->nplan.grid = xcd_grid(c->n_nblocks);
-    const int Q = c->Q, dim = c->dim;
+    const int dim = c->dim;
     const size_t ng = (size_t)dim * (dim + 1) / 2;
     int e = 0;
     auto up = [&](size_t off, const void *src, size_t n) {
@@ -560,19 +560,16 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     up(c->off.eplan, ep.data(), sizeof(int) * ep.size());
     up(c->off.nplan, np_.data(), sizeof(int) * np_.size());
     up(c->off.lgid, c->lgid.data(), sizeof(int) * c->Nl);
-    up(c->off.csr_ptr, c->csr_ptr.data(), sizeof(int) * (c->Ng + 1));
+    up(c->off.gcopy, c->gcopy.data(), sizeof(int) * c->gcopy.size());
     up(c->off.csr_idx, c->csr_idx.data(), sizeof(int) * c->Nl);
     up(c->off.lcp, c->lcp.data(), sizeof(int) * c->lcp.size());
-    up(c->off.wel_ptr, c->wel_ptr.data(), sizeof(int) * (c->E + 1));
-    up(c->off.w_node, c->w_node.data(), sizeof(int) * c->nw);
+    up(c->off.lwall, c->lwall.data(), sizeof(int) * c->Nl);
+    up(c->off.w_dat, c->w_dat.data(), sizeof(double) * c->w_dat.size());
     up(c->off.Ja, c->Ja.data(), sizeof(double) * dim * dim * c->Nl);
     up(c->off.G, c->Gm.data(), sizeof(double) * ng * c->Nl);
     up(c->off.Minv, c->Minv.data(), sizeof(double) * c->Ng);
     up(c->off.Dm, c->Dm.data(), sizeof(double) * c->Np * c->Np);
     up(c->off.wn, c->wn.data(), sizeof(double) * c->nloc);
-    up(c->off.w_lap, c->w_lap.data(), sizeof(double) * c->nw);
-    up(c->off.w_cn, c->w_cn.data(), sizeof(double) * Q * c->nw);
-    up(c->off.w_eub, c->w_eub.data(), sizeof(double) * Q * c->nw);
     if (e == 0) e = (int)hipMemsetAsync((char *)b + c->off.f, 0, c->off.diag - c->off.f, st);
     if (e == 0) e = (int)hipStreamSynchronize(st);
     if (e) return c->hip_check(e, "bind upload");
