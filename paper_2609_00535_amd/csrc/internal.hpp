@@ -72,6 +72,9 @@ struct LaunchPlan {
     int single;              // one member: no table lookup, XCD-aware block mapping
     int epb;                 // elements per block of element kernels (wide or 1)
     int grid;                // launched blocks (multiple of kXcds)
+    // single member: its descriptor by value in the kernel arguments, so a block reads it
+    // with one scalar load from the argument segment instead of two dependent ones
+    SolveDesc one;
 };
 
 // MI355X dispatches consecutive workgroups round-robin over its 8 accelerator dies (XCDs),

@@ -159,6 +159,14 @@ __device__ __forceinline__ BlockSlot block_slot(const LaunchPlan &p) {
     return b;
 }
 
+// The member's descriptor in registers, read before the kernel's first global store (a
+// store through a state pointer could otherwise alias the descriptor in memory and force
+// reloads).  A single solve passes it in the kernel arguments.
+__device__ __forceinline__ SolveDesc desc_of(const LaunchPlan &p, const BlockSlot &b) {
+    if (p.single) return p.one;
+    return *b.sd;
+}
+
 // ------------------------------------------------------------------------------------------
 // wall entries of a local node (at most d faces of its element): the first entry and the
 // count come from lwall; entries beyond the count repeat the last one so every slot can be
@@ -265,7 +273,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
     __shared__ double sv[D * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int tid = threadIdx.x;
     const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
@@ -307,7 +315,7 @@ template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
     const NodeCopies c = sd.gcopy[G];
@@ -325,7 +333,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_grad(LaunchPlan p) 
     __shared__ double sf[2 * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int tid = threadIdx.x;
     const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
@@ -366,7 +374,7 @@ template <int D, int N>
 __global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
     const NodeCopies cp = sd.gcopy[G];
@@ -419,7 +427,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_
     constexpr int Q = QOf<D>::Q;
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
     const size_t Ng = sd.Ng;
@@ -522,7 +530,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_stream(LaunchPlan p
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const double SLBM_GLOBAL *g = stage == 1 ? sd.g0 : sd.g1;
     const int tid = threadIdx.x;
     const double dmv = dm_fetch<NP>(sd, tid);
@@ -568,7 +576,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     constexpr int Q = QOf<D>::Q;
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
     const size_t Ng = sd.Ng, Nl = sd.Nl;
@@ -626,7 +634,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int whic
     constexpr int Q = QOf<D>::Q;
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int G = bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
     const double SLBM_GLOBAL *src = which == 0 ? sd.f : sd.g1;
@@ -643,7 +651,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag(LaunchPlan p) {
     __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int tid = threadIdx.x;
     const int G = bs.local * kNodeThreads + tid;
     double ke = 0.0, ms = 0.0;
@@ -726,38 +734,74 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *de
 // halves the number of grid-wide dependencies of a step (7 kernels instead of 14).
 // ------------------------------------------------------------------------------------------
 
-// Copy list of local node l in registers (K slots: 4 in 2-D, 8 in 3-D).  Unused slots
-// repeat the first copy so every slot can be loaded without a branch; sums mask them out,
-// adding +0.0 after the real terms, which leaves the ascending-order sum unchanged.  All
-// loads of a gather are thus in flight together.
+// Copy list of local node l in registers (K slots: 4 in 2-D, 8 in 3-D), ascending; slots
+// beyond the node's copies repeat the first copy.  Two gather forms, both with all loads of
+// a gather in flight together and both summing in ascending order:
+//   * PRED (wide blocks, bandwidth bound): element-interior nodes skip their copy list and
+//     slot k is loaded only in lanes with more than k copies (predicated loads);
+//   * branch-free (one element per block, latency bound): every slot is loaded and the
+//     unused ones are masked out of the sum, adding +0.0 after the real terms (the sum
+//     starts from +0.0 and never becomes -0.0, so the result is the same).
 template <int D> struct CopyList {
     static constexpr int K = kCopySlots[D - 2];
     int cp[K];
     int nc;
 };
-template <int D>
-__device__ __forceinline__ void load_copies(const SolveDesc &sd, int l, CopyList<D> &c) {
-    c.nc = 0;
-#pragma unroll
-    for (int k = 0; k < CopyList<D>::K; ++k) {
-        int v = -1;
-        if (k < sd.vmax) v = sd.lcp[(size_t)k * sd.Nl + l];  // uniform branch
-        c.cp[k] = v;
-        if (v >= 0) c.nc = k + 1;
+// element node n (i fastest) on the element's boundary?  Nodes inside an element belong to
+// it alone (the fused path is selected only for meshes where that holds).
+template <int D, int NP>
+__device__ __forceinline__ bool on_elem_boundary(int n) {
+    const int i = n % NP, j = (n / NP) % NP;
+    bool b = i == 0 || i == NP - 1 || j == 0 || j == NP - 1;
+    if constexpr (D == 3) {
+        const int k = n / (NP * NP);
+        b = b || k == 0 || k == NP - 1;
     }
-#pragma unroll
-    for (int k = 1; k < CopyList<D>::K; ++k)
-        if (k >= c.nc) c.cp[k] = c.cp[0];
+    return b;
 }
 
-template <int D, class P>
+template <int D, int NP, bool PRED>
+__device__ __forceinline__ void load_copies(const SolveDesc &sd, int n, int l, CopyList<D> &c) {
+    c.cp[0] = l;
+    c.nc = 1;
+#pragma unroll
+    for (int k = 1; k < CopyList<D>::K; ++k) c.cp[k] = l;
+    if (!PRED || on_elem_boundary<D, NP>(n)) {
+        c.nc = 0;
+#pragma unroll
+        for (int k = 0; k < CopyList<D>::K; ++k) {
+            int v = -1;
+            if (k < sd.vmax) v = sd.lcp[(size_t)k * sd.Nl + l];  // uniform branch
+            c.cp[k] = v;
+            if (v >= 0) c.nc = k + 1;
+        }
+#pragma unroll
+        for (int k = 1; k < CopyList<D>::K; ++k)
+            if (k >= c.nc) c.cp[k] = c.cp[0];
+    }
+}
+
+template <int D, bool PRED, class P>
 __device__ __forceinline__ double gather1(P v, const CopyList<D> &c) {
     double x[CopyList<D>::K];
-#pragma unroll
-    for (int k = 0; k < CopyList<D>::K; ++k) x[k] = v[c.cp[k]];
     double s = 0.0;
+    if constexpr (PRED) {
+        x[0] = v[c.cp[0]];
 #pragma unroll
-    for (int k = 0; k < CopyList<D>::K; ++k) s += k < c.nc ? x[k] : 0.0;
+        for (int k = 1; k < CopyList<D>::K; ++k) {
+            x[k] = 0.0;
+            if (k < c.nc) x[k] = v[c.cp[k]];
+        }
+        s += x[0];
+#pragma unroll
+        for (int k = 1; k < CopyList<D>::K; ++k)
+            if (k < c.nc) s += x[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < CopyList<D>::K; ++k) x[k] = v[c.cp[k]];
+#pragma unroll
+        for (int k = 0; k < CopyList<D>::K; ++k) s += k < c.nc ? x[k] : 0.0;
+    }
     return s;
 }
 
@@ -771,7 +815,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
     __shared__ double sf[2 * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int tid = threadIdx.x;
     const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
@@ -782,7 +826,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
     double w = 0.0;
     if (act) {
         CopyList<D> cl;
-        load_copies<D>(sd, l, cl);
+        load_copies<D, NP, WIDE>(sd, n, l, cl);
         const int G = sd.lgid[l];
 #pragma unroll
         for (int a = 0; a < D; ++a)
@@ -790,7 +834,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
             for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
         w = sd.wn[n];
         const double pr = sd.rho[G];
-        const double mu = mu_of(sd, pr, gather1<D>(sd.rl, cl) * sd.Minv[G]);
+        const double mu = mu_of(sd, pr, gather1<D, WIDE>(sd.rl, cl) * sd.Minv[G]);
         if (cl.cp[0] == l) sd.mu[G] = mu;
         sf[tid] = pr;
         sf[NB + tid] = mu;
@@ -824,7 +868,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int tid = threadIdx.x;
     const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
@@ -837,15 +881,15 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
     NodeGeo<D> geo;
     if (act) {
         CopyList<D> cl;
-        load_copies<D>(sd, l, cl);
+        load_copies<D, NP, WIDE>(sd, n, l, cl);
         const int G = sd.lgid[l];
         load_geo<D>(sd, n, l, geo);
         const double mi = sd.Minv[G];
         double gr[D], gm[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            gr[c] = gather1<D>(sd.gl + (size_t)c * sd.Nl, cl) * mi;
-            gm[c] = gather1<D>(sd.gl + (size_t)(D + c) * sd.Nl, cl) * mi;
+            gr[c] = gather1<D, WIDE>(sd.gl + (size_t)c * sd.Nl, cl) * mi;
+            gm[c] = gather1<D, WIDE>(sd.gl + (size_t)(D + c) * sd.Nl, cl) * mi;
         }
         double f[Q];
 #pragma unroll
@@ -882,7 +926,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
     __shared__ double sv[D * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int tid = threadIdx.x;
     const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
@@ -897,7 +941,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
     WallLap<D> wl;
     if (act) {
         CopyList<D> cl;
-        load_copies<D>(sd, l, cl);
+        load_copies<D, NP, WIDE>(sd, n, l, cl);
         const int G = sd.lgid[l];
 #pragma unroll
         for (int k = 0; k < S::NG; ++k) gm[k] = sd.G[(size_t)k * Nl + l];
@@ -910,14 +954,28 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
         double R[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) R[q] = 0.0;
+        double x[KU][Q];
 #pragma unroll
         for (int k = 0; k < KU; ++k) {
-            double x[Q];
 #pragma unroll
-            for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + cl.cp[k]];
+            for (int q = 1; q < Q; ++q) x[k][q] = 0.0;
+            if (!WIDE || k == 0 || k < cl.nc) {
+#pragma unroll
+                for (int q = 1; q < Q; ++q) x[k][q] = sd.rs[(size_t)(q - 1) * Nl + cl.cp[k]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
             const bool valid = k < cl.nc;
+            if (WIDE) {
+                if (k == 0 || valid) {
 #pragma unroll
-            for (int q = 1; q < Q; ++q) R[q] += valid ? x[q] : 0.0;
+                    for (int q = 1; q < Q; ++q) R[q] += x[k][q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 1; q < Q; ++q) R[q] += valid ? x[k][q] : 0.0;
+            }
         }
         if constexpr (KU < K) {
             for (int k = KU; k < cl.nc; ++k) {
@@ -976,7 +1034,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
     __shared__ double sh[(Q - 1) * NB];
     const BlockSlot bs = block_slot(p);
     if (!bs.valid) return;
-    const SolveDesc sd = *bs.sd;
+    const SolveDesc sd = desc_of(p, bs);
     const int tid = threadIdx.x;
     const double dmv = dm_fetch<NP>(sd, tid);
     const int es = tid / NLOC, n = tid - es * NLOC;
@@ -990,11 +1048,11 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
     NodeGeo<D> geo;
     if (act) {
         CopyList<D> cl;
-        load_copies<D>(sd, l, cl);
+        load_copies<D, NP, WIDE>(sd, n, l, cl);
         const int G = sd.lgid[l];
         load_geo<D>(sd, n, l, geo);
         pr = sd.rho[G];
-        smu[tid] = mu_of(sd, pr, gather1<D>(sd.rl, cl) * sd.Minv[G]);
+        smu[tid] = mu_of(sd, pr, gather1<D, WIDE>(sd.rl, cl) * sd.Minv[G]);
 #pragma unroll
         for (int q = 0; q < Q; ++q) gq[q] = g[q * Ng + G];
 #pragma unroll

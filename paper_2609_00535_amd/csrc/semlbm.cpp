@@ -271,7 +271,20 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         const char *nf = std::getenv("SLBM_UNFUSED");
         const char *ff = std::getenv("SLBM_FUSED");
         const bool large3d = dim == 3 && Nl > (int64_t)1 << 20;
-        const bool fits = c->vmax <= kCopySlots[dim - 2];
+        // nodes inside an element must belong to it alone (the fused kernels skip their
+        // copy lists)
+        bool interior_single = true;
+        for (int64_t l = 0; l < Nl && interior_single; ++l) {
+            const int n = (int)(l % nloc);
+            bool bnd = false;
+            for (int a = 0; a < dim; ++a) {
+                const int i = c->along(n, a);
+                bnd = bnd || i == 0 || i == N;
+            }
+            const int g = c->lgid[l];
+            if (!bnd && c->csr_ptr[g + 1] - c->csr_ptr[g] != 1) interior_single = false;
+        }
+        const bool fits = c->vmax <= kCopySlots[dim - 2] && interior_single;
         c->fused = fits && !large3d;
         if (nf && nf[0] == '1') c->fused = false;
         if (ff && ff[0] == '1' && fits) c->fused = true;
@@ -541,6 +554,7 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     c->eplan.blk_local = at<int>(b, c->off.eplan) + c->n_eblocks;
     c->eplan.nblocks = c->n_eblocks;
     c->eplan.single = 1;
+    c->eplan.one = d;
     c->eplan.epb = c->epb;
     c->eplan.grid = xcd_grid(c->n_eblocks);
     c->nplan.desc = at<SolveDesc>(b, c->off.desc);
@@ -548,6 +562,7 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     c->nplan.blk_local = at<int>(b, c->off.nplan) + c->n_nblocks;
     c->nplan.nblocks = c->n_nblocks;
     c->nplan.single = 1;
+    c->nplan.one = d;
     c->nplan.epb = 0;
     c->nplan.grid = xcd_grid(c->n_nblocks);
     const int dim = c->dim;

@@ -1,7 +1,7 @@
 // Batching, serving and the contact-angle query of the C ABI (include/semlbm.h).
 //
-// A batch groups its bound members by (dimension, N); every kernel of the time step runs
-// once per group and covers all of the group's members (block tables map each block to a
+// A batch groups its bound members by (dimension, N, kernel path); every kernel of the time
+// step runs once per group and covers all of the group's members (block tables map each block to a
 // member and to a block of that member).  The server keeps a queue of requests, admits
 // them while slots and arena bytes are free, advances all active solves as one batch in
 // rounds of check_every steps, and retires each solve when its kinetic energy has dropped
@@ -37,7 +37,7 @@ struct slbm_batch {
     bool dirty = true;
     struct Group {
         int d = 0, N = 0, epb = 1;
-        bool fused = true;     // every member can take the fused path
+        bool fused = true;     // kernel path of every member
         std::vector<int> idx;  // member indices
         LaunchPlan ep{}, np{};
         SolveDesc *desc = nullptr;  // device
@@ -101,23 +101,35 @@ struct slbm_batch {
         }
     }
 
+    // element blocks of member c under the group's block shape
+    static int eblocks(const slbm_ctx *c, int epb) { return (int)((c->E + epb - 1) / epb); }
+
     slbm_status rebuild() {
         drop_graphs();
         groups.clear();
+        // groups by (d, N, path): a member keeps the path (fused or not) it steps alone
+        // with, so its state buffers always carry what that path expects between steps
         for (int i = 0; i < (int)members.size(); ++i) {
             slbm_ctx *c = members[i];
             Group *g = nullptr;
             for (auto &x : groups)
-                if (x.d == c->dim && x.N == c->N && x.epb == c->epb) g = &x;
+                if (x.d == c->dim && x.N == c->N && x.fused == c->fused) g = &x;
             if (!g) {
                 groups.emplace_back();
                 g = &groups.back();
                 g->d = c->dim;
                 g->N = c->N;
-                g->epb = c->epb;
+                g->fused = c->fused;
             }
             g->idx.push_back(i);
-            g->fused = g->fused && c->fused;
+        }
+        // block shape per group: wide blocks (several elements each) once the group's
+        // elements fill the chip, one element per block otherwise
+        for (auto &g : groups) {
+            const int w = epb_wide(g.d, g.N);
+            int64_t nb = 0;
+            for (int i : g.idx) nb += eblocks(members[i], w);
+            g.epb = nb >= 256 ? w : 1;
         }
         // one device block: per group [descs][e tables][n tables][diag out]
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -127,7 +139,7 @@ struct slbm_batch {
             goff.push_back(total);
             int ne = 0, nn = 0;
             for (int i : g.idx) {
-                ne += members[i]->n_eblocks;
+                ne += eblocks(members[i], g.epb);
                 nn += members[i]->n_nblocks;
             }
             total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(int) * 2 * xcd_grid(ne)) +
@@ -155,7 +167,7 @@ struct slbm_batch {
             o += al(sizeof(SolveDesc) * g.idx.size());
             int ne = 0, nn = 0;
             for (int i : g.idx) {
-                ne += members[i]->n_eblocks;
+                ne += eblocks(members[i], g.epb);
                 nn += members[i]->n_nblocks;
             }
             // tables in XCD-aware order: hardware block b runs logical block
@@ -173,7 +185,7 @@ struct slbm_batch {
             for (int k = 0; k < (int)g.idx.size(); ++k) {
                 slbm_ctx *c = members[g.idx[k]];
                 dh[k] = c->desc;
-                for (int b = 0; b < c->n_eblocks; ++b) { le_s.push_back(k); le_l.push_back(b); }
+                for (int b = 0; b < eblocks(c, g.epb); ++b) { le_s.push_back(k); le_l.push_back(b); }
                 for (int b = 0; b < c->n_nblocks; ++b) { ln_s.push_back(k); ln_l.push_back(b); }
             }
             for (int b = 0; b < te; ++b) {
