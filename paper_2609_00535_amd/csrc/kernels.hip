@@ -80,6 +80,9 @@ template <int D, int N, bool WIDE = true> struct Shape {
     static constexpr int NB = EPB * NLOC;  // nodes of one block
     static constexpr int NT = ((NB + 63) / 64) * 64;
     static constexpr int NG = D * (D + 1) / 2;
+    // minimum waves per SIMD asked of the 3-D streaming kernels (caps their registers so
+    // that three 256-thread blocks share a compute unit)
+    static constexpr int WPE_STREAM = D == 3 ? 3 : 1;
     static_assert(NT >= NP * NP, "one differentiation-matrix entry per thread");
 };
 
@@ -521,7 +524,7 @@ __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const doubl
 
 // stage 1 streams g0, stages 2-3 stream g1
 template <int D, int N, bool WIDE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_stream(LaunchPlan p, int stage) {
+__global__ __launch_bounds__((Shape<D, N, WIDE>::NT), (Shape<D, N, WIDE>::WPE_STREAM)) void k_stream(LaunchPlan p, int stage) {
     using S = Shape<D, N, WIDE>;
     constexpr int Q = QOf<D>::Q;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
