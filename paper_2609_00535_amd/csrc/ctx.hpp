@@ -31,7 +31,7 @@ struct slbm_ctx {
     std::vector<double> xyz;
     std::vector<int32_t> lgid, ig2ug, csr_ptr, csr_idx, gcopy, lwall, lcp;
     int vmax = 0;
-    bool fused = true;  // fused element-kernel path (needs vmax <= kMaxCopies)
+    bool fused = true;  // fused element-kernel path (needs vmax <= the fused copy slots)
     std::vector<double> Ja, Gm, MA, Minv, w_dat;
     // device
     struct Offsets {

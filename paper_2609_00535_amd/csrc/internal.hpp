@@ -110,7 +110,6 @@ int launch_diag(int d, int N, const LaunchPlan &p, void *stream);
 int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream);
 // fused path: four element kernels per stage sequence (A: mu + gradients, B: collision +
 // stage-1 residual, C: DSS + Runge-Kutta combine + Laplacian residual, D: mu + residual)
-constexpr int kMaxCopies = 8;
 constexpr int kCopySlots[2] = {4, 8};  // register copy slots of the fused kernels (2-D, 3-D)
 int launch_fA(int d, int N, const LaunchPlan &p, void *stream);
 int launch_fB(int d, int N, const LaunchPlan &p, void *stream);

@@ -770,17 +770,16 @@ __device__ __forceinline__ void load_copies(const SolveDesc &sd, int n, int l, C
 #pragma unroll
     for (int k = 1; k < CopyList<D>::K; ++k) c.cp[k] = l;
     if (!PRED || on_elem_boundary<D, NP>(n)) {
-        c.nc = 0;
+        // all K rows of the table exist (-1 padded): the slot loads go out together
+        int v[CopyList<D>::K];
 #pragma unroll
-        for (int k = 0; k < CopyList<D>::K; ++k) {
-            int v = -1;
-            if (k < sd.vmax) v = sd.lcp[(size_t)k * sd.Nl + l];  // uniform branch
-            c.cp[k] = v;
-            if (v >= 0) c.nc = k + 1;
-        }
+        for (int k = 0; k < CopyList<D>::K; ++k) v[k] = sd.lcp[(size_t)k * sd.Nl + l];
+        c.nc = 1;
 #pragma unroll
-        for (int k = 1; k < CopyList<D>::K; ++k)
-            if (k >= c.nc) c.cp[k] = c.cp[0];
+        for (int k = 1; k < CopyList<D>::K; ++k) c.nc += v[k] >= 0 ? 1 : 0;
+        c.cp[0] = v[0];
+#pragma unroll
+        for (int k = 1; k < CopyList<D>::K; ++k) c.cp[k] = v[k] >= 0 ? v[k] : v[0];
     }
 }
 
@@ -802,8 +801,9 @@ __device__ __forceinline__ double gather1(P v, const CopyList<D> &c) {
     } else {
 #pragma unroll
         for (int k = 0; k < CopyList<D>::K; ++k) x[k] = v[c.cp[k]];
+        s += x[0];  // every node has its first copy
 #pragma unroll
-        for (int k = 0; k < CopyList<D>::K; ++k) s += k < c.nc ? x[k] : 0.0;
+        for (int k = 1; k < CopyList<D>::K; ++k) s += k < c.nc ? x[k] : 0.0;
     }
     return s;
 }
@@ -970,7 +970,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
 #pragma unroll
         for (int k = 0; k < KU; ++k) {
             const bool valid = k < cl.nc;
-            if (WIDE) {
+            if (WIDE || k == 0) {
                 if (k == 0 || valid) {
 #pragma unroll
                     for (int q = 1; q < Q; ++q) R[q] += x[k][q];

@@ -255,9 +255,11 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
     // per-local-node copy lists (fused path): the ascending local copies of its global node
     c->vmax = 0;
     for (int64_t g = 0; g < n_global; ++g) c->vmax = std::max<int>(c->vmax, c->csr_ptr[g + 1] - c->csr_ptr[g]);
+    // (kCopySlots[dim-2] rows, -1 padded, so the fused kernels load every slot without a
+    // branch)
     c->lcp.clear();
-    if (c->vmax <= kMaxCopies) {
-        c->lcp.assign((size_t)c->vmax * Nl, -1);
+    if (c->vmax <= kCopySlots[dim - 2]) {
+        c->lcp.assign((size_t)kCopySlots[dim - 2] * Nl, -1);
         for (int64_t l = 0; l < Nl; ++l) {
             const int g = c->lgid[l];
             for (int k = c->csr_ptr[g]; k < c->csr_ptr[g + 1]; ++k)
