@@ -80,16 +80,25 @@ def cpu_baseline(case, steps: int):
                        f"({dt:.1f} s wall)")
 
 
+def kernels_sha256() -> str:
+    """SHA-256 over the device sources (kernels.hpp, kernels*.hip, internal.hpp), in name order."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2609_00535_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.startswith("kernels") or name == "internal.hpp":
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_from_profiles(workload: str, kind: str):
     """HBM bytes per launch of the dominant kernel from the committed PMC summary, if it
     was taken on the current kernel source (else None)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2609_00535_amd", "csrc", "kernels.hip"), "rb").read()
-    if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("kernels_sha256") != kernels_sha256():
         return None
     v = rec.get("bytes_per_launch", {}).get(kind)
     return float(v) if v is not None else None

@@ -17,9 +17,11 @@ LIB = os.path.join(HERE, "libsemlbm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = os.environ.get("SLBM_ARCH", "gfx950")
 
+# -disable-machine-sink: keep the kernels' scalar argument loads together at entry (sunk
+# into the first branch they would cost a second dependent round trip per launch)
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-command-line-argument"]
+             "-mllvm", "-disable-machine-sink", "-Wno-unused-command-line-argument"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-pthread", "-ffp-contract=off", "-fno-fast-math", "-Wall",
              "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
 
@@ -30,9 +32,12 @@ def _run(cmd):
 
 
 def build(force: bool = True) -> str:
+    """Compile every translation unit (in parallel) and link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
-    objs = []
+    hdr_time = max(os.path.getmtime(os.path.join(CSRC, h)) for h in os.listdir(CSRC) if h.endswith(".hpp"))
+    objs, todo = [], []
     for src in sorted(os.listdir(CSRC)):
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
@@ -42,11 +47,13 @@ def build(force: bool = True) -> str:
             cmd = ["g++", *CXX_FLAGS, "-c", path, "-o", obj]
         else:
             continue
-        if force or not os.path.exists(obj) or os.path.getmtime(obj) < max(
-                os.path.getmtime(path), *[os.path.getmtime(os.path.join(CSRC, h))
-                                          for h in os.listdir(CSRC) if h.endswith(".hpp")]):
-            _run(cmd)
+        if force or not os.path.exists(obj) or os.path.getmtime(obj) < max(os.path.getmtime(path), hdr_time):
+            todo.append(cmd)
         objs.append(obj)
+    jobs = max(1, min(len(todo), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_run, c) for c in todo]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs,
           f"-L{ROCM}/lib", "-lamdhip64"])

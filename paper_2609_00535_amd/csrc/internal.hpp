@@ -14,6 +14,12 @@
 #else
 #define SLBM_GLOBAL
 #endif
+// helpers shared by host and device code (plain inline functions in host-only builds)
+#if defined(__HIPCC__)
+#define SLBM_HD __host__ __device__
+#else
+#define SLBM_HD
+#endif
 
 namespace slbm {
 
@@ -71,19 +77,27 @@ struct LaunchPlan {
     int nblocks;             // logical blocks (single member) or table length
     int single;              // one member: no table lookup, XCD-aware block mapping
     int epb;                 // elements per block of element kernels (wide or 1)
-    int grid;                // launched blocks (multiple of kXcds)
+    int grid;                // launched blocks (nblocks for a single member, else a multiple of kXcds)
     // single member: its descriptor by value in the kernel arguments, so a block reads it
     // with one scalar load from the argument segment instead of two dependent ones
     SolveDesc one;
 };
 
 // MI355X dispatches consecutive workgroups round-robin over its 8 accelerator dies (XCDs),
-// each with its own L2.  Logical block j is run by hardware block b with
-// j = (b % 8) * ceil(n / 8) + b / 8, so each die works on one contiguous range of
-// elements or nodes and neighbours share that die's L2.
+// each with its own L2.  Block tables (batches): logical block j is run by hardware block b
+// with j = (b % 8) * ceil(n / 8) + b / 8 over a grid padded to a multiple of 8 (padding
+// entries are -1), so each die works on one contiguous range of elements or nodes and
+// neighbours share that die's L2.  A single solve launches exactly n blocks and uses the
+// bijection xcd_single below (no padding block, so no block exits before its loads).
 constexpr int kXcds = 8;
 inline int xcd_grid(int n) { return ((n + kXcds - 1) / kXcds) * kXcds; }
 inline int xcd_logical(int b, int n) { const int per = (n + kXcds - 1) / kXcds; return (b % kXcds) * per + b / kXcds; }
+// hardware block b -> logical block for a grid of exactly n blocks: the first 8*(n/8)
+// blocks as above with n/8 per die, the remaining n % 8 blocks keep their index
+SLBM_HD inline int xcd_single(int b, int n) {
+    const int per = n / kXcds;
+    return b < per * kXcds ? (b % kXcds) * per + b / kXcds : b;
+}
 
 // Element-kernel shape for order N in d dimensions (must match kernels.hip): "wide" blocks
 // hold as many elements as fit in 256 threads; small meshes use one element per block so

@@ -1,705 +1,62 @@
-// HIP kernels (gfx950) of the two-phase spectral-element LBM time step.
-//
-// Two kernel families alternate inside a step:
-//   * element kernels: one thread per element node, several elements per 256-thread block,
-//     element fields staged in LDS; tensor-product GLL derivatives are contractions of an
-//     LDS line with a row (or column) of the differentiation matrix;
-//   * node kernels: one thread per global node; they finish the direct stiffness summation
-//     (DSS) by gathering the node's local copies in ascending order (deterministic, no
-//     atomics) and apply the pointwise physics.
-// Every kernel serves a whole batch: block b works on member blk_solve[b], block
-// blk_local[b] of it, with the member's tables and state in its SolveDesc.  A single solve
-// is a batch of one.
-//
-// Memory-level parallelism: each kernel issues all of its global loads (index tables
-// first, then the data they address) before its first global store, and reads the
-// descriptor into registers at entry.  A store through a state pointer may alias any
-// later load as far as the compiler knows, so loads placed after a store are issued only
-// after it and their latencies add up; this ordering keeps every wave to two dependent
-// memory round trips (index, data) plus its barriers.
-//
-// Floating point: the build disables contraction; the GLL contractions use fma explicitly
-// and every other expression is written with the operand order of the CPU oracle, so the
-// two implementations round identically.
-#include <hip/hip_runtime.h>
-
-#include "internal.hpp"
+// Dispatch of the kernel launchers (internal.hpp) to the per-order translation units, and
+// the batch-wide reduction kernel.
+#include "kernels.hpp"
 
 namespace slbm {
 
-// ------------------------------------------------------------------------------------------
-// lattice tables
-// ------------------------------------------------------------------------------------------
-template <int Q> struct Lat;
-template <> struct Lat<9> {
-    static constexpr int D = 2;
-    static constexpr int e[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
-                                    {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
-    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-};
-template <> struct Lat<19> {
-    static constexpr int D = 3;
-    static constexpr int e[19][3] = {
-        {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
-        {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
-        {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
-};
-template <int D> struct QOf;
-template <> struct QOf<2> { static constexpr int Q = 9; };
-template <> struct QOf<3> { static constexpr int Q = 19; };
+#define SLBM_DECLARE_SET(SFX)                                                                \
+    int launch_lap_##SFX(int, int, const LaunchPlan &, void *);                              \
+    int launch_mu_##SFX(int, int, const LaunchPlan &, void *);                               \
+    int launch_grad_##SFX(int, int, const LaunchPlan &, void *);                             \
+    int launch_gavg_##SFX(int, int, const LaunchPlan &, void *);                             \
+    int launch_collide_##SFX(int, int, const LaunchPlan &, int, void *);                     \
+    int launch_stream_##SFX(int, int, const LaunchPlan &, int, void *);                      \
+    int launch_rk_##SFX(int, int, const LaunchPlan &, int, void *);                          \
+    int launch_density_##SFX(int, int, const LaunchPlan &, int, void *);                     \
+    int launch_diag_##SFX(int, int, const LaunchPlan &, void *);                             \
+    int launch_fA_##SFX(int, int, const LaunchPlan &, void *);                               \
+    int launch_fB_##SFX(int, int, const LaunchPlan &, void *);                               \
+    int launch_fC_##SFX(int, int, const LaunchPlan &, int, void *);                          \
+    int launch_fD_##SFX(int, int, const LaunchPlan &, int, void *);
+SLBM_DECLARE_SET(2a)
+SLBM_DECLARE_SET(2b)
+SLBM_DECLARE_SET(3d)
 
-// weight class |e_q|^2 (0 rest, 1 axis, 2 diagonal): t_q = tw[class], t_q / cs^2 = twc[class]
-template <int Q>
-__device__ __forceinline__ constexpr int wcls(int q) {
-    return Lat<Q>::e[q][0] * Lat<Q>::e[q][0] + Lat<Q>::e[q][1] * Lat<Q>::e[q][1] +
-           Lat<Q>::e[q][2] * Lat<Q>::e[q][2];
+bool supported_order(int d, int N) {
+#define X(DD, NN) if (d == DD && N == NN) return true;
+    SLBM_ORDERS_2A(X)
+    SLBM_ORDERS_2B(X)
+    SLBM_ORDERS_3D(X)
+#undef X
+    return false;
 }
 
-// v . e_q summed in ascending component order from 0 (components of e are -1, 0, 1, so
-// the sum equals the plain dot product bit for bit)
-template <int Q, int D>
-__device__ __forceinline__ double dot_e(const double *v, int q) {
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-        const int ec = Lat<Q>::e[q][c];
-        if (ec == 1) s = s + v[c];
-        else if (ec == -1) s = s - v[c];
-    }
-    return s;
-}
+// (d, N) -> instance set
+#define SLBM_PICK(NAME, ...)                                                                 \
+    (d == 3 ? launch_##NAME##_3d(d, N, __VA_ARGS__)                                          \
+            : (N <= 7 ? launch_##NAME##_2a(d, N, __VA_ARGS__) : launch_##NAME##_2b(d, N, __VA_ARGS__)))
 
-// ------------------------------------------------------------------------------------------
-// element shapes
-// ------------------------------------------------------------------------------------------
-template <int D, int N, bool WIDE = true> struct Shape {
-    static constexpr int NP = N + 1;
-    static constexpr int NLOC = D == 2 ? NP * NP : NP * NP * NP;
-    static constexpr int EPB = WIDE && NLOC <= 256 ? 256 / NLOC : 1;
-    static constexpr int NB = EPB * NLOC;  // nodes of one block
-    static constexpr int NT = ((NB + 63) / 64) * 64;
-    static constexpr int NG = D * (D + 1) / 2;
-    // minimum waves per SIMD asked of the 3-D streaming kernels (caps their registers so
-    // that three 256-thread blocks share a compute unit)
-    static constexpr int WPE_STREAM = D == 3 ? 3 : 1;
-    static_assert(NT >= NP * NP, "one differentiation-matrix entry per thread");
-};
-
-template <int NP, int A> struct Stride { static constexpr int v = A == 0 ? 1 : (A == 1 ? NP : NP * NP); };
-
-// d/dxi_A at element node n of an LDS field s (element base): sum_m D[i][m] s[.. m ..]
-template <int NP, int A>
-__device__ __forceinline__ double dref(const double *__restrict__ sD, const double *__restrict__ s, int n) {
-    constexpr int st = Stride<NP, A>::v;
-    const int i = (n / st) % NP;
-    const double *row = sD + i * NP;
-    const double *line = s + (n - i * st);
-    double acc = 0.0;
-#pragma unroll
-    for (int m = 0; m < NP; ++m) acc = fma(row[m], line[m * st], acc);
-    return acc;
+int launch_lap(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(lap, p, stream); }
+int launch_mu(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(mu, p, stream); }
+int launch_grad(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(grad, p, stream); }
+int launch_gavg(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(gavg, p, stream); }
+int launch_collide(int d, int N, const LaunchPlan &p, int use_aux, void *stream) {
+    return SLBM_PICK(collide, p, use_aux, stream);
 }
+int launch_stream(int d, int N, const LaunchPlan &p, int stage, void *stream) {
+    return SLBM_PICK(stream, p, stage, stream);
+}
+int launch_rk(int d, int N, const LaunchPlan &p, int stage, void *stream) { return SLBM_PICK(rk, p, stage, stream); }
+int launch_density(int d, int N, const LaunchPlan &p, int which, void *stream) {
+    return SLBM_PICK(density, p, which, stream);
+}
+int launch_diag(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(diag, p, stream); }
+int launch_fA(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(fA, p, stream); }
+int launch_fB(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(fB, p, stream); }
+int launch_fC(int d, int N, const LaunchPlan &p, int stage, void *stream) { return SLBM_PICK(fC, p, stage, stream); }
+int launch_fD(int d, int N, const LaunchPlan &p, int stage, void *stream) { return SLBM_PICK(fD, p, stage, stream); }
 
-// transpose: sum_m D[m][i] v[.. m ..]
-template <int NP, int A>
-__device__ __forceinline__ double drefT(const double *__restrict__ sD, const double *__restrict__ v, int n) {
-    constexpr int st = Stride<NP, A>::v;
-    const int i = (n / st) % NP;
-    const double *line = v + (n - i * st);
-    double acc = 0.0;
-#pragma unroll
-    for (int m = 0; m < NP; ++m) acc = fma(sD[m * NP + i], line[m * st], acc);
-    return acc;
-}
-
-template <int D, int NP>
-__device__ __forceinline__ void grad_ref(const double *sD, const double *s, int n, double *out) {
-    out[0] = dref<NP, 0>(sD, s, n);
-    out[1] = dref<NP, 1>(sD, s, n);
-    if constexpr (D == 3) out[2] = dref<NP, 2>(sD, s, n);
-}
-
-template <int D, int NP>
-__device__ __forceinline__ double div_refT(const double *sD, const double *v, int stride_field, int n) {
-    double s = 0.0;
-    s += drefT<NP, 0>(sD, v, n);
-    s += drefT<NP, 1>(sD, v + stride_field, n);
-    if constexpr (D == 3) s += drefT<NP, 2>(sD, v + 2 * stride_field, n);
-    return s;
-}
-
-// The differentiation matrix is fetched into a register with the block's first loads and
-// written to LDS just before the first barrier, so its latency overlaps theirs.
-template <int NP>
-__device__ __forceinline__ double dm_fetch(const SolveDesc &sd, int tid) {
-    return sd.Dm[tid < NP * NP ? tid : 0];
-}
-template <int NP>
-__device__ __forceinline__ void dm_store(double *sD, int tid, double v) {
-    if (tid < NP * NP) sD[tid] = v;
-}
-
-// block -> (member descriptor, first element of the block)
-struct BlockSlot {
-    const SolveDesc SLBM_GLOBAL *sd;
-    int local;
-    bool valid;  // padding blocks of the XCD-aware grid do nothing
-};
-__device__ __forceinline__ BlockSlot block_slot(const LaunchPlan &p) {
-    BlockSlot b;
-    if (p.single) {
-        b.sd = p.desc;
-        const int per = (p.nblocks + kXcds - 1) / kXcds;
-        b.local = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-        b.valid = b.local < p.nblocks;
-    } else {
-        const int j = blockIdx.x < (unsigned)p.nblocks ? (int)blockIdx.x : 0;
-        b.local = p.blk_local[j];
-        b.valid = blockIdx.x < (unsigned)p.nblocks && b.local >= 0;
-        b.sd = p.desc + (b.valid ? p.blk_solve[j] : 0);
-    }
-    return b;
-}
-
-// The member's descriptor in registers, read before the kernel's first global store (a
-// store through a state pointer could otherwise alias the descriptor in memory and force
-// reloads).  A single solve passes it in the kernel arguments.
-__device__ __forceinline__ SolveDesc desc_of(const LaunchPlan &p, const BlockSlot &b) {
-    if (p.single) return p.one;
-    return *b.sd;
-}
-
-// ------------------------------------------------------------------------------------------
-// wall entries of a local node (at most d faces of its element): the first entry and the
-// count come from lwall; entries beyond the count repeat the last one so every slot can be
-// loaded without a branch (only nodes with walls load anything)
-// ------------------------------------------------------------------------------------------
-template <int D> struct WallLap {
-    int cnt;
-    double lap[D];  // s cos(theta) sqrt(2 beta / kappa) of each face through the node
-};
-template <int D>
-__device__ __forceinline__ void load_wall_lap(const SolveDesc &sd, int l, WallLap<D> &w) {
-    const int v = sd.lwall[l];
-    const int k0 = v >> 2;
-    w.cnt = v & 3;
-#pragma unroll
-    for (int j = 0; j < D; ++j) w.lap[j] = 0.0;
-    if (w.cnt > 0) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const int k = k0 + (j < w.cnt ? j : w.cnt - 1);
-            w.lap[j] = sd.w_dat[(size_t)k * (2 * D + 1) + 2 * D];
-        }
-    }
-}
-template <int D> struct WallFlux {
-    int cnt;
-    double sn[D][D];  // s n of each face through the node
-    double ub[D][D];  // wall velocity of that face
-};
-template <int D>
-__device__ __forceinline__ void load_wall_flux(const SolveDesc &sd, int l, WallFlux<D> &w) {
-    const int v = sd.lwall[l];
-    const int k0 = v >> 2;
-    w.cnt = v & 3;
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-#pragma unroll
-        for (int c = 0; c < D; ++c) w.sn[j][c] = w.ub[j][c] = 0.0;
-    if (w.cnt > 0) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const int k = k0 + (j < w.cnt ? j : w.cnt - 1);
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                w.sn[j][c] = sd.w_dat[(size_t)k * (2 * D + 1) + c];
-                w.ub[j][c] = sd.w_dat[(size_t)k * (2 * D + 1) + D + c];
-            }
-        }
-    }
-}
-
-// wetting term of Eq. (8) at a wall node: s n.grad(rho) = s cos(theta) sqrt(2 beta/kappa)
-// |(rho-rl)(rho-rv)| for every face through the node, in the caller's face order
-template <int D>
-__device__ __forceinline__ double wall_lap_term(const SolveDesc &sd, const WallLap<D> &w, double rh, double r) {
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-        if (j < w.cnt) r += w.lap[j] * fabs((rh - sd.rho_l) * (rh - sd.rho_v));
-    return r;
-}
-
-// ------------------------------------------------------------------------------------------
-// DSS through the CSR copy lists: the first two copies come from the node's NodeCopies
-// entry (one load); further copies, on nodes shared by more than two elements, through
-// csr_idx.  Ascending local order, from +0.0, as the oracle sums.
-// ------------------------------------------------------------------------------------------
-template <class P>
-__device__ __forceinline__ double dss_sum(P v, const NodeCopies &c, const int SLBM_GLOBAL *csr_idx) {
-    const double x0 = v[c.i0], x1 = v[c.i1];
-    double s = 0.0;
-    s += x0;
-    s += c.nc > 1 ? x1 : 0.0;
-    for (int k = 2; k < c.nc; ++k) s += v[csr_idx[c.k0 + k]];
-    return s;
-}
-
-// ------------------------------------------------------------------------------------------
-// Eq. (8): element part of the weak Laplacian, r = -sum_a D_a^T (G^{ab} D_b rho), plus the
-// wetting boundary integral s n.grad(rho) = s cos(theta) sqrt(2 beta/kappa) |(rho-rl)(rho-rv)|
-// ------------------------------------------------------------------------------------------
-template <int D, int NB, int NG>
-__device__ __forceinline__ void metric_times_grad(const double *g, const double *d, double *sv, int tid) {
-    // v_a = sum_b G_ab d_b (ascending b from 0)
-    if constexpr (D == 2) {
-        double v0 = 0.0, v1 = 0.0;
-        v0 += g[0] * d[0]; v0 += g[1] * d[1];
-        v1 += g[1] * d[0]; v1 += g[2] * d[1];
-        sv[tid] = v0; sv[NB + tid] = v1;
-    } else {
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        v0 += g[0] * d[0]; v0 += g[1] * d[1]; v0 += g[2] * d[2];
-        v1 += g[1] * d[0]; v1 += g[3] * d[1]; v1 += g[4] * d[2];
-        v2 += g[2] * d[0]; v2 += g[4] * d[1]; v2 += g[5] * d[2];
-        sv[tid] = v0; sv[NB + tid] = v1; sv[2 * NB + tid] = v2;
-    }
-}
-
-template <int D, int N, bool WIDE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    __shared__ double sD[NP * NP];
-    __shared__ double srho[NB];
-    __shared__ double sv[D * NB];
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int tid = threadIdx.x;
-    const double dmv = dm_fetch<NP>(sd, tid);
-    const int es = tid / NLOC, n = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    double rh = 0.0;
-    double g[S::NG];
-    WallLap<D> wl;
-    if (act) {
-        const int G = sd.lgid[l];
-#pragma unroll
-        for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * sd.Nl + l];
-        load_wall_lap<D>(sd, l, wl);
-        rh = sd.rho[G];
-        srho[tid] = rh;
-    }
-    dm_store<NP>(sD, tid, dmv);
-    __syncthreads();
-    if (act) {
-        double d[D];
-        grad_ref<D, NP>(sD, srho + es * NLOC, n, d);
-        metric_times_grad<D, NB, S::NG>(g, d, sv, tid);
-    }
-    __syncthreads();
-    if (!act) return;
-    const double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
-    sd.rl[l] = wall_lap_term<D>(sd, wl, rh, r);
-}
-
-// Eq. (2): mu = mu0(rho) - kappa lap, lap = DSS(r) / M (reading: mu0 = 2 beta (rho-rl)(rho-rv)(2rho-rl-rv))
-__device__ __forceinline__ double mu_of(const SolveDesc &sd, double pr, double lap) {
-    const double rl = sd.rho_l, rv = sd.rho_v;
-    const double mu0 = 2.0 * sd.beta * (pr - rl) * (pr - rv) * (2.0 * pr - rl - rv);
-    return mu0 - sd.kappa * lap;
-}
-
-template <int D, int N>
-__global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
-    if (G >= sd.Ng) return;
-    const NodeCopies c = sd.gcopy[G];
-    const double mi = sd.Minv[G], pr = sd.rho[G];
-    const double lap = dss_sum(sd.rl, c, sd.csr_idx) * mi;
-    sd.mu[G] = mu_of(sd, pr, lap);
-}
-
-// lumped-mass weighted element gradients w Ja^T grad_ref of rho and mu (for the collision)
-template <int D, int N, bool WIDE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_grad(LaunchPlan p) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    __shared__ double sD[NP * NP];
-    __shared__ double sf[2 * NB];
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int tid = threadIdx.x;
-    const double dmv = dm_fetch<NP>(sd, tid);
-    const int es = tid / NLOC, n = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    double J[D][D];
-    double w = 0.0;
-    if (act) {
-        const int G = sd.lgid[l];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
-        w = sd.wn[n];
-        sf[tid] = sd.rho[G];
-        sf[NB + tid] = sd.mu[G];
-    }
-    dm_store<NP>(sD, tid, dmv);
-    __syncthreads();
-    if (!act) return;
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-        double d[D];
-        grad_ref<D, NP>(sD, sf + f * NB + es * NLOC, n, d);
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) s += J[a][c] * d[a];
-            sd.gl[(size_t)(f * D + c) * sd.Nl + l] = w * s;
-        }
-    }
-}
-
-// averaged gradients DSS(gl) / M into aux [2d][Ng] (operator entry point)
-template <int D, int N>
-__global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
-    if (G >= sd.Ng) return;
-    const NodeCopies cp = sd.gcopy[G];
-    const double mi = sd.Minv[G];
-    double s[2 * D];
-#pragma unroll
-    for (int c = 0; c < 2 * D; ++c) s[c] = dss_sum(sd.gl + (size_t)c * sd.Nl, cp, sd.csr_idx);
-#pragma unroll
-    for (int c = 0; c < 2 * D; ++c) sd.aux[(size_t)c * sd.Ng + G] = s[c] * mi;
-}
-
-// Eq. (4) with (A.2), (A.6)-(A.7) and F** of Sec. 2.1 at one node:
-// f* = f - omega (f - (feq - dt/2 F**)) + dt F**, F = cs^2 grad(rho) - rho grad(mu)
-template <int Q, int D>
-__device__ __forceinline__ void collide_node(const SolveDesc &sd, const double *f, double pr,
-                                             const double *gr, const double *gm, double *fs) {
-    const double cs2 = 1.0 / 3.0, dt = sd.dt, om = sd.omega;
-    double u[D], F[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-        double m = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int ec = Lat<Q>::e[q][c];
-            if (ec == 1) m = m + f[q];
-            else if (ec == -1) m = m - f[q];
-        }
-        u[c] = m / pr;
-        F[c] = cs2 * gr[c] - pr * gm[c];
-    }
-    double uF = 0.0, uu = 0.0;
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-        uF += u[c] * F[c];
-        uu += u[c] * u[c];
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double eu = dot_e<Q, D>(u, q), eF = dot_e<Q, D>(F, q);
-        const double tq = sd.tw[wcls<Q>(q)], tc = sd.twc[wcls<Q>(q)];
-        const double Fss = tc * (eu * eF * 3.0 - uF);
-        const double feq = pr * tq * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        const double fbeq = feq - 0.5 * dt * Fss;
-        fs[q] = f[q] - om * (f[q] - fbeq) + dt * Fss;
-    }
-}
-
-template <int D, int N>
-__global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_aux) {
-    constexpr int Q = QOf<D>::Q;
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
-    if (G >= sd.Ng) return;
-    const size_t Ng = sd.Ng;
-    double gr[D], gm[D];
-    double f[Q];
-    if (use_aux) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            gr[c] = sd.aux[c * Ng + G];
-            gm[c] = sd.aux[(D + c) * Ng + G];
-        }
-    } else {
-        const NodeCopies cp = sd.gcopy[G];
-        const double mi = sd.Minv[G];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            gr[c] = dss_sum(sd.gl + (size_t)c * sd.Nl, cp, sd.csr_idx) * mi;
-            gm[c] = dss_sum(sd.gl + (size_t)(D + c) * sd.Nl, cp, sd.csr_idx) * mi;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
-    const double pr = sd.rho[G];
-    double fs[Q];
-    collide_node<Q, D>(sd, f, pr, gr, gm, fs);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) sd.g0[q * Ng + G] = fs[q];
-}
-
-// ------------------------------------------------------------------------------------------
-// Eqs. (5)-(6), (12), (9): element residual of the force-split weak streaming,
-//   r_a = -w [ (Ja e_a) . D(g_a - t_a rho) + (t_a/cs^2) rho (Ja e_a) . D mu ]
-// plus, on wall faces with (s n).e_a < 0, (s n . e_a) [g_a - g_opp - 2 (t_a/cs^2) rho e_a.u_b]
-// ------------------------------------------------------------------------------------------
-// per-node metric and wall data of the streaming, loaded with the block's first loads
-template <int D> struct NodeGeo {
-    double J[D][D];
-    double w;
-    WallFlux<D> wf;
-};
-template <int D>
-__device__ __forceinline__ void load_geo(const SolveDesc &sd, int n, int l, NodeGeo<D> &g) {
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) g.J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
-    g.w = sd.wn[n];
-    load_wall_flux<D>(sd, l, g.wf);
-}
-
-// residual at node n from LDS h_q = g_q - t_q rho (fields of stride NB, element base es),
-// LDS mu, register g (for the flux); the loop reads only LDS and registers, so its stores
-// delay no load
-template <int D, int N, bool WIDE>
-__device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
-                                                const double *smu_e, int es, int n, int l,
-                                                double pr, const double *gq, const NodeGeo<D> &geo) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    double dmu[D];
-    grad_ref<D, NP>(sD, smu_e, n, dmu);
-    const double w = geo.w;
-#pragma unroll
-    for (int q = 1; q < Q; ++q) {
-        double dh[D];
-        grad_ref<D, NP>(sD, sh + (q - 1) * NB + es * NLOC, n, dh);
-        double adv = 0.0, frc = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const double ca = dot_e<Q, D>(geo.J[a], q);
-            adv += ca * dh[a];
-            frc += ca * dmu[a];
-        }
-        const double tc = sd.twc[wcls<Q>(q)];
-        double r = -(w * (adv + tc * pr * frc));
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j < geo.wf.cnt) {
-                const double cn = dot_e<Q, D>(geo.wf.sn[j], q);
-                if (cn < 0.0) {
-                    const double eub = dot_e<Q, D>(geo.wf.ub[j], q);
-                    const double bc = gq[q] - gq[Lat<Q>::opp[q]] - 2.0 * tc * pr * eub;
-                    r += cn * bc;
-                }
-            }
-        }
-        sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
-    }
-}
-
-// stage 1 streams g0, stages 2-3 stream g1
-template <int D, int N, bool WIDE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT), (Shape<D, N, WIDE>::WPE_STREAM)) void k_stream(LaunchPlan p, int stage) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    __shared__ double sD[NP * NP];
-    __shared__ double smu[NB];
-    __shared__ double sh[(Q - 1) * NB];
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const double SLBM_GLOBAL *g = stage == 1 ? sd.g0 : sd.g1;
-    const int tid = threadIdx.x;
-    const double dmv = dm_fetch<NP>(sd, tid);
-    const int es = tid / NLOC, n = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    const size_t Ng = sd.Ng;
-    double pr = 0.0;
-    double gq[Q];
-    NodeGeo<D> geo;
-    if (act) {
-        const int G = sd.lgid[l];
-        load_geo<D>(sd, n, l, geo);
-        pr = sd.rho[G];
-        smu[tid] = sd.mu[G];
-#pragma unroll
-        for (int q = 1; q < Q; ++q) gq[q] = g[q * Ng + G];
-#pragma unroll
-        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = gq[q] - sd.tw[wcls<Q>(q)] * pr;
-    }
-    dm_store<NP>(sD, tid, dmv);
-    __syncthreads();
-    if (!act) return;
-    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
-}
-
-// SSP-RK3 stage combination after DSS(r)/M, and the new stage's density (Eq. (10))
-//   stage 0 (operator entry point only): g1 = L(g1)
-//   stage 1: g1 = g0 + dt L(g0); stage 2: g1 = 3/4 g0 + 1/4 (g1 + dt L(g1));
-//   stage 3: f = (g0 + 2 (g1 + dt L(g1))) / 3
-template <int Q>
-__device__ __forceinline__ double rk_combine(int stage, double L, double gin, double g0, double dt) {
-    const double x = gin + dt * L;
-    if (stage == 0) return L;  // operator entry point: the assembled right-hand side
-    if (stage == 1) return x;
-    if (stage == 2) return 0.75 * g0 + 0.25 * x;
-    return (g0 + 2.0 * x) / 3.0;
-}
-
-template <int D, int N>
-__global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
-    constexpr int Q = QOf<D>::Q;
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
-    if (G >= sd.Ng) return;
-    const size_t Ng = sd.Ng, Nl = sd.Nl;
-    const double SLBM_GLOBAL *gin = stage == 1 ? sd.g0 : sd.g1;
-    double SLBM_GLOBAL *gout = stage == 3 ? sd.f : sd.g1;
-    const NodeCopies cp = sd.gcopy[G];
-    const double mi = sd.Minv[G], dt = sd.dt;
-    // every load is issued before the first store: residuals of the first two copies,
-    // the stage input and g0
-    double x0[Q], x1[Q], gi[Q], g0v[Q];
-#pragma unroll
-    for (int q = 1; q < Q; ++q) {
-        x0[q] = sd.rs[(size_t)(q - 1) * Nl + cp.i0];
-        x1[q] = sd.rs[(size_t)(q - 1) * Nl + cp.i1];
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) gi[q] = gin[q * Ng + G];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) g0v[q] = 0.0;
-    if (stage >= 2) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) g0v[q] = sd.g0[q * Ng + G];
-    }
-    double R[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) R[q] = 0.0;
-#pragma unroll
-    for (int q = 1; q < Q; ++q) {
-        R[q] += x0[q];
-        R[q] += cp.nc > 1 ? x1[q] : 0.0;
-    }
-    // copies beyond the second (edges and corners): copies outer, populations inner
-    for (int k = 2; k < cp.nc; ++k) {
-        const int li = sd.csr_idx[cp.k0 + k];
-        double x[Q];
-#pragma unroll
-        for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + li];
-#pragma unroll
-        for (int q = 1; q < Q; ++q) R[q] += x[q];
-    }
-    double rho = 0.0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double L = q > 0 ? R[q] * mi : 0.0;
-        const double out = rk_combine<Q>(stage, L, gi[q], g0v[q], dt);
-        gout[q * Ng + G] = out;
-        rho += out;
-    }
-    sd.rho[G] = rho;
-}
-
-// rho = sum_a f_a (Eq. (10)) of the state (which = 0) or of g1 (which = 1)
-template <int D, int N>
-__global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int which) {
-    constexpr int Q = QOf<D>::Q;
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
-    if (G >= sd.Ng) return;
-    const double SLBM_GLOBAL *src = which == 0 ? sd.f : sd.g1;
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) s += src[(size_t)q * sd.Ng + G];
-    sd.rho[G] = s;
-}
-
-// KE_max = max 1/2 rho |u|^2 and mass = sum M rho; per-block partials in red[]
-template <int D, int N>
-__global__ __launch_bounds__(kNodeThreads) void k_diag(LaunchPlan p) {
-    constexpr int Q = QOf<D>::Q;
-    __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int tid = threadIdx.x;
-    const int G = bs.local * kNodeThreads + tid;
-    double ke = 0.0, ms = 0.0;
-    if (G < sd.Ng) {
-        const size_t Ng = sd.Ng;
-        double f[Q];
-        double pr = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            f[q] = sd.f[q * Ng + G];
-            pr += f[q];
-        }
-        double uu = 0.0;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            double m = 0.0;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int ec = Lat<Q>::e[q][c];
-                if (ec == 1) m = m + f[q];
-                else if (ec == -1) m = m - f[q];
-            }
-            const double u = m / pr;
-            uu += u * u;
-        }
-        ke = 0.5 * pr * uu;
-        ms = (1.0 / sd.Minv[G]) * pr;
-    }
-    smax[tid] = ke;
-    ssum[tid] = ms;
-    __syncthreads();
-    for (int s = kNodeThreads / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            const double a = smax[tid], b = smax[tid + s];
-            smax[tid] = (a >= b || a != a) ? a : b;  // NaN propagates
-            ssum[tid] += ssum[tid + s];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        sd.red[2 * bs.local] = smax[0];
-        sd.red[2 * bs.local + 1] = ssum[0];
-    }
-}
-
+// second pass of the KE / mass reduction: one block per member
 __global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *desc) {
     __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
     const SolveDesc &sd = desc[blockIdx.x];
@@ -728,435 +85,6 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *de
     }
 }
 
-// ------------------------------------------------------------------------------------------
-// Fused path.  Each element kernel finishes the previous pass's direct stiffness summation
-// itself: every thread gathers the per-copy partial sums of all local copies of its node
-// (ascending local order, the same sum as the node kernels) and applies the pointwise
-// update; the lowest local copy ("owner") stores the node's global value.  Shared nodes
-// are thus updated redundantly and identically by each element that holds them, which
-// halves the number of grid-wide dependencies of a step (7 kernels instead of 14).
-// ------------------------------------------------------------------------------------------
-
-// Copy list of local node l in registers (K slots: 4 in 2-D, 8 in 3-D), ascending; slots
-// beyond the node's copies repeat the first copy.  Two gather forms, both with all loads of
-// a gather in flight together and both summing in ascending order:
-//   * PRED (wide blocks, bandwidth bound): element-interior nodes skip their copy list and
-//     slot k is loaded only in lanes with more than k copies (predicated loads);
-//   * branch-free (one element per block, latency bound): every slot is loaded and the
-//     unused ones are masked out of the sum, adding +0.0 after the real terms (the sum
-//     starts from +0.0 and never becomes -0.0, so the result is the same).
-template <int D> struct CopyList {
-    static constexpr int K = kCopySlots[D - 2];
-    int cp[K];
-    int nc;
-};
-// element node n (i fastest) on the element's boundary?  Nodes inside an element belong to
-// it alone (the fused path is selected only for meshes where that holds).
-template <int D, int NP>
-__device__ __forceinline__ bool on_elem_boundary(int n) {
-    const int i = n % NP, j = (n / NP) % NP;
-    bool b = i == 0 || i == NP - 1 || j == 0 || j == NP - 1;
-    if constexpr (D == 3) {
-        const int k = n / (NP * NP);
-        b = b || k == 0 || k == NP - 1;
-    }
-    return b;
-}
-
-template <int D, int NP, bool PRED>
-__device__ __forceinline__ void load_copies(const SolveDesc &sd, int n, int l, CopyList<D> &c) {
-    c.cp[0] = l;
-    c.nc = 1;
-#pragma unroll
-    for (int k = 1; k < CopyList<D>::K; ++k) c.cp[k] = l;
-    if (!PRED || on_elem_boundary<D, NP>(n)) {
-        // all K rows of the table exist (-1 padded): the slot loads go out together
-        int v[CopyList<D>::K];
-#pragma unroll
-        for (int k = 0; k < CopyList<D>::K; ++k) v[k] = sd.lcp[(size_t)k * sd.Nl + l];
-        c.nc = 1;
-#pragma unroll
-        for (int k = 1; k < CopyList<D>::K; ++k) c.nc += v[k] >= 0 ? 1 : 0;
-        c.cp[0] = v[0];
-#pragma unroll
-        for (int k = 1; k < CopyList<D>::K; ++k) c.cp[k] = v[k] >= 0 ? v[k] : v[0];
-    }
-}
-
-template <int D, bool PRED, class P>
-__device__ __forceinline__ double gather1(P v, const CopyList<D> &c) {
-    double x[CopyList<D>::K];
-    double s = 0.0;
-    if constexpr (PRED) {
-        x[0] = v[c.cp[0]];
-#pragma unroll
-        for (int k = 1; k < CopyList<D>::K; ++k) {
-            x[k] = 0.0;
-            if (k < c.nc) x[k] = v[c.cp[k]];
-        }
-        s += x[0];
-#pragma unroll
-        for (int k = 1; k < CopyList<D>::K; ++k)
-            if (k < c.nc) s += x[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < CopyList<D>::K; ++k) x[k] = v[c.cp[k]];
-        s += x[0];  // every node has its first copy
-#pragma unroll
-        for (int k = 1; k < CopyList<D>::K; ++k) s += k < c.nc ? x[k] : 0.0;
-    }
-    return s;
-}
-
-// A: mu of the state's density (DSS of the Laplacian partials) and the lumped-mass
-// weighted element gradients of rho and mu for the collision
-template <int D, int N, bool WIDE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    __shared__ double sD[NP * NP];
-    __shared__ double sf[2 * NB];
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int tid = threadIdx.x;
-    const double dmv = dm_fetch<NP>(sd, tid);
-    const int es = tid / NLOC, n = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    double J[D][D];
-    double w = 0.0;
-    if (act) {
-        CopyList<D> cl;
-        load_copies<D, NP, WIDE>(sd, n, l, cl);
-        const int G = sd.lgid[l];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
-        w = sd.wn[n];
-        const double pr = sd.rho[G];
-        const double mu = mu_of(sd, pr, gather1<D, WIDE>(sd.rl, cl) * sd.Minv[G]);
-        if (cl.cp[0] == l) sd.mu[G] = mu;
-        sf[tid] = pr;
-        sf[NB + tid] = mu;
-    }
-    dm_store<NP>(sD, tid, dmv);
-    __syncthreads();
-    if (!act) return;
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-        double d[D];
-        grad_ref<D, NP>(sD, sf + f * NB + es * NLOC, n, d);
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) s += J[a][c] * d[a];
-            sd.gl[(size_t)(f * D + c) * sd.Nl + l] = w * s;
-        }
-    }
-}
-
-// B: averaged gradients (DSS), collision (Eq. (4)) at every element node, owners store f*
-// in g0, then the stage-1 streaming residual of f*
-template <int D, int N, bool WIDE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    __shared__ double sD[NP * NP];
-    __shared__ double smu[NB];
-    __shared__ double sh[(Q - 1) * NB];
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int tid = threadIdx.x;
-    const double dmv = dm_fetch<NP>(sd, tid);
-    const int es = tid / NLOC, n = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    const size_t Ng = sd.Ng;
-    double fs[Q];
-    double pr = 0.0;
-    NodeGeo<D> geo;
-    if (act) {
-        CopyList<D> cl;
-        load_copies<D, NP, WIDE>(sd, n, l, cl);
-        const int G = sd.lgid[l];
-        load_geo<D>(sd, n, l, geo);
-        const double mi = sd.Minv[G];
-        double gr[D], gm[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            gr[c] = gather1<D, WIDE>(sd.gl + (size_t)c * sd.Nl, cl) * mi;
-            gm[c] = gather1<D, WIDE>(sd.gl + (size_t)(D + c) * sd.Nl, cl) * mi;
-        }
-        double f[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
-        pr = sd.rho[G];
-        const double mu = sd.mu[G];
-        collide_node<Q, D>(sd, f, pr, gr, gm, fs);
-        if (cl.cp[0] == l) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) sd.g0[q * Ng + G] = fs[q];
-        }
-        smu[tid] = mu;
-#pragma unroll
-        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = fs[q] - sd.tw[wcls<Q>(q)] * pr;
-    }
-    dm_store<NP>(sD, tid, dmv);
-    __syncthreads();
-    if (!act) return;
-    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, fs, geo);
-}
-
-// C: DSS of the streaming residual, SSP-RK3 combination and the stage density at every
-// element node (owners store them), then the Laplacian partials of the new density
-//   stage 1: g1 = g0 + dt L;  stage 2: g2 = 3/4 g0 + 1/4 (g1 + dt L);
-//   stage 3: f = (g0 + 2 (g2 + dt L)) / 3
-template <int D, int N, bool WIDE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, int stage) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    constexpr int K = CopyList<D>::K;
-    __shared__ double sD[NP * NP];
-    __shared__ double srho[NB];
-    __shared__ double sv[D * NB];
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int tid = threadIdx.x;
-    const double dmv = dm_fetch<NP>(sd, tid);
-    const int es = tid / NLOC, n = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    const size_t Ng = sd.Ng, Nl = sd.Nl;
-    const double SLBM_GLOBAL *gin = stage == 1 ? sd.g0 : (stage == 2 ? sd.g1 : sd.g2);
-    double SLBM_GLOBAL *gout = stage == 1 ? sd.g1 : (stage == 2 ? sd.g2 : sd.f);
-    double rho = 0.0;
-    double gm[S::NG];
-    WallLap<D> wl;
-    if (act) {
-        CopyList<D> cl;
-        load_copies<D, NP, WIDE>(sd, n, l, cl);
-        const int G = sd.lgid[l];
-#pragma unroll
-        for (int k = 0; k < S::NG; ++k) gm[k] = sd.G[(size_t)k * Nl + l];
-        load_wall_lap<D>(sd, l, wl);
-        // every load before the first store: residual partials of all copies, the stage
-        // input and g0
-        // (3-D: the first two slots; copies of edge and corner nodes beyond them in a loop,
-        // which keeps the register footprint of 8 slots x 18 populations away)
-        constexpr int KU = D == 2 ? K : 2;
-        double R[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) R[q] = 0.0;
-        double x[KU][Q];
-#pragma unroll
-        for (int k = 0; k < KU; ++k) {
-#pragma unroll
-            for (int q = 1; q < Q; ++q) x[k][q] = 0.0;
-            if (!WIDE || k == 0 || k < cl.nc) {
-#pragma unroll
-                for (int q = 1; q < Q; ++q) x[k][q] = sd.rs[(size_t)(q - 1) * Nl + cl.cp[k]];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < KU; ++k) {
-            const bool valid = k < cl.nc;
-            if (WIDE || k == 0) {
-                if (k == 0 || valid) {
-#pragma unroll
-                    for (int q = 1; q < Q; ++q) R[q] += x[k][q];
-                }
-            } else {
-#pragma unroll
-                for (int q = 1; q < Q; ++q) R[q] += valid ? x[k][q] : 0.0;
-            }
-        }
-        if constexpr (KU < K) {
-            for (int k = KU; k < cl.nc; ++k) {
-                double x[Q];
-                const int c = k == 2 ? cl.cp[2] : (k == 3 ? cl.cp[3] : (k == 4 ? cl.cp[4] :
-                              (k == 5 ? cl.cp[5] : (k == 6 ? cl.cp[6] : cl.cp[7]))));
-#pragma unroll
-                for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + c];
-#pragma unroll
-                for (int q = 1; q < Q; ++q) R[q] += x[q];
-            }
-        }
-        double gi[Q], g0v[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) gi[q] = gin[q * Ng + G];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) g0v[q] = 0.0;
-        if (stage != 1) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) g0v[q] = sd.g0[q * Ng + G];
-        }
-        const double mi = sd.Minv[G], dt = sd.dt;
-        const bool owner = cl.cp[0] == l;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const double L = q > 0 ? R[q] * mi : 0.0;
-            const double out = rk_combine<Q>(stage, L, gi[q], g0v[q], dt);
-            rho += out;
-            if (owner) gout[q * Ng + G] = out;
-        }
-        if (owner) sd.rho[G] = rho;
-        srho[tid] = rho;
-    }
-    dm_store<NP>(sD, tid, dmv);
-    __syncthreads();
-    if (act) {
-        double d[D];
-        grad_ref<D, NP>(sD, srho + es * NLOC, n, d);
-        metric_times_grad<D, NB, S::NG>(gm, d, sv, tid);
-    }
-    __syncthreads();
-    if (!act) return;
-    const double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
-    sd.rl[l] = wall_lap_term<D>(sd, wl, rho, r);
-}
-
-// D: mu of the stage density (DSS of the Laplacian partials) and the streaming residual of
-// stage 2 (g1) or 3 (g2)
-template <int D, int N, bool WIDE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, int stage) {
-    using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    __shared__ double sD[NP * NP];
-    __shared__ double smu[NB];
-    __shared__ double sh[(Q - 1) * NB];
-    const BlockSlot bs = block_slot(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of(p, bs);
-    const int tid = threadIdx.x;
-    const double dmv = dm_fetch<NP>(sd, tid);
-    const int es = tid / NLOC, n = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    const size_t Ng = sd.Ng;
-    const double SLBM_GLOBAL *g = stage == 2 ? sd.g1 : sd.g2;
-    double gq[Q];
-    double pr = 0.0;
-    NodeGeo<D> geo;
-    if (act) {
-        CopyList<D> cl;
-        load_copies<D, NP, WIDE>(sd, n, l, cl);
-        const int G = sd.lgid[l];
-        load_geo<D>(sd, n, l, geo);
-        pr = sd.rho[G];
-        smu[tid] = mu_of(sd, pr, gather1<D, WIDE>(sd.rl, cl) * sd.Minv[G]);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) gq[q] = g[q * Ng + G];
-#pragma unroll
-        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = gq[q] - sd.tw[wcls<Q>(q)] * pr;
-    }
-    dm_store<NP>(sD, tid, dmv);
-    __syncthreads();
-    if (!act) return;
-    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
-}
-
-// ------------------------------------------------------------------------------------------
-// launchers: dispatch (d, N) to template instances
-// ------------------------------------------------------------------------------------------
-#define SLBM_FOR_ORDERS(X)                                                                     \
-    X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(2, 7) X(2, 8) X(2, 9) X(2, 10) X(2, 11) X(2, 12) \
-    X(2, 14) X(2, 16) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6)
-
-bool supported_order(int d, int N) {
-#define X(DD, NN) if (d == DD && N == NN) return true;
-    SLBM_FOR_ORDERS(X)
-#undef X
-    return false;
-}
-
-#define SLBM_DISPATCH(KERNEL, THREADS, ...)                                                  \
-    do {                                                                                     \
-        if (p.nblocks <= 0 || p.grid <= 0) return 0;                                         \
-        hipStream_t st = (hipStream_t)stream;                                                \
-        bool done = false;                                                                   \
-        SLBM_FOR_ORDERS(SLBM_CASE_##KERNEL)                                                  \
-        if (!done) return (int)hipErrorInvalidValue;                                         \
-        return (int)hipGetLastError();                                                       \
-    } while (0)
-
-#define SLBM_ELEM_CASE(KERNEL, DD, NN, ...)                                                  \
-    if (!done && d == DD && N == NN) {                                                       \
-        if (p.epb == Shape<DD, NN, true>::EPB)                                               \
-            KERNEL<DD, NN, true><<<p.grid, Shape<DD, NN, true>::NT, 0, st>>>(p, ##__VA_ARGS__); \
-        else                                                                                 \
-            KERNEL<DD, NN, false><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p, ##__VA_ARGS__); \
-        done = true;                                                                         \
-    }
-#define SLBM_NODE_CASE(KERNEL, DD, NN, ...)                                                  \
-    if (!done && d == DD && N == NN) {                                                       \
-        KERNEL<DD, NN><<<p.grid, kNodeThreads, 0, st>>>(p, ##__VA_ARGS__);                   \
-        done = true;                                                                         \
-    }
-
-int launch_lap(int d, int N, const LaunchPlan &p, void *stream) {
-#define SLBM_CASE_lap(DD, NN) SLBM_ELEM_CASE(k_lap, DD, NN)
-    SLBM_DISPATCH(lap, 0);
-}
-int launch_mu(int d, int N, const LaunchPlan &p, void *stream) {
-#define SLBM_CASE_mu(DD, NN) SLBM_NODE_CASE(k_mu, DD, NN)
-    SLBM_DISPATCH(mu, 0);
-}
-int launch_grad(int d, int N, const LaunchPlan &p, void *stream) {
-#define SLBM_CASE_grad(DD, NN) SLBM_ELEM_CASE(k_grad, DD, NN)
-    SLBM_DISPATCH(grad, 0);
-}
-int launch_gavg(int d, int N, const LaunchPlan &p, void *stream) {
-#define SLBM_CASE_gavg(DD, NN) SLBM_NODE_CASE(k_gavg, DD, NN)
-    SLBM_DISPATCH(gavg, 0);
-}
-int launch_collide(int d, int N, const LaunchPlan &p, int use_aux, void *stream) {
-#define SLBM_CASE_collide(DD, NN) SLBM_NODE_CASE(k_collide, DD, NN, use_aux)
-    SLBM_DISPATCH(collide, 0);
-}
-int launch_stream(int d, int N, const LaunchPlan &p, int stage, void *stream) {
-#define SLBM_CASE_stream(DD, NN) SLBM_ELEM_CASE(k_stream, DD, NN, stage)
-    SLBM_DISPATCH(stream, 0);
-}
-int launch_rk(int d, int N, const LaunchPlan &p, int stage, void *stream) {
-#define SLBM_CASE_rk(DD, NN) SLBM_NODE_CASE(k_rk, DD, NN, stage)
-    SLBM_DISPATCH(rk, 0);
-}
-int launch_density(int d, int N, const LaunchPlan &p, int which, void *stream) {
-#define SLBM_CASE_density(DD, NN) SLBM_NODE_CASE(k_density, DD, NN, which)
-    SLBM_DISPATCH(density, 0);
-}
-int launch_diag(int d, int N, const LaunchPlan &p, void *stream) {
-#define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)
-    SLBM_DISPATCH(diag, 0);
-}
-int launch_fA(int d, int N, const LaunchPlan &p, void *stream) {
-#define SLBM_CASE_fA(DD, NN) SLBM_ELEM_CASE(k_fA, DD, NN)
-    SLBM_DISPATCH(fA, 0);
-}
-int launch_fB(int d, int N, const LaunchPlan &p, void *stream) {
-#define SLBM_CASE_fB(DD, NN) SLBM_ELEM_CASE(k_fB, DD, NN)
-    SLBM_DISPATCH(fB, 0);
-}
-int launch_fC(int d, int N, const LaunchPlan &p, int stage, void *stream) {
-#define SLBM_CASE_fC(DD, NN) SLBM_ELEM_CASE(k_fC, DD, NN, stage)
-    SLBM_DISPATCH(fC, 0);
-}
-int launch_fD(int d, int N, const LaunchPlan &p, int stage, void *stream) {
-#define SLBM_CASE_fD(DD, NN) SLBM_ELEM_CASE(k_fD, DD, NN, stage)
-    SLBM_DISPATCH(fD, 0);
-}
 int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream) {
     if (nsolves <= 0) return 0;
     k_diag_final<<<nsolves, kNodeThreads, 0, (hipStream_t)stream>>>(desc);

@@ -558,7 +558,7 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     c->eplan.single = 1;
     c->eplan.one = d;
     c->eplan.epb = c->epb;
-    c->eplan.grid = xcd_grid(c->n_eblocks);
+    c->eplan.grid = c->n_eblocks;
     c->nplan.desc = at<SolveDesc>(b, c->off.desc);
     c->nplan.blk_solve = at<int>(b, c->off.nplan);
     c->nplan.blk_local = at<int>(b, c->off.nplan) + c->n_nblocks;
@@ -566,7 +566,7 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
     c->nplan.single = 1;
     c->nplan.one = d;
     c->nplan.epb = 0;
-    c->nplan.grid = xcd_grid(c->n_nblocks);
+    c->nplan.grid = c->n_nblocks;
     const int dim = c->dim;
     const size_t ng = (size_t)dim * (dim + 1) / 2;
     int e = 0;
