@@ -39,8 +39,9 @@ def algorithmic_bytes(kind: str, Q: int, d: int, Ng: int, Nl: int) -> float:
         "collide": Q * Ng + Ng + 2 * d * Ng + Ng + Q * Ng,
         # reads Q-1 populations, rho, mu, metric Ja; writes Q-1 residuals
         "stream": (Q - 1) * Ng + 2 * Ng + d * d * Nl + (Q - 1) * Ng,
-        # reads Q-1 residuals, g (Q), g0 (Q), 1/M; writes Q populations and rho
-        "rk": (Q - 1) * Ng + Q * Ng + Q * Ng + Ng + Q * Ng + Ng,
+        # reads Q-1 residuals, g (Q), g0 (2Q/3 on average over the three stages: stage 1's
+        # input is g0 itself), 1/M; writes Q populations and rho
+        "rk": (Q - 1) * Ng + Q * Ng + (2 * Q) / 3.0 * Ng + Ng + Q * Ng + Ng,
         # fused path: each kernel finishes the previous pass's summation itself
         # A: Laplacian sum, rho, 1/M -> mu; metric Ja -> 2d gradient sums
         "f_mu_grad": 4 * Ng + d * d * Nl + 2 * d * Ng,
