@@ -81,12 +81,13 @@ slbm_status slbm_create(const slbm_params *p, slbm_ctx **out);
  *                              (copies across a periodic wrap differ by the period)
  *   gid       [E][(N+1)^d]     caller's global id of every element node; ids shared by
  *                              several elements are summed by direct stiffness summation
- *   wall_face [F][2]           (element, face) of every physical wall face
+ *   wall_face [F][2]           (element, face) of every physical wall face, each at most once
  *   wall_cos  [F]              cos(theta_eq) imposed on the face (Eq. (7), Sec. 2.2)
  *   wall_ub   [F][d] or NULL   wall velocity u_b of Eq. (9) (NULL: resting walls)
  * The library copies everything and derives the metric terms (curl form in 3-D), the
  * lumped mass, wall normals and weights, and the time step.  Errors: SLBM_EINVAL for bad
- * sizes/ids or a non-positive Jacobian, SLBM_ESTATE if already bound. */
+ * sizes/ids, a wall face listed twice or a non-positive Jacobian, SLBM_ESTATE if already
+ * bound. */
 slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, const int32_t *gid,
                           int64_t n_global, int64_t n_wall_faces, const int32_t *wall_face,
                           const double *wall_cos, const double *wall_ub);

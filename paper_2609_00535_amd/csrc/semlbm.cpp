@@ -394,11 +394,24 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
     const double sq = std::sqrt(2.0 * c->beta / c->kappa);
     struct WE { int64_t l; double sn[3]; double ub[3]; double lap; };
     std::vector<WE> ents;
+    {
+        std::vector<int64_t> keys((size_t)n_wall_faces);
+        for (int64_t fidx = 0; fidx < n_wall_faces; ++fidx) {
+            const int64_t e = wall_face[2 * fidx];
+            const int face = wall_face[2 * fidx + 1];
+            if (e < 0 || e >= E || face < 0 || face >= 2 * dim)
+                return c->fail(SLBM_EINVAL, "wall face %lld: bad element or face", (long long)fidx);
+            keys[fidx] = e * 8 + face;
+        }
+        std::sort(keys.begin(), keys.end());
+        for (size_t k = 1; k < keys.size(); ++k)
+            if (keys[k] == keys[k - 1])
+                return c->fail(SLBM_EINVAL, "wall face (element %lld, face %d) listed twice (duplicate)",
+                               (long long)(keys[k] / 8), (int)(keys[k] % 8));
+    }
     for (int64_t fidx = 0; fidx < n_wall_faces; ++fidx) {
         const int64_t e = wall_face[2 * fidx];
         const int face = wall_face[2 * fidx + 1];
-        if (e < 0 || e >= E || face < 0 || face >= 2 * dim)
-            return c->fail(SLBM_EINVAL, "wall face %lld: bad element or face", (long long)fidx);
         const int a = face / 2, side = face % 2;
         const double sign = side ? 1.0 : -1.0;
         double ub[3] = {0.0, 0.0, 0.0};
@@ -435,9 +448,9 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
     for (int64_t k = 0; k < c->nw; ++k) {
         const int64_t l = ents[k].l;
         const int cnt = (c->lwall[l] & 3) + 1;
-        if (cnt > dim)
-            return c->fail(SLBM_EINVAL, "element %lld: a node lies on more than %d listed wall faces "
-                           "(duplicate face?)", (long long)(l / nloc), dim);
+        if (cnt > dim)  // cannot happen for distinct faces of one element
+            return c->fail(SLBM_EINVAL, "element %lld: a node lies on more than %d listed wall faces",
+                           (long long)(l / nloc), dim);
         c->lwall[l] = cnt == 1 ? (int32_t)((k << 2) | 1) : (c->lwall[l] & ~3) | cnt;
         for (int cc = 0; cc < dim; ++cc) {
             c->w_dat[(size_t)k * W + cc] = ents[k].sn[cc];

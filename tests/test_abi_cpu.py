@@ -141,3 +141,28 @@ def test_mesh_generators_structure():
     on = m.xyz[wall_e][:, ::Np, :]  # i = 0 nodes of cylinder elements
     assert np.abs(np.hypot(on[..., 0] - 128, on[..., 1] - 128) - 40.0).max() < 1e-12
     assert r.min() > 40.0 - 1e-12
+
+
+def test_time_kernel_and_wall_face_errors(L):
+    """Tracing entry point: argument and call-order errors (no GPU needed); a wall face
+    listed twice is rejected at set_mesh."""
+    import paper_2609_00535_amd as P
+    c = cases.small_flat()
+    h = _create(L, c)
+    ms = C.c_double(0.0)
+    assert L.slbm_time_kernel(h, 99, 10, C.byref(ms)) == P.binding.SLBM_EINVAL
+    assert L.slbm_time_kernel(h, 6, 0, C.byref(ms)) == P.binding.SLBM_EINVAL
+    assert L.slbm_time_kernel(h, 6, 10, None) == P.binding.SLBM_EINVAL
+    assert L.slbm_time_kernel(h, 6, 10, C.byref(ms)) == P.binding.SLBM_ESTATE
+    L.slbm_destroy(h)
+    m = c.mesh
+    h = _create(L, c)
+    wf = np.ascontiguousarray(np.concatenate([m.wall_face, m.wall_face[:1]]), dtype=np.int32)
+    wc = np.ascontiguousarray(np.concatenate([m.wall_cos, m.wall_cos[:1]]))
+    wu = np.ascontiguousarray(np.concatenate([m.wall_ub, m.wall_ub[:1]]))
+    xyz = np.ascontiguousarray(m.xyz)
+    gid = np.ascontiguousarray(m.gid, dtype=np.int32)
+    st = L.slbm_set_mesh(h, m.E, xyz.ctypes.data, gid.ctypes.data, m.n_global, wf.shape[0],
+                         wf.ctypes.data, wc.ctypes.data, wu.ctypes.data)
+    assert st == P.binding.SLBM_EINVAL and b"duplicate" in L.slbm_last_error(h)
+    L.slbm_destroy(h)

@@ -289,3 +289,34 @@ def test_unfused_path_matches(P, monkeypatch):
     assert "f_rk_lap" in f.step_profile(1)
     s.step(1)
     assert np.array_equal(f.get_state()[0], s.get_state()[0])
+
+
+def test_batch_mixed_paths_and_wide_blocks(P, monkeypatch):
+    """A batch whose members step on different kernel paths (fused / unfused, chosen at
+    set_mesh) and a group large enough for wide blocks: every member evolves exactly as
+    alone."""
+    import torch
+    stream = torch.cuda.current_stream()
+    b = P.Batch(stream)
+    alone, inbatch = [], []
+    specs = [(lambda: cases.c2(theta_deg=t), False) for t in (50.0, 70.0, 110.0)]
+    specs += [(lambda: cases.small_flat(), True), (lambda: cases.small_sphere(), True),
+              (lambda: cases.small_sphere(), False)]
+    for mk, unfused in specs:
+        if unfused:
+            monkeypatch.setenv("SLBM_UNFUSED", "1")
+        else:
+            monkeypatch.delenv("SLBM_UNFUSED", raising=False)
+        c = mk()
+        a = P.Solve(c)
+        a.init_tanh()
+        a.step(12)
+        alone.append(a.get_state()[0])
+        m = P.Solve(c)
+        m.init_tanh()
+        b.add(m)
+        inbatch.append(m)
+    monkeypatch.delenv("SLBM_UNFUSED", raising=False)
+    b.step(12)
+    for a, m in zip(alone, inbatch):
+        assert np.array_equal(a, m.get_state()[0])
