@@ -1,5 +1,5 @@
 // Internal interface between the host runtime (semlbm.cpp, serve.cpp) and the HIP
-// kernels (kernels.hip).  Not part of the public C ABI.
+// kernels (kernels.hpp and the kernels*.hip units).  Not part of the public C ABI.
 #pragma once
 
 #include <cstddef>
@@ -99,7 +99,7 @@ SLBM_HD inline int xcd_single(int b, int n) {
     return b < per * kXcds ? (b % kXcds) * per + b / kXcds : b;
 }
 
-// Element-kernel shape for order N in d dimensions (must match kernels.hip): "wide" blocks
+// Element-kernel shape for order N in d dimensions (must match Shape in kernels.hpp): "wide" blocks
 // hold as many elements as fit in 256 threads; small meshes use one element per block so
 // that every compute unit gets work.
 inline int nloc_of(int d, int N) { int p = N + 1; return d == 2 ? p * p : p * p * p; }
@@ -110,8 +110,8 @@ inline int epb_for(int d, int N, int64_t E) {
 }
 constexpr int kNodeThreads = 256;
 
-// Kernel launchers (kernels.hip).  'stage' is 1..3 for the RK stages.  All launch on
-// 'stream' and return the hipError_t of the launch as int.
+// Kernel launchers (kernels.hip dispatches them to the per-order units).  'stage' is 1..3
+// for the RK stages.  All launch on 'stream' and return the hipError_t of the launch as int.
 int launch_lap(int d, int N, const LaunchPlan &p, void *stream);
 int launch_mu(int d, int N, const LaunchPlan &p, void *stream);
 int launch_grad(int d, int N, const LaunchPlan &p, void *stream);
