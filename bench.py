@@ -81,14 +81,18 @@ def cpu_baseline(case, steps: int):
                        f"({dt:.1f} s wall)")
 
 
-def kernels_sha256() -> str:
-    """SHA-256 over the device sources (kernels.hpp, kernels*.hip, internal.hpp), in name order."""
+def kernels_sha256(csrc: str | None = None) -> str:
+    """SHA-256 over the device sources (kernels.hpp, kernels*.hip, internal.hpp) in name
+    order, with // comments and blank lines removed (comment edits leave it unchanged)."""
     import hashlib
-    csrc = os.path.join(ROOT, "paper_2609_00535_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2609_00535_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
         if name.startswith("kernels") or name == "internal.hpp":
-            h.update(open(os.path.join(csrc, name), "rb").read())
+            for line in open(os.path.join(csrc, name), encoding="utf-8"):
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 
