@@ -400,38 +400,53 @@ __global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
 
 // Eq. (4) with (A.2), (A.6)-(A.7) and F** of Sec. 2.1 at one node:
 // f* = f - omega (f - (feq - dt/2 F**)) + dt F**, F = cs^2 grad(rho) - rho grad(mu)
+// moments and force shared by the populations of a node: u = sum f e / rho, F, u.F, u.u
+template <int Q, int D> struct CollidePrep {
+    double u[D], F[D], uF, uu;
+};
 template <int Q, int D>
-__device__ __forceinline__ void collide_node(const SolveDesc &sd, const double *f, double pr,
-                                             const double *gr, const double *gm, double *fs) {
-    const double cs2 = 1.0 / 3.0, dt = sd.dt, om = sd.omega;
-    double u[D], F[D];
+__device__ __forceinline__ void collide_prep(const double *f, double pr, const double *gr, const double *gm,
+                                             CollidePrep<Q, D> &c) {
+    const double cs2 = 1.0 / 3.0;
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
+    for (int k = 0; k < D; ++k) {
         double m = 0.0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int ec = Lat<Q>::e[q][c];
+            const int ec = Lat<Q>::e[q][k];
             if (ec == 1) m = m + f[q];
             else if (ec == -1) m = m - f[q];
         }
-        u[c] = m / pr;
-        F[c] = cs2 * gr[c] - pr * gm[c];
+        c.u[k] = m / pr;
+        c.F[k] = cs2 * gr[k] - pr * gm[k];
     }
-    double uF = 0.0, uu = 0.0;
+    c.uF = 0.0;
+    c.uu = 0.0;
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-        uF += u[c] * F[c];
-        uu += u[c] * u[c];
+    for (int k = 0; k < D; ++k) {
+        c.uF += c.u[k] * c.F[k];
+        c.uu += c.u[k] * c.u[k];
     }
+}
+// f*_q of one population
+template <int Q, int D>
+__device__ __forceinline__ double collide_q(const SolveDesc &sd, int q, double fq, double pr,
+                                            const CollidePrep<Q, D> &c) {
+    const double dt = sd.dt, om = sd.omega;
+    const double eu = dot_e<Q, D>(c.u, q), eF = dot_e<Q, D>(c.F, q);
+    const double tq = sd.tw[wcls<Q>(q)], tc = sd.twc[wcls<Q>(q)];
+    const double Fss = tc * (eu * eF * 3.0 - c.uF);
+    const double feq = pr * tq * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * c.uu);
+    const double fbeq = feq - 0.5 * dt * Fss;
+    return fq - om * (fq - fbeq) + dt * Fss;
+}
+template <int Q, int D>
+__device__ __forceinline__ void collide_node(const SolveDesc &sd, const double *f, double pr,
+                                             const double *gr, const double *gm, double *fs) {
+    CollidePrep<Q, D> c;
+    collide_prep<Q, D>(f, pr, gr, gm, c);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double eu = dot_e<Q, D>(u, q), eF = dot_e<Q, D>(F, q);
-        const double tq = sd.tw[wcls<Q>(q)], tc = sd.twc[wcls<Q>(q)];
-        const double Fss = tc * (eu * eF * 3.0 - uF);
-        const double feq = pr * tq * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        const double fbeq = feq - 0.5 * dt * Fss;
-        fs[q] = f[q] - om * (f[q] - fbeq) + dt * Fss;
-    }
+    for (int q = 0; q < Q; ++q) fs[q] = collide_q<Q, D>(sd, q, f[q], pr, c);
 }
 
 template <int D, int N, bool SINGLE>
@@ -493,6 +508,37 @@ __device__ __forceinline__ void load_geo(const SolveDesc &sd, int n, int l, Node
 // residual at node n from LDS h_q = g_q - t_q rho (fields of stride NB, element base es),
 // LDS mu, register g (for the flux); the loop reads only LDS and registers, so its stores
 // delay no load
+// residual of population q at node n (h_q of the element in LDS at sh_q, stride 1 within
+// the element; dmu = reference gradient of mu; gq, gopp: g_q and g_opp(q) for the flux)
+template <int Q, int D, int NP>
+__device__ __forceinline__ double residual_q(const SolveDesc &sd, int q, const double *sD, const double *sh_q,
+                                             int n, const double *dmu, double pr, double gq, double gopp,
+                                             const NodeGeo<D> &geo) {
+    double dh[D];
+    grad_ref<D, NP>(sD, sh_q, n, dh);
+    double adv = 0.0, frc = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double ca = dot_e<Q, D>(geo.J[a], q);
+        adv += ca * dh[a];
+        frc += ca * dmu[a];
+    }
+    const double tc = sd.twc[wcls<Q>(q)];
+    double r = -(geo.w * (adv + tc * pr * frc));
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if (j < geo.wf.cnt) {
+            const double cn = dot_e<Q, D>(geo.wf.sn[j], q);
+            if (cn < 0.0) {
+                const double eub = dot_e<Q, D>(geo.wf.ub[j], q);
+                const double bc = gq - gopp - 2.0 * tc * pr * eub;
+                r += cn * bc;
+            }
+        }
+    }
+    return r;
+}
+
 template <int D, int N, bool WIDE>
 __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
                                                 const double *smu_e, int es, int n, int l,
@@ -502,31 +548,10 @@ __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const doubl
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     double dmu[D];
     grad_ref<D, NP>(sD, smu_e, n, dmu);
-    const double w = geo.w;
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-        double dh[D];
-        grad_ref<D, NP>(sD, sh + (q - 1) * NB + es * NLOC, n, dh);
-        double adv = 0.0, frc = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const double ca = dot_e<Q, D>(geo.J[a], q);
-            adv += ca * dh[a];
-            frc += ca * dmu[a];
-        }
-        const double tc = sd.twc[wcls<Q>(q)];
-        double r = -(w * (adv + tc * pr * frc));
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j < geo.wf.cnt) {
-                const double cn = dot_e<Q, D>(geo.wf.sn[j], q);
-                if (cn < 0.0) {
-                    const double eub = dot_e<Q, D>(geo.wf.ub[j], q);
-                    const double bc = gq[q] - gq[Lat<Q>::opp[q]] - 2.0 * tc * pr * eub;
-                    r += cn * bc;
-                }
-            }
-        }
+        const double r = residual_q<Q, D, NP>(sd, q, sD, sh + (q - 1) * NB + es * NLOC, n, dmu, pr, gq[q],
+                                              gq[Lat<Q>::opp[q]], geo);
         sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
     }
 }
@@ -1054,6 +1079,273 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
 }
 
 // ------------------------------------------------------------------------------------------
+// 2-D fused kernels B, C, D for one element per block (the latency-bound regime), with the
+// populations split over four groups of lanes: group g handles the opposite pair
+// (qa, opp(qa)), qa = 1, 2, 5, 6, and group 0 also q = 0.  Every group holds the whole
+// element (one lane per node); per-node quantities every group needs (moments, mu) are
+// computed by each group with the same arithmetic.  A wave thus runs a quarter of the
+// population work, and four waves per element fill the SIMDs that one wave per element
+// leaves idle.  Arithmetic and summation orders are those of k_fB, k_fC, k_fD.
+// ------------------------------------------------------------------------------------------
+template <int N> struct Split2 {
+    static constexpr int NP = N + 1;
+    static constexpr int NLOC = NP * NP;
+    static constexpr int NTP = ((NLOC + 63) / 64) * 64;  // lanes of one group
+    static constexpr int NT = 4 * NTP;
+};
+// first population of group g's pair (the second is Lat<9>::opp of it)
+template <int G> struct PairOf;
+template <> struct PairOf<0> { static constexpr int qa = 1; };
+template <> struct PairOf<1> { static constexpr int qa = 2; };
+template <> struct PairOf<2> { static constexpr int qa = 5; };
+template <> struct PairOf<3> { static constexpr int qa = 6; };
+
+// call f(GroupC<g>{}) for the calling group g (uniform within a wave)
+template <int G> struct GroupC { static constexpr int value = G; };
+template <class F>
+__device__ __forceinline__ void for_group(int grp, F &&f) {
+    switch (grp) {
+    case 0: f(GroupC<0>{}); break;
+    case 1: f(GroupC<1>{}); break;
+    case 2: f(GroupC<2>{}); break;
+    default: f(GroupC<3>{}); break;
+    }
+}
+
+template <int N, bool SINGLE>
+__global__ __launch_bounds__(Split2<N>::NT) void k_fB4(LaunchPlan p) {
+    using S = Split2<N>;
+    constexpr int D = 2, Q = 9, NP = S::NP, NLOC = S::NLOC, NTP = S::NTP;
+    __shared__ double sD[NP * NP];
+    __shared__ double smu[NTP];
+    __shared__ double sh[(Q - 1) * NTP];
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x, grp = tid / NTP, n = tid - grp * NTP;
+    const int e = bs.local;
+    const bool act = n < NLOC && e < sd.E;
+    const int l = e * NLOC + n;
+    const size_t Ng = sd.Ng;
+    double dmv = 0.0;
+    double pr = 0.0, fa = 0.0, fb = 0.0;
+    NodeGeo<D> geo;
+    if (act) {
+        if (grp == 0) dmv = dm_fetch<NP>(sd, n);
+        CopyList<D> cl;
+        load_copies<D, NP, false>(sd, n, l, cl);
+        const int G = sd.lgid[l];
+        load_geo<D>(sd, n, l, geo);
+        const double mi = sd.Minv[G];
+        double gr[D], gm[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            gr[c] = gather1<D, false>(sd.gl + (size_t)c * sd.Nl, cl) * mi;
+            gm[c] = gather1<D, false>(sd.gl + (size_t)(D + c) * sd.Nl, cl) * mi;
+        }
+        double f[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
+        pr = sd.rho[G];
+        const double mu = sd.mu[G];
+        CollidePrep<Q, D> cp;
+        collide_prep<Q, D>(f, pr, gr, gm, cp);
+        const bool owner = cl.cp[0] == l;
+        for_group(grp, [&](auto gc) {
+            constexpr int qa = PairOf<decltype(gc)::value>::qa, qb = Lat<Q>::opp[qa];
+            fa = collide_q<Q, D>(sd, qa, f[qa], pr, cp);
+            fb = collide_q<Q, D>(sd, qb, f[qb], pr, cp);
+            if (owner) {
+                sd.g0[qa * Ng + G] = fa;
+                sd.g0[qb * Ng + G] = fb;
+                if (decltype(gc)::value == 0) sd.g0[G] = collide_q<Q, D>(sd, 0, f[0], pr, cp);
+            }
+            sh[(qa - 1) * NTP + n] = fa - sd.tw[wcls<Q>(qa)] * pr;
+            sh[(qb - 1) * NTP + n] = fb - sd.tw[wcls<Q>(qb)] * pr;
+        });
+        if (grp == 0) smu[n] = mu;
+    }
+    if (grp == 0) dm_store<NP>(sD, n, dmv);
+    __syncthreads();
+    if (!act) return;
+    double dmu[D];
+    grad_ref<D, NP>(sD, smu, n, dmu);
+    for_group(grp, [&](auto gc) {
+        constexpr int qa = PairOf<decltype(gc)::value>::qa, qb = Lat<Q>::opp[qa];
+        const double ra = residual_q<Q, D, NP>(sd, qa, sD, sh + (qa - 1) * NTP, n, dmu, pr, fa, fb, geo);
+        const double rb = residual_q<Q, D, NP>(sd, qb, sD, sh + (qb - 1) * NTP, n, dmu, pr, fb, fa, geo);
+        sd.rs[(size_t)(qa - 1) * sd.Nl + l] = ra;
+        sd.rs[(size_t)(qb - 1) * sd.Nl + l] = rb;
+    });
+}
+
+template <int N, bool SINGLE>
+__global__ __launch_bounds__(Split2<N>::NT) void k_fC4(LaunchPlan p, int stage) {
+    using S = Split2<N>;
+    constexpr int D = 2, Q = 9, NP = S::NP, NLOC = S::NLOC, NTP = S::NTP;
+    constexpr int K = CopyList<D>::K;
+    __shared__ double sD[NP * NP];
+    __shared__ double sout[Q * NTP];
+    __shared__ double srho[NTP];
+    __shared__ double sv[D * NTP];
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x, grp = tid / NTP, n = tid - grp * NTP;
+    const int e = bs.local;
+    const bool act = n < NLOC && e < sd.E;
+    const int l = e * NLOC + n;
+    const size_t Ng = sd.Ng, Nl = sd.Nl;
+    const double SLBM_GLOBAL *gin = stage == 1 ? sd.g0 : (stage == 2 ? sd.g1 : sd.g2);
+    double SLBM_GLOBAL *gout = stage == 1 ? sd.g1 : (stage == 2 ? sd.g2 : sd.f);
+    double dmv = 0.0;
+    double gm[3] = {0.0, 0.0, 0.0};
+    WallLap<D> wl;
+    wl.cnt = 0;
+    bool owner = false;
+    int G = 0;
+    if (act) {
+        CopyList<D> cl;
+        load_copies<D, NP, false>(sd, n, l, cl);
+        G = sd.lgid[l];
+        owner = cl.cp[0] == l;
+        if (grp == 0) {
+            dmv = dm_fetch<NP>(sd, n);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gm[k] = sd.G[(size_t)k * Nl + l];
+            load_wall_lap<D>(sd, l, wl);
+        }
+        const double mi = sd.Minv[G], dt = sd.dt;
+        // DSS of the residual of q over the copies and the RK combination; q = 0 has L = 0
+        auto one = [&](int q, double gi, double g0) {
+            double L = 0.0;
+            if (q > 0) {
+                double x[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) x[k] = sd.rs[(size_t)(q - 1) * Nl + cl.cp[k]];
+                double R = 0.0;
+                R += x[0];
+#pragma unroll
+                for (int k = 1; k < K; ++k) R += k < cl.nc ? x[k] : 0.0;
+                L = R * mi;
+            }
+            return rk_combine<Q>(stage, L, gi, g0, dt);
+        };
+        for_group(grp, [&](auto gc) {
+            constexpr int GR = decltype(gc)::value;
+            constexpr int qa = PairOf<GR>::qa, qb = Lat<Q>::opp[qa];
+            const double gia = gin[qa * Ng + G], gib = gin[qb * Ng + G];
+            const double gi0 = GR == 0 ? gin[G] : 0.0;
+            double g0a = 0.0, g0b = 0.0, g00 = 0.0;
+            if (stage != 1) {
+                g0a = sd.g0[qa * Ng + G];
+                g0b = sd.g0[qb * Ng + G];
+                if (GR == 0) g00 = sd.g0[G];
+            }
+            const double oa = one(qa, gia, g0a), ob = one(qb, gib, g0b);
+            sout[qa * NTP + n] = oa;
+            sout[qb * NTP + n] = ob;
+            if (owner) {
+                gout[qa * Ng + G] = oa;
+                gout[qb * Ng + G] = ob;
+            }
+            if (GR == 0) {
+                const double o0 = one(0, gi0, g00);
+                sout[n] = o0;
+                if (owner) gout[G] = o0;
+            }
+        });
+    }
+    if (grp == 0) dm_store<NP>(sD, n, dmv);
+    __syncthreads();
+    // stage density in ascending population order, then the Laplacian partials (group 0)
+    double rho = 0.0;
+    if (act && grp == 0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) rho += sout[q * NTP + n];
+        if (owner) sd.rho[G] = rho;
+        srho[n] = rho;
+    }
+    __syncthreads();
+    if (act && grp == 0) {
+        double d[D];
+        grad_ref<D, NP>(sD, srho, n, d);
+        metric_times_grad<D, NTP, 3>(gm, d, sv, n);
+    }
+    __syncthreads();
+    if (!act || grp != 0) return;
+    const double r = -div_refT<D, NP>(sD, sv, NTP, n);
+    sd.rl[l] = wall_lap_term<D>(sd, wl, rho, r);
+}
+
+template <int N, bool SINGLE>
+__global__ __launch_bounds__(Split2<N>::NT) void k_fD4(LaunchPlan p, int stage) {
+    using S = Split2<N>;
+    constexpr int D = 2, Q = 9, NP = S::NP, NLOC = S::NLOC, NTP = S::NTP;
+    __shared__ double sD[NP * NP];
+    __shared__ double smu[NTP];
+    __shared__ double sh[(Q - 1) * NTP];
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x, grp = tid / NTP, n = tid - grp * NTP;
+    const int e = bs.local;
+    const bool act = n < NLOC && e < sd.E;
+    const int l = e * NLOC + n;
+    const size_t Ng = sd.Ng;
+    const double SLBM_GLOBAL *g = stage == 2 ? sd.g1 : sd.g2;
+    double dmv = 0.0;
+    double pr = 0.0, ga = 0.0, gb = 0.0;
+    NodeGeo<D> geo;
+    if (act) {
+        if (grp == 0) dmv = dm_fetch<NP>(sd, n);
+        CopyList<D> cl;
+        load_copies<D, NP, false>(sd, n, l, cl);
+        const int G = sd.lgid[l];
+        load_geo<D>(sd, n, l, geo);
+        pr = sd.rho[G];
+        const double mu = mu_of(sd, pr, gather1<D, false>(sd.rl, cl) * sd.Minv[G]);
+        if (grp == 0) smu[n] = mu;
+        for_group(grp, [&](auto gc) {
+            constexpr int qa = PairOf<decltype(gc)::value>::qa, qb = Lat<Q>::opp[qa];
+            ga = g[qa * Ng + G];
+            gb = g[qb * Ng + G];
+            sh[(qa - 1) * NTP + n] = ga - sd.tw[wcls<Q>(qa)] * pr;
+            sh[(qb - 1) * NTP + n] = gb - sd.tw[wcls<Q>(qb)] * pr;
+        });
+    }
+    if (grp == 0) dm_store<NP>(sD, n, dmv);
+    __syncthreads();
+    if (!act) return;
+    double dmu[D];
+    grad_ref<D, NP>(sD, smu, n, dmu);
+    for_group(grp, [&](auto gc) {
+        constexpr int qa = PairOf<decltype(gc)::value>::qa, qb = Lat<Q>::opp[qa];
+        const double ra = residual_q<Q, D, NP>(sd, qa, sD, sh + (qa - 1) * NTP, n, dmu, pr, ga, gb, geo);
+        const double rb = residual_q<Q, D, NP>(sd, qb, sD, sh + (qb - 1) * NTP, n, dmu, pr, gb, ga, geo);
+        sd.rs[(size_t)(qa - 1) * sd.Nl + l] = ra;
+        sd.rs[(size_t)(qb - 1) * sd.Nl + l] = rb;
+    });
+}
+
+// narrow (one element per block) launches of B, C, D: the population-split kernels in 2-D
+template <int DD, int NN, bool S>
+inline void launch_narrow_fB(const LaunchPlan &p, hipStream_t st) {
+    if constexpr (DD == 2) k_fB4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p);
+    else k_fB<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p);
+}
+template <int DD, int NN, bool S>
+inline void launch_narrow_fC(const LaunchPlan &p, hipStream_t st, int stage) {
+    if constexpr (DD == 2) k_fC4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p, stage);
+    else k_fC<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p, stage);
+}
+template <int DD, int NN, bool S>
+inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
+    if constexpr (DD == 2) k_fD4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p, stage);
+    else k_fD<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p, stage);
+}
+
+// ------------------------------------------------------------------------------------------
 // launchers of one set of (d, N) instances: SLBM_LAUNCHER_SET(sfx, ORDERS) defines
 // launch_<kernel>_<sfx>(d, N, plan, ..., stream) for the orders listed by ORDERS(X)
 // ------------------------------------------------------------------------------------------
@@ -1066,6 +1358,15 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
         else if (wide) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, true, false, ##__VA_ARGS__);         \
         else if (p.single) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, false, true, ##__VA_ARGS__);     \
         else SLBM_ELEM_LAUNCH(KERNEL, DD, NN, false, false, ##__VA_ARGS__);                  \
+        done = true;                                                                         \
+    }
+#define SLBM_SPLIT_CASE(KERNEL, NARROW, DD, NN, ...)                                        \
+    if (!done && d == DD && N == NN) {                                                       \
+        const bool wide = p.epb == Shape<DD, NN, true>::EPB;                                 \
+        if (wide && p.single) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, true, true, ##__VA_ARGS__);   \
+        else if (wide) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, true, false, ##__VA_ARGS__);         \
+        else if (p.single) NARROW<DD, NN, true>(p, st, ##__VA_ARGS__);                       \
+        else NARROW<DD, NN, false>(p, st, ##__VA_ARGS__);                                    \
         done = true;                                                                         \
     }
 #define SLBM_NODE_CASE(KERNEL, DD, NN, ...)                                                  \
@@ -1084,9 +1385,9 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
 #define SLBM_CASE_density(DD, NN) SLBM_NODE_CASE(k_density, DD, NN, which)
 #define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)
 #define SLBM_CASE_fA(DD, NN) SLBM_ELEM_CASE(k_fA, DD, NN)
-#define SLBM_CASE_fB(DD, NN) SLBM_ELEM_CASE(k_fB, DD, NN)
-#define SLBM_CASE_fC(DD, NN) SLBM_ELEM_CASE(k_fC, DD, NN, stage)
-#define SLBM_CASE_fD(DD, NN) SLBM_ELEM_CASE(k_fD, DD, NN, stage)
+#define SLBM_CASE_fB(DD, NN) SLBM_SPLIT_CASE(k_fB, launch_narrow_fB, DD, NN)
+#define SLBM_CASE_fC(DD, NN) SLBM_SPLIT_CASE(k_fC, launch_narrow_fC, DD, NN, stage)
+#define SLBM_CASE_fD(DD, NN) SLBM_SPLIT_CASE(k_fD, launch_narrow_fD, DD, NN, stage)
 
 #define SLBM_DISPATCH(ORDERS, KERNEL)                                                        \
     do {                                                                                     \
