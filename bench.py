@@ -3,7 +3,7 @@
 
 Metric: FP64 node-updates/s.  One node-update advances one unique global GLL node by
 one full time step (collision + three SSP-RK3 streaming stages, all populations).
-Default workload: config 2 (D2Q9 sessile droplet on a 60-degree wetting wall, 128x64
+Default workload: c2, the D2Q9 sessile droplet on a 60-degree wetting wall (128x64
 domain, 32x16 jittered quads, N=6).  All inputs are seeded and synthetic and resident
 in device memory before the timed region.
 
@@ -125,7 +125,7 @@ def copy_calibration(torch, mib: int, reps: int = 3):
 
 def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
                   ke_stop: float = 1e-20, max_slots: int = 256, seed: int = 5):
-    """Config 5 (reduced): n_req droplet requests (flat or cylinder wall, N in {4,6,8},
+    """Request sweep c5 (reduced): n_req droplet requests (flat or cylinder wall, N in {4,6,8},
     theta ~ U[30,150], R ~ U[10,30]) run to KE_max < ke_stop or max_steps.
 
     Three runs of the same request list: (1) the plain stepper, one solve at a time with

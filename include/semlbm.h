@@ -194,8 +194,40 @@ slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out);
 slbm_status slbm_batch_add(slbm_batch *b, slbm_ctx *c);
 slbm_status slbm_batch_remove(slbm_batch *b, slbm_ctx *c);
 int slbm_batch_size(const slbm_batch *b);
-/* Advance every member n steps (asynchronous). */
+/* Advance every member n steps (asynchronous, except in a call that tunes, below). */
 slbm_status slbm_batch_step(slbm_batch *b, int64_t n);
+
+/* Launch-shape autotuning.  Members with the same (lattice, N, kernel path) form a group
+ * whose every kernel covers all of them in one launch; a group can launch in several
+ * shapes: one element per block of the element kernels, or as many elements as fit in
+ * 256 threads (where more than one fits), each with its block tables in XCD-aware order
+ * (every die of the chip works on a contiguous range of elements or nodes) or in plain
+ * order.  All shapes give the same bits.  With autotuning on (the default), the first
+ * slbm_batch_step of n >= 4 * n_shapes steps after a group of a new (lattice, N, path,
+ * floor(log2(elements))) appears spends 4 of those steps per shape on the group (one
+ * warm-up, three timed), keeps the fastest and remembers it for later groups of the same
+ * key in this batch; that call waits for the device.  Every member still advances exactly
+ * n steps.  Off, a group uses wide blocks in XCD order when they make at least 256
+ * blocks and one element per block otherwise.  on: 0 or 1, else SLBM_EINVAL. */
+slbm_status slbm_batch_set_autotune(slbm_batch *b, int on);
+
+#define SLBM_MAX_SHAPES 4
+typedef struct slbm_batch_shape {
+    int dim, order, fused;     /* group key: lattice dimension, N, fused kernel path (0/1) */
+    int members;               /* members in the group */
+    int64_t elements;          /* their elements */
+    int n_shapes;              /* candidate shapes, at most SLBM_MAX_SHAPES */
+    int epb[SLBM_MAX_SHAPES];  /* elements per block of the element kernels */
+    int xcd[SLBM_MAX_SHAPES];  /* 1: XCD-aware block order, 0: plain order */
+    double us_per_step[SLBM_MAX_SHAPES]; /* measured device us per step of the group, 0 if not */
+    int chosen;                /* index of the shape the group launches with */
+    int measured;              /* 1 if chosen by timing, 0 by the fixed rule above */
+} slbm_batch_shape;
+/* The groups of the current membership: writes min(count, max) entries to out[max] and
+ * the number of groups to *count (0 for an empty batch).  Errors: SLBM_EINVAL (null b or
+ * count, max < 0, or max > 0 with null out), or those of rebuilding the launch tables
+ * after a membership change (SLBM_ENOMEM, SLBM_EDEVICE). */
+slbm_status slbm_batch_shapes(slbm_batch *b, slbm_batch_shape *out, int max, int *count);
 /* Per-member KE_max and mass into ke[size], mass[size] (member order of insertion). */
 slbm_status slbm_batch_kinetic_energy(slbm_batch *b, double *ke, double *mass);
 void slbm_batch_destroy(slbm_batch *b);

@@ -45,6 +45,16 @@ class WallGeom(C.Structure):
                 ("radius", C.c_double)]
 
 
+MAX_SHAPES = 4
+
+
+class BatchShape(C.Structure):
+    _fields_ = [("dim", C.c_int), ("order", C.c_int), ("fused", C.c_int), ("members", C.c_int),
+                ("elements", C.c_int64), ("n_shapes", C.c_int), ("epb", C.c_int * MAX_SHAPES),
+                ("xcd", C.c_int * MAX_SHAPES), ("us_per_step", C.c_double * MAX_SHAPES),
+                ("chosen", C.c_int), ("measured", C.c_int)]
+
+
 class ServerCfg(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("hip_stream", C.c_void_p),
                 ("max_slots", C.c_int), ("check_every", C.c_int), ("ke_stop", C.c_double),
@@ -96,6 +106,8 @@ SIGNATURES = {
     "slbm_batch_remove": (C.c_int, [_vp, _vp]),
     "slbm_batch_size": (C.c_int, [_vp]),
     "slbm_batch_step": (C.c_int, [_vp, _i64]),
+    "slbm_batch_set_autotune": (C.c_int, [_vp, C.c_int]),
+    "slbm_batch_shapes": (C.c_int, [_vp, C.POINTER(BatchShape), C.c_int, C.POINTER(C.c_int)]),
     "slbm_batch_kinetic_energy": (C.c_int, [_vp, _dp, _dp]),
     "slbm_batch_destroy": (None, [_vp]),
     "slbm_server_create": (C.c_int, [C.POINTER(ServerCfg), C.POINTER(C.c_void_p)]),
@@ -339,6 +351,30 @@ class Batch:
         st = lib().slbm_batch_step(self._h, int(n))
         if st != SLBM_OK:
             raise SLBMError(st, "batch_step")
+
+    def set_autotune(self, on: bool):
+        st = lib().slbm_batch_set_autotune(self._h, 1 if on else 0)
+        if st != SLBM_OK:
+            raise SLBMError(st, "batch_set_autotune")
+
+    def shapes(self):
+        """Launch shapes per group: list of dicts (key, candidates with measured us/step,
+        chosen index, whether the choice was timed)."""
+        cnt = C.c_int(0)
+        st = lib().slbm_batch_shapes(self._h, None, 0, C.byref(cnt))
+        if st != SLBM_OK:
+            raise SLBMError(st, "batch_shapes")
+        arr = (BatchShape * max(cnt.value, 1))()
+        st = lib().slbm_batch_shapes(self._h, arr, cnt.value, C.byref(cnt))
+        if st != SLBM_OK:
+            raise SLBMError(st, "batch_shapes")
+        out = []
+        for r in arr[:cnt.value]:
+            out.append({"dim": r.dim, "N": r.order, "fused": bool(r.fused), "members": r.members,
+                        "elements": r.elements, "chosen": r.chosen, "measured": bool(r.measured),
+                        "shapes": [{"epb": r.epb[k], "xcd": bool(r.xcd[k]), "us_per_step": r.us_per_step[k]}
+                                   for k in range(r.n_shapes)]})
+        return out
 
     def kinetic_energy(self):
         n = len(self.members)

@@ -35,11 +35,25 @@ struct slbm_batch {
     void *stream = nullptr;
     std::vector<slbm_ctx *> members;
     bool dirty = true;
+    // One launch shape of a group's kernels: elements per block of the element kernels and
+    // the order of the block tables.  Every shape gives the same bits (each element's and
+    // node's arithmetic does not depend on which block runs it), so the tuner may switch
+    // shapes between any two steps.
+    struct Shape {
+        int epb = 1;       // elements per block (1, or as many as fit in 256 threads)
+        bool xcd = true;   // XCD-aware block order (contiguous ranges per die), else plain order
+        LaunchPlan ep{}, np{};
+        double us = 0.0;   // measured device time of one step of the group (0: not measured)
+    };
     struct Group {
-        int d = 0, N = 0, epb = 1;
+        int d = 0, N = 0;
         bool fused = true;     // kernel path of every member
         std::vector<int> idx;  // member indices
-        LaunchPlan ep{}, np{};
+        int64_t elements = 0;
+        std::vector<Shape> shapes;
+        int pick = 0;          // index into shapes
+        bool measured = false; // pick chosen by timing (here or earlier, from the tuning cache)
+        LaunchPlan ep{}, np{}; // shapes[pick]
         SolveDesc *desc = nullptr;  // device
         double *diag_out = nullptr; // device [2 * members]
     };
@@ -50,6 +64,18 @@ struct slbm_batch {
     // graphs of 1 and 10 batched steps for the current membership (captured lazily)
     void *graph[2] = {nullptr, nullptr};
     bool use_graph = true;
+    // autotuner: timed shapes per (d, N, path, size class of the group), kept across
+    // membership changes
+    bool autotune = true;
+    static constexpr int kTuneReps = 3;  // timed steps per shape (after one warm-up step)
+    struct Tuned { int pick; std::vector<double> us; };
+    std::map<std::vector<int64_t>, Tuned> cache;
+
+    static std::vector<int64_t> key_of(const Group &g) {
+        int64_t cls = 0;  // size class: floor(log2(elements))
+        while ((int64_t)2 << cls <= g.elements) ++cls;
+        return {g.d, g.N, g.fused ? 1 : 0, cls};
+    }
 
     void drop_graphs() {
         destroy_graph(graph[0]);
@@ -57,16 +83,21 @@ struct slbm_batch {
         graph[0] = graph[1] = nullptr;
     }
 
+    int enqueue_group(const Group &g, const LaunchPlan &ep, const LaunchPlan &np, int64_t n) const {
+        return enqueue_steps(g.d, g.N, ep, np, n, stream, g.fused);
+    }
+
     int enqueue(int64_t n) {
         for (int64_t s = 0; s < n; ++s)
             for (auto &g : groups) {
-                const int e = enqueue_steps(g.d, g.N, g.ep, g.np, 1, stream, g.fused);
+                const int e = enqueue_group(g, g.ep, g.np, 1);
                 if (e) return e;
             }
         return 0;
     }
 
     int run(int64_t n) {
+        if (n <= 0) return 0;
         if (use_graph && stream != nullptr) {
             const int sizes[2] = {1, 10};
             for (int k = 0; k < 2 && use_graph; ++k)
@@ -93,6 +124,85 @@ struct slbm_batch {
         return enqueue(n);
     }
 
+    // Steps the tuner spends on a group: one warm-up and kTuneReps timed steps per shape.
+    static int64_t tune_steps(const Group &g) { return (int64_t)g.shapes.size() * (1 + kTuneReps); }
+
+    // Time every shape of group g on its members' own time steps (each step a replay of a
+    // one-step graph of the group, or plain launches where the stream cannot be captured)
+    // and pick the fastest.  The group advances tune_steps(g) steps; waits for the device.
+    int tune(Group &g) {
+        hipStream_t st = (hipStream_t)stream;
+        hipEvent_t ev[kTuneReps + 1] = {};
+        int e = 0;
+        for (int r = 0; r <= kTuneReps && !e; ++r) e = (int)hipEventCreate(&ev[r]);
+        for (size_t k = 0; k < g.shapes.size() && !e; ++k) {
+            struct A { const slbm_batch *b; const Group *g; const Shape *s; } a{this, &g, &g.shapes[k]};
+            auto fn = [](void *, void *p) -> int {
+                const A *x = (const A *)p;
+                return x->b->enqueue_group(*x->g, x->s->ep, x->s->np, 1);
+            };
+            void *gr = nullptr;
+            if (use_graph && stream != nullptr && capture_graph(stream, &gr, fn, &a)) {
+                (void)hipGetLastError();
+                gr = nullptr;
+            }
+            auto once = [&]() { return gr ? launch_graph(gr, stream) : fn(nullptr, &a); };
+            e = once();
+            for (int r = 0; r <= kTuneReps && !e; ++r) {
+                e = (int)hipEventRecord(ev[r], st);
+                if (!e && r < kTuneReps) e = once();
+            }
+            if (!e) e = (int)hipEventSynchronize(ev[kTuneReps]);
+            float best = -1.0f;
+            for (int r = 0; r < kTuneReps && !e; ++r) {
+                float ms = 0.0f;
+                e = (int)hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
+                if (!e && (best < 0.0f || ms < best)) best = ms;
+            }
+            destroy_graph(gr);
+            g.shapes[k].us = 1e3 * (double)best;
+        }
+        for (auto &x : ev)
+            if (x) (void)hipEventDestroy(x);
+        if (e) return e;
+        int pick = 0;
+        for (size_t k = 1; k < g.shapes.size(); ++k)
+            if (g.shapes[k].us < g.shapes[pick].us) pick = (int)k;
+        select(g, pick, true);
+        Tuned t{pick, {}};
+        for (auto &s : g.shapes) t.us.push_back(s.us);
+        cache[key_of(g)] = t;
+        return 0;
+    }
+
+    static void select(Group &g, int k, bool measured) {
+        g.pick = k;
+        g.measured = measured;
+        g.ep = g.shapes[k].ep;
+        g.np = g.shapes[k].np;
+    }
+
+    // Tune the groups that have more than one shape and no timing yet, when this call's
+    // n steps cover the tuner's steps; every group then catches up to the same step count
+    // with plain launches.  Returns the steps every member has advanced (or -1).
+    int64_t tune_pending(int64_t n) {
+        std::vector<int64_t> used(groups.size(), 0);
+        int64_t mx = 0;
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            Group &g = groups[gi];
+            if (g.measured || g.shapes.size() < 2 || tune_steps(g) > n) continue;
+            if (tune(g)) return -1;
+            used[gi] = tune_steps(g);
+            mx = std::max(mx, used[gi]);
+        }
+        if (mx == 0) return 0;
+        drop_graphs();  // captured with the previous shapes
+        for (size_t gi = 0; gi < groups.size(); ++gi)
+            if (used[gi] < mx && enqueue_group(groups[gi], groups[gi].ep, groups[gi].np, mx - used[gi]))
+                return -1;
+        return mx;
+    }
+
     ~slbm_batch() {
         drop_graphs();
         if (dmem) {
@@ -101,8 +211,21 @@ struct slbm_batch {
         }
     }
 
-    // element blocks of member c under the group's block shape
+    // element blocks of member c under a block shape
     static int eblocks(const slbm_ctx *c, int epb) { return (int)((c->E + epb - 1) / epb); }
+
+    // block table [2][len] (member, block within member) over n logical blocks in XCD-aware
+    // order (hardware block b runs logical block xcd_logical(b, n), so each die works on a
+    // contiguous range; padded with -1) or in plain order
+    static int table_len(int n, bool xcd) { return xcd ? xcd_grid(n) : n; }
+    static void fill_table(int *h, int n, bool xcd, const std::vector<int> &s, const std::vector<int> &l) {
+        const int len = table_len(n, xcd);
+        for (int b = 0; b < len; ++b) {
+            const int j = xcd ? xcd_logical(b, n) : b;
+            h[b] = j < n ? s[j] : 0;
+            h[len + b] = j < n ? l[j] : -1;
+        }
+    }
 
     slbm_status rebuild() {
         drop_graphs();
@@ -122,28 +245,41 @@ struct slbm_batch {
                 g->fused = c->fused;
             }
             g->idx.push_back(i);
+            g->elements += c->E;
         }
-        // block shape per group: wide blocks (several elements each) once the group's
-        // elements fill the chip, one element per block otherwise
+        // candidate shapes per group: one element per block and (where more than one
+        // element fits) wide blocks, each in XCD-aware and plain block order
         for (auto &g : groups) {
             const int w = epb_wide(g.d, g.N);
-            int64_t nb = 0;
-            for (int i : g.idx) nb += eblocks(members[i], w);
-            g.epb = nb >= 256 ? w : 1;
+            for (int epb : {1, w}) {
+                if (epb == w && w == 1 && !g.shapes.empty()) break;
+                for (bool xcd : {true, false}) {
+                    Shape s;
+                    s.epb = epb;
+                    s.xcd = xcd;
+                    g.shapes.push_back(s);
+                }
+            }
         }
-        // one device block: per group [descs][e tables][n tables][diag out]
+        // one device block: per group [descs][e tables per shape][n tables per order][diag out]
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        auto counts = [&](const Group &g, int epb, int *ne, int *nn) {
+            *ne = *nn = 0;
+            for (int i : g.idx) {
+                *ne += eblocks(members[i], epb);
+                *nn += members[i]->n_nblocks;
+            }
+        };
         size_t total = 0;
         std::vector<size_t> goff;
         for (auto &g : groups) {
             goff.push_back(total);
+            total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(double) * 2 * g.idx.size());
             int ne = 0, nn = 0;
-            for (int i : g.idx) {
-                ne += eblocks(members[i], g.epb);
-                nn += members[i]->n_nblocks;
+            for (auto &s : g.shapes) {
+                counts(g, s.epb, &ne, &nn);
+                total += al(sizeof(int) * 2 * table_len(ne, s.xcd)) + al(sizeof(int) * 2 * table_len(nn, s.xcd));
             }
-            total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(int) * 2 * xcd_grid(ne)) +
-                     al(sizeof(int) * 2 * xcd_grid(nn)) + al(sizeof(double) * 2 * g.idx.size());
         }
         hipStream_t st = (hipStream_t)stream;
         if (total > dcap) {
@@ -160,51 +296,50 @@ struct slbm_batch {
             dcap = cap;
         }
         std::vector<char> host(total, 0);
+        char *base = (char *)dmem;
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             Group &g = groups[gi];
             size_t o = goff[gi];
-            const size_t o_desc = o;
+            g.desc = reinterpret_cast<SolveDesc *>(base + o);
+            SolveDesc *dh = reinterpret_cast<SolveDesc *>(host.data() + o);
             o += al(sizeof(SolveDesc) * g.idx.size());
-            int ne = 0, nn = 0;
-            for (int i : g.idx) {
-                ne += eblocks(members[i], g.epb);
-                nn += members[i]->n_nblocks;
+            g.diag_out = reinterpret_cast<double *>(base + o);
+            o += al(sizeof(double) * 2 * g.idx.size());
+            for (int k = 0; k < (int)g.idx.size(); ++k) dh[k] = members[g.idx[k]]->desc;
+            for (auto &s : g.shapes) {
+                std::vector<int> le_s, le_l, ln_s, ln_l;  // logical order
+                for (int k = 0; k < (int)g.idx.size(); ++k) {
+                    slbm_ctx *c = members[g.idx[k]];
+                    for (int b = 0; b < eblocks(c, s.epb); ++b) { le_s.push_back(k); le_l.push_back(b); }
+                    for (int b = 0; b < c->n_nblocks; ++b) { ln_s.push_back(k); ln_l.push_back(b); }
+                }
+                const int ne = (int)le_s.size(), nn = (int)ln_s.size();
+                const int te = table_len(ne, s.xcd), tn = table_len(nn, s.xcd);
+                fill_table(reinterpret_cast<int *>(host.data() + o), ne, s.xcd, le_s, le_l);
+                int *et = reinterpret_cast<int *>(base + o);
+                o += al(sizeof(int) * 2 * te);
+                fill_table(reinterpret_cast<int *>(host.data() + o), nn, s.xcd, ln_s, ln_l);
+                int *nt = reinterpret_cast<int *>(base + o);
+                o += al(sizeof(int) * 2 * tn);
+                s.ep = LaunchPlan{g.desc, et, et + te, te, 0, s.epb, te};
+                s.np = LaunchPlan{g.desc, nt, nt + tn, tn, 0, 0, tn};
             }
-            // tables in XCD-aware order: hardware block b runs logical block
-            // xcd_logical(b, n) (contiguous logical ranges per die), padded with -1
-            const int te = xcd_grid(ne), tn = xcd_grid(nn);
-            const size_t o_e = o;
-            o += al(sizeof(int) * 2 * te);
-            const size_t o_n = o;
-            o += al(sizeof(int) * 2 * tn);
-            const size_t o_d = o;
-            SolveDesc *dh = reinterpret_cast<SolveDesc *>(host.data() + o_desc);
-            int *eh = reinterpret_cast<int *>(host.data() + o_e);
-            int *nh = reinterpret_cast<int *>(host.data() + o_n);
-            std::vector<int> le_s, le_l, ln_s, ln_l;  // logical order
-            for (int k = 0; k < (int)g.idx.size(); ++k) {
-                slbm_ctx *c = members[g.idx[k]];
-                dh[k] = c->desc;
-                for (int b = 0; b < eblocks(c, g.epb); ++b) { le_s.push_back(k); le_l.push_back(b); }
-                for (int b = 0; b < c->n_nblocks; ++b) { ln_s.push_back(k); ln_l.push_back(b); }
+            // shape: the tuned one for this group's key, else wide blocks (XCD order) once
+            // the group's elements fill the chip and one element per block otherwise
+            auto it = cache.find(key_of(g));
+            if (it != cache.end() && it->second.us.size() == g.shapes.size()) {
+                for (size_t k = 0; k < g.shapes.size(); ++k) g.shapes[k].us = it->second.us[k];
+                select(g, it->second.pick, true);
+            } else {
+                const int w = epb_wide(g.d, g.N);
+                int nbw = 0, nn = 0;
+                counts(g, w, &nbw, &nn);
+                const int want = nbw >= 256 ? w : 1;
+                int k0 = 0;
+                for (size_t k = 0; k < g.shapes.size(); ++k)
+                    if (g.shapes[k].epb == want && g.shapes[k].xcd) { k0 = (int)k; break; }
+                select(g, k0, false);
             }
-            for (int b = 0; b < te; ++b) {
-                const int j = xcd_logical(b, ne);
-                eh[b] = j < ne ? le_s[j] : 0;
-                eh[te + b] = j < ne ? le_l[j] : -1;
-            }
-            for (int b = 0; b < tn; ++b) {
-                const int j = xcd_logical(b, nn);
-                nh[b] = j < nn ? ln_s[j] : 0;
-                nh[tn + b] = j < nn ? ln_l[j] : -1;
-            }
-            char *base = (char *)dmem;
-            g.desc = reinterpret_cast<SolveDesc *>(base + o_desc);
-            g.ep = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_e), reinterpret_cast<int *>(base + o_e) + te, te,
-                              0, g.epb, te};
-            g.np = LaunchPlan{g.desc, reinterpret_cast<int *>(base + o_n), reinterpret_cast<int *>(base + o_n) + tn, tn,
-                              0, 0, tn};
-            g.diag_out = reinterpret_cast<double *>(base + o_d);
         }
         if (total) {
             if (hipMemcpyAsync(dmem, host.data(), total, hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -247,12 +382,47 @@ extern "C" slbm_status slbm_batch_remove(slbm_batch *b, slbm_ctx *c) {
 
 extern "C" int slbm_batch_size(const slbm_batch *b) { return b ? (int)b->members.size() : 0; }
 
+extern "C" slbm_status slbm_batch_set_autotune(slbm_batch *b, int on) {
+    if (!b || (on != 0 && on != 1)) return SLBM_EINVAL;
+    b->autotune = on == 1;
+    return SLBM_OK;
+}
+
+extern "C" slbm_status slbm_batch_shapes(slbm_batch *b, slbm_batch_shape *out, int max, int *count) {
+    if (!b || !count || max < 0 || (max > 0 && !out)) return SLBM_EINVAL;
+    if (b->dirty && !b->members.empty())
+        if (slbm_status s = b->rebuild()) return s;
+    const int ng = b->members.empty() ? 0 : (int)b->groups.size();
+    *count = ng;
+    for (int gi = 0; gi < std::min(ng, max); ++gi) {
+        const auto &g = b->groups[gi];
+        slbm_batch_shape &r = out[gi];
+        r = slbm_batch_shape{};
+        r.dim = g.d;
+        r.order = g.N;
+        r.fused = g.fused ? 1 : 0;
+        r.members = (int)g.idx.size();
+        r.elements = g.elements;
+        r.n_shapes = std::min((int)g.shapes.size(), SLBM_MAX_SHAPES);
+        for (int k = 0; k < r.n_shapes; ++k) {
+            r.epb[k] = g.shapes[k].epb;
+            r.xcd[k] = g.shapes[k].xcd ? 1 : 0;
+            r.us_per_step[k] = g.shapes[k].us;
+        }
+        r.chosen = g.pick;
+        r.measured = g.measured ? 1 : 0;
+    }
+    return SLBM_OK;
+}
+
 extern "C" slbm_status slbm_batch_step(slbm_batch *b, int64_t n) {
     if (!b || n < 0) return SLBM_EINVAL;
     if (b->members.empty() || n == 0) return SLBM_OK;
     if (b->dirty)
         if (slbm_status s = b->rebuild()) return s;
-    if (b->run(n)) return SLBM_EDEVICE;
+    int64_t done = 0;
+    if (b->autotune && (done = b->tune_pending(n)) < 0) return SLBM_EDEVICE;
+    if (b->run(n - done)) return SLBM_EDEVICE;
     for (slbm_ctx *c : b->members) c->step += n;
     return SLBM_OK;
 }

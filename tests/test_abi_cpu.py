@@ -166,3 +166,19 @@ def test_time_kernel_and_wall_face_errors(L):
                          wf.ctypes.data, wc.ctypes.data, wu.ctypes.data)
     assert st == P.binding.SLBM_EINVAL and b"duplicate" in L.slbm_last_error(h)
     L.slbm_destroy(h)
+
+
+def test_batch_tuning_argument_errors(L):
+    """Autotuning entry points: argument errors and the empty batch (no GPU needed)."""
+    import paper_2609_00535_amd as P
+    b = C.c_void_p()
+    assert L.slbm_batch_create(None, C.byref(b)) == 0
+    assert L.slbm_batch_set_autotune(b, 2) == P.binding.SLBM_EINVAL
+    assert L.slbm_batch_set_autotune(None, 1) == P.binding.SLBM_EINVAL
+    assert L.slbm_batch_set_autotune(b, 0) == 0 and L.slbm_batch_set_autotune(b, 1) == 0
+    cnt = C.c_int(-1)
+    assert L.slbm_batch_shapes(b, None, 0, C.byref(cnt)) == 0 and cnt.value == 0
+    assert L.slbm_batch_shapes(b, None, 1, C.byref(cnt)) == P.binding.SLBM_EINVAL
+    assert L.slbm_batch_shapes(b, None, -1, C.byref(cnt)) == P.binding.SLBM_EINVAL
+    assert L.slbm_batch_shapes(b, None, 0, None) == P.binding.SLBM_EINVAL
+    L.slbm_batch_destroy(b)

@@ -4,7 +4,8 @@ The bar is the relative infinity-norm difference ||gpu - oracle|| / ||oracle|| o
 and u.  Both implementations follow the same expression trees (GLL contractions by fma,
 no other contraction), so they usually agree bit for bit; the asserted tolerance is the
 1e-11 of the method's parity target, far above the 1e-14 (rho) / 2e-11 (u) spread that
-FMA contraction alone produces after 1000 steps of config 1.
+FMA contraction alone produces after 1000 steps of the isolated droplet c1 (8x8 quads,
+N=4).
 """
 import numpy as np
 import pytest
@@ -320,3 +321,56 @@ def test_batch_mixed_paths_and_wide_blocks(P, monkeypatch):
     b.step(12)
     for a, m in zip(alone, inbatch):
         assert np.array_equal(a, m.get_state()[0])
+
+
+def test_batch_autotune_same_bits(P):
+    """The autotuner times every launch shape of a group on the members' own steps and
+    switches shapes between steps: members still evolve exactly as alone and as in an
+    untuned batch, advance exactly the steps asked for, and a group of a key already
+    timed reuses that timing after a membership change."""
+    import torch
+    stream = torch.cuda.current_stream()
+    mk = [lambda: cases.c2(theta_deg=50.0), lambda: cases.c2(theta_deg=110.0),
+          lambda: cases.small_flat(), lambda: cases.small_sphere(),
+          lambda: cases.small_flat(theta_deg=120.0, N=6)]
+    tuned, plain = P.Batch(stream), P.Batch(stream)
+    plain.set_autotune(False)
+    alone, mt, mp = [], [], []
+    for f in mk:
+        c = f()
+        print(f"[autotune] member {c.name} E={c.mesh.E} N={c.N}", flush=True)
+        a = P.Solve(c)
+        a.init_tanh()
+        a.step(40)
+        alone.append(a.get_state()[0])
+        for b, lst in ((tuned, mt), (plain, mp)):
+            m = P.Solve(c)
+            m.init_tanh()
+            b.add(m)
+            lst.append(m)
+    tuned.step(7)    # too few steps to time a group of 4 shapes (16 steps)
+    assert not any(g["measured"] for g in tuned.shapes())
+    tuned.step(33)   # times every group
+    plain.step(40)
+    for a, m, q in zip(alone, mt, mp):
+        assert np.array_equal(a, m.get_state()[0])
+        assert np.array_equal(a, q.get_state()[0])
+        assert m.info().step == 40
+    sh = tuned.shapes()
+    # groups: 2-D N=6 (both c2 and the N=6 flat cap), 2-D N=4, 3-D N=4
+    assert len(sh) == 3 and sum(g["members"] for g in sh) == len(mk)
+    for g in sh:
+        us = [s["us_per_step"] for s in g["shapes"]]
+        print(f"[autotune] d={g['dim']} N={g['N']} fused={g['fused']} us={us} chosen={g['chosen']}",
+              flush=True)
+        assert len(us) == 4 and g["measured"] and min(us) > 0.0
+        assert us[g["chosen"]] == min(us)
+    assert not any(g["measured"] for g in plain.shapes())
+    # dropping a c2 member (2-D N=6 group) keeps the 2-D N=4 group, its key and its
+    # timed shape
+    tuned.remove(mt[0])
+    sh2 = {(g["dim"], g["N"]): g for g in tuned.shapes()}
+    g4 = [g for g in sh if g["dim"] == 2 and g["N"] == 4][0]
+    assert sh2[(2, 4)]["measured"] and sh2[(2, 4)]["chosen"] == g4["chosen"]
+    tuned.step(3)
+    assert np.all(np.isfinite(mt[1].get_state()[0]))
