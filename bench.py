@@ -123,6 +123,58 @@ def copy_calibration(torch, mib: int, reps: int = 3):
                                  "bytes_written": n * 8, "launches": reps}}
 
 
+def batch_bench(P, torch, n_req: int, steps: int, warmup: int = 40, seed: int = 5):
+    """Batched stepping: n_req solves of the request mix (see serving_bench) advanced as one
+    batch, against the same solves stepped one at a time.  The warm-up covers the launch
+    shape autotuner (four steps per candidate shape of each group).  Both timings are HIP
+    events on the solves' stream around graph-replayed steps, inputs resident."""
+    from synth import cases
+    reqs = cases.request_stream(n_req, seed=seed)
+    stream = torch.cuda.Stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        ss = []
+        for r in reqs:
+            s = P.Solve(cases.request_case(r), stream=stream)
+            s.init_tanh()
+            ss.append(s)
+        ng = sum(s.Ng for s in ss)
+        b = P.Batch(stream)
+        for s in ss:
+            b.add(s)
+        b.step(warmup)
+        torch.cuda.synchronize()
+        t0, t1 = ev(), ev()
+        t0.record(stream)
+        b.step(steps)
+        t1.record(stream)
+        t1.synchronize()
+        ms_batch = t0.elapsed_time(t1) / steps
+        shapes = b.shapes()
+        del b
+        # one at a time: every solve's own graph-replayed steps
+        plain_ms = 0.0
+        p_steps = max(10, steps // 5)
+        for s in ss:
+            s.step(2)
+            a, z = ev(), ev()
+            a.record(stream)
+            s.step(p_steps)
+            z.record(stream)
+            z.synchronize()
+            plain_ms += a.elapsed_time(z) / p_steps
+    return {
+        "members": n_req, "steps": steps, "warmup": warmup, "n_global_total": int(ng),
+        "ms_per_step": ms_batch, "node_updates_per_s": ng / (ms_batch * 1e-3),
+        "plain_ms_per_step_all_members": plain_ms,
+        "batched_over_plain": plain_ms / ms_batch,
+        "groups": [{"lattice": f"D{g['dim']}Q{9 if g['dim'] == 2 else 19}", "N": g["N"],
+                    "fused": g["fused"], "members": g["members"], "elements": g["elements"],
+                    "chosen": g["shapes"][g["chosen"]], "timed": g["measured"],
+                    "candidates": g["shapes"]} for g in shapes],
+    }
+
+
 def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
                   ke_stop: float = 1e-20, max_slots: int = 256, seed: int = 5):
     """Request sweep c5 (reduced): n_req droplet requests (flat or cylinder wall, N in {4,6,8},
@@ -220,6 +272,11 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-steps", type=int, default=2000)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--batch-members", type=int, default=256,
+                    help="request-mix solves in the batched-stepping measurement (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched-stepping measurement (one JSON line)")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--kernel-reps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=300)
@@ -241,6 +298,13 @@ def main():
         sys.exit(1)
     if args.copy_calibration > 0:
         print(json.dumps(copy_calibration(torch, args.copy_calibration)))
+        return
+    if args.batch_only:
+        out = batch_bench(P, torch, args.batch_members, args.batch_steps)
+        out.update({"metric": "batched FP64 node-updates/s", "value": out["node_updates_per_s"],
+                    "unit": "node-updates/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+                    "data": "synthetic", "config": {"workload": f"{args.batch_members} request-mix solves"}})
+        print(json.dumps(out))
         return
     if args.workload == "c5":
         out = serving_bench(P, torch, args.serve_requests, args.serve_max_steps)
@@ -306,6 +370,8 @@ def main():
                      "kernel_ms_per_step": {k: v[0] / args.profile_steps for k, v in prof.items()}},
     }
     if not args.no_serving and args.workload == "c2":
+        if args.batch_members > 0:
+            out["batch"] = batch_bench(P, torch, args.batch_members, args.batch_steps)
         out["serving"] = serving_bench(P, torch, args.serve_requests, args.serve_max_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_steps)
