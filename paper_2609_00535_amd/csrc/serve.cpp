@@ -83,17 +83,54 @@ struct slbm_batch {
         graph[0] = graph[1] = nullptr;
     }
 
-    int enqueue_group(const Group &g, const LaunchPlan &ep, const LaunchPlan &np, int64_t n) const {
-        return enqueue_steps(g.d, g.N, ep, np, n, stream, g.fused);
+    int enqueue_group(const Group &g, const LaunchPlan &ep, const LaunchPlan &np, int64_t n,
+                      void *on = nullptr) const {
+        return enqueue_steps(g.d, g.N, ep, np, n, on ? on : stream, g.fused);
+    }
+
+    // Concurrent groups: the groups share no data, so each group's chain of steps runs on a
+    // stream of its own, forked from and joined back into the batch's stream by events (in a
+    // captured graph these are parallel branches).  Small groups then overlap their launch
+    // and latency floors, and large ones each other's tails.
+    bool concurrent = true;
+    std::vector<void *> side;     // hipStream_t per group (default priority)
+    std::vector<void *> join_ev;  // hipEvent_t per group
+    void *fork_ev = nullptr;      // hipEvent_t
+
+    int ensure_side() {
+        if (!fork_ev && hipEventCreateWithFlags((hipEvent_t *)&fork_ev, hipEventDisableTiming) != hipSuccess)
+            return (int)hipErrorOutOfMemory;
+        while (side.size() < groups.size()) {
+            hipStream_t s = nullptr;
+            hipEvent_t e = nullptr;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return (int)hipErrorOutOfMemory;
+            side.push_back(s);
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return (int)hipErrorOutOfMemory;
+            join_ev.push_back(e);
+        }
+        return 0;
     }
 
     int enqueue(int64_t n) {
-        for (int64_t s = 0; s < n; ++s)
-            for (auto &g : groups) {
-                const int e = enqueue_group(g, g.ep, g.np, 1);
-                if (e) return e;
-            }
-        return 0;
+        if (!concurrent || groups.size() < 2) {
+            for (int64_t s = 0; s < n; ++s)
+                for (auto &g : groups) {
+                    const int e = enqueue_group(g, g.ep, g.np, 1);
+                    if (e) return e;
+                }
+            return 0;
+        }
+        int e = ensure_side();
+        hipStream_t st = (hipStream_t)stream;
+        if (!e) e = (int)hipEventRecord((hipEvent_t)fork_ev, st);
+        for (size_t gi = 0; gi < groups.size() && !e; ++gi) {
+            hipStream_t ss = (hipStream_t)side[gi];
+            e = (int)hipStreamWaitEvent(ss, (hipEvent_t)fork_ev, 0);
+            if (!e) e = enqueue_group(groups[gi], groups[gi].ep, groups[gi].np, n, ss);
+            if (!e) e = (int)hipEventRecord((hipEvent_t)join_ev[gi], ss);
+            if (!e) e = (int)hipStreamWaitEvent(st, (hipEvent_t)join_ev[gi], 0);
+        }
+        return e;
     }
 
     int run(int64_t n) {
@@ -205,10 +242,11 @@ struct slbm_batch {
 
     ~slbm_batch() {
         drop_graphs();
-        if (dmem) {
-            (void)hipStreamSynchronize((hipStream_t)stream);
-            (void)hipFree(dmem);
-        }
+        if (dmem || !side.empty()) (void)hipStreamSynchronize((hipStream_t)stream);
+        for (void *x : side) (void)hipStreamDestroy((hipStream_t)x);
+        for (void *x : join_ev) (void)hipEventDestroy((hipEvent_t)x);
+        if (fork_ev) (void)hipEventDestroy((hipEvent_t)fork_ev);
+        if (dmem) (void)hipFree(dmem);
     }
 
     // element blocks of member c under a block shape
@@ -358,6 +396,8 @@ extern "C" slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out) {
     (*out)->stream = hip_stream;
     const char *ng = std::getenv("SLBM_NO_GRAPH");
     (*out)->use_graph = !(ng && ng[0] == '1');
+    const char *sg = std::getenv("SLBM_SERIAL_GROUPS");
+    (*out)->concurrent = !(sg && sg[0] == '1');
     return SLBM_OK;
 }
 
