@@ -121,7 +121,7 @@ int launch_stream(int d, int N, const LaunchPlan &p, int stage, void *stream);
 int launch_rk(int d, int N, const LaunchPlan &p, int stage, void *stream);
 int launch_density(int d, int N, const LaunchPlan &p, int which, void *stream);
 int launch_diag(int d, int N, const LaunchPlan &p, void *stream);
-int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream);
+int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream, double *out = nullptr);
 // fused path: four element kernels per stage sequence (A: mu + gradients, B: collision +
 // stage-1 residual, C: DSS + Runge-Kutta combine + Laplacian residual, D: mu + residual)
 constexpr int kCopySlots[2] = {4, 8};  // register copy slots of the fused kernels (2-D, 3-D)

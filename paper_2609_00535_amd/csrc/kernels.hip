@@ -56,8 +56,9 @@ int launch_fB(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PIC
 int launch_fC(int d, int N, const LaunchPlan &p, int stage, void *stream) { return SLBM_PICK(fC, p, stage, stream); }
 int launch_fD(int d, int N, const LaunchPlan &p, int stage, void *stream) { return SLBM_PICK(fD, p, stage, stream); }
 
-// second pass of the KE / mass reduction: one block per member
-__global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *desc) {
+// second pass of the KE / mass reduction: one block per member; also into out[2 * member]
+// when out is given (a batch reads all members with one copy)
+__global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *desc, double *out) {
     __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
     const SolveDesc &sd = desc[blockIdx.x];
     const int nb = (sd.Ng + kNodeThreads - 1) / kNodeThreads;
@@ -82,12 +83,16 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag_final(const SolveDesc *de
     if (tid == 0) {
         sd.diag[0] = smax[0];
         sd.diag[1] = ssum[0];
+        if (out) {
+            out[2 * blockIdx.x] = smax[0];
+            out[2 * blockIdx.x + 1] = ssum[0];
+        }
     }
 }
 
-int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream) {
+int launch_diag_final(const SolveDesc *desc, int nsolves, void *stream, double *out) {
     if (nsolves <= 0) return 0;
-    k_diag_final<<<nsolves, kNodeThreads, 0, (hipStream_t)stream>>>(desc);
+    k_diag_final<<<nsolves, kNodeThreads, 0, (hipStream_t)stream>>>(desc, out);
     return (int)hipGetLastError();
 }
 

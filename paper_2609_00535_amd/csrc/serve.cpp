@@ -477,14 +477,12 @@ extern "C" slbm_status slbm_batch_kinetic_energy(slbm_batch *b, double *ke, doub
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         auto &g = b->groups[gi];
         int e = launch_diag(g.d, g.N, g.np, b->stream);
-        if (e == 0) e = launch_diag_final(g.desc, (int)g.idx.size(), b->stream);
+        if (e == 0) e = launch_diag_final(g.desc, (int)g.idx.size(), b->stream, g.diag_out);
         if (e) return SLBM_EDEVICE;
         outs[gi].resize(2 * g.idx.size());
-        // diag_final writes each member's own diag slot; gather them
-        for (size_t k = 0; k < g.idx.size(); ++k)
-            if (hipMemcpyAsync(&outs[gi][2 * k], b->members[g.idx[k]]->desc.diag, 2 * sizeof(double),
-                               hipMemcpyDeviceToHost, st) != hipSuccess)
-                return SLBM_EDEVICE;
+        if (hipMemcpyAsync(outs[gi].data(), g.diag_out, 2 * sizeof(double) * g.idx.size(),
+                           hipMemcpyDeviceToHost, st) != hipSuccess)
+            return SLBM_EDEVICE;
     }
     if (hipStreamSynchronize(st) != hipSuccess) return SLBM_EDEVICE;
     for (size_t gi = 0; gi < b->groups.size(); ++gi)
