@@ -759,15 +759,17 @@ template <int D> struct CopyList {
 };
 // element node n (i fastest) on the element's boundary?  Nodes inside an element belong to
 // it alone (the fused path is selected only for meshes where that holds).
+// (bitwise, not short-circuit: a chain of || becomes a chain of divergent branches, and
+// hipcc has been seen to reuse a live register inside such a chain at N = 3 in 2-D)
 template <int D, int NP>
 __device__ __forceinline__ bool on_elem_boundary(int n) {
     const int i = n % NP, j = (n / NP) % NP;
-    bool b = i == 0 || i == NP - 1 || j == 0 || j == NP - 1;
+    int b = (int)(i == 0) | (int)(i == NP - 1) | (int)(j == 0) | (int)(j == NP - 1);
     if constexpr (D == 3) {
         const int k = n / (NP * NP);
-        b = b || k == 0 || k == NP - 1;
+        b |= (int)(k == 0) | (int)(k == NP - 1);
     }
-    return b;
+    return b != 0;
 }
 
 template <int D, int NP, bool PRED>
@@ -1329,19 +1331,22 @@ __global__ __launch_bounds__(Split2<N>::NT) void k_fD4(LaunchPlan p, int stage) 
 }
 
 // narrow (one element per block) launches of B, C, D: the population-split kernels in 2-D
+// where four groups of an element's lanes fit in one block of at most 1024 threads
+// (N <= 14), the one-lane-per-node kernels otherwise
+template <int DD, int NN> constexpr bool kSplit = DD == 2 && Split2<NN>::NT <= 1024;
 template <int DD, int NN, bool S>
 inline void launch_narrow_fB(const LaunchPlan &p, hipStream_t st) {
-    if constexpr (DD == 2) k_fB4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p);
+    if constexpr (kSplit<DD, NN>) k_fB4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p);
     else k_fB<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p);
 }
 template <int DD, int NN, bool S>
 inline void launch_narrow_fC(const LaunchPlan &p, hipStream_t st, int stage) {
-    if constexpr (DD == 2) k_fC4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p, stage);
+    if constexpr (kSplit<DD, NN>) k_fC4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p, stage);
     else k_fC<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p, stage);
 }
 template <int DD, int NN, bool S>
 inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
-    if constexpr (DD == 2) k_fD4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p, stage);
+    if constexpr (kSplit<DD, NN>) k_fD4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p, stage);
     else k_fD<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p, stage);
 }
 

@@ -165,6 +165,49 @@ def walled_droplet(nx: int = 8, N: int = 4, L: float = 64.0, R: float = 16.0,
                 steps=10500)
 
 
+ORDERS_2D = (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16)
+ORDERS_3D = (2, 3, 4, 5, 6)
+
+
+def order_case(dim: int, N: int) -> Case:
+    """Small walled, jittered mesh of order N for the order sweep: a 70-degree wetting
+    wall and a sessile cap, 5x3 quads (2-D) or 2x3x2 hexes (3-D, D3Q19); the element
+    counts are not multiples of the wide block sizes, so wide launches end ragged."""
+    cb = math.cos(math.radians(70.0))
+    if dim == 2:
+        return small_flat(theta_deg=70.0, nx=5, ny=3, N=N, Lx=40.0, Ly=24.0, R=9.0)
+    m = meshes.box3d(2, 3, 2, N, (16.0, 24.0, 16.0), periodic=(True, False, True), jitter=0.15,
+                     seed=16, cos_theta={"y-": cb}, name=f"order3d_N{N}")
+    R = 7.0
+    return Case(f"order3d_N{N}", m, LATTICE_D3Q19, x0=(8.0, -R * cb, 8.0), R=R, seed=16, steps=10,
+                wall_geom=dict(kind="plane", point=(0.0, 0.0, 0.0), normal=(0.0, -1.0, 0.0)),
+                theta_deg=70.0)
+
+
+def wide_case(dim: int, N: int) -> Case:
+    """Mesh of order N large enough that a single solve launches its element kernels in
+    wide blocks (at least 256 blocks of 256 // (N+1)^d elements) with a ragged last block:
+    a walled jittered box (2-D, 70-degree wetting bottom wall) or a periodic-x walled-y
+    box (3-D)."""
+    nloc = (N + 1) ** dim
+    epb = max(1, 256 // nloc)
+    E = 256 * epb + max(1, epb // 2)
+    if dim == 2:
+        ny = max(2, int(round((E / 2) ** 0.5)))
+        nx = -(-E // ny)
+        return small_flat(theta_deg=70.0, nx=nx, ny=ny, N=N, Lx=8.0 * nx, Ly=8.0 * ny,
+                          R=min(3.0 * ny, 24.0))
+    n = max(2, int(round(E ** (1.0 / 3.0))))
+    nz = -(-E // (n * n))
+    cb = math.cos(math.radians(70.0))
+    m = meshes.box3d(n, n, nz, N, (6.0 * n, 6.0 * n, 6.0 * nz), periodic=(True, False, True),
+                     jitter=0.1, seed=17, cos_theta={"y-": cb}, name=f"wide3d_N{N}")
+    R = 2.0 * n
+    return Case(f"wide3d_N{N}", m, LATTICE_D3Q19, x0=(3.0 * n, -R * cb, 3.0 * nz), R=R, seed=17,
+                steps=3, wall_geom=dict(kind="plane", point=(0.0, 0.0, 0.0), normal=(0.0, -1.0, 0.0)),
+                theta_deg=70.0)
+
+
 CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}
 
 

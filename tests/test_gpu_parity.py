@@ -82,7 +82,7 @@ def _run_pair(c, P, steps):
     return s, o
 
 
-def test_config1_1000_steps(P):
+def test_c1_isolated_droplet_1000_steps(P):
     """c1: D2Q9 isolated droplet, periodic, N=4, 1e-4 noise: 1000 steps, 1e-11 on rho, u."""
     c = cases.c1()
     s, o = _run_pair(c, P, 1000)
@@ -104,7 +104,7 @@ def test_walls_and_3d_parity(P, mk, steps):
     assert er <= TOL and eu <= TOL
 
 
-def test_config2_full_size(P):
+def test_c2_full_size(P):
     """c2 at full size (32x16 jittered quads, N=6, 60 deg wetting wall), 200 steps."""
     c = cases.c2()
     s, o = _run_pair(c, P, 200)
@@ -113,7 +113,7 @@ def test_config2_full_size(P):
     assert er <= TOL and eu <= TOL
 
 
-def test_config3_full_size(P):
+def test_c3_full_size(P):
     """c3 at full size (O-grid of 2048 curved quads, N=8, cylinder wall), 10 steps."""
     c = cases.c3()
     s, o = _run_pair(c, P, 10)
@@ -122,7 +122,7 @@ def test_config3_full_size(P):
     assert er <= TOL and eu <= TOL
 
 
-def test_config4_full_size(P):
+def test_c4_full_size(P):
     """c4 at full size (24000 curved hexes, N=5, D3Q19, sphere wall): the launch
     configuration the benchmark times, 2 steps against the oracle (~1 min of CPU)."""
     c = cases.c4()
@@ -374,3 +374,56 @@ def test_batch_autotune_same_bits(P):
     assert sh2[(2, 4)]["measured"] and sh2[(2, 4)]["chosen"] == g4["chosen"]
     tuned.step(3)
     assert np.all(np.isfinite(mt[1].get_state()[0]))
+
+
+ORDER_CASES = [(2, n) for n in cases.ORDERS_2D] + [(3, n) for n in cases.ORDERS_3D]
+
+
+def test_every_order_matches_oracle(P, monkeypatch):
+    """Every supported (lattice, N) on a small walled, jittered mesh with a wetting wall:
+    20 steps against the oracle (1e-11 on rho and u), the unfused path equal to the fused
+    one bit for bit, and all orders stepped as one autotuned batch (every launch shape of
+    every order, wide blocks ending ragged) equal to alone bit for bit."""
+    import torch
+    alone = {}
+    for d, n in ORDER_CASES:
+        c = cases.order_case(d, n)
+        s, o = _run_pair(c, P, 20)
+        er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+        print(f"[orders] d={d} N={n} E={c.mesh.E}: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+        assert np.all(np.isfinite(s.rho())) and er <= TOL and eu <= TOL
+        alone[(d, n)] = s.get_state()[0]
+        monkeypatch.setenv("SLBM_UNFUSED", "1")
+        su = P.Solve(c)
+        monkeypatch.delenv("SLBM_UNFUSED")
+        su.init_tanh()
+        su.step(20)
+        assert np.array_equal(su.get_state()[0], alone[(d, n)])
+    print("[orders] batch of every order", flush=True)
+    b = P.Batch(torch.cuda.current_stream())
+    members = {}
+    for d, n in ORDER_CASES:
+        m = P.Solve(cases.order_case(d, n))
+        m.init_tanh()
+        b.add(m)
+        members[(d, n)] = m
+    b.step(20)   # covers the tuner's 4 steps per shape (2 or 4 shapes per group)
+    for k, m in members.items():
+        assert np.array_equal(m.get_state()[0], alone[k]), k
+    sh = b.shapes()
+    assert len(sh) == len(ORDER_CASES) and all(g["measured"] for g in sh)
+
+
+WIDE_ORDERS = [(2, n) for n in range(2, 11)] + [(3, n) for n in (2, 3, 4)]
+
+
+@pytest.mark.parametrize("d,n", WIDE_ORDERS)
+def test_wide_single_solve_every_order(P, d, n):
+    """A single solve large enough for wide element blocks (at least 256 blocks, the last
+    one ragged) at every order where more than one element fits in a block: 3 steps
+    against the oracle."""
+    c = cases.wide_case(d, n)
+    s, o = _run_pair(c, P, 3)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[wide] d={d} N={n} E={c.mesh.E}: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert np.all(np.isfinite(s.rho())) and er <= TOL and eu <= TOL
