@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/semlbm.h"
@@ -252,20 +253,9 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         c->gcopy[4 * g + 2] = c->csr_idx[k0];
         c->gcopy[4 * g + 3] = c->csr_idx[nc > 1 ? k0 + 1 : k0];
     }
-    // per-local-node copy lists (fused path): the ascending local copies of its global node
+    // most local copies of any global node
     c->vmax = 0;
     for (int64_t g = 0; g < n_global; ++g) c->vmax = std::max<int>(c->vmax, c->csr_ptr[g + 1] - c->csr_ptr[g]);
-    // (kCopySlots[dim-2] rows, -1 padded, so the fused kernels load every slot without a
-    // branch)
-    c->lcp.clear();
-    if (c->vmax <= kCopySlots[dim - 2]) {
-        c->lcp.assign((size_t)kCopySlots[dim - 2] * Nl, -1);
-        for (int64_t l = 0; l < Nl; ++l) {
-            const int g = c->lgid[l];
-            for (int k = c->csr_ptr[g]; k < c->csr_ptr[g + 1]; ++k)
-                c->lcp[(size_t)(k - c->csr_ptr[g]) * Nl + l] = c->csr_idx[k];
-        }
-    }
     {
         // fused kernels finish each summation by gathering all copies at every copy: the
         // right trade for latency-bound meshes; large 3-D meshes (up to 8 copies per node,
@@ -275,21 +265,34 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         const bool large3d = dim == 3 && Nl > (int64_t)1 << 20;
         // nodes inside an element must belong to it alone (the fused kernels skip their
         // copy lists)
-        bool interior_single = true;
-        for (int64_t l = 0; l < Nl && interior_single; ++l) {
-            const int n = (int)(l % nloc);
-            bool bnd = false;
+        std::vector<char> on_bnd(nloc, 0);
+        for (int n = 0; n < nloc; ++n)
             for (int a = 0; a < dim; ++a) {
                 const int i = c->along(n, a);
-                bnd = bnd || i == 0 || i == N;
+                if (i == 0 || i == N) on_bnd[n] = 1;
             }
-            const int g = c->lgid[l];
-            if (!bnd && c->csr_ptr[g + 1] - c->csr_ptr[g] != 1) interior_single = false;
-        }
+        bool interior_single = true;
+        for (int64_t e = 0; e < E && interior_single; ++e)
+            for (int n = 0; n < nloc; ++n) {
+                const int g = c->lgid[e * nloc + n];
+                if (!on_bnd[n] && c->csr_ptr[g + 1] - c->csr_ptr[g] != 1) interior_single = false;
+            }
         const bool fits = c->vmax <= kCopySlots[dim - 2] && interior_single;
         c->fused = fits && !large3d;
         if (nf && nf[0] == '1') c->fused = false;
         if (ff && ff[0] == '1' && fits) c->fused = true;
+    }
+    // per-local-node copy lists (fused path only): the ascending local copies of its global
+    // node in kCopySlots[dim-2] rows, -1 padded, so the fused kernels load every slot
+    // without a branch
+    c->lcp.clear();
+    if (c->fused) {
+        c->lcp.assign((size_t)kCopySlots[dim - 2] * Nl, -1);
+        for (int64_t l = 0; l < Nl; ++l) {
+            const int g = c->lgid[l];
+            for (int k = c->csr_ptr[g]; k < c->csr_ptr[g + 1]; ++k)
+                c->lcp[(size_t)(k - c->csr_ptr[g]) * Nl + l] = c->csr_idx[k];
+        }
     }
     c->xyz.assign(xyz, xyz + Nl * dim);
     // --- metric terms, Jacobian, G, lumped mass ---
@@ -297,84 +300,127 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
     c->Ja.assign((size_t)dim * dim * Nl, 0.0);
     c->Gm.assign((size_t)ng * Nl, 0.0);
     std::vector<double> MA(n_global, 0.0);
-    std::vector<double> X(3 * nloc), dX(9 * nloc), V(3 * nloc), J(nloc);
-    double hmin = INFINITY;
-    std::vector<double> Jloc(9 * nloc);
-    for (int64_t e = 0; e < E; ++e) {
-        for (int n = 0; n < nloc; ++n)
-            for (int cc = 0; cc < dim; ++cc) X[cc * nloc + n] = xyz[(e * nloc + n) * dim + cc];
-        for (int cc = 0; cc < dim; ++cc)
-            for (int a = 0; a < dim; ++a)
-                for (int n = 0; n < nloc; ++n) dX[(cc * 3 + a) * nloc + n] = c->dline(&X[cc * nloc], n, a);
-        if (dim == 2) {
-            for (int n = 0; n < nloc; ++n) {
-                const double xa = dX[0 * nloc + n], xb = dX[1 * nloc + n];
-                const double ya = dX[3 * nloc + n], yb = dX[4 * nloc + n];
-                double *Jn = &Jloc[9 * n];
-                Jn[0] = yb; Jn[1] = -xb;   // J grad(xi)
-                Jn[3] = -ya; Jn[4] = xa;   // J grad(eta)
-                J[n] = xa * yb - xb * ya;
-            }
-        } else {
-            // conservative curl form (Kopriva 2006): J grad(xi_i)_c = -[curl_xi(x_l grad_xi x_m)]_i
-            for (int cn = 0; cn < 3; ++cn) {
-                const int cm = (cn + 1) % 3, cl = (cn + 2) % 3;
-                for (int k = 0; k < 3; ++k)
-                    for (int n = 0; n < nloc; ++n)
-                        V[k * nloc + n] = X[cl * nloc + n] * dX[(cm * 3 + k) * nloc + n];
-                for (int n = 0; n < nloc; ++n) {
-                    const double c0 = c->dline(&V[2 * nloc], n, 1) - c->dline(&V[1 * nloc], n, 2);
-                    const double c1 = c->dline(&V[0 * nloc], n, 2) - c->dline(&V[2 * nloc], n, 0);
-                    const double c2 = c->dline(&V[1 * nloc], n, 0) - c->dline(&V[0 * nloc], n, 1);
-                    Jloc[9 * n + 0 * 3 + cn] = -c0;
-                    Jloc[9 * n + 1 * 3 + cn] = -c1;
-                    Jloc[9 * n + 2 * 3 + cn] = -c2;
-                }
-            }
-            for (int n = 0; n < nloc; ++n) {
-                const double a0 = dX[0 * nloc + n], a1 = dX[3 * nloc + n], a2 = dX[6 * nloc + n];
-                const double b0 = dX[1 * nloc + n], b1 = dX[4 * nloc + n], b2 = dX[7 * nloc + n];
-                const double d0 = dX[2 * nloc + n], d1 = dX[5 * nloc + n], d2 = dX[8 * nloc + n];
-                const double cx = b1 * d2 - b2 * d1, cy = b2 * d0 - b0 * d2, cz = b0 * d1 - b1 * d0;
-                J[n] = a0 * cx + a1 * cy + a2 * cz;
-            }
-        }
+    std::vector<double> wJ(Nl);  // w_n J of every local node, summed into MA below
+    // per (direction, node): position along the direction and first node of its GLL line,
+    // so the derivative below does no integer division (same fma sequence as dline)
+    std::vector<int> ln_i(3 * nloc), ln_b(3 * nloc);
+    for (int a = 0; a < dim; ++a)
         for (int n = 0; n < nloc; ++n) {
-            const int64_t l = e * nloc + n;
-            if (!(J[n] > 0.0))
-                return c->fail(SLBM_EINVAL, "non-positive Jacobian %g in element %lld node %d", J[n],
-                               (long long)e, n);
-            for (int a = 0; a < dim; ++a)
-                for (int cc = 0; cc < dim; ++cc) c->Ja[(size_t)(a * dim + cc) * Nl + l] = Jloc[9 * n + a * 3 + cc];
-            int k = 0;
-            for (int a = 0; a < dim; ++a)
-                for (int b = a; b < dim; ++b) {
-                    double s = 0.0;
-                    for (int cc = 0; cc < dim; ++cc) s += Jloc[9 * n + a * 3 + cc] * Jloc[9 * n + b * 3 + cc];
-                    c->Gm[(size_t)k * Nl + l] = c->wn[n] * s / J[n];
-                    ++k;
-                }
-            MA[c->lgid[l]] += c->wn[n] * J[n];
+            ln_i[a * nloc + n] = c->along(n, a);
+            ln_b[a * nloc + n] = n - ln_i[a * nloc + n] * c->stride(a);
         }
-        for (int a = 0; a < dim; ++a) {
-            const int s = c->stride(a);
-            for (int n = 0; n < nloc; ++n) {
-                if (c->along(n, a) == N) continue;
-                double d2 = 0.0;
-                for (int cc = 0; cc < dim; ++cc) {
-                    const double dd = X[cc * nloc + n + s] - X[cc * nloc + n];
-                    d2 += dd * dd;
+    const int Np = c->Np;
+    const double *Dm = c->Dm.data();
+    auto dl = [&](const double *h, int n, int a) {
+        const int i = ln_i[a * nloc + n], b = ln_b[a * nloc + n], st = c->stride(a);
+        const double *row = Dm + i * Np;
+        double acc = 0.0;
+        for (int m = 0; m < Np; ++m) acc = std::fma(row[m], h[b + m * st], acc);
+        return acc;
+    };
+    // metric terms of the elements [e0, e1): Ja, G, wJ and the smallest node spacing; the
+    // first element with a non-positive Jacobian (in element order) is reported back
+    struct Part { double hmin = INFINITY; int64_t bad_e = -1; int bad_n = 0; double bad_J = 0.0; };
+    auto metrics = [&](int64_t e0, int64_t e1, Part &pt) {
+        std::vector<double> X(3 * nloc), dX(9 * nloc), V(3 * nloc), J(nloc), Jloc(9 * nloc);
+        double hmin = INFINITY;
+        for (int64_t e = e0; e < e1; ++e) {
+            for (int n = 0; n < nloc; ++n)
+                for (int cc = 0; cc < dim; ++cc) X[cc * nloc + n] = xyz[(e * nloc + n) * dim + cc];
+            for (int cc = 0; cc < dim; ++cc)
+                for (int a = 0; a < dim; ++a)
+                    for (int n = 0; n < nloc; ++n) dX[(cc * 3 + a) * nloc + n] = dl(&X[cc * nloc], n, a);
+            if (dim == 2) {
+                for (int n = 0; n < nloc; ++n) {
+                    const double xa = dX[0 * nloc + n], xb = dX[1 * nloc + n];
+                    const double ya = dX[3 * nloc + n], yb = dX[4 * nloc + n];
+                    double *Jn = &Jloc[9 * n];
+                    Jn[0] = yb; Jn[1] = -xb;   // J grad(xi)
+                    Jn[3] = -ya; Jn[4] = xa;   // J grad(eta)
+                    J[n] = xa * yb - xb * ya;
                 }
-                const double d = std::sqrt(d2);
-                if (d < hmin) hmin = d;
+            } else {
+                // conservative curl form (Kopriva 2006): J grad(xi_i)_c = -[curl_xi(x_l grad_xi x_m)]_i
+                for (int cn = 0; cn < 3; ++cn) {
+                    const int cm = (cn + 1) % 3, cl = (cn + 2) % 3;
+                    for (int k = 0; k < 3; ++k)
+                        for (int n = 0; n < nloc; ++n)
+                            V[k * nloc + n] = X[cl * nloc + n] * dX[(cm * 3 + k) * nloc + n];
+                    for (int n = 0; n < nloc; ++n) {
+                        const double c0 = dl(&V[2 * nloc], n, 1) - dl(&V[1 * nloc], n, 2);
+                        const double c1 = dl(&V[0 * nloc], n, 2) - dl(&V[2 * nloc], n, 0);
+                        const double c2 = dl(&V[1 * nloc], n, 0) - dl(&V[0 * nloc], n, 1);
+                        Jloc[9 * n + 0 * 3 + cn] = -c0;
+                        Jloc[9 * n + 1 * 3 + cn] = -c1;
+                        Jloc[9 * n + 2 * 3 + cn] = -c2;
+                    }
+                }
+                for (int n = 0; n < nloc; ++n) {
+                    const double a0 = dX[0 * nloc + n], a1 = dX[3 * nloc + n], a2 = dX[6 * nloc + n];
+                    const double b0 = dX[1 * nloc + n], b1 = dX[4 * nloc + n], b2 = dX[7 * nloc + n];
+                    const double d0 = dX[2 * nloc + n], d1 = dX[5 * nloc + n], d2 = dX[8 * nloc + n];
+                    const double cx = b1 * d2 - b2 * d1, cy = b2 * d0 - b0 * d2, cz = b0 * d1 - b1 * d0;
+                    J[n] = a0 * cx + a1 * cy + a2 * cz;
+                }
+            }
+            for (int n = 0; n < nloc; ++n) {
+                const int64_t l = e * nloc + n;
+                if (!(J[n] > 0.0)) {
+                    pt.bad_e = e;
+                    pt.bad_n = n;
+                    pt.bad_J = J[n];
+                    return;
+                }
+                for (int a = 0; a < dim; ++a)
+                    for (int cc = 0; cc < dim; ++cc) c->Ja[(size_t)(a * dim + cc) * Nl + l] = Jloc[9 * n + a * 3 + cc];
+                int k = 0;
+                for (int a = 0; a < dim; ++a)
+                    for (int b = a; b < dim; ++b) {
+                        double s = 0.0;
+                        for (int cc = 0; cc < dim; ++cc) s += Jloc[9 * n + a * 3 + cc] * Jloc[9 * n + b * 3 + cc];
+                        c->Gm[(size_t)k * Nl + l] = c->wn[n] * s / J[n];
+                        ++k;
+                    }
+                wJ[l] = c->wn[n] * J[n];
+            }
+            for (int a = 0; a < dim; ++a) {
+                const int s = c->stride(a);
+                for (int n = 0; n < nloc; ++n) {
+                    if (ln_i[a * nloc + n] == N) continue;
+                    double d2 = 0.0;
+                    for (int cc = 0; cc < dim; ++cc) {
+                        const double dd = X[cc * nloc + n + s] - X[cc * nloc + n];
+                        d2 += dd * dd;
+                    }
+                    const double d = std::sqrt(d2);
+                    if (d < hmin) hmin = d;
+                }
             }
         }
-        // keep the element's metric for the wall tables below
-        if (n_wall_faces > 0) {
-            // (nothing: wall tables read c->Ja directly)
-        }
+        pt.hmin = hmin;
+    };
+    // large meshes: element ranges on several host threads (each range writes only its own
+    // nodes' entries)
+    const int64_t kPerThread = 512;
+    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({8, (E + kPerThread - 1) / kPerThread,
+                                                                (int64_t)std::max(1u, std::thread::hardware_concurrency())}));
+    std::vector<Part> parts(nth);
+    {
+        std::vector<std::thread> th;
+        for (int t = 1; t < nth; ++t)
+            th.emplace_back(metrics, E * t / nth, E * (t + 1) / nth, std::ref(parts[t]));
+        metrics(0, E / nth, parts[0]);
+        for (auto &x : th) x.join();
     }
-    // MA accumulated in local order over the internal numbering equals the caller-order sum
+    double hmin = INFINITY;
+    for (const Part &pt : parts) {
+        if (pt.bad_e >= 0)
+            return c->fail(SLBM_EINVAL, "non-positive Jacobian %g in element %lld node %d", pt.bad_J,
+                           (long long)pt.bad_e, pt.bad_n);
+        hmin = std::min(hmin, pt.hmin);
+    }
+    // lumped mass: wJ summed in local order over the internal numbering (the caller-order sum)
+    for (int64_t l = 0; l < Nl; ++l) MA[c->lgid[l]] += wJ[l];
     c->Minv.resize(n_global);
     c->MA = MA;
     for (int64_t g = 0; g < n_global; ++g) c->Minv[g] = 1.0 / MA[g];

@@ -136,9 +136,12 @@ struct slbm_batch {
     int run(int64_t n) {
         if (n <= 0) return 0;
         if (use_graph && stream != nullptr) {
+            // each graph is captured when a call first needs it (n % 10 single steps, n / 10
+            // runs of ten)
             const int sizes[2] = {1, 10};
+            const bool need[2] = {n % 10 != 0, n >= 10};
             for (int k = 0; k < 2 && use_graph; ++k)
-                if (!graph[k]) {
+                if (need[k] && !graph[k]) {
                     struct A { slbm_batch *b; int steps; } a{this, sizes[k]};
                     auto fn = [](void *, void *p) -> int {
                         A *x = (A *)p;
@@ -398,6 +401,8 @@ extern "C" slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out) {
     (*out)->use_graph = !(ng && ng[0] == '1');
     const char *sg = std::getenv("SLBM_SERIAL_GROUPS");
     (*out)->concurrent = !(sg && sg[0] == '1');
+    const char *at = std::getenv("SLBM_AUTOTUNE");
+    (*out)->autotune = !(at && at[0] == '0');
     return SLBM_OK;
 }
 
@@ -685,6 +690,7 @@ struct slbm_server {
     int preparing = 0;
     bool stopping = false;
     std::vector<std::thread> workers;
+    static constexpr std::chrono::milliseconds kColdStartWait{50};
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -831,6 +837,14 @@ extern "C" slbm_status slbm_server_submit(slbm_server *s, const slbm_request *r,
 
 extern "C" slbm_status slbm_server_tick(slbm_server *s, int *pending) {
     if (!s) return SLBM_EINVAL;
+    // cold start (no active solve, the device idle): let the preparations already submitted
+    // finish (at most kColdStartWait) so that they start together rather than one round
+    // apart, which would leave their last round with only the late ones on the device
+    if (s->active.empty()) {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv.wait_for(lk, slbm_server::kColdStartWait,
+                       [&] { return s->stopping || (s->preparing == 0 && s->to_prepare.empty()); });
+    }
     // admission: prepared requests in submission order while slots and arena bytes allow
     for (;;) {
         if ((int)s->active.size() >= s->cfg.max_slots) break;
