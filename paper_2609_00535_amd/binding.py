@@ -415,10 +415,12 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, case, noise: float | None = None) -> int:
+    def submit(self, case, noise: float | None = None, ke_limit: float = 0.0) -> int:
+        """Queue a solve of ``case``; ``ke_limit`` > 0 marks it diverged (SLBM_EDIVERGED)
+        at the first check with KE_max above it (default limit 1)."""
         m = case.mesh
         r = Request()
-        r.params = make_params(case)
+        r.params = make_params(case, 0, ke_limit)
         arrs = dict(xyz=np.ascontiguousarray(m.xyz, dtype=np.float64),
                     gid=np.ascontiguousarray(m.gid, dtype=np.int32),
                     wf=np.ascontiguousarray(m.wall_face, dtype=np.int32),

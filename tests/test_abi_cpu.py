@@ -182,3 +182,25 @@ def test_batch_tuning_argument_errors(L):
     assert L.slbm_batch_shapes(b, None, -1, C.byref(cnt)) == P.binding.SLBM_EINVAL
     assert L.slbm_batch_shapes(b, None, 0, None) == P.binding.SLBM_EINVAL
     L.slbm_batch_destroy(b)
+
+
+def test_server_config_errors(L):
+    """Server creation rejects a missing arena and non-positive slots or check cadence
+    (no GPU needed); a valid server that never ran is created and destroyed cleanly."""
+    import paper_2609_00535_amd as P
+    B = P.binding
+    cfg = B.ServerCfg()
+    cfg.arena, cfg.arena_bytes, cfg.hip_stream = None, 1 << 20, None
+    cfg.max_slots, cfg.check_every, cfg.ke_stop, cfg.max_steps = 4, 100, 1e-20, 1000
+    h = C.c_void_p()
+    assert L.slbm_server_create(C.byref(cfg), C.byref(h)) == B.SLBM_EINVAL
+    cfg.arena = 256
+    cfg.max_slots = 0
+    assert L.slbm_server_create(C.byref(cfg), C.byref(h)) == B.SLBM_EINVAL
+    cfg.max_slots, cfg.check_every = 4, 0
+    assert L.slbm_server_create(C.byref(cfg), C.byref(h)) == B.SLBM_EINVAL
+    cfg.check_every = 100
+    assert L.slbm_server_create(C.byref(cfg), C.byref(h)) == 0 and h.value
+    res = B.Result()
+    assert L.slbm_server_poll(h, 12345, C.byref(res)) == B.SLBM_EINVAL
+    L.slbm_server_destroy(h)

@@ -427,3 +427,54 @@ def test_wide_single_solve_every_order(P, d, n):
     er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
     print(f"[wide] d={d} N={n} E={c.mesh.E}: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
     assert np.all(np.isfinite(s.rho())) and er <= TOL and eu <= TOL
+
+
+def test_server_admission_retirement_and_errors(P):
+    """Server edge cases: admission limited by arena bytes (room for two solves), a request
+    larger than the whole arena (SLBM_ENOMEM), retirement at the KE threshold at the first
+    check below it, a diverged request (SLBM_EDIVERGED), and a request submitted while
+    others run; every completed result equals the same solve run alone."""
+    B = P.binding
+    mk = lambda t, n: cases.small_flat(theta_deg=t, nx=16, ny=8, N=n, Lx=128.0, Ly=64.0, R=32.0)
+    base = [mk(60.0, 4), mk(90.0, 4), mk(120.0, 4)]
+    ws = max(int(P.lib().slbm_workspace_bytes(P.Solve(c).handle)) for c in base)
+    # KE of the first solve alone at every check, to place the KE threshold
+    a = P.Solve(base[0])
+    a.init_tanh()
+    ke_checks = []
+    for _ in range(6):
+        a.step(50)
+        ke_checks.append(a.kinetic_energy()[0])
+    # threshold at the first new minimum before the step cap (else at the smallest check)
+    k_stop = next((k for k in range(1, 5) if ke_checks[k] < min(ke_checks[:k])),
+                  int(np.argmin(ke_checks)))
+    ke_stop = ke_checks[k_stop] * (1.0 + 1e-9)
+    expect_stop = 50 * (next(k for k, v in enumerate(ke_checks) if v < ke_stop) + 1)
+    big = cases.small_flat(nx=32, ny=16, N=8, Lx=256.0, Ly=128.0, R=40.0)
+    srv = P.Server(arena_bytes=2 * ws + 4096, max_slots=8, check_every=50, ke_stop=ke_stop,
+                   max_steps=300)
+    ids = [srv.submit(c) for c in base]
+    i_big = srv.submit(big)
+    i_div = srv.submit(mk(75.0, 4), ke_limit=1e-300)
+    srv.tick()
+    late = mk(100.0, 4)
+    i_late = srv.submit(late)
+    srv.drain()
+    assert srv.poll(i_big).status == B.SLBM_ENOMEM
+    rd = srv.poll(i_div)
+    assert rd.status == B.SLBM_EDIVERGED and rd.steps == 50
+    r0 = srv.poll(ids[0])
+    print(f"[server] KE checks {ke_checks}, stop at {expect_stop}, got {r0.steps}", flush=True)
+    assert r0.status == 0 and r0.steps == expect_stop
+    for rid, c in zip(ids + [i_late], base + [late]):
+        res = srv.poll(rid)
+        assert res.status == 0 and 0 < res.steps <= 300
+        s = P.Solve(c)
+        s.init_tanh()
+        s.step(res.steps)
+        assert res.ke_max == s.kinetic_energy()[0]
+        assert res.t_arrive <= res.t_admit <= res.t_done
+    # arena room for two: the third base request waits for a retirement
+    admits = sorted(srv.poll(i).t_admit for i in ids)
+    dones = sorted(srv.poll(i).t_done for i in ids)
+    assert admits[2] >= dones[0]
