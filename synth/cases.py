@@ -80,6 +80,20 @@ def c2(theta_deg: float = 60.0) -> Case:
                 theta_deg=theta_deg)
 
 
+def c2xl(theta_deg: float = 60.0) -> Case:
+    """c2's recipe at 16x the element count: 512x256 jittered quads (h = 4) over a 2048x1024
+    walled box, N=6, 60-degree bottom wall, cap R=32 at the middle of the bottom wall.
+    About 4.7 M global nodes: the working set exceeds the 256 MB Infinity Cache, so the
+    2-D step runs from HBM."""
+    cb = math.cos(math.radians(theta_deg))
+    m = meshes.box2d(512, 256, 6, 2048.0, 1024.0, periodic=(False, False), jitter=0.2, seed=2,
+                     cos_theta={"bottom": cb}, name="c2xl")
+    R = 32.0
+    return Case("c2xl", m, LATTICE_D2Q9, x0=(1024.0, -R * cb), R=R, seed=2, steps=1000,
+                wall_geom=dict(kind="plane", point=(0.0, 0.0), normal=(0.0, -1.0)),
+                theta_deg=theta_deg)
+
+
 def c3(theta_deg: float = 90.0, n_az: int = 128, n_rad: int = 16, N: int = 8) -> Case:
     """D2Q9 droplet on a cylinder (R=40) in a 256^2 box: O-grid of 2048 curved quads, N=8."""
     Rc = 40.0
@@ -208,7 +222,7 @@ def wide_case(dim: int, N: int) -> Case:
                 theta_deg=70.0)
 
 
-CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}
+CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c2xl": c2xl}
 
 
 def sizes(case: Case) -> dict:

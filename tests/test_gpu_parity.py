@@ -113,6 +113,16 @@ def test_c2_full_size(P):
     assert er <= TOL and eu <= TOL
 
 
+def test_c2xl_full_size(P):
+    """c2's recipe at 512x256 quads (4.7 M global nodes, N=6, wide blocks, working set
+    beyond the Infinity Cache): 1 step against the oracle (~15 s of CPU)."""
+    c = cases.c2xl()
+    s, o = _run_pair(c, P, 1)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] c2xl 1 step: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+
+
 def test_c3_full_size(P):
     """c3 at full size (O-grid of 2048 curved quads, N=8, cylinder wall), 10 steps."""
     c = cases.c3()
