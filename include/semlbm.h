@@ -28,6 +28,16 @@
  *     memory is the caller's workspace (slbm_bind); the library never frees it.
  *   - No call throws; every call returns an slbm_status.  A context must be used from one
  *     host thread at a time.  slbm_last_error() describes the last failure.
+ *
+ * Environment switches (read where noted; none changes any result, bit for bit):
+ *   SLBM_UNFUSED=1        slbm_set_mesh: step with the separate element and node kernels
+ *   SLBM_FUSED=1          slbm_set_mesh: step with the fused element kernels wherever the
+ *                         mesh allows them (by default not for 3-D meshes over 2^20 local
+ *                         nodes)
+ *   SLBM_NO_GRAPH=1       slbm_bind / slbm_batch_create: plain launches, no HIP graphs
+ *   SLBM_SERIAL_GROUPS=1  slbm_batch_create: a batch's groups one after another on its
+ *                         stream instead of on concurrent streams
+ *   SLBM_AUTOTUNE=0       slbm_batch_create: no launch-shape timing (fixed shape rule)
  */
 #ifndef SEMLBM_H
 #define SEMLBM_H
