@@ -1,0 +1,72 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU refusal, the byte models, the
+kernel-source hash that keys the committed byte-counter records, and the records
+themselves."""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def _bench():
+    argv = sys.argv
+    sys.argv = ["bench.py"]
+    try:
+        import bench
+    finally:
+        sys.argv = argv
+    return bench
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_byte_models_by_hand():
+    b = _bench()
+    # c2: Q=9, d=2, N_g=18,721, N_l=25,088: 8 * (81 N_g + 3 (8 N_l + 4 N_g)) bytes
+    assert b.step_model_bytes(9, 2, 18721, 25088) == 8.0 * (81 * 18721 + 3 * (8 * 25088 + 4 * 18721))
+    # kernel C of the fused path: ((Q-1) + 1 + Q + 2Q/3 + Q + 2) N_g + d(d+1)/2 N_l doubles
+    ng, nl = 1000, 1500
+    assert b.algorithmic_bytes("f_rk_lap", 9, 2, ng, nl) == 8.0 * ((8 + 1 + 9 + 6 + 9 + 2) * ng + 3 * nl)
+    # node kernel rk: (Q-1) + Q + 2Q/3 + 1 + Q + 1 doubles per global node
+    assert b.algorithmic_bytes("rk", 19, 3, ng, nl) == 8.0 * (18 + 19 + 38 / 3.0 + 1 + 19 + 1) * ng
+
+
+def test_kernel_hash_ignores_comments_but_not_code(tmp_path):
+    b = _bench()
+    src = os.path.join(ROOT, "paper_2609_00535_amd", "csrc")
+    dst = tmp_path / "csrc"
+    shutil.copytree(src, dst)
+    h0 = b.kernels_sha256(str(dst))
+    assert h0 == b.kernels_sha256(src)
+    k = dst / "kernels.hpp"
+    text = k.read_text()
+    k.write_text("// a comment line\n\n" + text.replace("\n", "\n// another\n", 1))
+    assert b.kernels_sha256(str(dst)) == h0
+    k.write_text(text + "\nconstexpr int kUnused = 1;\n")
+    assert b.kernels_sha256(str(dst)) != h0
+
+
+def test_committed_traffic_records_match_the_kernels():
+    """bench.py reports the committed byte counts only while they were taken on the
+    current kernel source; records of older kernels are skipped here and reported as
+    null by bench.py."""
+    import pytest
+    b = _bench()
+    for w, kind in (("c2", "f_rk_lap"), ("c4", "rk")):
+        rec = json.load(open(os.path.join(ROOT, "profiles", f"traffic_{w}.json")))
+        if rec["kernels_sha256"] != b.kernels_sha256():
+            assert b.traffic_from_profiles(w, kind) is None
+            pytest.skip(f"traffic_{w}.json predates the current kernels")
+        assert b.traffic_from_profiles(w, kind) == float(rec["bytes_per_launch"][kind])
+        cal = rec["calibration"]
+        assert abs(cal["fetch_scale"] - 2.0) < 1e-3 and abs(cal["write_scale"] - 1.0) < 1e-3
+    assert b.traffic_from_profiles("no_such_workload", "rk") is None
