@@ -488,3 +488,39 @@ def test_server_admission_retirement_and_errors(P):
     admits = sorted(srv.poll(i).t_admit for i in ids)
     dones = sorted(srv.poll(i).t_done for i in ids)
     assert admits[2] >= dones[0]
+
+
+def test_launch_switches_change_no_bits(P, monkeypatch):
+    """Plain launches instead of HIP graphs (SLBM_NO_GRAPH=1), a batch's groups one after
+    another (SLBM_SERIAL_GROUPS=1) and a batch without launch-shape tuning
+    (SLBM_AUTOTUNE=0) give the same bits as the defaults, alone and batched."""
+    import torch
+    mk = [lambda: cases.small_flat(), lambda: cases.small_cyl(), lambda: cases.small_sphere()]
+
+    def run(env):
+        for k in ("SLBM_NO_GRAPH", "SLBM_SERIAL_GROUPS", "SLBM_AUTOTUNE"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        a = P.Solve(mk[0]())
+        a.init_tanh()
+        a.step(23)
+        out = [a.get_state()[0]]
+        b = P.Batch(torch.cuda.current_stream())
+        ms = []
+        for f in mk:
+            m = P.Solve(f())
+            m.init_tanh()
+            b.add(m)
+            ms.append(m)
+        b.step(23)
+        b.step(4)
+        out += [m.get_state()[0] for m in ms]
+        return out
+
+    ref = run({})
+    for env in ({"SLBM_NO_GRAPH": "1"}, {"SLBM_SERIAL_GROUPS": "1"}, {"SLBM_AUTOTUNE": "0"}):
+        print(f"[switches] {env}", flush=True)
+        got = run(env)
+        for x, y in zip(ref, got):
+            assert np.array_equal(x, y), env
