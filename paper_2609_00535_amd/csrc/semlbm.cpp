@@ -407,9 +407,15 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
     std::vector<Part> parts(nth);
     {
         std::vector<std::thread> th;
-        for (int t = 1; t < nth; ++t)
-            th.emplace_back(metrics, E * t / nth, E * (t + 1) / nth, std::ref(parts[t]));
+        int started = 1;
+        try {
+            for (; started < nth; ++started)
+                th.emplace_back(metrics, E * started / nth, E * (started + 1) / nth, std::ref(parts[started]));
+        } catch (...) {
+            // no thread to be had: the remaining ranges run here
+        }
         metrics(0, E / nth, parts[0]);
+        for (int t = started; t < nth; ++t) metrics(E * t / nth, E * (t + 1) / nth, parts[t]);
         for (auto &x : th) x.join();
     }
     double hmin = INFINITY;

@@ -798,7 +798,15 @@ extern "C" slbm_status slbm_server_create(const slbm_server_cfg *cfg, slbm_serve
     if (slbm_batch_create(cfg->hip_stream, &s->batch) != SLBM_OK) { delete s; return SLBM_ENOMEM; }
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const unsigned nw = std::min(8u, std::max(1u, hw / 2));
-    for (unsigned k = 0; k < nw; ++k) s->workers.emplace_back([s] { s->worker(); });
+    try {
+        for (unsigned k = 0; k < nw; ++k) s->workers.emplace_back([s] { s->worker(); });
+    } catch (...) {
+        // fewer workers than asked for: fine while at least one runs
+    }
+    if (s->workers.empty()) {
+        delete s;
+        return SLBM_ENOMEM;
+    }
     *out = s;
     return SLBM_OK;
 }
