@@ -7,7 +7,21 @@
 #include "../../include/semlbm.h"
 #include "internal.hpp"
 
+#include <new>
+
 namespace slbm {
+// Every slbm_status entry point runs its body through this: no exception leaves the C ABI
+// (host allocation failures come back as SLBM_ENOMEM, anything else as SLBM_EINVAL).
+template <class F>
+inline slbm_status slbm_guard(F &&f) noexcept {
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return SLBM_ENOMEM;
+    } catch (...) {
+        return SLBM_EINVAL;
+    }
+}
 // enqueue n full time steps for one (d, N) group of solves
 int enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &np, int64_t n, void *stream,
                   bool fused);

@@ -160,360 +160,364 @@ double slbm_ctx::dline(const double *h, int n, int a) const {
 // create / mesh
 // ------------------------------------------------------------------------------------------
 extern "C" slbm_status slbm_create(const slbm_params *p, slbm_ctx **out) {
-    if (!out) return SLBM_EINVAL;
-    *out = nullptr;
-    if (!p) return SLBM_EINVAL;
-    slbm_ctx *c = new (std::nothrow) slbm_ctx();
-    if (!c) return SLBM_ENOMEM;
-    c->prm = *p;
-    if (p->lattice != 9 && p->lattice != 19) {
-        c->fail(SLBM_EINVAL, "lattice must be 9 (D2Q9) or 19 (D3Q19)");
-        delete c;
-        return SLBM_EINVAL;
-    }
-    c->Q = p->lattice;
-    c->dim = c->Q == 9 ? 2 : 3;
-    c->N = p->N;
-    if (!supported_order(c->dim, c->N)) {
-        delete c;
-        return SLBM_EINVAL;
-    }
-    const double dr = p->rho_l - p->rho_v;
-    if (!(dr > 0.0) || !(p->delta > 0.0) || !(p->sigma > 0.0) || !(p->tau > 0.0) ||
-        !(p->dt > 0.0 || p->cfl > 0.0)) {
-        delete c;
-        return SLBM_EINVAL;
-    }
-    c->Np = c->N + 1;
-    c->nloc = nloc_of(c->dim, c->N);
-    // (A.4)-(A.5) solved for beta and kappa with gamma = sigma
-    c->beta = 12.0 * p->sigma / (p->delta * dr * dr * dr * dr);
-    c->kappa = 3.0 * p->sigma * p->delta / (2.0 * dr * dr);
-    c->omega = 1.0 / (p->tau + 0.5);
-    lattice_tables(c->Q, c->ev, c->tw, c->opp);
-    for (int q = 0; q < c->Q; ++q) c->tc[q] = 3.0 * c->tw[q];
-    gll_tables(c->N, c->xi, c->wq, c->Dm);
-    c->wn.resize(c->nloc);
-    for (int n = 0; n < c->nloc; ++n) {
-        double pw = c->wq[c->along(n, 0)] * c->wq[c->along(n, 1)];
-        if (c->dim == 3) pw = pw * c->wq[c->along(n, 2)];
-        c->wn[n] = pw;
-    }
-    *out = c;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!out) return SLBM_EINVAL;
+        *out = nullptr;
+        if (!p) return SLBM_EINVAL;
+        slbm_ctx *c = new (std::nothrow) slbm_ctx();
+        if (!c) return SLBM_ENOMEM;
+        c->prm = *p;
+        if (p->lattice != 9 && p->lattice != 19) {
+            c->fail(SLBM_EINVAL, "lattice must be 9 (D2Q9) or 19 (D3Q19)");
+            delete c;
+            return SLBM_EINVAL;
+        }
+        c->Q = p->lattice;
+        c->dim = c->Q == 9 ? 2 : 3;
+        c->N = p->N;
+        if (!supported_order(c->dim, c->N)) {
+            delete c;
+            return SLBM_EINVAL;
+        }
+        const double dr = p->rho_l - p->rho_v;
+        if (!(dr > 0.0) || !(p->delta > 0.0) || !(p->sigma > 0.0) || !(p->tau > 0.0) ||
+            !(p->dt > 0.0 || p->cfl > 0.0)) {
+            delete c;
+            return SLBM_EINVAL;
+        }
+        c->Np = c->N + 1;
+        c->nloc = nloc_of(c->dim, c->N);
+        // (A.4)-(A.5) solved for beta and kappa with gamma = sigma
+        c->beta = 12.0 * p->sigma / (p->delta * dr * dr * dr * dr);
+        c->kappa = 3.0 * p->sigma * p->delta / (2.0 * dr * dr);
+        c->omega = 1.0 / (p->tau + 0.5);
+        lattice_tables(c->Q, c->ev, c->tw, c->opp);
+        for (int q = 0; q < c->Q; ++q) c->tc[q] = 3.0 * c->tw[q];
+        gll_tables(c->N, c->xi, c->wq, c->Dm);
+        c->wn.resize(c->nloc);
+        for (int n = 0; n < c->nloc; ++n) {
+            double pw = c->wq[c->along(n, 0)] * c->wq[c->along(n, 1)];
+            if (c->dim == 3) pw = pw * c->wq[c->along(n, 2)];
+            c->wn[n] = pw;
+        }
+        *out = c;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, const int32_t *gid,
                                      int64_t n_global, int64_t n_wall_faces,
                                      const int32_t *wall_face, const double *wall_cos,
                                      const double *wall_ub) {
-    if (!c) return SLBM_EINVAL;
-    if (c->bound) return c->fail(SLBM_ESTATE, "set_mesh after bind");
-    const int dim = c->dim, nloc = c->nloc, N = c->N;
-    if (E <= 0 || !xyz || !gid || n_global <= 0 || n_wall_faces < 0 ||
-        (n_wall_faces > 0 && (!wall_face || !wall_cos)))
-        return c->fail(SLBM_EINVAL, "bad mesh arguments");
-    if (E * (int64_t)nloc >= (int64_t)1 << 31 || n_global >= (int64_t)1 << 31)
-        return c->fail(SLBM_EINVAL, "mesh too large for 32-bit indices");
-    const int64_t Nl = E * nloc;
-    // --- ids: internal numbering by first appearance in local order ---
-    std::vector<int32_t> ug2ig(n_global, -1);
-    c->ig2ug.clear();
-    c->lgid.assign(Nl, 0);
-    for (int64_t l = 0; l < Nl; ++l) {
-        const int32_t g = gid[l];
-        if (g < 0 || g >= n_global) return c->fail(SLBM_EINVAL, "global id %d out of range", g);
-        if (ug2ig[g] < 0) {
-            ug2ig[g] = (int32_t)c->ig2ug.size();
-            c->ig2ug.push_back(g);
-        }
-        c->lgid[l] = ug2ig[g];
-    }
-    if ((int64_t)c->ig2ug.size() != n_global)
-        return c->fail(SLBM_EINVAL, "global ids are not contiguous (%zu of %lld used)",
-                       c->ig2ug.size(), (long long)n_global);
-    c->E = E;
-    c->Nl = Nl;
-    c->Ng = n_global;
-    // DSS gather lists: local copies of each global node in ascending local order
-    c->csr_ptr.assign(n_global + 1, 0);
-    for (int64_t l = 0; l < Nl; ++l) c->csr_ptr[c->lgid[l] + 1]++;
-    for (int64_t g = 0; g < n_global; ++g) c->csr_ptr[g + 1] += c->csr_ptr[g];
-    c->csr_idx.assign(Nl, 0);
-    {
-        std::vector<int32_t> fill(c->csr_ptr.begin(), c->csr_ptr.end() - 1);
-        for (int64_t l = 0; l < Nl; ++l) c->csr_idx[fill[c->lgid[l]]++] = (int32_t)l;
-    }
-    // first two copies of every global node, read by the node kernels in one load
-    c->gcopy.assign((size_t)4 * n_global, 0);
-    for (int64_t g = 0; g < n_global; ++g) {
-        const int k0 = c->csr_ptr[g], nc = c->csr_ptr[g + 1] - k0;
-        c->gcopy[4 * g] = k0;
-        c->gcopy[4 * g + 1] = nc;
-        c->gcopy[4 * g + 2] = c->csr_idx[k0];
-        c->gcopy[4 * g + 3] = c->csr_idx[nc > 1 ? k0 + 1 : k0];
-    }
-    // most local copies of any global node
-    c->vmax = 0;
-    for (int64_t g = 0; g < n_global; ++g) c->vmax = std::max<int>(c->vmax, c->csr_ptr[g + 1] - c->csr_ptr[g]);
-    {
-        // fused kernels finish each summation by gathering all copies at every copy: the
-        // right trade for latency-bound meshes; large 3-D meshes (up to 8 copies per node,
-        // 18 moving populations) move less data through the separate node kernels
-        const char *nf = std::getenv("SLBM_UNFUSED");
-        const char *ff = std::getenv("SLBM_FUSED");
-        const bool large3d = dim == 3 && Nl > (int64_t)1 << 20;
-        // nodes inside an element must belong to it alone (the fused kernels skip their
-        // copy lists)
-        std::vector<char> on_bnd(nloc, 0);
-        for (int n = 0; n < nloc; ++n)
-            for (int a = 0; a < dim; ++a) {
-                const int i = c->along(n, a);
-                if (i == 0 || i == N) on_bnd[n] = 1;
-            }
-        bool interior_single = true;
-        for (int64_t e = 0; e < E && interior_single; ++e)
-            for (int n = 0; n < nloc; ++n) {
-                const int g = c->lgid[e * nloc + n];
-                if (!on_bnd[n] && c->csr_ptr[g + 1] - c->csr_ptr[g] != 1) interior_single = false;
-            }
-        const bool fits = c->vmax <= kCopySlots[dim - 2] && interior_single;
-        c->fused = fits && !large3d;
-        if (nf && nf[0] == '1') c->fused = false;
-        if (ff && ff[0] == '1' && fits) c->fused = true;
-    }
-    // per-local-node copy lists (fused path only): the ascending local copies of its global
-    // node in kCopySlots[dim-2] rows, -1 padded, so the fused kernels load every slot
-    // without a branch
-    c->lcp.clear();
-    if (c->fused) {
-        c->lcp.assign((size_t)kCopySlots[dim - 2] * Nl, -1);
+    return slbm_guard([&]() -> slbm_status {
+        if (!c) return SLBM_EINVAL;
+        if (c->bound) return c->fail(SLBM_ESTATE, "set_mesh after bind");
+        const int dim = c->dim, nloc = c->nloc, N = c->N;
+        if (E <= 0 || !xyz || !gid || n_global <= 0 || n_wall_faces < 0 ||
+            (n_wall_faces > 0 && (!wall_face || !wall_cos)))
+            return c->fail(SLBM_EINVAL, "bad mesh arguments");
+        if (E * (int64_t)nloc >= (int64_t)1 << 31 || n_global >= (int64_t)1 << 31)
+            return c->fail(SLBM_EINVAL, "mesh too large for 32-bit indices");
+        const int64_t Nl = E * nloc;
+        // --- ids: internal numbering by first appearance in local order ---
+        std::vector<int32_t> ug2ig(n_global, -1);
+        c->ig2ug.clear();
+        c->lgid.assign(Nl, 0);
         for (int64_t l = 0; l < Nl; ++l) {
-            const int g = c->lgid[l];
-            for (int k = c->csr_ptr[g]; k < c->csr_ptr[g + 1]; ++k)
-                c->lcp[(size_t)(k - c->csr_ptr[g]) * Nl + l] = c->csr_idx[k];
+            const int32_t g = gid[l];
+            if (g < 0 || g >= n_global) return c->fail(SLBM_EINVAL, "global id %d out of range", g);
+            if (ug2ig[g] < 0) {
+                ug2ig[g] = (int32_t)c->ig2ug.size();
+                c->ig2ug.push_back(g);
+            }
+            c->lgid[l] = ug2ig[g];
         }
-    }
-    c->xyz.assign(xyz, xyz + Nl * dim);
-    // --- metric terms, Jacobian, G, lumped mass ---
-    const int ng = dim * (dim + 1) / 2;
-    c->Ja.assign((size_t)dim * dim * Nl, 0.0);
-    c->Gm.assign((size_t)ng * Nl, 0.0);
-    std::vector<double> MA(n_global, 0.0);
-    std::vector<double> wJ(Nl);  // w_n J of every local node, summed into MA below
-    // per (direction, node): position along the direction and first node of its GLL line,
-    // so the derivative below does no integer division (same fma sequence as dline)
-    std::vector<int> ln_i(3 * nloc), ln_b(3 * nloc);
-    for (int a = 0; a < dim; ++a)
-        for (int n = 0; n < nloc; ++n) {
-            ln_i[a * nloc + n] = c->along(n, a);
-            ln_b[a * nloc + n] = n - ln_i[a * nloc + n] * c->stride(a);
+        if ((int64_t)c->ig2ug.size() != n_global)
+            return c->fail(SLBM_EINVAL, "global ids are not contiguous (%zu of %lld used)",
+                           c->ig2ug.size(), (long long)n_global);
+        c->E = E;
+        c->Nl = Nl;
+        c->Ng = n_global;
+        // DSS gather lists: local copies of each global node in ascending local order
+        c->csr_ptr.assign(n_global + 1, 0);
+        for (int64_t l = 0; l < Nl; ++l) c->csr_ptr[c->lgid[l] + 1]++;
+        for (int64_t g = 0; g < n_global; ++g) c->csr_ptr[g + 1] += c->csr_ptr[g];
+        c->csr_idx.assign(Nl, 0);
+        {
+            std::vector<int32_t> fill(c->csr_ptr.begin(), c->csr_ptr.end() - 1);
+            for (int64_t l = 0; l < Nl; ++l) c->csr_idx[fill[c->lgid[l]]++] = (int32_t)l;
         }
-    const int Np = c->Np;
-    const double *Dm = c->Dm.data();
-    auto dl = [&](const double *h, int n, int a) {
-        const int i = ln_i[a * nloc + n], b = ln_b[a * nloc + n], st = c->stride(a);
-        const double *row = Dm + i * Np;
-        double acc = 0.0;
-        for (int m = 0; m < Np; ++m) acc = std::fma(row[m], h[b + m * st], acc);
-        return acc;
-    };
-    // metric terms of the elements [e0, e1): Ja, G, wJ and the smallest node spacing; the
-    // first element with a non-positive Jacobian (in element order) is reported back
-    struct Part { double hmin = INFINITY; int64_t bad_e = -1; int bad_n = 0; double bad_J = 0.0; };
-    auto metrics = [&](int64_t e0, int64_t e1, Part &pt) {
-        std::vector<double> X(3 * nloc), dX(9 * nloc), V(3 * nloc), J(nloc), Jloc(9 * nloc);
-        double hmin = INFINITY;
-        for (int64_t e = e0; e < e1; ++e) {
+        // first two copies of every global node, read by the node kernels in one load
+        c->gcopy.assign((size_t)4 * n_global, 0);
+        for (int64_t g = 0; g < n_global; ++g) {
+            const int k0 = c->csr_ptr[g], nc = c->csr_ptr[g + 1] - k0;
+            c->gcopy[4 * g] = k0;
+            c->gcopy[4 * g + 1] = nc;
+            c->gcopy[4 * g + 2] = c->csr_idx[k0];
+            c->gcopy[4 * g + 3] = c->csr_idx[nc > 1 ? k0 + 1 : k0];
+        }
+        // most local copies of any global node
+        c->vmax = 0;
+        for (int64_t g = 0; g < n_global; ++g) c->vmax = std::max<int>(c->vmax, c->csr_ptr[g + 1] - c->csr_ptr[g]);
+        {
+            // fused kernels finish each summation by gathering all copies at every copy: the
+            // right trade for latency-bound meshes; large 3-D meshes (up to 8 copies per node,
+            // 18 moving populations) move less data through the separate node kernels
+            const char *nf = std::getenv("SLBM_UNFUSED");
+            const char *ff = std::getenv("SLBM_FUSED");
+            const bool large3d = dim == 3 && Nl > (int64_t)1 << 20;
+            // nodes inside an element must belong to it alone (the fused kernels skip their
+            // copy lists)
+            std::vector<char> on_bnd(nloc, 0);
             for (int n = 0; n < nloc; ++n)
-                for (int cc = 0; cc < dim; ++cc) X[cc * nloc + n] = xyz[(e * nloc + n) * dim + cc];
-            for (int cc = 0; cc < dim; ++cc)
-                for (int a = 0; a < dim; ++a)
-                    for (int n = 0; n < nloc; ++n) dX[(cc * 3 + a) * nloc + n] = dl(&X[cc * nloc], n, a);
-            if (dim == 2) {
+                for (int a = 0; a < dim; ++a) {
+                    const int i = c->along(n, a);
+                    if (i == 0 || i == N) on_bnd[n] = 1;
+                }
+            bool interior_single = true;
+            for (int64_t e = 0; e < E && interior_single; ++e)
                 for (int n = 0; n < nloc; ++n) {
-                    const double xa = dX[0 * nloc + n], xb = dX[1 * nloc + n];
-                    const double ya = dX[3 * nloc + n], yb = dX[4 * nloc + n];
-                    double *Jn = &Jloc[9 * n];
-                    Jn[0] = yb; Jn[1] = -xb;   // J grad(xi)
-                    Jn[3] = -ya; Jn[4] = xa;   // J grad(eta)
-                    J[n] = xa * yb - xb * ya;
+                    const int g = c->lgid[e * nloc + n];
+                    if (!on_bnd[n] && c->csr_ptr[g + 1] - c->csr_ptr[g] != 1) interior_single = false;
                 }
-            } else {
-                // conservative curl form (Kopriva 2006): J grad(xi_i)_c = -[curl_xi(x_l grad_xi x_m)]_i
-                for (int cn = 0; cn < 3; ++cn) {
-                    const int cm = (cn + 1) % 3, cl = (cn + 2) % 3;
-                    for (int k = 0; k < 3; ++k)
-                        for (int n = 0; n < nloc; ++n)
-                            V[k * nloc + n] = X[cl * nloc + n] * dX[(cm * 3 + k) * nloc + n];
-                    for (int n = 0; n < nloc; ++n) {
-                        const double c0 = dl(&V[2 * nloc], n, 1) - dl(&V[1 * nloc], n, 2);
-                        const double c1 = dl(&V[0 * nloc], n, 2) - dl(&V[2 * nloc], n, 0);
-                        const double c2 = dl(&V[1 * nloc], n, 0) - dl(&V[0 * nloc], n, 1);
-                        Jloc[9 * n + 0 * 3 + cn] = -c0;
-                        Jloc[9 * n + 1 * 3 + cn] = -c1;
-                        Jloc[9 * n + 2 * 3 + cn] = -c2;
-                    }
-                }
-                for (int n = 0; n < nloc; ++n) {
-                    const double a0 = dX[0 * nloc + n], a1 = dX[3 * nloc + n], a2 = dX[6 * nloc + n];
-                    const double b0 = dX[1 * nloc + n], b1 = dX[4 * nloc + n], b2 = dX[7 * nloc + n];
-                    const double d0 = dX[2 * nloc + n], d1 = dX[5 * nloc + n], d2 = dX[8 * nloc + n];
-                    const double cx = b1 * d2 - b2 * d1, cy = b2 * d0 - b0 * d2, cz = b0 * d1 - b1 * d0;
-                    J[n] = a0 * cx + a1 * cy + a2 * cz;
-                }
+            const bool fits = c->vmax <= kCopySlots[dim - 2] && interior_single;
+            c->fused = fits && !large3d;
+            if (nf && nf[0] == '1') c->fused = false;
+            if (ff && ff[0] == '1' && fits) c->fused = true;
+        }
+        // per-local-node copy lists (fused path only): the ascending local copies of its global
+        // node in kCopySlots[dim-2] rows, -1 padded, so the fused kernels load every slot
+        // without a branch
+        c->lcp.clear();
+        if (c->fused) {
+            c->lcp.assign((size_t)kCopySlots[dim - 2] * Nl, -1);
+            for (int64_t l = 0; l < Nl; ++l) {
+                const int g = c->lgid[l];
+                for (int k = c->csr_ptr[g]; k < c->csr_ptr[g + 1]; ++k)
+                    c->lcp[(size_t)(k - c->csr_ptr[g]) * Nl + l] = c->csr_idx[k];
             }
+        }
+        c->xyz.assign(xyz, xyz + Nl * dim);
+        // --- metric terms, Jacobian, G, lumped mass ---
+        const int ng = dim * (dim + 1) / 2;
+        c->Ja.assign((size_t)dim * dim * Nl, 0.0);
+        c->Gm.assign((size_t)ng * Nl, 0.0);
+        std::vector<double> MA(n_global, 0.0);
+        std::vector<double> wJ(Nl);  // w_n J of every local node, summed into MA below
+        // per (direction, node): position along the direction and first node of its GLL line,
+        // so the derivative below does no integer division (same fma sequence as dline)
+        std::vector<int> ln_i(3 * nloc), ln_b(3 * nloc);
+        for (int a = 0; a < dim; ++a)
             for (int n = 0; n < nloc; ++n) {
-                const int64_t l = e * nloc + n;
-                if (!(J[n] > 0.0)) {
-                    pt.bad_e = e;
-                    pt.bad_n = n;
-                    pt.bad_J = J[n];
-                    return;
-                }
-                for (int a = 0; a < dim; ++a)
-                    for (int cc = 0; cc < dim; ++cc) c->Ja[(size_t)(a * dim + cc) * Nl + l] = Jloc[9 * n + a * 3 + cc];
-                int k = 0;
-                for (int a = 0; a < dim; ++a)
-                    for (int b = a; b < dim; ++b) {
-                        double s = 0.0;
-                        for (int cc = 0; cc < dim; ++cc) s += Jloc[9 * n + a * 3 + cc] * Jloc[9 * n + b * 3 + cc];
-                        c->Gm[(size_t)k * Nl + l] = c->wn[n] * s / J[n];
-                        ++k;
-                    }
-                wJ[l] = c->wn[n] * J[n];
+                ln_i[a * nloc + n] = c->along(n, a);
+                ln_b[a * nloc + n] = n - ln_i[a * nloc + n] * c->stride(a);
             }
-            for (int a = 0; a < dim; ++a) {
-                const int s = c->stride(a);
+        const int Np = c->Np;
+        const double *Dm = c->Dm.data();
+        auto dl = [&](const double *h, int n, int a) {
+            const int i = ln_i[a * nloc + n], b = ln_b[a * nloc + n], st = c->stride(a);
+            const double *row = Dm + i * Np;
+            double acc = 0.0;
+            for (int m = 0; m < Np; ++m) acc = std::fma(row[m], h[b + m * st], acc);
+            return acc;
+        };
+        // metric terms of the elements [e0, e1): Ja, G, wJ and the smallest node spacing; the
+        // first element with a non-positive Jacobian (in element order) is reported back
+        struct Part { double hmin = INFINITY; int64_t bad_e = -1; int bad_n = 0; double bad_J = 0.0; };
+        auto metrics = [&](int64_t e0, int64_t e1, Part &pt) {
+            std::vector<double> X(3 * nloc), dX(9 * nloc), V(3 * nloc), J(nloc), Jloc(9 * nloc);
+            double hmin = INFINITY;
+            for (int64_t e = e0; e < e1; ++e) {
+                for (int n = 0; n < nloc; ++n)
+                    for (int cc = 0; cc < dim; ++cc) X[cc * nloc + n] = xyz[(e * nloc + n) * dim + cc];
+                for (int cc = 0; cc < dim; ++cc)
+                    for (int a = 0; a < dim; ++a)
+                        for (int n = 0; n < nloc; ++n) dX[(cc * 3 + a) * nloc + n] = dl(&X[cc * nloc], n, a);
+                if (dim == 2) {
+                    for (int n = 0; n < nloc; ++n) {
+                        const double xa = dX[0 * nloc + n], xb = dX[1 * nloc + n];
+                        const double ya = dX[3 * nloc + n], yb = dX[4 * nloc + n];
+                        double *Jn = &Jloc[9 * n];
+                        Jn[0] = yb; Jn[1] = -xb;   // J grad(xi)
+                        Jn[3] = -ya; Jn[4] = xa;   // J grad(eta)
+                        J[n] = xa * yb - xb * ya;
+                    }
+                } else {
+                    // conservative curl form (Kopriva 2006): J grad(xi_i)_c = -[curl_xi(x_l grad_xi x_m)]_i
+                    for (int cn = 0; cn < 3; ++cn) {
+                        const int cm = (cn + 1) % 3, cl = (cn + 2) % 3;
+                        for (int k = 0; k < 3; ++k)
+                            for (int n = 0; n < nloc; ++n)
+                                V[k * nloc + n] = X[cl * nloc + n] * dX[(cm * 3 + k) * nloc + n];
+                        for (int n = 0; n < nloc; ++n) {
+                            const double c0 = dl(&V[2 * nloc], n, 1) - dl(&V[1 * nloc], n, 2);
+                            const double c1 = dl(&V[0 * nloc], n, 2) - dl(&V[2 * nloc], n, 0);
+                            const double c2 = dl(&V[1 * nloc], n, 0) - dl(&V[0 * nloc], n, 1);
+                            Jloc[9 * n + 0 * 3 + cn] = -c0;
+                            Jloc[9 * n + 1 * 3 + cn] = -c1;
+                            Jloc[9 * n + 2 * 3 + cn] = -c2;
+                        }
+                    }
+                    for (int n = 0; n < nloc; ++n) {
+                        const double a0 = dX[0 * nloc + n], a1 = dX[3 * nloc + n], a2 = dX[6 * nloc + n];
+                        const double b0 = dX[1 * nloc + n], b1 = dX[4 * nloc + n], b2 = dX[7 * nloc + n];
+                        const double d0 = dX[2 * nloc + n], d1 = dX[5 * nloc + n], d2 = dX[8 * nloc + n];
+                        const double cx = b1 * d2 - b2 * d1, cy = b2 * d0 - b0 * d2, cz = b0 * d1 - b1 * d0;
+                        J[n] = a0 * cx + a1 * cy + a2 * cz;
+                    }
+                }
                 for (int n = 0; n < nloc; ++n) {
-                    if (ln_i[a * nloc + n] == N) continue;
-                    double d2 = 0.0;
-                    for (int cc = 0; cc < dim; ++cc) {
-                        const double dd = X[cc * nloc + n + s] - X[cc * nloc + n];
-                        d2 += dd * dd;
+                    const int64_t l = e * nloc + n;
+                    if (!(J[n] > 0.0)) {
+                        pt.bad_e = e;
+                        pt.bad_n = n;
+                        pt.bad_J = J[n];
+                        return;
                     }
-                    const double d = std::sqrt(d2);
-                    if (d < hmin) hmin = d;
+                    for (int a = 0; a < dim; ++a)
+                        for (int cc = 0; cc < dim; ++cc) c->Ja[(size_t)(a * dim + cc) * Nl + l] = Jloc[9 * n + a * 3 + cc];
+                    int k = 0;
+                    for (int a = 0; a < dim; ++a)
+                        for (int b = a; b < dim; ++b) {
+                            double s = 0.0;
+                            for (int cc = 0; cc < dim; ++cc) s += Jloc[9 * n + a * 3 + cc] * Jloc[9 * n + b * 3 + cc];
+                            c->Gm[(size_t)k * Nl + l] = c->wn[n] * s / J[n];
+                            ++k;
+                        }
+                    wJ[l] = c->wn[n] * J[n];
+                }
+                for (int a = 0; a < dim; ++a) {
+                    const int s = c->stride(a);
+                    for (int n = 0; n < nloc; ++n) {
+                        if (ln_i[a * nloc + n] == N) continue;
+                        double d2 = 0.0;
+                        for (int cc = 0; cc < dim; ++cc) {
+                            const double dd = X[cc * nloc + n + s] - X[cc * nloc + n];
+                            d2 += dd * dd;
+                        }
+                        const double d = std::sqrt(d2);
+                        if (d < hmin) hmin = d;
+                    }
                 }
             }
+            pt.hmin = hmin;
+        };
+        // large meshes: element ranges on several host threads (each range writes only its own
+        // nodes' entries)
+        const int64_t kPerThread = 512;
+        const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({8, (E + kPerThread - 1) / kPerThread,
+                                                                    (int64_t)std::max(1u, std::thread::hardware_concurrency())}));
+        std::vector<Part> parts(nth);
+        {
+            std::vector<std::thread> th;
+            int started = 1;
+            try {
+                for (; started < nth; ++started)
+                    th.emplace_back(metrics, E * started / nth, E * (started + 1) / nth, std::ref(parts[started]));
+            } catch (...) {
+                // no thread to be had: the remaining ranges run here
+            }
+            metrics(0, E / nth, parts[0]);
+            for (int t = started; t < nth; ++t) metrics(E * t / nth, E * (t + 1) / nth, parts[t]);
+            for (auto &x : th) x.join();
         }
-        pt.hmin = hmin;
-    };
-    // large meshes: element ranges on several host threads (each range writes only its own
-    // nodes' entries)
-    const int64_t kPerThread = 512;
-    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({8, (E + kPerThread - 1) / kPerThread,
-                                                                (int64_t)std::max(1u, std::thread::hardware_concurrency())}));
-    std::vector<Part> parts(nth);
-    {
-        std::vector<std::thread> th;
-        int started = 1;
-        try {
-            for (; started < nth; ++started)
-                th.emplace_back(metrics, E * started / nth, E * (started + 1) / nth, std::ref(parts[started]));
-        } catch (...) {
-            // no thread to be had: the remaining ranges run here
+        double hmin = INFINITY;
+        for (const Part &pt : parts) {
+            if (pt.bad_e >= 0)
+                return c->fail(SLBM_EINVAL, "non-positive Jacobian %g in element %lld node %d", pt.bad_J,
+                               (long long)pt.bad_e, pt.bad_n);
+            hmin = std::min(hmin, pt.hmin);
         }
-        metrics(0, E / nth, parts[0]);
-        for (int t = started; t < nth; ++t) metrics(E * t / nth, E * (t + 1) / nth, parts[t]);
-        for (auto &x : th) x.join();
-    }
-    double hmin = INFINITY;
-    for (const Part &pt : parts) {
-        if (pt.bad_e >= 0)
-            return c->fail(SLBM_EINVAL, "non-positive Jacobian %g in element %lld node %d", pt.bad_J,
-                           (long long)pt.bad_e, pt.bad_n);
-        hmin = std::min(hmin, pt.hmin);
-    }
-    // lumped mass: wJ summed in local order over the internal numbering (the caller-order sum)
-    for (int64_t l = 0; l < Nl; ++l) MA[c->lgid[l]] += wJ[l];
-    c->Minv.resize(n_global);
-    c->MA = MA;
-    for (int64_t g = 0; g < n_global; ++g) c->Minv[g] = 1.0 / MA[g];
-    c->hmin = hmin;
-    if (c->prm.dt > 0.0) {
-        c->dt = c->prm.dt;
-    } else {
-        // advective CFL bound, and the capillary bound: the kappa lap(rho) part of the
-        // streaming force has a discrete spectrum growing like h^-2
-        const double dt_adv = c->prm.cfl * hmin;
-        const double dt_cap = 0.25 * hmin * hmin / std::sqrt(c->kappa * c->prm.rho_l);
-        c->dt = dt_adv < dt_cap ? dt_adv : dt_cap;
-    }
-    if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return c->fail(SLBM_EINVAL, "invalid time step");
-    // --- wall tables: one entry per (face, face node); the entries of a local node are
-    // adjacent, in the order of the caller's face list ---
-    const double sq = std::sqrt(2.0 * c->beta / c->kappa);
-    struct WE { int64_t l; double sn[3]; double ub[3]; double lap; };
-    std::vector<WE> ents;
-    {
-        std::vector<int64_t> keys((size_t)n_wall_faces);
+        // lumped mass: wJ summed in local order over the internal numbering (the caller-order sum)
+        for (int64_t l = 0; l < Nl; ++l) MA[c->lgid[l]] += wJ[l];
+        c->Minv.resize(n_global);
+        c->MA = MA;
+        for (int64_t g = 0; g < n_global; ++g) c->Minv[g] = 1.0 / MA[g];
+        c->hmin = hmin;
+        if (c->prm.dt > 0.0) {
+            c->dt = c->prm.dt;
+        } else {
+            // advective CFL bound, and the capillary bound: the kappa lap(rho) part of the
+            // streaming force has a discrete spectrum growing like h^-2
+            const double dt_adv = c->prm.cfl * hmin;
+            const double dt_cap = 0.25 * hmin * hmin / std::sqrt(c->kappa * c->prm.rho_l);
+            c->dt = dt_adv < dt_cap ? dt_adv : dt_cap;
+        }
+        if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return c->fail(SLBM_EINVAL, "invalid time step");
+        // --- wall tables: one entry per (face, face node); the entries of a local node are
+        // adjacent, in the order of the caller's face list ---
+        const double sq = std::sqrt(2.0 * c->beta / c->kappa);
+        struct WE { int64_t l; double sn[3]; double ub[3]; double lap; };
+        std::vector<WE> ents;
+        {
+            std::vector<int64_t> keys((size_t)n_wall_faces);
+            for (int64_t fidx = 0; fidx < n_wall_faces; ++fidx) {
+                const int64_t e = wall_face[2 * fidx];
+                const int face = wall_face[2 * fidx + 1];
+                if (e < 0 || e >= E || face < 0 || face >= 2 * dim)
+                    return c->fail(SLBM_EINVAL, "wall face %lld: bad element or face", (long long)fidx);
+                keys[fidx] = e * 8 + face;
+            }
+            std::sort(keys.begin(), keys.end());
+            for (size_t k = 1; k < keys.size(); ++k)
+                if (keys[k] == keys[k - 1])
+                    return c->fail(SLBM_EINVAL, "wall face (element %lld, face %d) listed twice (duplicate)",
+                                   (long long)(keys[k] / 8), (int)(keys[k] % 8));
+        }
         for (int64_t fidx = 0; fidx < n_wall_faces; ++fidx) {
             const int64_t e = wall_face[2 * fidx];
             const int face = wall_face[2 * fidx + 1];
-            if (e < 0 || e >= E || face < 0 || face >= 2 * dim)
-                return c->fail(SLBM_EINVAL, "wall face %lld: bad element or face", (long long)fidx);
-            keys[fidx] = e * 8 + face;
+            const int a = face / 2, side = face % 2;
+            const double sign = side ? 1.0 : -1.0;
+            double ub[3] = {0.0, 0.0, 0.0};
+            if (wall_ub)
+                for (int cc = 0; cc < dim; ++cc) ub[cc] = wall_ub[fidx * dim + cc];
+            for (int n = 0; n < nloc; ++n) {
+                if (c->along(n, a) != (side ? N : 0)) continue;
+                double wf = 1.0;
+                for (int b = 0; b < dim; ++b)
+                    if (b != a) wf = wf * c->wq[c->along(n, b)];
+                const int64_t l = e * nloc + n;
+                double Jv[3];
+                double nrm2 = 0.0;
+                for (int cc = 0; cc < dim; ++cc) {
+                    Jv[cc] = c->Ja[(size_t)(a * dim + cc) * Nl + l];
+                    nrm2 += Jv[cc] * Jv[cc];
+                }
+                WE w;
+                w.l = l;
+                for (int cc = 0; cc < 3; ++cc) {
+                    w.sn[cc] = cc < dim ? sign * wf * Jv[cc] : 0.0;
+                    w.ub[cc] = ub[cc];
+                }
+                // s cos(theta) sqrt(2 beta / kappa), s = w_face |J_s|
+                w.lap = wf * std::sqrt(nrm2) * wall_cos[fidx] * sq;
+                ents.push_back(w);
+            }
         }
-        std::sort(keys.begin(), keys.end());
-        for (size_t k = 1; k < keys.size(); ++k)
-            if (keys[k] == keys[k - 1])
-                return c->fail(SLBM_EINVAL, "wall face (element %lld, face %d) listed twice (duplicate)",
-                               (long long)(keys[k] / 8), (int)(keys[k] % 8));
-    }
-    for (int64_t fidx = 0; fidx < n_wall_faces; ++fidx) {
-        const int64_t e = wall_face[2 * fidx];
-        const int face = wall_face[2 * fidx + 1];
-        const int a = face / 2, side = face % 2;
-        const double sign = side ? 1.0 : -1.0;
-        double ub[3] = {0.0, 0.0, 0.0};
-        if (wall_ub)
-            for (int cc = 0; cc < dim; ++cc) ub[cc] = wall_ub[fidx * dim + cc];
-        for (int n = 0; n < nloc; ++n) {
-            if (c->along(n, a) != (side ? N : 0)) continue;
-            double wf = 1.0;
-            for (int b = 0; b < dim; ++b)
-                if (b != a) wf = wf * c->wq[c->along(n, b)];
-            const int64_t l = e * nloc + n;
-            double Jv[3];
-            double nrm2 = 0.0;
+        std::stable_sort(ents.begin(), ents.end(), [](const WE &x, const WE &y) { return x.l < y.l; });
+        c->nw = (int64_t)ents.size();
+        const int W = 2 * dim + 1;
+        c->lwall.assign(Nl, 0);
+        c->w_dat.assign((size_t)W * std::max<int64_t>(c->nw, 1), 0.0);
+        for (int64_t k = 0; k < c->nw; ++k) {
+            const int64_t l = ents[k].l;
+            const int cnt = (c->lwall[l] & 3) + 1;
+            if (cnt > dim)  // cannot happen for distinct faces of one element
+                return c->fail(SLBM_EINVAL, "element %lld: a node lies on more than %d listed wall faces",
+                               (long long)(l / nloc), dim);
+            c->lwall[l] = cnt == 1 ? (int32_t)((k << 2) | 1) : (c->lwall[l] & ~3) | cnt;
             for (int cc = 0; cc < dim; ++cc) {
-                Jv[cc] = c->Ja[(size_t)(a * dim + cc) * Nl + l];
-                nrm2 += Jv[cc] * Jv[cc];
+                c->w_dat[(size_t)k * W + cc] = ents[k].sn[cc];
+                c->w_dat[(size_t)k * W + dim + cc] = ents[k].ub[cc];
             }
-            WE w;
-            w.l = l;
-            for (int cc = 0; cc < 3; ++cc) {
-                w.sn[cc] = cc < dim ? sign * wf * Jv[cc] : 0.0;
-                w.ub[cc] = ub[cc];
-            }
-            // s cos(theta) sqrt(2 beta / kappa), s = w_face |J_s|
-            w.lap = wf * std::sqrt(nrm2) * wall_cos[fidx] * sq;
-            ents.push_back(w);
+            c->w_dat[(size_t)k * W + 2 * dim] = ents[k].lap;
         }
-    }
-    std::stable_sort(ents.begin(), ents.end(), [](const WE &x, const WE &y) { return x.l < y.l; });
-    c->nw = (int64_t)ents.size();
-    const int W = 2 * dim + 1;
-    c->lwall.assign(Nl, 0);
-    c->w_dat.assign((size_t)W * std::max<int64_t>(c->nw, 1), 0.0);
-    for (int64_t k = 0; k < c->nw; ++k) {
-        const int64_t l = ents[k].l;
-        const int cnt = (c->lwall[l] & 3) + 1;
-        if (cnt > dim)  // cannot happen for distinct faces of one element
-            return c->fail(SLBM_EINVAL, "element %lld: a node lies on more than %d listed wall faces",
-                           (long long)(l / nloc), dim);
-        c->lwall[l] = cnt == 1 ? (int32_t)((k << 2) | 1) : (c->lwall[l] & ~3) | cnt;
-        for (int cc = 0; cc < dim; ++cc) {
-            c->w_dat[(size_t)k * W + cc] = ents[k].sn[cc];
-            c->w_dat[(size_t)k * W + dim + cc] = ents[k].ub[cc];
-        }
-        c->w_dat[(size_t)k * W + 2 * dim] = ents[k].lap;
-    }
-    if (c->nw >= (int64_t)1 << 29) return c->fail(SLBM_EINVAL, "too many wall nodes");
-    c->has_mesh = true;
-    c->layout();
-    return SLBM_OK;
+        if (c->nw >= (int64_t)1 << 29) return c->fail(SLBM_EINVAL, "too many wall nodes");
+        c->has_mesh = true;
+        c->layout();
+        return SLBM_OK;
+    });
 }
 
 // ------------------------------------------------------------------------------------------
@@ -562,105 +566,107 @@ extern "C" size_t slbm_workspace_bytes(const slbm_ctx *c) { return (c && c->has_
 template <class T> static T *at(void *base, size_t off) { return reinterpret_cast<T *>((char *)base + off); }
 
 extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
-    if (!c) return SLBM_EINVAL;
-    if (!c->has_mesh) return c->fail(SLBM_ESTATE, "bind before set_mesh");
-    if (c->bound) return c->fail(SLBM_ESTATE, "already bound");
-    if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return c->fail(SLBM_EINVAL, "workspace must be 256-byte aligned");
-    if (bytes < c->ws_bytes)
-        return c->fail(SLBM_ENOMEM, "workspace %zu bytes < required %zu", bytes, c->ws_bytes);
-    c->dev = dev_ptr;
-    c->stream = hip_stream;
-    hipStream_t st = (hipStream_t)hip_stream;
-    void *b = dev_ptr;
-    SolveDesc &d = c->desc;
-    std::memset(&d, 0, sizeof d);
-    d.E = (int)c->E;
-    d.Nl = (int)c->Nl;
-    d.Ng = (int)c->Ng;
-    d.lgid = at<int>(b, c->off.lgid);
-    d.Ja = at<double>(b, c->off.Ja);
-    d.G = at<double>(b, c->off.G);
-    d.Minv = at<double>(b, c->off.Minv);
-    d.gcopy = at<NodeCopies>(b, c->off.gcopy);
-    d.csr_idx = at<int>(b, c->off.csr_idx);
-    d.lcp = at<int>(b, c->off.lcp);
-    d.vmax = c->vmax;
-    d.lwall = at<int>(b, c->off.lwall);
-    d.w_dat = at<double>(b, c->off.w_dat);
-    d.Dm = at<double>(b, c->off.Dm);
-    d.wn = at<double>(b, c->off.wn);
-    d.f = at<double>(b, c->off.f);
-    d.g0 = at<double>(b, c->off.g0);
-    d.g1 = at<double>(b, c->off.g1);
-    d.g2 = at<double>(b, c->off.g2);
-    d.rho = at<double>(b, c->off.rho);
-    d.mu = at<double>(b, c->off.mu);
-    d.rl = at<double>(b, c->off.rl);
-    d.gl = at<double>(b, c->off.gl);
-    d.rs = at<double>(b, c->off.rs);
-    d.aux = at<double>(b, c->off.aux);
-    d.diag = at<double>(b, c->off.diag);
-    d.red = at<double>(b, c->off.red);
-    d.rho_l = c->prm.rho_l;
-    d.rho_v = c->prm.rho_v;
-    d.beta = c->beta;
-    d.kappa = c->kappa;
-    d.omega = c->omega;
-    d.dt = c->dt;
-    for (int q = 0; q < c->Q; ++q) {
-        const int cls = (int)(std::fabs(c->ev[q][0]) + std::fabs(c->ev[q][1]) + std::fabs(c->ev[q][2]));
-        d.tw[cls] = c->tw[q];
-        d.twc[cls] = c->tc[q];
-    }
-    // block tables of the single-member plans
-    std::vector<int> ep(2 * (size_t)c->n_eblocks), np_(2 * (size_t)c->n_nblocks);
-    for (int i = 0; i < c->n_eblocks; ++i) { ep[i] = 0; ep[c->n_eblocks + i] = i; }
-    for (int i = 0; i < c->n_nblocks; ++i) { np_[i] = 0; np_[c->n_nblocks + i] = i; }
-    c->eplan.desc = at<SolveDesc>(b, c->off.desc);
-    c->eplan.blk_solve = at<int>(b, c->off.eplan);
-    c->eplan.blk_local = at<int>(b, c->off.eplan) + c->n_eblocks;
-    c->eplan.nblocks = c->n_eblocks;
-    c->eplan.single = 1;
-    c->eplan.one = d;
-    c->eplan.epb = c->epb;
-    c->eplan.grid = c->n_eblocks;
-    c->nplan.desc = at<SolveDesc>(b, c->off.desc);
-    c->nplan.blk_solve = at<int>(b, c->off.nplan);
-    c->nplan.blk_local = at<int>(b, c->off.nplan) + c->n_nblocks;
-    c->nplan.nblocks = c->n_nblocks;
-    c->nplan.single = 1;
-    c->nplan.one = d;
-    c->nplan.epb = 0;
-    c->nplan.grid = c->n_nblocks;
-    const int dim = c->dim;
-    const size_t ng = (size_t)dim * (dim + 1) / 2;
-    int e = 0;
-    auto up = [&](size_t off, const void *src, size_t n) {
-        if (e == 0 && n) e = (int)hipMemcpyAsync((char *)b + off, src, n, hipMemcpyHostToDevice, st);
-    };
-    up(c->off.desc, &d, sizeof d);
-    up(c->off.eplan, ep.data(), sizeof(int) * ep.size());
-    up(c->off.nplan, np_.data(), sizeof(int) * np_.size());
-    up(c->off.lgid, c->lgid.data(), sizeof(int) * c->Nl);
-    up(c->off.gcopy, c->gcopy.data(), sizeof(int) * c->gcopy.size());
-    up(c->off.csr_idx, c->csr_idx.data(), sizeof(int) * c->Nl);
-    up(c->off.lcp, c->lcp.data(), sizeof(int) * c->lcp.size());
-    up(c->off.lwall, c->lwall.data(), sizeof(int) * c->Nl);
-    up(c->off.w_dat, c->w_dat.data(), sizeof(double) * c->w_dat.size());
-    up(c->off.Ja, c->Ja.data(), sizeof(double) * dim * dim * c->Nl);
-    up(c->off.G, c->Gm.data(), sizeof(double) * ng * c->Nl);
-    up(c->off.Minv, c->Minv.data(), sizeof(double) * c->Ng);
-    up(c->off.Dm, c->Dm.data(), sizeof(double) * c->Np * c->Np);
-    up(c->off.wn, c->wn.data(), sizeof(double) * c->nloc);
-    if (e == 0) e = (int)hipMemsetAsync((char *)b + c->off.f, 0, c->off.diag - c->off.f, st);
-    if (e == 0) e = (int)hipStreamSynchronize(st);
-    if (e) return c->hip_check(e, "bind upload");
-    c->bound = true;
-    c->has_state = false;
-    c->step = 0;
-    const char *nog = std::getenv("SLBM_NO_GRAPH");
-    c->use_graph = !(nog && nog[0] == '1');
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!c) return SLBM_EINVAL;
+        if (!c->has_mesh) return c->fail(SLBM_ESTATE, "bind before set_mesh");
+        if (c->bound) return c->fail(SLBM_ESTATE, "already bound");
+        if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return c->fail(SLBM_EINVAL, "workspace must be 256-byte aligned");
+        if (bytes < c->ws_bytes)
+            return c->fail(SLBM_ENOMEM, "workspace %zu bytes < required %zu", bytes, c->ws_bytes);
+        c->dev = dev_ptr;
+        c->stream = hip_stream;
+        hipStream_t st = (hipStream_t)hip_stream;
+        void *b = dev_ptr;
+        SolveDesc &d = c->desc;
+        std::memset(&d, 0, sizeof d);
+        d.E = (int)c->E;
+        d.Nl = (int)c->Nl;
+        d.Ng = (int)c->Ng;
+        d.lgid = at<int>(b, c->off.lgid);
+        d.Ja = at<double>(b, c->off.Ja);
+        d.G = at<double>(b, c->off.G);
+        d.Minv = at<double>(b, c->off.Minv);
+        d.gcopy = at<NodeCopies>(b, c->off.gcopy);
+        d.csr_idx = at<int>(b, c->off.csr_idx);
+        d.lcp = at<int>(b, c->off.lcp);
+        d.vmax = c->vmax;
+        d.lwall = at<int>(b, c->off.lwall);
+        d.w_dat = at<double>(b, c->off.w_dat);
+        d.Dm = at<double>(b, c->off.Dm);
+        d.wn = at<double>(b, c->off.wn);
+        d.f = at<double>(b, c->off.f);
+        d.g0 = at<double>(b, c->off.g0);
+        d.g1 = at<double>(b, c->off.g1);
+        d.g2 = at<double>(b, c->off.g2);
+        d.rho = at<double>(b, c->off.rho);
+        d.mu = at<double>(b, c->off.mu);
+        d.rl = at<double>(b, c->off.rl);
+        d.gl = at<double>(b, c->off.gl);
+        d.rs = at<double>(b, c->off.rs);
+        d.aux = at<double>(b, c->off.aux);
+        d.diag = at<double>(b, c->off.diag);
+        d.red = at<double>(b, c->off.red);
+        d.rho_l = c->prm.rho_l;
+        d.rho_v = c->prm.rho_v;
+        d.beta = c->beta;
+        d.kappa = c->kappa;
+        d.omega = c->omega;
+        d.dt = c->dt;
+        for (int q = 0; q < c->Q; ++q) {
+            const int cls = (int)(std::fabs(c->ev[q][0]) + std::fabs(c->ev[q][1]) + std::fabs(c->ev[q][2]));
+            d.tw[cls] = c->tw[q];
+            d.twc[cls] = c->tc[q];
+        }
+        // block tables of the single-member plans
+        std::vector<int> ep(2 * (size_t)c->n_eblocks), np_(2 * (size_t)c->n_nblocks);
+        for (int i = 0; i < c->n_eblocks; ++i) { ep[i] = 0; ep[c->n_eblocks + i] = i; }
+        for (int i = 0; i < c->n_nblocks; ++i) { np_[i] = 0; np_[c->n_nblocks + i] = i; }
+        c->eplan.desc = at<SolveDesc>(b, c->off.desc);
+        c->eplan.blk_solve = at<int>(b, c->off.eplan);
+        c->eplan.blk_local = at<int>(b, c->off.eplan) + c->n_eblocks;
+        c->eplan.nblocks = c->n_eblocks;
+        c->eplan.single = 1;
+        c->eplan.one = d;
+        c->eplan.epb = c->epb;
+        c->eplan.grid = c->n_eblocks;
+        c->nplan.desc = at<SolveDesc>(b, c->off.desc);
+        c->nplan.blk_solve = at<int>(b, c->off.nplan);
+        c->nplan.blk_local = at<int>(b, c->off.nplan) + c->n_nblocks;
+        c->nplan.nblocks = c->n_nblocks;
+        c->nplan.single = 1;
+        c->nplan.one = d;
+        c->nplan.epb = 0;
+        c->nplan.grid = c->n_nblocks;
+        const int dim = c->dim;
+        const size_t ng = (size_t)dim * (dim + 1) / 2;
+        int e = 0;
+        auto up = [&](size_t off, const void *src, size_t n) {
+            if (e == 0 && n) e = (int)hipMemcpyAsync((char *)b + off, src, n, hipMemcpyHostToDevice, st);
+        };
+        up(c->off.desc, &d, sizeof d);
+        up(c->off.eplan, ep.data(), sizeof(int) * ep.size());
+        up(c->off.nplan, np_.data(), sizeof(int) * np_.size());
+        up(c->off.lgid, c->lgid.data(), sizeof(int) * c->Nl);
+        up(c->off.gcopy, c->gcopy.data(), sizeof(int) * c->gcopy.size());
+        up(c->off.csr_idx, c->csr_idx.data(), sizeof(int) * c->Nl);
+        up(c->off.lcp, c->lcp.data(), sizeof(int) * c->lcp.size());
+        up(c->off.lwall, c->lwall.data(), sizeof(int) * c->Nl);
+        up(c->off.w_dat, c->w_dat.data(), sizeof(double) * c->w_dat.size());
+        up(c->off.Ja, c->Ja.data(), sizeof(double) * dim * dim * c->Nl);
+        up(c->off.G, c->Gm.data(), sizeof(double) * ng * c->Nl);
+        up(c->off.Minv, c->Minv.data(), sizeof(double) * c->Ng);
+        up(c->off.Dm, c->Dm.data(), sizeof(double) * c->Np * c->Np);
+        up(c->off.wn, c->wn.data(), sizeof(double) * c->nloc);
+        if (e == 0) e = (int)hipMemsetAsync((char *)b + c->off.f, 0, c->off.diag - c->off.f, st);
+        if (e == 0) e = (int)hipStreamSynchronize(st);
+        if (e) return c->hip_check(e, "bind upload");
+        c->bound = true;
+        c->has_state = false;
+        c->step = 0;
+        const char *nog = std::getenv("SLBM_NO_GRAPH");
+        c->use_graph = !(nog && nog[0] == '1');
+        return SLBM_OK;
+    });
 }
 
 // ------------------------------------------------------------------------------------------
@@ -684,66 +690,74 @@ slbm_status slbm_ctx::require_bound(bool need_state) {
 }
 
 extern "C" slbm_status slbm_set_rho(slbm_ctx *c, const double *rho) {
-    if (!c || !rho) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(false)) return s;
-    std::vector<double> f((size_t)c->Q * c->Ng);
-    for (int64_t g = 0; g < c->Ng; ++g) {
-        const double r = rho[c->ig2ug[g]];
-        for (int q = 0; q < c->Q; ++q) f[(size_t)q * c->Ng + g] = c->tw[q] * r;
-    }
-    c->step = 0;
-    return c->upload_f_and_density(f);
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !rho) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(false)) return s;
+        std::vector<double> f((size_t)c->Q * c->Ng);
+        for (int64_t g = 0; g < c->Ng; ++g) {
+            const double r = rho[c->ig2ug[g]];
+            for (int q = 0; q < c->Q; ++q) f[(size_t)q * c->Ng + g] = c->tw[q] * r;
+        }
+        c->step = 0;
+        return c->upload_f_and_density(f);
+    });
 }
 
 extern "C" slbm_status slbm_init_tanh(slbm_ctx *c, const double *x0, double R, double noise_amp,
                                       uint64_t seed) {
-    if (!c || !x0) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(false)) return s;
-    const int dim = c->dim;
-    const double rl = c->prm.rho_l, rv = c->prm.rho_v, dl = c->prm.delta;
-    std::vector<double> rho_user(c->Ng);
-    for (int64_t g = 0; g < c->Ng; ++g) {
-        const int64_t l = c->csr_idx[c->csr_ptr[g]];  // lowest local copy
-        double r2 = 0.0;
-        for (int cc = 0; cc < dim; ++cc) {
-            const double d = c->xyz[l * dim + cc] - x0[cc];
-            r2 += d * d;
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !x0) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(false)) return s;
+        const int dim = c->dim;
+        const double rl = c->prm.rho_l, rv = c->prm.rho_v, dl = c->prm.delta;
+        std::vector<double> rho_user(c->Ng);
+        for (int64_t g = 0; g < c->Ng; ++g) {
+            const int64_t l = c->csr_idx[c->csr_ptr[g]];  // lowest local copy
+            double r2 = 0.0;
+            for (int cc = 0; cc < dim; ++cc) {
+                const double d = c->xyz[l * dim + cc] - x0[cc];
+                r2 += d * d;
+            }
+            const double x = std::sqrt(r2) - R;
+            double p = 0.5 * (rl + rv) - 0.5 * (rl - rv) * std::tanh(2.0 * x / dl);
+            const uint64_t ug = (uint64_t)c->ig2ug[g];
+            if (noise_amp != 0.0) {
+                const uint64_t h = splitmix64(seed ^ ug);
+                const double U = (double)(h >> 11) * 0x1.0p-53;
+                p += noise_amp * (2.0 * U - 1.0);
+            }
+            rho_user[ug] = p;
         }
-        const double x = std::sqrt(r2) - R;
-        double p = 0.5 * (rl + rv) - 0.5 * (rl - rv) * std::tanh(2.0 * x / dl);
-        const uint64_t ug = (uint64_t)c->ig2ug[g];
-        if (noise_amp != 0.0) {
-            const uint64_t h = splitmix64(seed ^ ug);
-            const double U = (double)(h >> 11) * 0x1.0p-53;
-            p += noise_amp * (2.0 * U - 1.0);
-        }
-        rho_user[ug] = p;
-    }
-    return slbm_set_rho(c, rho_user.data());
+        return slbm_set_rho(c, rho_user.data());
+    });
 }
 
 extern "C" slbm_status slbm_get_state(slbm_ctx *c, double *f, int64_t *step) {
-    if (!c || !f) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(true)) return s;
-    std::vector<double> fi((size_t)c->Q * c->Ng);
-    int e = (int)hipMemcpyAsync(fi.data(), c->desc.f, sizeof(double) * fi.size(), hipMemcpyDeviceToHost,
-                                (hipStream_t)c->stream);
-    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
-    if (e) return c->hip_check(e, "get_state");
-    for (int q = 0; q < c->Q; ++q)
-        for (int64_t g = 0; g < c->Ng; ++g) f[(size_t)q * c->Ng + c->ig2ug[g]] = fi[(size_t)q * c->Ng + g];
-    if (step) *step = c->step;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !f) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(true)) return s;
+        std::vector<double> fi((size_t)c->Q * c->Ng);
+        int e = (int)hipMemcpyAsync(fi.data(), c->desc.f, sizeof(double) * fi.size(), hipMemcpyDeviceToHost,
+                                    (hipStream_t)c->stream);
+        if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+        if (e) return c->hip_check(e, "get_state");
+        for (int q = 0; q < c->Q; ++q)
+            for (int64_t g = 0; g < c->Ng; ++g) f[(size_t)q * c->Ng + c->ig2ug[g]] = fi[(size_t)q * c->Ng + g];
+        if (step) *step = c->step;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_set_state(slbm_ctx *c, const double *f, int64_t step) {
-    if (!c || !f) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(false)) return s;
-    std::vector<double> fi((size_t)c->Q * c->Ng);
-    for (int q = 0; q < c->Q; ++q)
-        for (int64_t g = 0; g < c->Ng; ++g) fi[(size_t)q * c->Ng + g] = f[(size_t)q * c->Ng + c->ig2ug[g]];
-    c->step = step;
-    return c->upload_f_and_density(fi);
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !f) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(false)) return s;
+        std::vector<double> fi((size_t)c->Q * c->Ng);
+        for (int q = 0; q < c->Q; ++q)
+            for (int64_t g = 0; g < c->Ng; ++g) fi[(size_t)q * c->Ng + g] = f[(size_t)q * c->Ng + c->ig2ug[g]];
+        c->step = step;
+        return c->upload_f_and_density(fi);
+    });
 }
 
 // ------------------------------------------------------------------------------------------
@@ -863,79 +877,83 @@ slbm_status slbm_ctx::enqueue(int64_t n) {
 }
 
 extern "C" slbm_status slbm_step(slbm_ctx *c, int64_t n) {
-    if (!c || n < 0) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(true)) return s;
-    const int every = c->prm.ke_every;
-    const double lim = c->prm.ke_limit > 0.0 ? c->prm.ke_limit : 1.0;
-    int64_t done = 0;
-    while (done < n) {
-        int64_t chunk = n - done;
-        if (every > 0) chunk = std::min<int64_t>(chunk, every - (c->step % every));
-        if (slbm_status s = c->enqueue(chunk)) return s;
-        done += chunk;
-        c->step += chunk;
-        if (every > 0 && c->step % every == 0) {
-            double ke = 0.0;
-            if (slbm_status s = c->read_diag(&ke, nullptr)) return s;
-            if (!(ke <= lim)) return c->fail(SLBM_EDIVERGED, "KE_max = %g at step %lld", ke, (long long)c->step);
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || n < 0) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(true)) return s;
+        const int every = c->prm.ke_every;
+        const double lim = c->prm.ke_limit > 0.0 ? c->prm.ke_limit : 1.0;
+        int64_t done = 0;
+        while (done < n) {
+            int64_t chunk = n - done;
+            if (every > 0) chunk = std::min<int64_t>(chunk, every - (c->step % every));
+            if (slbm_status s = c->enqueue(chunk)) return s;
+            done += chunk;
+            c->step += chunk;
+            if (every > 0 && c->step % every == 0) {
+                double ke = 0.0;
+                if (slbm_status s = c->read_diag(&ke, nullptr)) return s;
+                if (!(ke <= lim)) return c->fail(SLBM_EDIVERGED, "KE_max = %g at step %lld", ke, (long long)c->step);
+            }
         }
-    }
-    return SLBM_OK;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
-    if (!c || n < 0 || !ms || !launches) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(true)) return s;
-    hipStream_t st = (hipStream_t)c->stream;
-    constexpr int kPerStep = 14;
-    hipEvent_t ev[2 * kPerStep];
-    for (auto &e : ev)
-        if (hipEventCreate(&e) != hipSuccess) return c->fail(SLBM_EDEVICE, "event create");
-    for (int k = 0; k < SLBM_NUM_KERNEL_KINDS; ++k) { ms[k] = 0.0; launches[k] = 0; }
-    const int d = c->dim, N = c->N;
-    int kinds[kPerStep];
-    int e = 0;
-    for (int64_t s = 0; s < n && e == 0; ++s) {
-        int i = 0;
-        auto rec = [&](int kind, auto &&fn) {
-            if (e) return;
-            e = (int)hipEventRecord(ev[2 * i], st);
-            if (!e) e = fn();
-            if (!e) e = (int)hipEventRecord(ev[2 * i + 1], st);
-            kinds[i++] = kind;
-        };
-        if (c->fused) {
-            rec(6, [&] { return launch_fA(d, N, c->eplan, c->stream); });
-            rec(7, [&] { return launch_fB(d, N, c->eplan, c->stream); });
-            rec(8, [&] { return launch_fC(d, N, c->eplan, 1, c->stream); });
-            rec(9, [&] { return launch_fD(d, N, c->eplan, 2, c->stream); });
-            rec(8, [&] { return launch_fC(d, N, c->eplan, 2, c->stream); });
-            rec(9, [&] { return launch_fD(d, N, c->eplan, 3, c->stream); });
-            rec(8, [&] { return launch_fC(d, N, c->eplan, 3, c->stream); });
-        }
-        if (!c->fused) rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
-        if (!c->fused) rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
-        if (!c->fused) rec(2, [&] { return launch_grad(d, N, c->eplan, c->stream); });
-        if (!c->fused) rec(3, [&] { return launch_collide(d, N, c->nplan, 0, c->stream); });
-        for (int stage = 1; stage <= 3 && !c->fused; ++stage) {
-            if (stage > 1) {
-                rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
-                rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || n < 0 || !ms || !launches) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(true)) return s;
+        hipStream_t st = (hipStream_t)c->stream;
+        constexpr int kPerStep = 14;
+        hipEvent_t ev[2 * kPerStep];
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return c->fail(SLBM_EDEVICE, "event create");
+        for (int k = 0; k < SLBM_NUM_KERNEL_KINDS; ++k) { ms[k] = 0.0; launches[k] = 0; }
+        const int d = c->dim, N = c->N;
+        int kinds[kPerStep];
+        int e = 0;
+        for (int64_t s = 0; s < n && e == 0; ++s) {
+            int i = 0;
+            auto rec = [&](int kind, auto &&fn) {
+                if (e) return;
+                e = (int)hipEventRecord(ev[2 * i], st);
+                if (!e) e = fn();
+                if (!e) e = (int)hipEventRecord(ev[2 * i + 1], st);
+                kinds[i++] = kind;
+            };
+            if (c->fused) {
+                rec(6, [&] { return launch_fA(d, N, c->eplan, c->stream); });
+                rec(7, [&] { return launch_fB(d, N, c->eplan, c->stream); });
+                rec(8, [&] { return launch_fC(d, N, c->eplan, 1, c->stream); });
+                rec(9, [&] { return launch_fD(d, N, c->eplan, 2, c->stream); });
+                rec(8, [&] { return launch_fC(d, N, c->eplan, 2, c->stream); });
+                rec(9, [&] { return launch_fD(d, N, c->eplan, 3, c->stream); });
+                rec(8, [&] { return launch_fC(d, N, c->eplan, 3, c->stream); });
             }
-            rec(4, [&] { return launch_stream(d, N, c->eplan, stage, c->stream); });
-            rec(5, [&] { return launch_rk(d, N, c->nplan, stage, c->stream); });
+            if (!c->fused) rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
+            if (!c->fused) rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
+            if (!c->fused) rec(2, [&] { return launch_grad(d, N, c->eplan, c->stream); });
+            if (!c->fused) rec(3, [&] { return launch_collide(d, N, c->nplan, 0, c->stream); });
+            for (int stage = 1; stage <= 3 && !c->fused; ++stage) {
+                if (stage > 1) {
+                    rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
+                    rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
+                }
+                rec(4, [&] { return launch_stream(d, N, c->eplan, stage, c->stream); });
+                rec(5, [&] { return launch_rk(d, N, c->nplan, stage, c->stream); });
+            }
+            if (!e) e = (int)hipEventSynchronize(ev[2 * i - 1]);
+            for (int j = 0; j < i && !e; ++j) {
+                float t = 0.0f;
+                e = (int)hipEventElapsedTime(&t, ev[2 * j], ev[2 * j + 1]);
+                ms[kinds[j]] += t;
+                launches[kinds[j]] += 1;
+            }
+            c->step += 1;
         }
-        if (!e) e = (int)hipEventSynchronize(ev[2 * i - 1]);
-        for (int j = 0; j < i && !e; ++j) {
-            float t = 0.0f;
-            e = (int)hipEventElapsedTime(&t, ev[2 * j], ev[2 * j + 1]);
-            ms[kinds[j]] += t;
-            launches[kinds[j]] += 1;
-        }
-        c->step += 1;
-    }
-    for (auto &x : ev) (void)hipEventDestroy(x);
-    return c->hip_check(e, "step_profile");
+        for (auto &x : ev) (void)hipEventDestroy(x);
+        return c->hip_check(e, "step_profile");
+    });
 }
 
 namespace {
@@ -966,122 +984,136 @@ struct KindLaunches {
 }  // namespace
 
 extern "C" slbm_status slbm_time_kernel(slbm_ctx *c, int kind, int64_t reps, double *ms_per_launch) {
-    if (!c || !ms_per_launch || kind < 0 || kind >= SLBM_NUM_KERNEL_KINDS || reps < 1 || reps > 4096)
-        return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(true)) return s;
-    if ((kind >= 6) != c->fused) return c->fail(SLBM_EINVAL, "kernel kind is not on this context's path");
-    hipStream_t st = (hipStream_t)c->stream;
-    // the launches overwrite stage buffers and the state's density: keep f-bar to restore
-    std::vector<double> f((size_t)c->Q * c->Ng);
-    int e = (int)hipMemcpyAsync(f.data(), c->desc.f, sizeof(double) * f.size(), hipMemcpyDeviceToHost, st);
-    if (e == 0) e = (int)hipStreamSynchronize(st);
-    if (e) return c->hip_check(e, "time_kernel save");
-    KindLaunches a{c, kind, reps};
-    auto fn = +[](void *, void *arg) -> int {
-        const KindLaunches *x = (const KindLaunches *)arg;
-        int r = 0;
-        for (int64_t i = 0; i < x->reps && r == 0; ++i) r = launch_kind(x->c, x->kind, i);
-        return r;
-    };
-    void *exec = nullptr;
-    if (c->use_graph && capture_graph(c->stream, &exec, fn, &a) != 0) {
-        (void)hipGetLastError();  // stream not capturable (the null stream): plain launches
-        exec = nullptr;
-    }
-    auto replay = [&]() { return exec ? launch_graph(exec, c->stream) : fn(c->stream, &a); };
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    if (e == 0) e = (int)hipEventCreate(&ev[0]);
-    if (e == 0) e = (int)hipEventCreate(&ev[1]);
-    if (e == 0) e = replay();  // warm-up
-    if (e == 0) e = (int)hipEventRecord(ev[0], st);
-    if (e == 0) e = replay();
-    if (e == 0) e = (int)hipEventRecord(ev[1], st);
-    if (e == 0) e = (int)hipEventSynchronize(ev[1]);
-    float t = 0.0f;
-    if (e == 0) e = (int)hipEventElapsedTime(&t, ev[0], ev[1]);
-    for (hipEvent_t x : ev)
-        if (x) (void)hipEventDestroy(x);
-    if (exec) destroy_graph(exec);
-    if (e) return c->hip_check(e, "time_kernel");
-    *ms_per_launch = (double)t / (double)reps;
-    return c->upload_f_and_density(f);
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !ms_per_launch || kind < 0 || kind >= SLBM_NUM_KERNEL_KINDS || reps < 1 || reps > 4096)
+            return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(true)) return s;
+        if ((kind >= 6) != c->fused) return c->fail(SLBM_EINVAL, "kernel kind is not on this context's path");
+        hipStream_t st = (hipStream_t)c->stream;
+        // the launches overwrite stage buffers and the state's density: keep f-bar to restore
+        std::vector<double> f((size_t)c->Q * c->Ng);
+        int e = (int)hipMemcpyAsync(f.data(), c->desc.f, sizeof(double) * f.size(), hipMemcpyDeviceToHost, st);
+        if (e == 0) e = (int)hipStreamSynchronize(st);
+        if (e) return c->hip_check(e, "time_kernel save");
+        KindLaunches a{c, kind, reps};
+        auto fn = +[](void *, void *arg) -> int {
+            const KindLaunches *x = (const KindLaunches *)arg;
+            int r = 0;
+            for (int64_t i = 0; i < x->reps && r == 0; ++i) r = launch_kind(x->c, x->kind, i);
+            return r;
+        };
+        void *exec = nullptr;
+        if (c->use_graph && capture_graph(c->stream, &exec, fn, &a) != 0) {
+            (void)hipGetLastError();  // stream not capturable (the null stream): plain launches
+            exec = nullptr;
+        }
+        auto replay = [&]() { return exec ? launch_graph(exec, c->stream) : fn(c->stream, &a); };
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        if (e == 0) e = (int)hipEventCreate(&ev[0]);
+        if (e == 0) e = (int)hipEventCreate(&ev[1]);
+        if (e == 0) e = replay();  // warm-up
+        if (e == 0) e = (int)hipEventRecord(ev[0], st);
+        if (e == 0) e = replay();
+        if (e == 0) e = (int)hipEventRecord(ev[1], st);
+        if (e == 0) e = (int)hipEventSynchronize(ev[1]);
+        float t = 0.0f;
+        if (e == 0) e = (int)hipEventElapsedTime(&t, ev[0], ev[1]);
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+        if (exec) destroy_graph(exec);
+        if (e) return c->hip_check(e, "time_kernel");
+        *ms_per_launch = (double)t / (double)reps;
+        return c->upload_f_and_density(f);
+    });
 }
 
 // ------------------------------------------------------------------------------------------
 // queries
 // ------------------------------------------------------------------------------------------
 extern "C" slbm_status slbm_get_rho(slbm_ctx *c, double *rho) {
-    if (!c || !rho) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(true)) return s;
-    std::vector<double> r(c->Ng);
-    int e = (int)hipMemcpyAsync(r.data(), c->desc.rho, sizeof(double) * c->Ng, hipMemcpyDeviceToHost,
-                                (hipStream_t)c->stream);
-    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
-    if (e) return c->hip_check(e, "get_rho");
-    for (int64_t g = 0; g < c->Ng; ++g) rho[c->ig2ug[g]] = r[g];
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !rho) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(true)) return s;
+        std::vector<double> r(c->Ng);
+        int e = (int)hipMemcpyAsync(r.data(), c->desc.rho, sizeof(double) * c->Ng, hipMemcpyDeviceToHost,
+                                    (hipStream_t)c->stream);
+        if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+        if (e) return c->hip_check(e, "get_rho");
+        for (int64_t g = 0; g < c->Ng; ++g) rho[c->ig2ug[g]] = r[g];
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_get_u(slbm_ctx *c, double *u) {
-    if (!c || !u) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(true)) return s;
-    std::vector<double> f((size_t)c->Q * c->Ng);
-    int e = (int)hipMemcpyAsync(f.data(), c->desc.f, sizeof(double) * f.size(), hipMemcpyDeviceToHost,
-                                (hipStream_t)c->stream);
-    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
-    if (e) return c->hip_check(e, "get_u");
-    // Eq. (11) on the host from the downloaded state (a query, not part of the step)
-    for (int64_t g = 0; g < c->Ng; ++g) {
-        double p = 0.0;
-        for (int q = 0; q < c->Q; ++q) p += f[(size_t)q * c->Ng + g];
-        for (int cc = 0; cc < c->dim; ++cc) {
-            double m = 0.0;
-            for (int q = 0; q < c->Q; ++q) m += f[(size_t)q * c->Ng + g] * c->ev[q][cc];
-            u[(size_t)cc * c->Ng + c->ig2ug[g]] = m / p;
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !u) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(true)) return s;
+        std::vector<double> f((size_t)c->Q * c->Ng);
+        int e = (int)hipMemcpyAsync(f.data(), c->desc.f, sizeof(double) * f.size(), hipMemcpyDeviceToHost,
+                                    (hipStream_t)c->stream);
+        if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+        if (e) return c->hip_check(e, "get_u");
+        // Eq. (11) on the host from the downloaded state (a query, not part of the step)
+        for (int64_t g = 0; g < c->Ng; ++g) {
+            double p = 0.0;
+            for (int q = 0; q < c->Q; ++q) p += f[(size_t)q * c->Ng + g];
+            for (int cc = 0; cc < c->dim; ++cc) {
+                double m = 0.0;
+                for (int q = 0; q < c->Q; ++q) m += f[(size_t)q * c->Ng + g] * c->ev[q][cc];
+                u[(size_t)cc * c->Ng + c->ig2ug[g]] = m / p;
+            }
         }
-    }
-    return SLBM_OK;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_kinetic_energy(slbm_ctx *c, double *ke_max, double *mass) {
-    if (!c) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(true)) return s;
-    return c->read_diag(ke_max, mass);
+    return slbm_guard([&]() -> slbm_status {
+        if (!c) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(true)) return s;
+        return c->read_diag(ke_max, mass);
+    });
 }
 
 extern "C" slbm_status slbm_get_info(const slbm_ctx *c, slbm_info *info) {
-    if (!c || !info) return SLBM_EINVAL;
-    std::memset(info, 0, sizeof *info);
-    info->dt = c->dt;
-    info->beta = c->beta;
-    info->kappa = c->kappa;
-    info->omega = c->omega;
-    info->h_min = c->hmin;
-    info->n_elements = c->E;
-    info->n_local = c->Nl;
-    info->n_global = c->Ng;
-    info->n_wall_nodes = c->nw;
-    info->step = c->step;
-    info->workspace_bytes = c->has_mesh ? c->ws_bytes : 0;
-    info->dim = c->dim;
-    info->Q = c->Q;
-    info->N = c->N;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !info) return SLBM_EINVAL;
+        std::memset(info, 0, sizeof *info);
+        info->dt = c->dt;
+        info->beta = c->beta;
+        info->kappa = c->kappa;
+        info->omega = c->omega;
+        info->h_min = c->hmin;
+        info->n_elements = c->E;
+        info->n_local = c->Nl;
+        info->n_global = c->Ng;
+        info->n_wall_nodes = c->nw;
+        info->step = c->step;
+        info->workspace_bytes = c->has_mesh ? c->ws_bytes : 0;
+        info->dim = c->dim;
+        info->Q = c->Q;
+        info->N = c->N;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_get_gll(const slbm_ctx *c, double *x, double *w, double *D) {
-    if (!c || !x || !w || !D) return SLBM_EINVAL;
-    std::memcpy(x, c->xi.data(), sizeof(double) * c->Np);
-    std::memcpy(w, c->wq.data(), sizeof(double) * c->Np);
-    std::memcpy(D, c->Dm.data(), sizeof(double) * c->Np * c->Np);
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !x || !w || !D) return SLBM_EINVAL;
+        std::memcpy(x, c->xi.data(), sizeof(double) * c->Np);
+        std::memcpy(w, c->wq.data(), sizeof(double) * c->Np);
+        std::memcpy(D, c->Dm.data(), sizeof(double) * c->Np * c->Np);
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_get_mass(const slbm_ctx *c, double *MA) {
-    if (!c || !MA) return SLBM_EINVAL;
-    if (!c->has_mesh) return SLBM_ESTATE;
-    for (int64_t g = 0; g < c->Ng; ++g) MA[c->ig2ug[g]] = c->MA[g];
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !MA) return SLBM_EINVAL;
+        if (!c->has_mesh) return SLBM_ESTATE;
+        for (int64_t g = 0; g < c->Ng; ++g) MA[c->ig2ug[g]] = c->MA[g];
+        return SLBM_OK;
+    });
 }
 
 extern "C" const char *slbm_last_error(const slbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
@@ -1122,68 +1154,76 @@ slbm_status slbm_ctx::restore_density() {
 }
 
 extern "C" slbm_status slbm_op_mu(slbm_ctx *c, const double *rho, double *mu) {
-    if (!c || !rho || !mu) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(false)) return s;
-    if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
-    int e = launch_lap(c->dim, c->N, c->eplan, c->stream);
-    if (e == 0) e = launch_mu(c->dim, c->N, c->nplan, c->stream);
-    if (e) return c->hip_check(e, "op_mu");
-    if (slbm_status s = c->get(c->desc.mu, mu, 1)) return s;
-    return c->restore_density();
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !rho || !mu) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(false)) return s;
+        if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
+        int e = launch_lap(c->dim, c->N, c->eplan, c->stream);
+        if (e == 0) e = launch_mu(c->dim, c->N, c->nplan, c->stream);
+        if (e) return c->hip_check(e, "op_mu");
+        if (slbm_status s = c->get(c->desc.mu, mu, 1)) return s;
+        return c->restore_density();
+    });
 }
 
 extern "C" slbm_status slbm_op_grad(slbm_ctx *c, const double *phi, double *grad) {
-    if (!c || !phi || !grad) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(false)) return s;
-    if (slbm_status s = c->put(c->desc.rho, phi, 1)) return s;
-    int e = launch_grad(c->dim, c->N, c->eplan, c->stream);
-    if (e == 0) e = launch_gavg(c->dim, c->N, c->nplan, c->stream);
-    if (e) return c->hip_check(e, "op_grad");
-    if (slbm_status s = c->get(c->desc.aux, grad, c->dim)) return s;
-    return c->restore_density();
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !phi || !grad) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(false)) return s;
+        if (slbm_status s = c->put(c->desc.rho, phi, 1)) return s;
+        int e = launch_grad(c->dim, c->N, c->eplan, c->stream);
+        if (e == 0) e = launch_gavg(c->dim, c->N, c->nplan, c->stream);
+        if (e) return c->hip_check(e, "op_grad");
+        if (slbm_status s = c->get(c->desc.aux, grad, c->dim)) return s;
+        return c->restore_density();
+    });
 }
 
 extern "C" slbm_status slbm_op_stream(slbm_ctx *c, const double *g, const double *rho,
                                       const double *mu, double *L) {
-    if (!c || !g || !rho || !mu || !L) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(false)) return s;
-    if (slbm_status s = c->put(c->desc.g1, g, c->Q)) return s;
-    if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
-    if (slbm_status s = c->put(c->desc.mu, mu, 1)) return s;
-    int e = launch_stream(c->dim, c->N, c->eplan, 2, c->stream);
-    if (e == 0) e = launch_rk(c->dim, c->N, c->nplan, 0, c->stream);  // stage 0: L into g1
-    if (e) return c->hip_check(e, "op_stream");
-    if (slbm_status s = c->get(c->desc.g1, L, c->Q)) return s;
-    return c->restore_density();
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !g || !rho || !mu || !L) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(false)) return s;
+        if (slbm_status s = c->put(c->desc.g1, g, c->Q)) return s;
+        if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
+        if (slbm_status s = c->put(c->desc.mu, mu, 1)) return s;
+        int e = launch_stream(c->dim, c->N, c->eplan, 2, c->stream);
+        if (e == 0) e = launch_rk(c->dim, c->N, c->nplan, 0, c->stream);  // stage 0: L into g1
+        if (e) return c->hip_check(e, "op_stream");
+        if (slbm_status s = c->get(c->desc.g1, L, c->Q)) return s;
+        return c->restore_density();
+    });
 }
 
 extern "C" slbm_status slbm_op_collide(slbm_ctx *c, const double *f, const double *rho,
                                        const double *grho, const double *gmu, double *fstar) {
-    if (!c || !f || !rho || !grho || !gmu || !fstar) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(false)) return s;
-    // the collision kernel reads the state buffer: save it, run, restore
-    std::vector<double> saved;
-    if (c->has_state) {
-        saved.resize((size_t)c->Q * c->Ng);
-        int e = (int)hipMemcpyAsync(saved.data(), c->desc.f, sizeof(double) * saved.size(),
-                                    hipMemcpyDeviceToHost, (hipStream_t)c->stream);
-        if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
-        if (e) return c->hip_check(e, "op_collide save");
-    }
-    std::vector<double> gg((size_t)2 * c->dim * c->Ng);
-    std::memcpy(gg.data(), grho, sizeof(double) * c->dim * c->Ng);
-    std::memcpy(gg.data() + (size_t)c->dim * c->Ng, gmu, sizeof(double) * c->dim * c->Ng);
-    if (slbm_status s = c->put(c->desc.f, f, c->Q)) return s;
-    if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
-    if (slbm_status s = c->put(c->desc.aux, gg.data(), 2 * c->dim)) return s;
-    int e = launch_collide(c->dim, c->N, c->nplan, 1, c->stream);
-    if (e) return c->hip_check(e, "op_collide");
-    if (slbm_status s = c->get(c->desc.g0, fstar, c->Q)) return s;
-    if (c->has_state) {
-        int e2 = (int)hipMemcpyAsync(c->desc.f, saved.data(), sizeof(double) * saved.size(),
-                                     hipMemcpyHostToDevice, (hipStream_t)c->stream);
-        if (e2 == 0) e2 = (int)hipStreamSynchronize((hipStream_t)c->stream);
-        if (e2) return c->hip_check(e2, "op_collide restore");
-    }
-    return c->restore_density();
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !f || !rho || !grho || !gmu || !fstar) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(false)) return s;
+        // the collision kernel reads the state buffer: save it, run, restore
+        std::vector<double> saved;
+        if (c->has_state) {
+            saved.resize((size_t)c->Q * c->Ng);
+            int e = (int)hipMemcpyAsync(saved.data(), c->desc.f, sizeof(double) * saved.size(),
+                                        hipMemcpyDeviceToHost, (hipStream_t)c->stream);
+            if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+            if (e) return c->hip_check(e, "op_collide save");
+        }
+        std::vector<double> gg((size_t)2 * c->dim * c->Ng);
+        std::memcpy(gg.data(), grho, sizeof(double) * c->dim * c->Ng);
+        std::memcpy(gg.data() + (size_t)c->dim * c->Ng, gmu, sizeof(double) * c->dim * c->Ng);
+        if (slbm_status s = c->put(c->desc.f, f, c->Q)) return s;
+        if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
+        if (slbm_status s = c->put(c->desc.aux, gg.data(), 2 * c->dim)) return s;
+        int e = launch_collide(c->dim, c->N, c->nplan, 1, c->stream);
+        if (e) return c->hip_check(e, "op_collide");
+        if (slbm_status s = c->get(c->desc.g0, fstar, c->Q)) return s;
+        if (c->has_state) {
+            int e2 = (int)hipMemcpyAsync(c->desc.f, saved.data(), sizeof(double) * saved.size(),
+                                         hipMemcpyHostToDevice, (hipStream_t)c->stream);
+            if (e2 == 0) e2 = (int)hipStreamSynchronize((hipStream_t)c->stream);
+            if (e2) return c->hip_check(e2, "op_collide restore");
+        }
+        return c->restore_density();
+    });
 }

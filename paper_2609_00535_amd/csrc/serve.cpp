@@ -393,110 +393,124 @@ struct slbm_batch {
 };
 
 extern "C" slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out) {
-    if (!out) return SLBM_EINVAL;
-    *out = new (std::nothrow) slbm_batch();
-    if (!*out) return SLBM_ENOMEM;
-    (*out)->stream = hip_stream;
-    const char *ng = std::getenv("SLBM_NO_GRAPH");
-    (*out)->use_graph = !(ng && ng[0] == '1');
-    const char *sg = std::getenv("SLBM_SERIAL_GROUPS");
-    (*out)->concurrent = !(sg && sg[0] == '1');
-    const char *at = std::getenv("SLBM_AUTOTUNE");
-    (*out)->autotune = !(at && at[0] == '0');
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!out) return SLBM_EINVAL;
+        *out = new (std::nothrow) slbm_batch();
+        if (!*out) return SLBM_ENOMEM;
+        (*out)->stream = hip_stream;
+        const char *ng = std::getenv("SLBM_NO_GRAPH");
+        (*out)->use_graph = !(ng && ng[0] == '1');
+        const char *sg = std::getenv("SLBM_SERIAL_GROUPS");
+        (*out)->concurrent = !(sg && sg[0] == '1');
+        const char *at = std::getenv("SLBM_AUTOTUNE");
+        (*out)->autotune = !(at && at[0] == '0');
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_batch_add(slbm_batch *b, slbm_ctx *c) {
-    if (!b || !c) return SLBM_EINVAL;
-    if (!c->bound || !c->has_state) return SLBM_ESTATE;
-    if (c->stream != b->stream) return SLBM_EINVAL;
-    if (std::find(b->members.begin(), b->members.end(), c) != b->members.end()) return SLBM_EINVAL;
-    b->members.push_back(c);
-    b->dirty = true;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!b || !c) return SLBM_EINVAL;
+        if (!c->bound || !c->has_state) return SLBM_ESTATE;
+        if (c->stream != b->stream) return SLBM_EINVAL;
+        if (std::find(b->members.begin(), b->members.end(), c) != b->members.end()) return SLBM_EINVAL;
+        b->members.push_back(c);
+        b->dirty = true;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_batch_remove(slbm_batch *b, slbm_ctx *c) {
-    if (!b || !c) return SLBM_EINVAL;
-    auto it = std::find(b->members.begin(), b->members.end(), c);
-    if (it == b->members.end()) return SLBM_EINVAL;
-    b->members.erase(it);
-    b->dirty = true;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!b || !c) return SLBM_EINVAL;
+        auto it = std::find(b->members.begin(), b->members.end(), c);
+        if (it == b->members.end()) return SLBM_EINVAL;
+        b->members.erase(it);
+        b->dirty = true;
+        return SLBM_OK;
+    });
 }
 
 extern "C" int slbm_batch_size(const slbm_batch *b) { return b ? (int)b->members.size() : 0; }
 
 extern "C" slbm_status slbm_batch_set_autotune(slbm_batch *b, int on) {
-    if (!b || (on != 0 && on != 1)) return SLBM_EINVAL;
-    b->autotune = on == 1;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!b || (on != 0 && on != 1)) return SLBM_EINVAL;
+        b->autotune = on == 1;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_batch_shapes(slbm_batch *b, slbm_batch_shape *out, int max, int *count) {
-    if (!b || !count || max < 0 || (max > 0 && !out)) return SLBM_EINVAL;
-    if (b->dirty && !b->members.empty())
-        if (slbm_status s = b->rebuild()) return s;
-    const int ng = b->members.empty() ? 0 : (int)b->groups.size();
-    *count = ng;
-    for (int gi = 0; gi < std::min(ng, max); ++gi) {
-        const auto &g = b->groups[gi];
-        slbm_batch_shape &r = out[gi];
-        r = slbm_batch_shape{};
-        r.dim = g.d;
-        r.order = g.N;
-        r.fused = g.fused ? 1 : 0;
-        r.members = (int)g.idx.size();
-        r.elements = g.elements;
-        r.n_shapes = std::min((int)g.shapes.size(), SLBM_MAX_SHAPES);
-        for (int k = 0; k < r.n_shapes; ++k) {
-            r.epb[k] = g.shapes[k].epb;
-            r.xcd[k] = g.shapes[k].xcd ? 1 : 0;
-            r.us_per_step[k] = g.shapes[k].us;
+    return slbm_guard([&]() -> slbm_status {
+        if (!b || !count || max < 0 || (max > 0 && !out)) return SLBM_EINVAL;
+        if (b->dirty && !b->members.empty())
+            if (slbm_status s = b->rebuild()) return s;
+        const int ng = b->members.empty() ? 0 : (int)b->groups.size();
+        *count = ng;
+        for (int gi = 0; gi < std::min(ng, max); ++gi) {
+            const auto &g = b->groups[gi];
+            slbm_batch_shape &r = out[gi];
+            r = slbm_batch_shape{};
+            r.dim = g.d;
+            r.order = g.N;
+            r.fused = g.fused ? 1 : 0;
+            r.members = (int)g.idx.size();
+            r.elements = g.elements;
+            r.n_shapes = std::min((int)g.shapes.size(), SLBM_MAX_SHAPES);
+            for (int k = 0; k < r.n_shapes; ++k) {
+                r.epb[k] = g.shapes[k].epb;
+                r.xcd[k] = g.shapes[k].xcd ? 1 : 0;
+                r.us_per_step[k] = g.shapes[k].us;
+            }
+            r.chosen = g.pick;
+            r.measured = g.measured ? 1 : 0;
         }
-        r.chosen = g.pick;
-        r.measured = g.measured ? 1 : 0;
-    }
-    return SLBM_OK;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_batch_step(slbm_batch *b, int64_t n) {
-    if (!b || n < 0) return SLBM_EINVAL;
-    if (b->members.empty() || n == 0) return SLBM_OK;
-    if (b->dirty)
-        if (slbm_status s = b->rebuild()) return s;
-    int64_t done = 0;
-    if (b->autotune && (done = b->tune_pending(n)) < 0) return SLBM_EDEVICE;
-    if (b->run(n - done)) return SLBM_EDEVICE;
-    for (slbm_ctx *c : b->members) c->step += n;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!b || n < 0) return SLBM_EINVAL;
+        if (b->members.empty() || n == 0) return SLBM_OK;
+        if (b->dirty)
+            if (slbm_status s = b->rebuild()) return s;
+        int64_t done = 0;
+        if (b->autotune && (done = b->tune_pending(n)) < 0) return SLBM_EDEVICE;
+        if (b->run(n - done)) return SLBM_EDEVICE;
+        for (slbm_ctx *c : b->members) c->step += n;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_batch_kinetic_energy(slbm_batch *b, double *ke, double *mass) {
-    if (!b) return SLBM_EINVAL;
-    if (b->members.empty()) return SLBM_OK;
-    if (b->dirty)
-        if (slbm_status s = b->rebuild()) return s;
-    hipStream_t st = (hipStream_t)b->stream;
-    std::vector<std::vector<double>> outs(b->groups.size());
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-        auto &g = b->groups[gi];
-        int e = launch_diag(g.d, g.N, g.np, b->stream);
-        if (e == 0) e = launch_diag_final(g.desc, (int)g.idx.size(), b->stream, g.diag_out);
-        if (e) return SLBM_EDEVICE;
-        outs[gi].resize(2 * g.idx.size());
-        if (hipMemcpyAsync(outs[gi].data(), g.diag_out, 2 * sizeof(double) * g.idx.size(),
-                           hipMemcpyDeviceToHost, st) != hipSuccess)
-            return SLBM_EDEVICE;
-    }
-    if (hipStreamSynchronize(st) != hipSuccess) return SLBM_EDEVICE;
-    for (size_t gi = 0; gi < b->groups.size(); ++gi)
-        for (size_t k = 0; k < b->groups[gi].idx.size(); ++k) {
-            const int m = b->groups[gi].idx[k];
-            if (ke) ke[m] = outs[gi][2 * k];
-            if (mass) mass[m] = outs[gi][2 * k + 1];
+    return slbm_guard([&]() -> slbm_status {
+        if (!b) return SLBM_EINVAL;
+        if (b->members.empty()) return SLBM_OK;
+        if (b->dirty)
+            if (slbm_status s = b->rebuild()) return s;
+        hipStream_t st = (hipStream_t)b->stream;
+        std::vector<std::vector<double>> outs(b->groups.size());
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            auto &g = b->groups[gi];
+            int e = launch_diag(g.d, g.N, g.np, b->stream);
+            if (e == 0) e = launch_diag_final(g.desc, (int)g.idx.size(), b->stream, g.diag_out);
+            if (e) return SLBM_EDEVICE;
+            outs[gi].resize(2 * g.idx.size());
+            if (hipMemcpyAsync(outs[gi].data(), g.diag_out, 2 * sizeof(double) * g.idx.size(),
+                               hipMemcpyDeviceToHost, st) != hipSuccess)
+                return SLBM_EDEVICE;
         }
-    return SLBM_OK;
+        if (hipStreamSynchronize(st) != hipSuccess) return SLBM_EDEVICE;
+        for (size_t gi = 0; gi < b->groups.size(); ++gi)
+            for (size_t k = 0; k < b->groups[gi].idx.size(); ++k) {
+                const int m = b->groups[gi].idx[k];
+                if (ke) ke[m] = outs[gi][2 * k];
+                if (mass) mass[m] = outs[gi][2 * k + 1];
+            }
+        return SLBM_OK;
+    });
 }
 
 extern "C" void slbm_batch_destroy(slbm_batch *b) { delete b; }
@@ -534,92 +548,94 @@ bool solve_small(int n, double A[4][4], double *r, double *x) {
 }  // namespace
 
 extern "C" slbm_status slbm_contact_angle(slbm_ctx *c, const slbm_wall_geom *w, double *theta_deg) {
-    if (!c || !w || !theta_deg) return SLBM_EINVAL;
-    if (slbm_status s = c->require_bound(true)) return s;
-    const int dim = c->dim, Np = c->Np, nloc = c->nloc;
-    std::vector<double> rho(c->Ng);
-    int e = (int)hipMemcpyAsync(rho.data(), c->desc.rho, sizeof(double) * c->Ng, hipMemcpyDeviceToHost,
-                                (hipStream_t)c->stream);
-    if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
-    if (e) return c->hip_check(e, "contact_angle");
-    const double level = 0.5 * (c->prm.rho_l + c->prm.rho_v);
-    const double excl = 2.0 * c->prm.delta;
-    std::unordered_set<uint64_t> seen;
-    std::vector<double> pts;
-    for (int64_t el = 0; el < c->E; ++el)
-        for (int a = 0; a < dim; ++a) {
-            const int s = c->stride(a);
-            for (int n = 0; n < nloc; ++n) {
-                if (c->along(n, a) == Np - 1) continue;
-                const int64_t l1 = el * nloc + n, l2 = l1 + s;
-                const uint32_t g1 = (uint32_t)c->lgid[l1], g2 = (uint32_t)c->lgid[l2];
-                const uint64_t key = ((uint64_t)std::min(g1, g2) << 32) | std::max(g1, g2);
-                const double r1 = rho[g1] - level, r2 = rho[g2] - level;
-                if ((r1 == 0.0 && r2 == 0.0) || r1 * r2 > 0.0) continue;
-                if (!seen.insert(key).second) continue;
-                const double t = r1 / (r1 - r2);
-                double p[3] = {0, 0, 0};
-                for (int k = 0; k < dim; ++k) {
-                    const double x1 = c->xyz[l1 * dim + k], x2 = c->xyz[l2 * dim + k];
-                    p[k] = x1 + t * (x2 - x1);
+    return slbm_guard([&]() -> slbm_status {
+        if (!c || !w || !theta_deg) return SLBM_EINVAL;
+        if (slbm_status s = c->require_bound(true)) return s;
+        const int dim = c->dim, Np = c->Np, nloc = c->nloc;
+        std::vector<double> rho(c->Ng);
+        int e = (int)hipMemcpyAsync(rho.data(), c->desc.rho, sizeof(double) * c->Ng, hipMemcpyDeviceToHost,
+                                    (hipStream_t)c->stream);
+        if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)c->stream);
+        if (e) return c->hip_check(e, "contact_angle");
+        const double level = 0.5 * (c->prm.rho_l + c->prm.rho_v);
+        const double excl = 2.0 * c->prm.delta;
+        std::unordered_set<uint64_t> seen;
+        std::vector<double> pts;
+        for (int64_t el = 0; el < c->E; ++el)
+            for (int a = 0; a < dim; ++a) {
+                const int s = c->stride(a);
+                for (int n = 0; n < nloc; ++n) {
+                    if (c->along(n, a) == Np - 1) continue;
+                    const int64_t l1 = el * nloc + n, l2 = l1 + s;
+                    const uint32_t g1 = (uint32_t)c->lgid[l1], g2 = (uint32_t)c->lgid[l2];
+                    const uint64_t key = ((uint64_t)std::min(g1, g2) << 32) | std::max(g1, g2);
+                    const double r1 = rho[g1] - level, r2 = rho[g2] - level;
+                    if ((r1 == 0.0 && r2 == 0.0) || r1 * r2 > 0.0) continue;
+                    if (!seen.insert(key).second) continue;
+                    const double t = r1 / (r1 - r2);
+                    double p[3] = {0, 0, 0};
+                    for (int k = 0; k < dim; ++k) {
+                        const double x1 = c->xyz[l1 * dim + k], x2 = c->xyz[l2 * dim + k];
+                        p[k] = x1 + t * (x2 - x1);
+                    }
+                    double dist;
+                    if (w->kind == 0) {
+                        double dd = 0.0;
+                        for (int k = 0; k < dim; ++k) dd += (p[k] - w->point[k]) * w->normal[k];
+                        dist = std::fabs(dd);
+                    } else {
+                        double r2s = 0.0;
+                        for (int k = 0; k < dim; ++k) r2s += (p[k] - w->point[k]) * (p[k] - w->point[k]);
+                        dist = std::sqrt(r2s) - w->radius;
+                    }
+                    if (dist < excl) continue;
+                    for (int k = 0; k < dim; ++k) pts.push_back(p[k]);
                 }
-                double dist;
-                if (w->kind == 0) {
-                    double dd = 0.0;
-                    for (int k = 0; k < dim; ++k) dd += (p[k] - w->point[k]) * w->normal[k];
-                    dist = std::fabs(dd);
-                } else {
-                    double r2s = 0.0;
-                    for (int k = 0; k < dim; ++k) r2s += (p[k] - w->point[k]) * (p[k] - w->point[k]);
-                    dist = std::sqrt(r2s) - w->radius;
-                }
-                if (dist < excl) continue;
-                for (int k = 0; k < dim; ++k) pts.push_back(p[k]);
+            }
+        const int64_t np = (int64_t)pts.size() / dim;
+        if (np < dim + 2) return c->fail(SLBM_EINVAL, "contact angle: too few interface points (%lld)", (long long)np);
+        // Kasa fit about the centroid: |y|^2 + b.y + k = 0 with y = p - m
+        double m[3] = {0, 0, 0};
+        for (int64_t i = 0; i < np; ++i)
+            for (int k = 0; k < dim; ++k) m[k] += pts[i * dim + k];
+        for (int k = 0; k < dim; ++k) m[k] /= (double)np;
+        const int nu = dim + 1;
+        double A[4][4] = {}, rhs[4] = {}, x[4] = {};
+        for (int64_t i = 0; i < np; ++i) {
+            double row[4], y2 = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                row[k] = pts[i * dim + k] - m[k];
+                y2 += row[k] * row[k];
+            }
+            row[dim] = 1.0;
+            for (int r = 0; r < nu; ++r) {
+                for (int q = 0; q < nu; ++q) A[r][q] += row[r] * row[q];
+                rhs[r] -= row[r] * y2;
             }
         }
-    const int64_t np = (int64_t)pts.size() / dim;
-    if (np < dim + 2) return c->fail(SLBM_EINVAL, "contact angle: too few interface points (%lld)", (long long)np);
-    // Kasa fit about the centroid: |y|^2 + b.y + k = 0 with y = p - m
-    double m[3] = {0, 0, 0};
-    for (int64_t i = 0; i < np; ++i)
-        for (int k = 0; k < dim; ++k) m[k] += pts[i * dim + k];
-    for (int k = 0; k < dim; ++k) m[k] /= (double)np;
-    const int nu = dim + 1;
-    double A[4][4] = {}, rhs[4] = {}, x[4] = {};
-    for (int64_t i = 0; i < np; ++i) {
-        double row[4], y2 = 0.0;
+        if (!solve_small(nu, A, rhs, x)) return c->fail(SLBM_EINVAL, "contact angle: singular fit");
+        double cen[3] = {0, 0, 0}, c2 = 0.0;
         for (int k = 0; k < dim; ++k) {
-            row[k] = pts[i * dim + k] - m[k];
-            y2 += row[k] * row[k];
+            cen[k] = -0.5 * x[k];
+            c2 += cen[k] * cen[k];
+            cen[k] += m[k];
         }
-        row[dim] = 1.0;
-        for (int r = 0; r < nu; ++r) {
-            for (int q = 0; q < nu; ++q) A[r][q] += row[r] * row[q];
-            rhs[r] -= row[r] * y2;
+        const double R = std::sqrt(c2 - x[dim]);
+        double cth;
+        if (w->kind == 0) {
+            double dd = 0.0;
+            for (int k = 0; k < dim; ++k) dd += (cen[k] - w->point[k]) * w->normal[k];
+            cth = dd / R;
+        } else {
+            double d2 = 0.0;
+            for (int k = 0; k < dim; ++k) d2 += (cen[k] - w->point[k]) * (cen[k] - w->point[k]);
+            const double Rw = w->radius;
+            cth = (Rw * Rw + R * R - d2) / (2.0 * R * Rw);
         }
-    }
-    if (!solve_small(nu, A, rhs, x)) return c->fail(SLBM_EINVAL, "contact angle: singular fit");
-    double cen[3] = {0, 0, 0}, c2 = 0.0;
-    for (int k = 0; k < dim; ++k) {
-        cen[k] = -0.5 * x[k];
-        c2 += cen[k] * cen[k];
-        cen[k] += m[k];
-    }
-    const double R = std::sqrt(c2 - x[dim]);
-    double cth;
-    if (w->kind == 0) {
-        double dd = 0.0;
-        for (int k = 0; k < dim; ++k) dd += (cen[k] - w->point[k]) * w->normal[k];
-        cth = dd / R;
-    } else {
-        double d2 = 0.0;
-        for (int k = 0; k < dim; ++k) d2 += (cen[k] - w->point[k]) * (cen[k] - w->point[k]);
-        const double Rw = w->radius;
-        cth = (Rw * Rw + R * R - d2) / (2.0 * R * Rw);
-    }
-    cth = std::max(-1.0, std::min(1.0, cth));
-    *theta_deg = std::acos(cth) * 180.0 / M_PI;
-    return SLBM_OK;
+        cth = std::max(-1.0, std::min(1.0, cth));
+        *theta_deg = std::acos(cth) * 180.0 / M_PI;
+        return SLBM_OK;
+    });
 }
 
 // ------------------------------------------------------------------------------------------
@@ -789,134 +805,144 @@ struct slbm_server {
 };
 
 extern "C" slbm_status slbm_server_create(const slbm_server_cfg *cfg, slbm_server **out) {
-    if (!cfg || !out || !cfg->arena || cfg->max_slots <= 0 || cfg->check_every <= 0) return SLBM_EINVAL;
-    slbm_server *s = new (std::nothrow) slbm_server();
-    if (!s) return SLBM_ENOMEM;
-    s->cfg = *cfg;
-    s->t0 = std::chrono::steady_clock::now();
-    s->arena.init(cfg->arena_bytes);
-    if (slbm_batch_create(cfg->hip_stream, &s->batch) != SLBM_OK) { delete s; return SLBM_ENOMEM; }
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const unsigned nw = std::min(8u, std::max(1u, hw / 2));
-    try {
-        for (unsigned k = 0; k < nw; ++k) s->workers.emplace_back([s] { s->worker(); });
-    } catch (...) {
-        // fewer workers than asked for: fine while at least one runs
-    }
-    if (s->workers.empty()) {
-        delete s;
-        return SLBM_ENOMEM;
-    }
-    *out = s;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!cfg || !out || !cfg->arena || cfg->max_slots <= 0 || cfg->check_every <= 0) return SLBM_EINVAL;
+        slbm_server *s = new (std::nothrow) slbm_server();
+        if (!s) return SLBM_ENOMEM;
+        s->cfg = *cfg;
+        s->t0 = std::chrono::steady_clock::now();
+        s->arena.init(cfg->arena_bytes);
+        if (slbm_batch_create(cfg->hip_stream, &s->batch) != SLBM_OK) { delete s; return SLBM_ENOMEM; }
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const unsigned nw = std::min(8u, std::max(1u, hw / 2));
+        try {
+            for (unsigned k = 0; k < nw; ++k) s->workers.emplace_back([s] { s->worker(); });
+        } catch (...) {
+            // fewer workers than asked for: fine while at least one runs
+        }
+        if (s->workers.empty()) {
+            delete s;
+            return SLBM_ENOMEM;
+        }
+        *out = s;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_server_submit(slbm_server *s, const slbm_request *r, uint64_t *id) {
-    if (!s || !r || !r->xyz || !r->gid || r->E <= 0) return SLBM_EINVAL;
-    const int dim = r->params.lattice == 19 ? 3 : 2;
-    const int64_t nloc = nloc_of(dim, r->params.N);
-    Request *q = new (std::nothrow) Request();
-    if (!q) return SLBM_ENOMEM;
-    q->id = s->next_id++;
-    q->r = *r;
-    q->xyz.assign(r->xyz, r->xyz + r->E * nloc * dim);
-    q->gid.assign(r->gid, r->gid + r->E * nloc);
-    if (r->n_wall_faces > 0) {
-        q->wface.assign(r->wall_face, r->wall_face + 2 * r->n_wall_faces);
-        q->wcos.assign(r->wall_cos, r->wall_cos + r->n_wall_faces);
-        if (r->wall_ub) q->wub.assign(r->wall_ub, r->wall_ub + dim * r->n_wall_faces);
-    }
-    q->r.xyz = nullptr;
-    q->r.gid = nullptr;
-    q->r.wall_face = nullptr;
-    q->r.wall_cos = nullptr;
-    q->r.wall_ub = nullptr;
-    q->res.status = 1;
-    q->res.t_arrive = s->now();
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->all[q->id] = q;
-        s->to_prepare.push_back(q);
-    }
-    s->cv.notify_one();
-    if (id) *id = q->id;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!s || !r || !r->xyz || !r->gid || r->E <= 0) return SLBM_EINVAL;
+        const int dim = r->params.lattice == 19 ? 3 : 2;
+        const int64_t nloc = nloc_of(dim, r->params.N);
+        Request *q = new (std::nothrow) Request();
+        if (!q) return SLBM_ENOMEM;
+        q->id = s->next_id++;
+        q->r = *r;
+        q->xyz.assign(r->xyz, r->xyz + r->E * nloc * dim);
+        q->gid.assign(r->gid, r->gid + r->E * nloc);
+        if (r->n_wall_faces > 0) {
+            q->wface.assign(r->wall_face, r->wall_face + 2 * r->n_wall_faces);
+            q->wcos.assign(r->wall_cos, r->wall_cos + r->n_wall_faces);
+            if (r->wall_ub) q->wub.assign(r->wall_ub, r->wall_ub + dim * r->n_wall_faces);
+        }
+        q->r.xyz = nullptr;
+        q->r.gid = nullptr;
+        q->r.wall_face = nullptr;
+        q->r.wall_cos = nullptr;
+        q->r.wall_ub = nullptr;
+        q->res.status = 1;
+        q->res.t_arrive = s->now();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->all[q->id] = q;
+            s->to_prepare.push_back(q);
+        }
+        s->cv.notify_one();
+        if (id) *id = q->id;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_server_tick(slbm_server *s, int *pending) {
-    if (!s) return SLBM_EINVAL;
-    // cold start (no active solve, the device idle): let the preparations already submitted
-    // finish (at most kColdStartWait) so that they start together rather than one round
-    // apart, which would leave their last round with only the late ones on the device
-    if (s->active.empty()) {
-        std::unique_lock<std::mutex> lk(s->mu);
-        s->cv.wait_for(lk, slbm_server::kColdStartWait,
-                       [&] { return s->stopping || (s->preparing == 0 && s->to_prepare.empty()); });
-    }
-    // admission: prepared requests in submission order while slots and arena bytes allow
-    for (;;) {
-        if ((int)s->active.size() >= s->cfg.max_slots) break;
-        Request *r = nullptr;
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            if (s->prepared.empty()) break;
-            r = s->prepared.begin()->second;
+    return slbm_guard([&]() -> slbm_status {
+        if (!s) return SLBM_EINVAL;
+        // cold start (no active solve, the device idle): let the preparations already submitted
+        // finish (at most kColdStartWait) so that they start together rather than one round
+        // apart, which would leave their last round with only the late ones on the device
+        if (s->active.empty()) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait_for(lk, slbm_server::kColdStartWait,
+                           [&] { return s->stopping || (s->preparing == 0 && s->to_prepare.empty()); });
         }
-        if (!s->admit(r)) break;
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->prepared.erase(r->id);
-    }
-    if (!s->active.empty()) {
-        // the device advances every active solve while the workers prepare new requests
-        if (slbm_status st = slbm_batch_step(s->batch, s->cfg.check_every)) return st;
-        std::vector<double> ke(s->active.size()), mass(s->active.size());
-        if (slbm_status st = slbm_batch_kinetic_energy(s->batch, ke.data(), mass.data())) return st;
-        std::vector<Request *> keep;
-        for (size_t i = 0; i < s->active.size(); ++i) {
-            Request *r = s->active[i];
-            r->steps += s->cfg.check_every;
-            r->res.ke_max = ke[i];
-            const double lim = r->r.params.ke_limit > 0.0 ? r->r.params.ke_limit : 1.0;
-            const bool bad = !(ke[i] <= lim);
-            const bool done = ke[i] < s->cfg.ke_stop || r->steps >= s->cfg.max_steps;
-            if (bad || done) {
-                slbm_batch_remove(s->batch, r->ctx);
-                slbm_status st = bad ? SLBM_EDIVERGED : SLBM_OK;
-                if (!bad) {
-                    double th = NAN;
-                    if (slbm_contact_angle(r->ctx, &r->r.wall, &th) == SLBM_OK) r->res.theta_deg = th;
-                    else r->res.theta_deg = NAN;
-                }
-                s->finish(r, st);
-            } else {
-                keep.push_back(r);
+        // admission: prepared requests in submission order while slots and arena bytes allow
+        for (;;) {
+            if ((int)s->active.size() >= s->cfg.max_slots) break;
+            Request *r = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                if (s->prepared.empty()) break;
+                r = s->prepared.begin()->second;
             }
+            if (!s->admit(r)) break;
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->prepared.erase(r->id);
         }
-        s->active.swap(keep);
-    } else {
-        // nothing to run: wait for a worker to finish a preparation
-        std::unique_lock<std::mutex> lk(s->mu);
-        if (s->prepared.empty() && (s->preparing > 0 || !s->to_prepare.empty()))
-            s->cv.wait_for(lk, std::chrono::milliseconds(5));
-    }
-    if (pending) *pending = s->pending();
-    return SLBM_OK;
+        if (!s->active.empty()) {
+            // the device advances every active solve while the workers prepare new requests
+            if (slbm_status st = slbm_batch_step(s->batch, s->cfg.check_every)) return st;
+            std::vector<double> ke(s->active.size()), mass(s->active.size());
+            if (slbm_status st = slbm_batch_kinetic_energy(s->batch, ke.data(), mass.data())) return st;
+            std::vector<Request *> keep;
+            for (size_t i = 0; i < s->active.size(); ++i) {
+                Request *r = s->active[i];
+                r->steps += s->cfg.check_every;
+                r->res.ke_max = ke[i];
+                const double lim = r->r.params.ke_limit > 0.0 ? r->r.params.ke_limit : 1.0;
+                const bool bad = !(ke[i] <= lim);
+                const bool done = ke[i] < s->cfg.ke_stop || r->steps >= s->cfg.max_steps;
+                if (bad || done) {
+                    slbm_batch_remove(s->batch, r->ctx);
+                    slbm_status st = bad ? SLBM_EDIVERGED : SLBM_OK;
+                    if (!bad) {
+                        double th = NAN;
+                        if (slbm_contact_angle(r->ctx, &r->r.wall, &th) == SLBM_OK) r->res.theta_deg = th;
+                        else r->res.theta_deg = NAN;
+                    }
+                    s->finish(r, st);
+                } else {
+                    keep.push_back(r);
+                }
+            }
+            s->active.swap(keep);
+        } else {
+            // nothing to run: wait for a worker to finish a preparation
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->prepared.empty() && (s->preparing > 0 || !s->to_prepare.empty()))
+                s->cv.wait_for(lk, std::chrono::milliseconds(5));
+        }
+        if (pending) *pending = s->pending();
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_server_poll(slbm_server *s, uint64_t id, slbm_result *out) {
-    if (!s || !out) return SLBM_EINVAL;
-    auto it = s->all.find(id);
-    if (it == s->all.end()) return SLBM_EINVAL;
-    *out = it->second->res;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!s || !out) return SLBM_EINVAL;
+        auto it = s->all.find(id);
+        if (it == s->all.end()) return SLBM_EINVAL;
+        *out = it->second->res;
+        return SLBM_OK;
+    });
 }
 
 extern "C" slbm_status slbm_server_drain(slbm_server *s) {
-    if (!s) return SLBM_EINVAL;
-    int pending = 1;
-    while (pending > 0)
-        if (slbm_status st = slbm_server_tick(s, &pending)) return st;
-    return SLBM_OK;
+    return slbm_guard([&]() -> slbm_status {
+        if (!s) return SLBM_EINVAL;
+        int pending = 1;
+        while (pending > 0)
+            if (slbm_status st = slbm_server_tick(s, &pending)) return st;
+        return SLBM_OK;
+    });
 }
 
 extern "C" double slbm_server_clock(const slbm_server *s) { return s ? s->now() : 0.0; }
