@@ -285,7 +285,7 @@ def main():
                     help="only run the byte-counter calibration kernel over MIB MiB")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: --gpus must be 1 "
+        print(json.dumps({"error": "the library runs on one GPU: --gpus must be 1 "
                                    "(multi-GPU element partitioning is design-only)"}))
         sys.exit(2)
 

@@ -4,7 +4,7 @@
  * with partial wetting boundary condition").
  *
  * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, FP64 CPU implementation that
- * the tests, the smoke check and the benchmark's CPU-baseline leg use to judge the GPU
+ * the tests, the smoke check and the benchmark's CPU-baseline leg use to check the GPU
  * library.  Nothing in the product path may load it, and it shares no code with the
  * GPU library: the two are written separately from the paper.
  *
