@@ -524,3 +524,35 @@ def test_launch_switches_change_no_bits(P, monkeypatch):
         got = run(env)
         for x, y in zip(ref, got):
             assert np.array_equal(x, y), env
+
+
+def test_request_mix_spot_parity(P):
+    """Serving request mix (flat walls and cylinder O-grids, N in {4, 6, 8}): the smallest
+    request of each (geometry, N) for 60 steps and the largest of each geometry for 5
+    steps, stepped as batches, against the oracle at 1e-11 on rho and u."""
+    import torch
+    from oracle import Oracle
+    reqs = cases.request_stream(256, seed=5)
+    size = lambda r: r["nx"] * r["ny"] * (r["N"] + 1) ** 2
+    small, large = {}, {}
+    for k, r in sorted(enumerate(reqs), key=lambda kr: size(kr[1])):
+        small.setdefault((r["geom"], r["N"]), k)
+        large[r["geom"]] = k
+    for picks, steps in ((sorted(small.values()), 60), (sorted(large.values()), 5)):
+        b = P.Batch(torch.cuda.current_stream())
+        runs = []
+        for k in picks:
+            c = cases.request_case(reqs[k])
+            s = P.Solve(c)
+            s.init_tanh()
+            b.add(s)
+            o = Oracle(c)
+            o.init_tanh()
+            runs.append((k, c, s, o))
+        b.step(steps)
+        for k, c, s, o in runs:
+            o.step(steps)
+            er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+            print(f"[mix] request {k} {reqs[k]['geom']} N={c.N} E={c.mesh.E} {steps} steps: "
+                  f"rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+            assert er <= TOL and eu <= TOL
