@@ -179,6 +179,18 @@ def walled_droplet(nx: int = 8, N: int = 4, L: float = 64.0, R: float = 16.0,
                 steps=10500)
 
 
+def spreading(theta_deg: float = 60.0, R: float = 24.0) -> Case:
+    """Dynamic wetting: a droplet of radius R whose circle just touches a flat wall of
+    equilibrium angle theta (16x8 square quads over a 128x64 walled box, N=6), so that it
+    spreads (or retracts) from a 180-degree start to its equilibrium cap."""
+    cb = math.cos(math.radians(theta_deg))
+    m = meshes.box2d(16, 8, 6, 128.0, 64.0, periodic=(False, False), jitter=0.0, seed=21,
+                     cos_theta={"bottom": cb}, name="spreading")
+    return Case("spreading", m, LATTICE_D2Q9, x0=(64.0, R), R=R, seed=21, steps=30000,
+                wall_geom=dict(kind="plane", point=(0.0, 0.0), normal=(0.0, -1.0)),
+                theta_deg=theta_deg)
+
+
 ORDERS_2D = (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16)
 ORDERS_3D = (2, 3, 4, 5, 6)
 

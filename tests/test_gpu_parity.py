@@ -556,3 +556,29 @@ def test_request_mix_spot_parity(P):
             print(f"[mix] request {k} {reqs[k]['geom']} N={c.N} E={c.mesh.E} {steps} steps: "
                   f"rel rho {er:.3e} rel u {eu:.3e}", flush=True)
             assert er <= TOL and eu <= TOL
+
+
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_dynamic_wetting_from_touching_start(P, theta):
+    """A droplet that just touches the wall (180 degrees) spreads or retracts to its
+    equilibrium cap: 300 steps of the spreading phase against the oracle, then the
+    contact angle, measured every 2000 steps, leaves 180 degrees, and after 30000 steps
+    lies within 5 degrees of theta with KE_max below 1e-6."""
+    from oracle import Oracle, contact_angle
+    c = cases.spreading(theta)
+    s, o = _run_pair(c, P, 300)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    a_g = s.contact_angle()
+    a_o, _, _ = contact_angle(c.mesh, o.rho(), c.rho_l, c.rho_v, c.delta, c.wall_geom)
+    print(f"[spread] theta={theta} 300 steps: rel rho {er:.3e} rel u {eu:.3e} angle {a_g:.3f} / {a_o:.3f}",
+          flush=True)
+    assert er <= TOL and eu <= TOL and abs(a_g - a_o) < 1e-9
+    angles = []
+    for _ in range(15):
+        s.step(2000)
+        angles.append(s.contact_angle())
+    ke, _ = s.kinetic_energy()
+    print(f"[spread] theta={theta} angles every 2000 steps {[round(a, 2) for a in angles]} KE {ke:.2e}",
+          flush=True)
+    assert angles[1] < 170.0  # under way after 4000 steps
+    assert abs(angles[-1] - theta) < 5.0 and ke < 1e-6
