@@ -65,12 +65,14 @@ typedef struct slbm_params {
     double delta;     /* interface thickness of Eq. (A.1) */
     double sigma;     /* surface tension gamma; beta = 12 sigma/(delta drho^4),
                          kappa = 3 sigma delta/(2 drho^2) solve Eqs. (A.4)-(A.5) */
-    double tau;       /* dimensionless relaxation time of Eq. (4) (0.5 in Sec. 3.3) */
+    double tau;       /* dimensionless relaxation time of Eq. (4) (0.5 in Sec. 3.3), in units
+                         of dt: the kinematic viscosity is tau dt / 3, so a smaller dt (a
+                         higher order, a finer mesh) at the same tau is a less viscous fluid
+                         with a Laplace number larger by the square of the ratio.  To keep
+                         the physics when dt changes, scale tau by 1/dt. */
     double dt;        /* > 0: time step; otherwise dt = min(cfl h_min,
-                         0.25 h_min^2 / sqrt(kappa rho_l)) (advective and capillary bounds).
-                         The capillary constant is marginal at N = 16: a 60-degree droplet
-                         with an interface width of half an element ran unstable at it and
-                         stable at half of it, so pass dt explicitly at that order. */
+                         C h_min^2 / sqrt(kappa rho_l)) (advective and capillary bounds), with
+                         C = 0.25 for N <= 12 and 0.125 for N >= 13. */
     double cfl;       /* h_min = smallest distance of neighbouring GLL nodes on element lines */
     int ke_every;     /* slbm_step checks finiteness and KE_max every ke_every steps (0: never) */
     double ke_limit;  /* KE_max above this (or non-finite) -> SLBM_EDIVERGED; <= 0: 1.0 */

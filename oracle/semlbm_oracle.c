@@ -36,9 +36,10 @@
  *   R9  wall terms are evaluated per element face with that face's own normal.
  *   R10 rho, mu and their gradients are recomputed at every Runge-Kutta stage; stage 1
  *       uses the collision's rho and mu (collision conserves mass).
- *   R11 dt = min(CFL h_min, 0.25 h_min^2 / sqrt(kappa rho_l)) when no dt is given
- *       (h_min: smallest distance between neighbouring GLL nodes along element lines; the
- *       second bound is the capillary stiffness limit of the force term).
+ *   R11 dt = min(CFL h_min, C h_min^2 / sqrt(kappa rho_l)) when no dt is given, C = 1/4
+ *       for N <= 12 and 1/8 for N >= 13 (h_min: smallest distance between neighbouring GLL
+ *       nodes along element lines; the second bound is the capillary stiffness limit of the
+ *       force term).
  *   R12 tau is dimensionless: omega = 1/(tau + 1/2).
  *   R16 seeded density noise: rho += a (2U - 1), U from SplitMix64 of (seed xor gid).
  *
@@ -341,9 +342,11 @@ orc *orc_new(int dim, int N, int Q, long E, const double *xyz, const int *gid, l
     for (long g = 0; g < ng; ++g) o->Minv[g] = 1.0 / o->MA[g];
     if (!(o->dt > 0.0)) {
         /* advective limit, and the capillary limit of the kappa lap(rho) term inside the
-         * streaming force, whose discrete spectrum grows like h^-2 (stable dt ~ h^2) */
+         * streaming force, whose discrete spectrum grows like h^-2 (stable dt ~ h^2); the
+         * capillary constant is 1/4 up to order 12 and 1/8 above (R11) */
         double dt_adv = o->cfl * o->hmin;
-        double dt_cap = 0.25 * o->hmin * o->hmin / sqrt(o->kappa * o->rho_l);
+        double c_cap = o->N > 12 ? 0.125 : 0.25;
+        double dt_cap = c_cap * o->hmin * o->hmin / sqrt(o->kappa * o->rho_l);
         o->dt = dt_adv < dt_cap ? dt_adv : dt_cap;
     }
 

@@ -100,7 +100,7 @@ def test_argument_and_order_errors(L):
 
 
 @pytest.mark.parametrize("mk", [cases.c1, cases.c2, cases.small_cyl, cases.small_sphere,
-                                cases.small_box3d])
+                                cases.small_box3d, lambda: cases.order_case(2, 14)])
 def test_host_tables_match_oracle_bitwise(L, mk):
     """GLL tables, lumped mass, h_min and dt of the library equal the oracle's exactly:
     parity of the time step to 1e-11 needs identical inputs to every kernel."""

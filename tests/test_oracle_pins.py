@@ -116,6 +116,20 @@ def test_parameters_reproduce_surface_tension():
     assert abs(o.dt - 0.4 * o.hmin) < 1e-15
 
 
+@pytest.mark.parametrize("N, ccap", [(8, 0.25), (12, 0.25), (13, 0.125), (16, 0.125)])
+def test_automatic_dt_capillary_bound(N, ccap):
+    """R11 reading: on an 8-wide regular element the capillary bound binds from N = 8 on;
+    h_min comes from the end interval of the GLL points, here the roots of P_N' found by
+    numpy, and the capillary constant halves above order 12."""
+    o = Oracle(_case(meshes.box2d(2, 2, N, 16.0, 16.0)))
+    xi = np.sort(np.polynomial.legendre.Legendre.basis(N).deriv().roots().real)
+    hmin = 4.0 * (xi[0] + 1.0)
+    assert abs(o.hmin - hmin) < 1e-12 * hmin
+    cap = ccap * hmin * hmin / math.sqrt(o.kappa * 1.0)
+    assert cap < 0.4 * hmin
+    assert abs(o.dt - cap) < 1e-12 * cap
+
+
 # ---------------------------------------------------------------------------
 # collision (Eq. 4, A.2, A.6-A.7)
 # ---------------------------------------------------------------------------
