@@ -291,9 +291,12 @@ slbm_status slbm_server_submit(slbm_server *s, const slbm_request *r, uint64_t *
 /* Advance the server by one scheduling round: admit prepared requests that fit (slots and
  * arena bytes), run check_every steps of all active solves as one batch, retire finished
  * ones.  Submitted requests are prepared (context creation, mesh processing) by host worker
- * threads while the device runs.  With no active solve (cold start) a round first waits up
- * to 50 ms for the preparations already submitted, so that requests submitted together
- * start together.  Returns the number of unfinished requests in *pending. */
+ * threads while the device runs.  The same workers bind the requests a round admits
+ * (workspace uploads and initial state, each worker on a stream of its own) and compute the
+ * contact angles of the ones it retires; the round waits for them.  With no active solve
+ * (cold start) a round first waits up to 50 ms for the preparations already submitted, so
+ * that requests submitted together start together.  Returns the number of unfinished
+ * requests in *pending. */
 slbm_status slbm_server_tick(slbm_server *s, int *pending);
 /* Result of a request (status 1 while pending). */
 slbm_status slbm_server_poll(slbm_server *s, uint64_t id, slbm_result *out);

@@ -652,6 +652,7 @@ struct Request {
     slbm_ctx *ctx = nullptr;
     size_t off = 0, bytes = 0;
     int64_t steps = 0;
+    slbm_status job_status = SLBM_OK;  // result of the last worker job run for it
 };
 
 // first-fit allocator over the arena (offsets 256-byte aligned)
@@ -707,21 +708,52 @@ struct slbm_server {
     bool stopping = false;
     std::vector<std::thread> workers;
     static constexpr std::chrono::milliseconds kColdStartWait{50};
+    // jobs the tick hands to the workers and waits for, ahead of any preparation: binding
+    // the requests it has just admitted (workspace uploads and initial state, each worker on
+    // a stream of its own) and the contact angles of the solves it retires.  A round then
+    // pays for the slowest of these rather than for their sum.
+    enum JobKind { kBind, kAngle };
+    std::deque<std::pair<JobKind, Request *>> jobs;
+    int jobs_left = 0;
+    int device = 0;
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
     void worker() {
+        (void)hipSetDevice(device);
+        hipStream_t ws = nullptr;
+        if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) ws = nullptr;
+        void *own = ws ? (void *)ws : cfg.hip_stream;
         for (;;) {
             Request *r = nullptr;
+            bool job = false;
+            JobKind kind = kBind;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv.wait(lk, [&] { return stopping || !to_prepare.empty(); });
-                if (stopping && to_prepare.empty()) return;
-                r = to_prepare.front();
-                to_prepare.pop_front();
-                ++preparing;
+                cv.wait(lk, [&] { return stopping || !jobs.empty() || !to_prepare.empty(); });
+                if (!jobs.empty()) {
+                    job = true;
+                    kind = jobs.front().first;
+                    r = jobs.front().second;
+                    jobs.pop_front();
+                } else if (!to_prepare.empty()) {
+                    r = to_prepare.front();
+                    to_prepare.pop_front();
+                    ++preparing;
+                } else {
+                    break;  // stopping
+                }
+            }
+            if (job) {
+                run_job(kind, r, own);
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    --jobs_left;
+                }
+                cv.notify_all();
+                continue;
             }
             slbm_ctx *c = nullptr;
             slbm_params p = r->r.params;
@@ -744,6 +776,38 @@ struct slbm_server {
             }
             cv.notify_all();
         }
+        if (ws) (void)hipStreamDestroy(ws);
+    }
+
+    void run_job(JobKind kind, Request *r, void *own) {
+        if (kind == kBind) {
+            slbm_status st = slbm_bind(r->ctx, (char *)cfg.arena + r->off, r->bytes, own);
+            if (st == SLBM_OK) st = slbm_init_tanh(r->ctx, r->r.x0, r->r.R, r->r.noise_amp, r->r.params.seed);
+            // the uploads have completed (bind and init synchronise their stream): from here
+            // on the solve is stepped and queried on the server's stream
+            if (st == SLBM_OK) r->ctx->stream = cfg.hip_stream;
+            r->job_status = st;
+        } else {
+            // a retired solve is no longer stepped: read its density on this worker's stream
+            // (the server's stream, which produced it, is idle)
+            r->ctx->stream = own;
+            double th = NAN;
+            r->job_status = slbm_contact_angle(r->ctx, &r->r.wall, &th);
+            r->res.theta_deg = r->job_status == SLBM_OK ? th : NAN;
+        }
+    }
+
+    // hand one job per request to the workers and wait until all have finished
+    void run_jobs(JobKind kind, const std::vector<Request *> &rs) {
+        if (rs.empty()) return;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (Request *r : rs) jobs.emplace_back(kind, r);
+            jobs_left += (int)rs.size();
+        }
+        cv.notify_all();
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return jobs_left == 0; });
     }
 
     ~slbm_server() {
@@ -775,27 +839,24 @@ struct slbm_server {
         r->gid.clear(); r->gid.shrink_to_fit();
     }
 
-    // admit a prepared request if a slot and arena bytes are free; false if it must wait
-    bool admit(Request *r) {
-        if (r->prep_status != SLBM_OK || !r->ctx) { finish(r, r->prep_status ? r->prep_status : SLBM_EINVAL); return true; }
-        slbm_ctx *c = r->ctx;
-        const size_t need = slbm_workspace_bytes(c);
+    // admission of a prepared request: reserve its arena bytes (it is then bound by a
+    // worker), or finish it with its error.  Returns 0 if it must wait for arena bytes,
+    // 1 if it was finished, 2 if it was reserved.  `reserved` counts the requests reserved
+    // in this round and not yet active.
+    int admit(Request *r, size_t reserved) {
+        if (r->prep_status != SLBM_OK || !r->ctx) { finish(r, r->prep_status ? r->prep_status : SLBM_EINVAL); return 1; }
+        const size_t need = slbm_workspace_bytes(r->ctx);
         size_t off = 0;
-        if (need > cfg.arena_bytes) { finish(r, SLBM_ENOMEM); return true; }
+        if (need > cfg.arena_bytes) { finish(r, SLBM_ENOMEM); return 1; }
         if (!arena.alloc(need, off)) {
-            // with no active solve the arena is entirely free: this request can never fit
-            if (active.empty()) { finish(r, SLBM_ENOMEM); return true; }
-            return false;
+            // with no active or reserved solve the arena is entirely free: this request can
+            // never fit
+            if (active.empty() && reserved == 0) { finish(r, SLBM_ENOMEM); return 1; }
+            return 0;
         }
         r->off = off;
         r->bytes = need;
-        slbm_status s = slbm_bind(c, (char *)cfg.arena + off, need, cfg.hip_stream);
-        if (s == SLBM_OK) s = slbm_init_tanh(c, r->r.x0, r->r.R, r->r.noise_amp, r->r.params.seed);
-        if (s == SLBM_OK) s = slbm_batch_add(batch, c);
-        if (s != SLBM_OK) { finish(r, s); return true; }
-        r->res.t_admit = now();
-        active.push_back(r);
-        return true;
+        return 2;
     }
 
     int pending() {
@@ -812,6 +873,7 @@ extern "C" slbm_status slbm_server_create(const slbm_server_cfg *cfg, slbm_serve
         s->cfg = *cfg;
         s->t0 = std::chrono::steady_clock::now();
         s->arena.init(cfg->arena_bytes);
+        if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
         if (slbm_batch_create(cfg->hip_stream, &s->batch) != SLBM_OK) { delete s; return SLBM_ENOMEM; }
         const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
         const unsigned nw = std::min(8u, std::max(1u, hw / 2));
@@ -874,25 +936,37 @@ extern "C" slbm_status slbm_server_tick(slbm_server *s, int *pending) {
             s->cv.wait_for(lk, slbm_server::kColdStartWait,
                            [&] { return s->stopping || (s->preparing == 0 && s->to_prepare.empty()); });
         }
-        // admission: prepared requests in submission order while slots and arena bytes allow
+        // admission: prepared requests in submission order while slots and arena bytes allow;
+        // the workers bind the admitted ones together, then they join the batch
+        std::vector<Request *> admitted;
         for (;;) {
-            if ((int)s->active.size() >= s->cfg.max_slots) break;
+            if ((int)(s->active.size() + admitted.size()) >= s->cfg.max_slots) break;
             Request *r = nullptr;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
                 if (s->prepared.empty()) break;
                 r = s->prepared.begin()->second;
             }
-            if (!s->admit(r)) break;
+            const int a = s->admit(r, admitted.size());
+            if (a == 0) break;
+            if (a == 2) admitted.push_back(r);
             std::lock_guard<std::mutex> lk(s->mu);
             s->prepared.erase(r->id);
+        }
+        s->run_jobs(slbm_server::kBind, admitted);
+        for (Request *r : admitted) {
+            slbm_status st = r->job_status;
+            if (st == SLBM_OK) st = slbm_batch_add(s->batch, r->ctx);
+            if (st != SLBM_OK) { s->finish(r, st); continue; }
+            r->res.t_admit = s->now();
+            s->active.push_back(r);
         }
         if (!s->active.empty()) {
             // the device advances every active solve while the workers prepare new requests
             if (slbm_status st = slbm_batch_step(s->batch, s->cfg.check_every)) return st;
             std::vector<double> ke(s->active.size()), mass(s->active.size());
             if (slbm_status st = slbm_batch_kinetic_energy(s->batch, ke.data(), mass.data())) return st;
-            std::vector<Request *> keep;
+            std::vector<Request *> keep, retired;
             for (size_t i = 0; i < s->active.size(); ++i) {
                 Request *r = s->active[i];
                 r->steps += s->cfg.check_every;
@@ -902,18 +976,17 @@ extern "C" slbm_status slbm_server_tick(slbm_server *s, int *pending) {
                 const bool done = ke[i] < s->cfg.ke_stop || r->steps >= s->cfg.max_steps;
                 if (bad || done) {
                     slbm_batch_remove(s->batch, r->ctx);
-                    slbm_status st = bad ? SLBM_EDIVERGED : SLBM_OK;
-                    if (!bad) {
-                        double th = NAN;
-                        if (slbm_contact_angle(r->ctx, &r->r.wall, &th) == SLBM_OK) r->res.theta_deg = th;
-                        else r->res.theta_deg = NAN;
-                    }
-                    s->finish(r, st);
+                    if (bad) s->finish(r, SLBM_EDIVERGED);
+                    else retired.push_back(r);
                 } else {
                     keep.push_back(r);
                 }
             }
             s->active.swap(keep);
+            // contact angles of the retired solves, on the workers (the device is idle: the
+            // kinetic-energy readout above synchronised the server's stream)
+            s->run_jobs(slbm_server::kAngle, retired);
+            for (Request *r : retired) s->finish(r, SLBM_OK);
         } else {
             // nothing to run: wait for a worker to finish a preparation
             std::unique_lock<std::mutex> lk(s->mu);
