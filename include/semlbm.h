@@ -32,7 +32,7 @@
  * Environment switches (read where noted; none changes any result, bit for bit):
  *   SLBM_UNFUSED=1        slbm_set_mesh: step with the separate element and node kernels
  *   SLBM_FUSED=1          slbm_set_mesh: step with the fused element kernels wherever the
- *                         mesh allows them (by default not for 3-D meshes over 2^20 local
+ *                         mesh allows them (by default not for meshes over 2^20 local
  *                         nodes)
  *   SLBM_NO_GRAPH=1       slbm_bind / slbm_batch_create: plain launches, no HIP graphs
  *   SLBM_SERIAL_GROUPS=1  slbm_batch_create: a batch's groups one after another on its

@@ -261,11 +261,12 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         for (int64_t g = 0; g < n_global; ++g) c->vmax = std::max<int>(c->vmax, c->csr_ptr[g + 1] - c->csr_ptr[g]);
         {
             // fused kernels finish each summation by gathering all copies at every copy: the
-            // right trade for latency-bound meshes; large 3-D meshes (up to 8 copies per node,
-            // 18 moving populations) move less data through the separate node kernels
+            // right trade while the state stays in the device's caches; meshes over 2^20 local
+            // nodes move less data through the separate node kernels, which gather each node
+            // once (measured crossover near 0.8 M local nodes in 2-D at N = 6 and 8)
             const char *nf = std::getenv("SLBM_UNFUSED");
             const char *ff = std::getenv("SLBM_FUSED");
-            const bool large3d = dim == 3 && Nl > (int64_t)1 << 20;
+            const bool large = Nl > (int64_t)1 << 20;
             // nodes inside an element must belong to it alone (the fused kernels skip their
             // copy lists)
             std::vector<char> on_bnd(nloc, 0);
@@ -281,7 +282,7 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
                     if (!on_bnd[n] && c->csr_ptr[g + 1] - c->csr_ptr[g] != 1) interior_single = false;
                 }
             const bool fits = c->vmax <= kCopySlots[dim - 2] && interior_single;
-            c->fused = fits && !large3d;
+            c->fused = fits && !large;
             if (nf && nf[0] == '1') c->fused = false;
             if (ff && ff[0] == '1' && fits) c->fused = true;
         }
