@@ -44,6 +44,7 @@ class Case:
     ke_every: int = 100
     wall_geom: dict = field(default_factory=dict)
     theta_deg: float | None = None
+    nu: float = 0.0               # > 0: kinematic viscosity to hold (tau = nu / (cs^2 dt))
 
     @property
     def N(self) -> int:
@@ -189,6 +190,30 @@ def spreading(theta_deg: float = 60.0, R: float = 24.0) -> Case:
     return Case("spreading", m, LATTICE_D2Q9, x0=(64.0, R), R=R, seed=21, steps=30000,
                 wall_geom=dict(kind="plane", point=(0.0, 0.0), normal=(0.0, -1.0)),
                 theta_deg=theta_deg)
+
+
+def paper_flat(theta_deg: float = 60.0, N: int = 16, nx: int = 16, ny: int = 8,
+               La: float = 122.0) -> Case:
+    """The flat-wall parasitic-current test of Sec. 3.1 in lattice units: 16x8 square quads
+    over a 128x64 walled box (the domain read as 2 wide by 1 high), N = 16, a droplet of
+    diameter D = 32 (half the height) and interface thickness delta = 1.92 (0.03 of the
+    height), Laplace number La = sigma D / (rho_l nu^2) = 122.
+
+    The droplet starts as its equilibrium cap: the circular segment at angle theta (through
+    the liquid) with the area of the D circle, R^2 (theta - sin theta cos theta) = pi D^2/4.
+    `nu` is the kinematic viscosity that gives La; the relaxation time follows from the
+    time step as tau = nu / (cs^2 dt), so the caller sets it once dt is known."""
+    th = math.radians(theta_deg)
+    cb = math.cos(th)
+    D, sigma, rho_l = 32.0, 0.01, 1.0
+    R = 0.5 * D * math.sqrt(math.pi / (th - math.sin(th) * cb))
+    m = meshes.box2d(nx, ny, N, 128.0, 64.0, periodic=(False, False), jitter=0.0, seed=31,
+                     cos_theta={"bottom": cb}, name=f"paper_flat_N{N}")
+    c = Case(f"paper_flat_{theta_deg:g}", m, LATTICE_D2Q9, rho_l=rho_l, delta=1.92, sigma=sigma,
+             x0=(64.0, -R * cb), R=R, seed=31, steps=0,
+             wall_geom=dict(kind="plane", point=(0.0, 0.0), normal=(0.0, -1.0)), theta_deg=theta_deg,
+             nu=math.sqrt(sigma * D / (rho_l * La)))
+    return c
 
 
 ORDERS_2D = (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16)

@@ -4,6 +4,8 @@ import ctypes as C
 import os
 import re
 
+import math
+
 import numpy as np
 import pytest
 
@@ -124,6 +126,27 @@ def test_host_tables_match_oracle_bitwise(L, mk):
     assert inf.dt == o.dt and inf.h_min == o.hmin and inf.beta == o.beta and inf.kappa == o.kappa
     assert inf.n_wall_nodes == o.nw
     L.slbm_destroy(h)
+
+
+@pytest.mark.parametrize("theta", [30.0, 60.0, 90.0, 120.0, 150.0])
+def test_paper_flat_case_geometry(theta):
+    """Inputs of the flat-wall runs: the equilibrium cap has the area of the D = 32 circle
+    (counted on a 0.05 grid, not from the segment formula), it meets the wall at theta, it
+    stays clear of the other walls, and nu gives La = 122."""
+    c = cases.paper_flat(theta)
+    xc, yc = c.x0
+    h = 0.05
+    xs = np.arange(0.0, 128.0, h) + 0.5 * h
+    ys = np.arange(0.0, 64.0, h) + 0.5 * h
+    X, Y = np.meshgrid(xs, ys)
+    inside = (X - xc) ** 2 + (Y - yc) ** 2 < c.R ** 2
+    area = inside.sum() * h * h
+    assert abs(area - math.pi * 16.0 ** 2) < 2e-3 * math.pi * 16.0 ** 2
+    # the cap's edge crosses y = 0 where the circle's tangent makes theta with the wall
+    assert abs(math.degrees(math.acos(-yc / c.R)) - theta) < 1e-9
+    assert not inside[:, 0].any() and not inside[:, -1].any() and not inside[-1, :].any()
+    assert abs(c.sigma * 32.0 / (c.rho_l * c.nu ** 2) - 122.0) < 1e-9
+    assert c.N == 16 and c.mesh.E == 128
 
 
 def test_mesh_generators_structure():
