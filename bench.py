@@ -264,52 +264,74 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
     }
 
 
-def paper_flat_runs(P, torch, steps: int, every: int, thetas=(30.0, 60.0, 90.0, 120.0, 150.0)):
-    """Parasitic currents of the flat-wall test (Sec. 3.1) in the paper's setting: N = 16,
-    16x8 elements, La = 122, each droplet started as its equilibrium cap.  All angles step
-    as one batch; KE_max of every solve is read every `every` steps, and the contact angle
-    at the end.  The relaxation time holds the viscosity of La = 122 at the library's time
-    step: nu = tau cs^2 dt."""
+def paper_runs(P, torch, kind: str, steps: int, every: int):
+    """The paper's parasitic-current tests in its own settings, in lattice units; every
+    run of a kind steps as one batch, KE_max of each is read every `every` steps and, for
+    the flat wall, the contact angle at the end.  The relaxation time holds the viscosity of
+    each run's Laplace number at one time step for the set (the smallest of the runs'
+    automatic steps): nu = tau cs^2 dt.
+      flat:     Sec. 3.1, N = 16, 16x8 elements, La = 122, equilibrium caps at 30-150 deg;
+      isolated: Sec. 3.3, droplet in a 64x64 box, N = 16 on 4x4 elements and N = 4 on
+                16x16, La = 3.07, 15, 61.5."""
     from synth import cases
+    if kind == "flat":
+        labels = [f"theta {t:g}" for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
+        cs = [cases.paper_flat(t) for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
+    else:
+        runs = [(La, N, nel) for N, nel in ((16, 4), (4, 16)) for La in (3.07, 15.0, 61.5)]
+        labels = [f"La {La:g} N {N} {nel}x{nel}" for La, N, nel in runs]
+        cs = [cases.paper_isolated(La, N, nel) for La, N, nel in runs]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        solves, cs = [], []
-        for t in thetas:
-            c = cases.paper_flat(t)
+        dts = []
+        for c in cs:
             probe = P.Solve(c, stream=stream)
-            dt = probe.info().dt
+            dts.append(probe.info().dt)
             del probe
+        solves, meta = [], []
+        for c in cs:
+            # one time step for the whole set (the smallest automatic one), so that every
+            # run reaches the same T / t_eta at its Laplace number, at both orders
+            dt = min(dts)
+            c.dt = dt
             c.tau = c.nu / (dt / 3.0)
             s = P.Solve(c, stream=stream)
             s.init_tanh()
             solves.append(s)
-            cs.append(c)
+            t_eta = c.rho_l * c.nu * 32.0 / c.sigma
+            meta.append({"N": c.N, "elements": c.mesh.E, "nu": c.nu, "dt": dt, "tau": c.tau,
+                         "t_eta": t_eta, "La": c.sigma * 32.0 / (c.rho_l * c.nu ** 2)})
         b = P.Batch(stream)
         for s in solves:
             b.add(s)
+        # a run that turns non-finite is reported with the first step it was seen at; the
+        # others keep stepping (members of a batch share no data)
         hist, n, t0 = [], 0, time.perf_counter()
-        while n < steps:
+        diverged = [None] * len(solves)
+        while n < steps and any(d is None for d in diverged):
             b.step(every)
             n += every
             ke = [float(k) for k in b.kinetic_energy()[0]]
-            hist.append([n] + ke)
-            print(f"[paper-flat] step {n}: KE_max " + " ".join(f"{k:.2e}" for k in ke), file=sys.stderr, flush=True)
-            if not all(math.isfinite(k) for k in ke):
-                break
+            for j, k in enumerate(ke):
+                if diverged[j] is None and not math.isfinite(k):
+                    diverged[j] = n
+            hist.append([n] + [k if math.isfinite(k) else None for k in ke])
+            print(f"[paper-{kind}] step {n}: KE_max " + " ".join(f"{k:.2e}" for k in ke),
+                  file=sys.stderr, flush=True)
         wall_s = time.perf_counter() - t0
         del b
         angles = []
-        for s in solves:
-            try:
-                angles.append(s.contact_angle())
-            except Exception:  # noqa: BLE001 - an unfit interface is reported as null
-                angles.append(None)
-    c = cs[0]
-    t_eta = c.rho_l * c.nu * 2.0 * 16.0 / c.sigma
-    return {"metric": "flat-wall parasitic currents (KE_max history)", "thetas_deg": list(thetas),
-            "N": c.N, "elements": c.mesh.E, "La": 122.0, "nu": c.nu, "dt": solves[0].info().dt,
-            "tau": c.tau, "t_eta": t_eta, "steps": n, "T_over_t_eta": n * solves[0].info().dt / t_eta,
-            "ke_history": hist, "contact_angle_deg": angles, "wall_s": wall_s,
+        if kind == "flat":
+            for s, dv in zip(solves, diverged):
+                try:
+                    angles.append(s.contact_angle() if dv is None else None)
+                except Exception:  # noqa: BLE001 - an unfit interface is reported as null
+                    angles.append(None)
+    for m in meta:
+        m["T_over_t_eta"] = n * m["dt"] / m["t_eta"]
+    return {"metric": f"{kind} parasitic currents (KE_max history)", "runs": labels, "params": meta,
+            "steps": n, "ke_history": hist, "diverged_at_step": diverged,
+            "contact_angle_deg": angles, "wall_s": wall_s,
             "data": "synthetic", "n_gpus": 1, "dtype": "f64"}
 
 
@@ -331,8 +353,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paper-flat", type=int, default=0, metavar="STEPS",
-                    help="only the flat-wall parasitic-current runs (N=16, La=122) for STEPS steps")
+    ap.add_argument("--paper", choices=["flat", "isolated"],
+                    help="only the paper's parasitic-current runs of that test (see paper_runs)")
+    ap.add_argument("--paper-steps", type=int, default=4300000)
     ap.add_argument("--paper-every", type=int, default=100000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the byte-counter calibration kernel over MIB MiB")
@@ -352,8 +375,8 @@ def main():
     if args.copy_calibration > 0:
         print(json.dumps(copy_calibration(torch, args.copy_calibration)))
         return
-    if args.paper_flat > 0:
-        print(json.dumps(paper_flat_runs(P, torch, args.paper_flat, args.paper_every)))
+    if args.paper:
+        print(json.dumps(paper_runs(P, torch, args.paper, args.paper_steps, args.paper_every)))
         return
     if args.batch_only:
         out = batch_bench(P, torch, args.batch_members, args.batch_steps)

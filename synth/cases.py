@@ -216,6 +216,20 @@ def paper_flat(theta_deg: float = 60.0, N: int = 16, nx: int = 16, ny: int = 8,
     return c
 
 
+def paper_isolated(La: float = 61.5, N: int = 16, nel: int = 4) -> Case:
+    """The boundary-free droplet test of Sec. 3.3 in lattice units: a droplet of diameter
+    D = 32 at the centre of a 64x64 box of nel x nel square quads at order N (4x4 at N = 16,
+    or 16x16 at N = 4: the same number of nodes), Cahn number delta / D = 0.063, Laplace
+    number La = sigma D / (rho_l nu^2).  The box has non-wetting walls, since a fully
+    periodic box leaves the uniform-momentum mode undamped.  `nu` gives La; the caller
+    sets tau = nu / (cs^2 dt) once dt is known."""
+    D, sigma, rho_l = 32.0, 0.01, 1.0
+    m = meshes.box2d(nel, nel, N, 64.0, 64.0, periodic=(False, False), name=f"paper_isolated_N{N}")
+    return Case(f"paper_isolated_La{La:g}_N{N}", m, LATTICE_D2Q9, rho_l=rho_l, delta=0.063 * D,
+                sigma=sigma, x0=(32.0, 32.0), R=0.5 * D, seed=33, steps=0,
+                nu=math.sqrt(sigma * D / (rho_l * La)))
+
+
 ORDERS_2D = (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16)
 ORDERS_3D = (2, 3, 4, 5, 6)
 

@@ -149,6 +149,17 @@ def test_paper_flat_case_geometry(theta):
     assert c.N == 16 and c.mesh.E == 128
 
 
+def test_paper_isolated_case():
+    """Inputs of the isolated-droplet runs: the same node count at N = 16 on 4x4 and N = 4
+    on 16x16, Cn = 0.063, the La of nu, the droplet clear of the walls."""
+    a, b = cases.paper_isolated(61.5, 16, 4), cases.paper_isolated(3.07, 4, 16)
+    assert a.mesh.n_global == b.mesh.n_global == 65 * 65
+    for c, La in ((a, 61.5), (b, 3.07)):
+        assert abs(c.delta / (2.0 * c.R) - 0.063) < 1e-12
+        assert abs(c.sigma * 2.0 * c.R / (c.rho_l * c.nu ** 2) - La) < 1e-9
+        assert c.x0[0] - c.R > 4.0 * c.delta and c.x0[1] - c.R > 4.0 * c.delta
+
+
 def test_mesh_generators_structure():
     """Inputs: shared nodes bitwise equal (no periodic wrap), Jacobians positive."""
     for m in [cases.c2().mesh, cases.small_cyl().mesh, cases.small_sphere().mesh]:

@@ -589,7 +589,7 @@ def test_paper_flat_wall_decay(P):
     equilibrium caps at 30-150 degrees, one batch): over 200k steps (9 viscous times) the
     parasitic currents decay by over a decade at every angle and the caps keep their angles
     (to 1 degree, 3 at 150 degrees).  The decay to the 1e-24..1e-26 floors takes 4.3 M steps;
-    bench.py --paper-flat runs it."""
+    bench.py --paper flat runs it."""
     import torch
     thetas = (30.0, 60.0, 90.0, 120.0, 150.0)
     stream = torch.cuda.Stream()
@@ -618,3 +618,33 @@ def test_paper_flat_wall_decay(P):
             th = s.contact_angle()
             print(f"[parity] paper flat theta {t}: {th:.2f}", flush=True)
             assert abs(th - t) < (3.0 if t > 140.0 else 1.0)
+
+
+def test_paper_isolated_decay(P):
+    """Boundary-free droplet test of Sec. 3.3 in the paper's setting (Cn = 0.063, La = 61.5)
+    at N = 16 on 4x4 elements and N = 4 on 16x16, one batch at one time step: KE_max falls
+    below 1e-21 within 300k steps (39 viscous times) at both orders.  bench.py --paper
+    isolated runs the La sweep to the floors."""
+    import torch
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cs = [cases.paper_isolated(61.5, 16, 4), cases.paper_isolated(61.5, 4, 16)]
+        dts = []
+        for c in cs:
+            probe = P.Solve(c, stream=stream)
+            dts.append(probe.info().dt)
+            del probe
+        b = P.Batch(stream)
+        solves = []
+        for c in cs:
+            c.dt = min(dts)
+            c.tau = c.nu / (c.dt / 3.0)
+            s = P.Solve(c, stream=stream)
+            s.init_tanh()
+            solves.append(s)
+            b.add(s)
+        b.step(300000)
+        ke = b.kinetic_energy()[0].copy()
+        del b
+        print(f"[parity] paper isolated KE after 300k steps {ke}", flush=True)
+        assert np.all(ke < 1e-21)
