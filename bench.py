@@ -271,12 +271,15 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
     each run's Laplace number at one time step for the set (the smallest of the runs'
     automatic steps): nu = tau cs^2 dt.
       flat:     Sec. 3.1, N = 16, 16x8 elements, La = 122, equilibrium caps at 30-150 deg;
+      curved:   Sec. 3.2, N = 11, circular wall on a 256-element O-grid, La = 341, equilibrium
+                caps at 30-150 deg;
       isolated: Sec. 3.3, droplet in a 64x64 box, N = 16 on 4x4 elements and N = 4 on
                 16x16, La = 3.07, 15, 61.5."""
     from synth import cases
-    if kind == "flat":
+    if kind in ("flat", "curved"):
+        mk = cases.paper_flat if kind == "flat" else cases.paper_curved
         labels = [f"theta {t:g}" for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
-        cs = [cases.paper_flat(t) for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
+        cs = [mk(t) for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
     else:
         runs = [(La, N, nel) for N, nel in ((16, 4), (4, 16)) for La in (3.07, 15.0, 61.5)]
         labels = [f"La {La:g} N {N} {nel}x{nel}" for La, N, nel in runs]
@@ -298,9 +301,10 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
             s = P.Solve(c, stream=stream)
             s.init_tanh()
             solves.append(s)
-            t_eta = c.rho_l * c.nu * 32.0 / c.sigma
+            D = 25.6 if kind == "curved" else 32.0
+            t_eta = c.rho_l * c.nu * D / c.sigma
             meta.append({"N": c.N, "elements": c.mesh.E, "nu": c.nu, "dt": dt, "tau": c.tau,
-                         "t_eta": t_eta, "La": c.sigma * 32.0 / (c.rho_l * c.nu ** 2)})
+                         "t_eta": t_eta, "La": c.sigma * D / (c.rho_l * c.nu ** 2)})
         b = P.Batch(stream)
         for s in solves:
             b.add(s)
@@ -321,7 +325,7 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
         wall_s = time.perf_counter() - t0
         del b
         angles = []
-        if kind == "flat":
+        if kind != "isolated":
             for s, dv in zip(solves, diverged):
                 try:
                     angles.append(s.contact_angle() if dv is None else None)
@@ -353,7 +357,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paper", choices=["flat", "isolated"],
+    ap.add_argument("--paper", choices=["flat", "curved", "isolated"],
                     help="only the paper's parasitic-current runs of that test (see paper_runs)")
     ap.add_argument("--paper-steps", type=int, default=4300000)
     ap.add_argument("--paper-every", type=int, default=100000)

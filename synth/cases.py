@@ -230,6 +230,50 @@ def paper_isolated(La: float = 61.5, N: int = 16, nel: int = 4) -> Case:
                 nu=math.sqrt(sigma * D / (rho_l * La)))
 
 
+def lens_area(R: float, Rw: float, d: float) -> float:
+    """Area of the intersection of two disks of radii R and Rw whose centres are d apart."""
+    if d >= R + Rw:
+        return 0.0
+    if d <= abs(R - Rw):
+        return math.pi * min(R, Rw) ** 2
+    a = R * R * math.acos((d * d + R * R - Rw * Rw) / (2.0 * d * R))
+    b = Rw * Rw * math.acos((d * d + Rw * Rw - R * R) / (2.0 * d * Rw))
+    c = 0.5 * math.sqrt((-d + R + Rw) * (d + R - Rw) * (d - R + Rw) * (d + R + Rw))
+    return a + b - c
+
+
+def paper_curved(theta_deg: float = 90.0, N: int = 11, n_az: int = 32, n_rad: int = 8,
+                 La: float = 341.0) -> Case:
+    """The curved-wall parasitic-current test of Sec. 3.2 in lattice units: a circular wall
+    of diameter D = 25.6 (0.2 of the side) at the centre of a 128x128 walled box, meshed as
+    a jittered O-grid (standing in for the paper's unstructured mesh), N = 11, La = 341,
+    interface thickness delta = 0.06 D (the flat-wall test's ratio).
+
+    The droplet starts as its equilibrium cap: the circle meeting the wall at theta (through
+    the liquid) whose part outside the wall has the area of a diameter-D circle (bisection
+    on its radius).  `nu` gives La; the caller sets tau = nu / (cs^2 dt)."""
+    D, sigma, rho_l = 25.6, 0.01, 1.0
+    Rw, A0 = 0.5 * D, math.pi * (0.5 * D) ** 2
+    lo, hi = 1e-3 * Rw, 50.0 * Rw
+    for _ in range(200):
+        R = 0.5 * (lo + hi)
+        d = young_center_distance(Rw, R, theta_deg)
+        if math.pi * R * R - lens_area(R, Rw, d) < A0:
+            lo = R
+        else:
+            hi = R
+    R = 0.5 * (lo + hi)
+    d = young_center_distance(Rw, R, theta_deg)
+    cc = math.cos(math.radians(theta_deg))
+    m = meshes.ogrid2d(n_az, n_rad, N, center=(64.0, 64.0), Rc=Rw, half_width=64.0,
+                       grading=2.0, jitter=0.1, seed=32, cos_cyl=cc, cos_box=0.0,
+                       name=f"paper_curved_N{N}")
+    return Case(f"paper_curved_{theta_deg:g}", m, LATTICE_D2Q9, rho_l=rho_l, delta=0.06 * D,
+                sigma=sigma, x0=(64.0, 64.0 + d), R=R, seed=32, steps=0,
+                wall_geom=dict(kind="circle", center=(64.0, 64.0), radius=Rw),
+                theta_deg=theta_deg, nu=math.sqrt(sigma * D / (rho_l * La)))
+
+
 ORDERS_2D = (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16)
 ORDERS_3D = (2, 3, 4, 5, 6)
 

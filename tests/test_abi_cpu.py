@@ -160,6 +160,33 @@ def test_paper_isolated_case():
         assert c.x0[0] - c.R > 4.0 * c.delta and c.x0[1] - c.R > 4.0 * c.delta
 
 
+@pytest.mark.parametrize("theta", [30.0, 90.0, 150.0])
+def test_paper_curved_case_geometry(theta):
+    """Inputs of the curved-wall runs: the liquid outside the circular wall (area counted
+    on a 0.05 grid) equals the D = 25.6 circle, the cap meets the wall at theta (from the
+    two outward normals at an intersection point), and nu gives La = 341."""
+    c = cases.paper_curved(theta)
+    (xc, yc), R = c.x0, c.R
+    Rw = c.wall_geom["radius"]
+    cx, cy = c.wall_geom["center"]
+    h = 0.05
+    xs = np.arange(cx - 64.0, cx + 64.0, h) + 0.5 * h
+    X, Y = np.meshgrid(xs, xs)
+    liquid = ((X - xc) ** 2 + (Y - yc) ** 2 < R * R) & ((X - cx) ** 2 + (Y - cy) ** 2 > Rw * Rw)
+    assert abs(liquid.sum() * h * h - math.pi * 12.8 ** 2) < 3e-3 * math.pi * 12.8 ** 2
+    # an intersection point P of the two circles, then the contact angle through the liquid
+    # from the outward normals there: cos(theta) = n_wall . n_drop
+    ux, uy = xc - cx, yc - cy
+    d = math.hypot(ux, uy)
+    a = (Rw * Rw - R * R + d * d) / (2.0 * d)
+    hh = math.sqrt(Rw * Rw - a * a)
+    px, py = cx + (a * ux - hh * uy) / d, cy + (a * uy + hh * ux) / d
+    assert abs(math.hypot(px - cx, py - cy) - Rw) < 1e-9 and abs(math.hypot(px - xc, py - yc) - R) < 1e-9
+    cos_t = ((px - cx) * (px - xc) + (py - cy) * (py - yc)) / (Rw * R)
+    assert abs(math.degrees(math.acos(cos_t)) - theta) < 1e-7
+    assert abs(c.sigma * 25.6 / (c.rho_l * c.nu ** 2) - 341.0) < 1e-9
+
+
 def test_mesh_generators_structure():
     """Inputs: shared nodes bitwise equal (no periodic wrap), Jacobians positive."""
     for m in [cases.c2().mesh, cases.small_cyl().mesh, cases.small_sphere().mesh]:
