@@ -243,11 +243,11 @@ def lens_area(R: float, Rw: float, d: float) -> float:
 
 
 def paper_curved(theta_deg: float = 90.0, N: int = 11, n_az: int = 32, n_rad: int = 8,
-                 La: float = 341.0) -> Case:
+                 La: float = 341.0, jitter: float = 0.1, cn: float = 0.06) -> Case:
     """The curved-wall parasitic-current test of Sec. 3.2 in lattice units: a circular wall
     of diameter D = 25.6 (0.2 of the side) at the centre of a 128x128 walled box, meshed as
     a jittered O-grid (standing in for the paper's unstructured mesh), N = 11, La = 341,
-    interface thickness delta = 0.06 D (the flat-wall test's ratio).
+    interface thickness delta = cn D (by default 0.06, the flat-wall test's ratio).
 
     The droplet starts as its equilibrium cap: the circle meeting the wall at theta (through
     the liquid) whose part outside the wall has the area of a diameter-D circle (bisection
@@ -266,9 +266,9 @@ def paper_curved(theta_deg: float = 90.0, N: int = 11, n_az: int = 32, n_rad: in
     d = young_center_distance(Rw, R, theta_deg)
     cc = math.cos(math.radians(theta_deg))
     m = meshes.ogrid2d(n_az, n_rad, N, center=(64.0, 64.0), Rc=Rw, half_width=64.0,
-                       grading=2.0, jitter=0.1, seed=32, cos_cyl=cc, cos_box=0.0,
+                       grading=2.0, jitter=jitter, seed=32, cos_cyl=cc, cos_box=0.0,
                        name=f"paper_curved_N{N}")
-    return Case(f"paper_curved_{theta_deg:g}", m, LATTICE_D2Q9, rho_l=rho_l, delta=0.06 * D,
+    return Case(f"paper_curved_{theta_deg:g}", m, LATTICE_D2Q9, rho_l=rho_l, delta=cn * D,
                 sigma=sigma, x0=(64.0, 64.0 + d), R=R, seed=32, steps=0,
                 wall_geom=dict(kind="circle", center=(64.0, 64.0), radius=Rw),
                 theta_deg=theta_deg, nu=math.sqrt(sigma * D / (rho_l * La)))
