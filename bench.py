@@ -267,9 +267,9 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
 def paper_runs(P, torch, kind: str, steps: int, every: int):
     """The paper's parasitic-current tests in its own settings, in lattice units; every
     run of a kind steps as one batch, KE_max of each is read every `every` steps and, for
-    the flat wall, the contact angle at the end.  The relaxation time holds the viscosity of
-    each run's Laplace number at one time step for the set (the smallest of the runs'
-    automatic steps): nu = tau cs^2 dt.
+    the walled caps, the contact angle at the end.  Each case carries the viscosity nu of its
+    Laplace number and the library sets tau = nu / (cs^2 dt) at the time step; the isolated
+    set runs at one time step (the smallest of its automatic ones).
       flat:     Sec. 3.1, N = 16, 16x8 elements, La = 122, equilibrium caps at 30-150 deg;
       curved:   Sec. 3.2, N = 11, circular wall on a 256-element O-grid, La = 341, equilibrium
                 caps at 30-150 deg;
@@ -286,21 +286,24 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
         cs = [cases.paper_isolated(La, N, nel) for La, N, nel in runs]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        dts = []
-        for c in cs:
-            probe = P.Solve(c, stream=stream)
-            dts.append(probe.info().dt)
-            del probe
-        solves, meta = [], []
-        for c in cs:
+        if kind == "isolated":
             # one time step for the whole set (the smallest automatic one), so that every
             # run reaches the same T / t_eta at its Laplace number, at both orders
-            dt = min(dts)
-            c.dt = dt
-            c.tau = c.nu / (dt / 3.0)
+            dts = []
+            for c in cs:
+                probe = P.Solve(c, stream=stream)
+                dts.append(probe.info().dt)
+                del probe
+            for c in cs:
+                c.dt = min(dts)
+        solves, meta = [], []
+        for c in cs:
+            # the library sets tau from the case's viscosity nu at the time step
             s = P.Solve(c, stream=stream)
             s.init_tanh()
             solves.append(s)
+            dt = s.info().dt
+            c.tau = s.info().tau
             D = 25.6 if kind == "curved" else 32.0
             t_eta = c.rho_l * c.nu * D / c.sigma
             meta.append({"N": c.N, "elements": c.mesh.E, "nu": c.nu, "dt": dt, "tau": c.tau,

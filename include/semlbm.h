@@ -68,8 +68,8 @@ typedef struct slbm_params {
     double tau;       /* dimensionless relaxation time of Eq. (4) (0.5 in Sec. 3.3), in units
                          of dt: the kinematic viscosity is tau dt / 3, so a smaller dt (a
                          higher order, a finer mesh) at the same tau is a less viscous fluid
-                         with a Laplace number larger by the square of the ratio.  To keep
-                         the physics when dt changes, scale tau by 1/dt. */
+                         with a Laplace number larger by the square of the ratio.  Ignored
+                         when nu > 0. */
     double dt;        /* > 0: time step; otherwise dt = min(cfl h_min,
                          C h_min^2 / sqrt(kappa rho_l)) (advective and capillary bounds), with
                          C = 0.25 for N <= 12 and 0.125 for N >= 13. */
@@ -77,6 +77,10 @@ typedef struct slbm_params {
     int ke_every;     /* slbm_step checks finiteness and KE_max every ke_every steps (0: never) */
     double ke_limit;  /* KE_max above this (or non-finite) -> SLBM_EDIVERGED; <= 0: 1.0 */
     uint64_t seed;    /* default seed of slbm_init_tanh noise */
+    double nu;        /* > 0: kinematic viscosity to hold; slbm_set_mesh then sets
+                         tau = (3 nu) / dt once dt is known (cs^2 = 1/3), so the fluid is the
+                         same at every order, mesh and time step.  0: use tau.  A caller that
+                         zero-initialises the struct gets the tau behaviour. */
 } slbm_params;
 
 typedef struct slbm_info {
@@ -84,6 +88,7 @@ typedef struct slbm_info {
     int64_t n_elements, n_local, n_global, n_wall_nodes, step;
     size_t workspace_bytes;
     int dim, Q, N;
+    double tau;       /* relaxation time in use (from nu once the mesh is set, if nu > 0) */
 } slbm_info;
 
 typedef struct slbm_ctx slbm_ctx;

@@ -77,7 +77,8 @@ class Oracle:
             self._wc = np.zeros(1)
             self._wu = np.zeros(3)
         phys = np.array([case.rho_l, case.rho_v, case.delta, case.sigma, case.tau,
-                         case.dt if dt is None else dt, case.cfl], dtype=np.float64)
+                         case.dt if dt is None else dt, case.cfl,
+                         float(getattr(case, "nu", 0.0) or 0.0)], dtype=np.float64)
         self._h = lib.orc_new(self.dim, self.N, self.Q, m.E, _d(self._xyz),
                               self._gid.ctypes.data_as(_ip), self.Ng, m.wall_face.shape[0],
                               self._wf.ctypes.data_as(_ip), _d(self._wc), _d(self._wu), _d(phys),

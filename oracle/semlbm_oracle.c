@@ -40,7 +40,8 @@
  *       for N <= 12 and 1/8 for N >= 13 (h_min: smallest distance between neighbouring GLL
  *       nodes along element lines; the second bound is the capillary stiffness limit of the
  *       force term).
- *   R12 tau is dimensionless: omega = 1/(tau + 1/2).
+ *   R12 tau is dimensionless: omega = 1/(tau + 1/2), and the kinematic viscosity is
+ *       tau cs^2 dt; given a viscosity nu > 0, tau = 3 nu / dt.
  *   R16 seeded density noise: rho += a (2U - 1), U from SplitMix64 of (seed xor gid).
  *
  * Arithmetic conventions (so that a separately written implementation can follow the
@@ -82,7 +83,7 @@ typedef struct {
     double *wcos; /* [nw] */
     double *wub;  /* [nw*3] */
     /* parameters */
-    double rho_l, rho_v, delta, sigma, tau, dt, cfl, beta, kappa, omega, hmin;
+    double rho_l, rho_v, delta, sigma, tau, dt, cfl, nu, beta, kappa, omega, hmin;
     /* state */
     double *f; /* [Q*Ng] */
     long nstep;
@@ -224,7 +225,8 @@ static double drefT(const orc *o, const double *v, int n, int a) {
 
 void orc_free(orc *o);
 
-/* phys = {rho_l, rho_v, delta, sigma, tau, dt, cfl}; mode 0 = two-phase step,
+/* phys = {rho_l, rho_v, delta, sigma, tau, dt, cfl, nu}; nu > 0 replaces tau by the
+ * relaxation time of that kinematic viscosity at the time step (R12); mode 0 = two-phase step,
  * mode 1 = pure advection of every population (no force, no collision). */
 orc *orc_new(int dim, int N, int Q, long E, const double *xyz, const int *gid, long ng,
              long nwf, const int *wf, const double *wcos, const double *wub,
@@ -251,7 +253,7 @@ orc *orc_new(int dim, int N, int Q, long E, const double *xyz, const int *gid, l
     o->xyz = malloc(sizeof(double) * o->Nl * dim);
     memcpy(o->xyz, xyz, sizeof(double) * o->Nl * dim);
     o->rho_l = phys[0]; o->rho_v = phys[1]; o->delta = phys[2]; o->sigma = phys[3];
-    o->tau = phys[4]; o->dt = phys[5]; o->cfl = phys[6];
+    o->tau = phys[4]; o->dt = phys[5]; o->cfl = phys[6]; o->nu = phys[7];
     /* (A.4)-(A.5) solved for beta, kappa at gamma = sigma */
     double dr = o->rho_l - o->rho_v;
     o->beta = 12.0 * o->sigma / (o->delta * dr * dr * dr * dr);
@@ -348,6 +350,11 @@ orc *orc_new(int dim, int N, int Q, long E, const double *xyz, const int *gid, l
         double c_cap = o->N > 12 ? 0.125 : 0.25;
         double dt_cap = c_cap * o->hmin * o->hmin / sqrt(o->kappa * o->rho_l);
         o->dt = dt_adv < dt_cap ? dt_adv : dt_cap;
+    }
+    if (o->nu > 0.0) {
+        /* R12: the kinematic viscosity is tau cs^2 dt with cs^2 = 1/3 */
+        o->tau = 3.0 * o->nu / o->dt;
+        o->omega = 1.0 / (o->tau + 0.5);
     }
 
     /* wall entries, in the order of the face list, face nodes ascending (R9) */

@@ -29,7 +29,7 @@ class Params(C.Structure):
     _fields_ = [("lattice", C.c_int), ("N", C.c_int), ("rho_l", C.c_double), ("rho_v", C.c_double),
                 ("delta", C.c_double), ("sigma", C.c_double), ("tau", C.c_double),
                 ("dt", C.c_double), ("cfl", C.c_double), ("ke_every", C.c_int),
-                ("ke_limit", C.c_double), ("seed", C.c_uint64)]
+                ("ke_limit", C.c_double), ("seed", C.c_uint64), ("nu", C.c_double)]
 
 
 class Info(C.Structure):
@@ -37,7 +37,7 @@ class Info(C.Structure):
                 ("omega", C.c_double), ("h_min", C.c_double), ("n_elements", C.c_int64),
                 ("n_local", C.c_int64), ("n_global", C.c_int64), ("n_wall_nodes", C.c_int64),
                 ("step", C.c_int64), ("workspace_bytes", C.c_size_t), ("dim", C.c_int),
-                ("Q", C.c_int), ("N", C.c_int)]
+                ("Q", C.c_int), ("N", C.c_int), ("tau", C.c_double)]
 
 
 class WallGeom(C.Structure):
@@ -174,6 +174,7 @@ def make_params(case, ke_every: int = 0, ke_limit: float = 0.0) -> Params:
     p.ke_every = int(ke_every)
     p.ke_limit = float(ke_limit)
     p.seed = int(case.seed)
+    p.nu = float(getattr(case, "nu", 0.0) or 0.0)
     return p
 
 

@@ -33,6 +33,7 @@ void destroy_graph(void *exec);
 
 struct slbm_ctx {
     slbm_params prm{};
+    double tau = 0.0;  // relaxation time in use (prm.tau, or from prm.nu at set_mesh)
     int dim = 0, Q = 0, N = 0, Np = 0, nloc = 0;
     double beta = 0, kappa = 0, omega = 0, dt = 0, hmin = 0;
     double ev[slbm::kMaxQ][3] = {};

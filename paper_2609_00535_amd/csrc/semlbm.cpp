@@ -180,8 +180,8 @@ extern "C" slbm_status slbm_create(const slbm_params *p, slbm_ctx **out) {
             return SLBM_EINVAL;
         }
         const double dr = p->rho_l - p->rho_v;
-        if (!(dr > 0.0) || !(p->delta > 0.0) || !(p->sigma > 0.0) || !(p->tau > 0.0) ||
-            !(p->dt > 0.0 || p->cfl > 0.0)) {
+        if (!(dr > 0.0) || !(p->delta > 0.0) || !(p->sigma > 0.0) || !(p->nu >= 0.0) ||
+            !(p->tau > 0.0 || p->nu > 0.0) || !std::isfinite(p->nu) || !(p->dt > 0.0 || p->cfl > 0.0)) {
             delete c;
             return SLBM_EINVAL;
         }
@@ -190,7 +190,9 @@ extern "C" slbm_status slbm_create(const slbm_params *p, slbm_ctx **out) {
         // (A.4)-(A.5) solved for beta and kappa with gamma = sigma
         c->beta = 12.0 * p->sigma / (p->delta * dr * dr * dr * dr);
         c->kappa = 3.0 * p->sigma * p->delta / (2.0 * dr * dr);
-        c->omega = 1.0 / (p->tau + 0.5);
+        // with nu > 0 the relaxation time follows from the time step at slbm_set_mesh
+        c->tau = p->nu > 0.0 ? 0.0 : p->tau;
+        c->omega = p->nu > 0.0 ? 0.0 : 1.0 / (p->tau + 0.5);
         lattice_tables(c->Q, c->ev, c->tw, c->opp);
         for (int q = 0; q < c->Q; ++q) c->tc[q] = 3.0 * c->tw[q];
         gll_tables(c->N, c->xi, c->wq, c->Dm);
@@ -448,6 +450,11 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
             c->dt = dt_adv < dt_cap ? dt_adv : dt_cap;
         }
         if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return c->fail(SLBM_EINVAL, "invalid time step");
+        if (c->prm.nu > 0.0) {
+            // nu = tau cs^2 dt with cs^2 = 1/3 (R12)
+            c->tau = 3.0 * c->prm.nu / c->dt;
+            c->omega = 1.0 / (c->tau + 0.5);
+        }
         // --- wall tables: one entry per (face, face node); the entries of a local node are
         // adjacent, in the order of the caller's face list ---
         const double sq = std::sqrt(2.0 * c->beta / c->kappa);
@@ -1087,6 +1094,7 @@ extern "C" slbm_status slbm_get_info(const slbm_ctx *c, slbm_info *info) {
         info->beta = c->beta;
         info->kappa = c->kappa;
         info->omega = c->omega;
+        info->tau = c->tau;
         info->h_min = c->hmin;
         info->n_elements = c->E;
         info->n_local = c->Nl;

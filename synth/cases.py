@@ -44,7 +44,7 @@ class Case:
     ke_every: int = 100
     wall_geom: dict = field(default_factory=dict)
     theta_deg: float | None = None
-    nu: float = 0.0               # > 0: kinematic viscosity to hold (tau = nu / (cs^2 dt))
+    nu: float = 0.0               # > 0: kinematic viscosity to hold (the library sets tau)
 
     @property
     def N(self) -> int:
@@ -201,8 +201,8 @@ def paper_flat(theta_deg: float = 60.0, N: int = 16, nx: int = 16, ny: int = 8,
 
     The droplet starts as its equilibrium cap: the circular segment at angle theta (through
     the liquid) with the area of the D circle, R^2 (theta - sin theta cos theta) = pi D^2/4.
-    `nu` is the kinematic viscosity that gives La; the relaxation time follows from the
-    time step as tau = nu / (cs^2 dt), so the caller sets it once dt is known."""
+    `nu` is the kinematic viscosity that gives La; the library sets the relaxation time
+    tau = nu / (cs^2 dt) once the time step is known."""
     th = math.radians(theta_deg)
     cb = math.cos(th)
     D, sigma, rho_l = 32.0, 0.01, 1.0
@@ -221,7 +221,7 @@ def paper_isolated(La: float = 61.5, N: int = 16, nel: int = 4) -> Case:
     D = 32 at the centre of a 64x64 box of nel x nel square quads at order N (4x4 at N = 16,
     or 16x16 at N = 4: the same number of nodes), Cahn number delta / D = 0.063, Laplace
     number La = sigma D / (rho_l nu^2).  The box has non-wetting walls, since a fully
-    periodic box leaves the uniform-momentum mode undamped.  `nu` gives La; the caller
+    periodic box leaves the uniform-momentum mode undamped.  `nu` gives La; the library
     sets tau = nu / (cs^2 dt) once dt is known."""
     D, sigma, rho_l = 32.0, 0.01, 1.0
     m = meshes.box2d(nel, nel, N, 64.0, 64.0, periodic=(False, False), name=f"paper_isolated_N{N}")
@@ -251,7 +251,7 @@ def paper_curved(theta_deg: float = 90.0, N: int = 11, n_az: int = 32, n_rad: in
 
     The droplet starts as its equilibrium cap: the circle meeting the wall at theta (through
     the liquid) whose part outside the wall has the area of a diameter-D circle (bisection
-    on its radius).  `nu` gives La; the caller sets tau = nu / (cs^2 dt)."""
+    on its radius).  `nu` gives La; the library sets tau = nu / (cs^2 dt)."""
     D, sigma, rho_l = 25.6, 0.01, 1.0
     Rw, A0 = 0.5 * D, math.pi * (0.5 * D) ** 2
     lo, hi = 1e-3 * Rw, 50.0 * Rw

@@ -73,6 +73,17 @@ def test_argument_and_order_errors(L):
     bad = P.make_params(c)
     bad.rho_v = 2.0
     assert L.slbm_create(C.byref(bad), C.byref(h)) == P.binding.SLBM_EINVAL
+    for nu in (-0.1, float("nan"), float("inf")):
+        bad = P.make_params(c)
+        bad.nu = nu
+        assert L.slbm_create(C.byref(bad), C.byref(h)) == P.binding.SLBM_EINVAL
+    bad = P.make_params(c)
+    bad.tau = 0.0
+    assert L.slbm_create(C.byref(bad), C.byref(h)) == P.binding.SLBM_EINVAL
+    ok = P.make_params(c)
+    ok.tau, ok.nu = 0.0, 0.05  # a viscosity stands in for tau
+    assert L.slbm_create(C.byref(ok), C.byref(h)) == 0
+    L.slbm_destroy(h)
     assert L.slbm_create(C.byref(p), C.byref(h)) == 0
     assert L.slbm_workspace_bytes(h) == 0
     assert L.slbm_step(h, 1) == P.binding.SLBM_ESTATE
@@ -102,7 +113,8 @@ def test_argument_and_order_errors(L):
 
 
 @pytest.mark.parametrize("mk", [cases.c1, cases.c2, cases.small_cyl, cases.small_sphere,
-                                cases.small_box3d, lambda: cases.order_case(2, 14)])
+                                cases.small_box3d, lambda: cases.order_case(2, 14),
+                                lambda: cases.paper_flat(60.0), lambda: cases.paper_isolated(15.0, 4, 16)])
 def test_host_tables_match_oracle_bitwise(L, mk):
     """GLL tables, lumped mass, h_min and dt of the library equal the oracle's exactly:
     parity of the time step to 1e-11 needs identical inputs to every kernel."""
@@ -124,6 +136,9 @@ def test_host_tables_match_oracle_bitwise(L, mk):
     inf = P.binding.Info()
     assert L.slbm_get_info(h, C.byref(inf)) == 0
     assert inf.dt == o.dt and inf.h_min == o.hmin and inf.beta == o.beta and inf.kappa == o.kappa
+    assert inf.omega == o.omega
+    if c.nu > 0.0:  # the relaxation time of the case's viscosity at this dt
+        assert abs(inf.tau * inf.dt / 3.0 - c.nu) < 1e-15 * c.nu
     assert inf.n_wall_nodes == o.nw
     L.slbm_destroy(h)
 
