@@ -358,7 +358,7 @@ def main():
                     help="only the batched-stepping measurement (one JSON line)")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--kernel-reps", type=int, default=300)
-    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--cpu-steps", type=int, default=700)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paper", choices=["flat", "curved", "isolated"],
                     help="only the paper's parasitic-current runs of that test (see paper_runs)")
