@@ -206,7 +206,11 @@ slbm_status slbm_op_collide(slbm_ctx *c, const double *f, const double *rho, con
 /* ------------------------------------------------------------------------------------ */
 /* Batching: many bound contexts (different meshes, N, dt) advanced together.  Each     */
 /* kernel of the step covers every member's elements or nodes in one launch, grouped by */
-/* (lattice, N); members keep their own workspace.                                      */
+/* (lattice, N, kernel path); members keep their own workspace.  Members start from the */
+/* path they step alone with; a fused group whose members together exceed 2^20 local    */
+/* nodes steps with the unfused kernels, as one mesh of that size would.  A member      */
+/* stepped that way has its Laplacian partials recomputed before it next steps fused    */
+/* (alone, or in a fused group), so every member's results are those of stepping alone. */
 /* ------------------------------------------------------------------------------------ */
 typedef struct slbm_batch slbm_batch;
 slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out);

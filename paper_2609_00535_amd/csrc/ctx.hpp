@@ -31,6 +31,11 @@ int launch_graph(void *exec, void *stream);
 void destroy_graph(void *exec);
 }  // namespace slbm
 
+// meshes (and batch groups) over this many local nodes step with the unfused kernels, which
+// gather each shared node once; below it the fused kernels' fewer launches win (measured
+// crossover near 0.8 M local nodes in 2-D)
+constexpr int64_t kUnfusedAboveLocalNodes = (int64_t)1 << 20;
+
 struct slbm_ctx {
     slbm_params prm{};
     double tau = 0.0;  // relaxation time in use (prm.tau, or from prm.nu at set_mesh)
@@ -56,6 +61,9 @@ struct slbm_ctx {
     size_t ws_bytes = 0;
     int n_eblocks = 0, n_nblocks = 0, epb = 1;
     bool bound = false, has_state = false;
+    // the Laplacian partials no longer belong to the state: a fused-path context stepped by
+    // the unfused kernels in a batch (their last stage leaves the partials of its input)
+    bool rl_stale = false;
     void *dev = nullptr;
     void *stream = nullptr;
     slbm::SolveDesc desc{};
@@ -78,6 +86,8 @@ struct slbm_ctx {
     void layout();
     slbm_status require_bound(bool need_state);
     slbm_status upload_f_and_density(const std::vector<double> &f_int);
+    // recompute the Laplacian partials of the state if they are stale (fused path only)
+    int refresh_lap();
     slbm_status read_diag(double *ke, double *mass);
     slbm_status put(double *dst, const double *src_user, int fields);
     slbm_status get(const double *src, double *dst_user, int fields);

@@ -268,7 +268,7 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
             // once (measured crossover near 0.8 M local nodes in 2-D at N = 6 and 8)
             const char *nf = std::getenv("SLBM_UNFUSED");
             const char *ff = std::getenv("SLBM_FUSED");
-            const bool large = Nl > (int64_t)1 << 20;
+            const bool large = Nl > kUnfusedAboveLocalNodes;
             // nodes inside an element must belong to it alone (the fused kernels skip their
             // copy lists)
             std::vector<char> on_bnd(nloc, 0);
@@ -691,6 +691,7 @@ slbm_status slbm_ctx::upload_f_and_density(const std::vector<double> &f_int) {
     if (e == 0) e = (int)hipStreamSynchronize(st);
     if (e) return hip_check(e, "upload state");
     has_state = true;
+    rl_stale = false;
     return SLBM_OK;
 }
 
@@ -887,10 +888,18 @@ slbm_status slbm_ctx::enqueue(int64_t n) {
     return hip_check(enqueue_steps(dim, N, eplan, nplan, n, stream, fused), "step launch");
 }
 
+int slbm_ctx::refresh_lap() {
+    if (!fused || !rl_stale) return 0;
+    const int e = launch_lap(dim, N, eplan, stream);
+    if (e == 0) rl_stale = false;
+    return e;
+}
+
 extern "C" slbm_status slbm_step(slbm_ctx *c, int64_t n) {
     return slbm_guard([&]() -> slbm_status {
         if (!c || n < 0) return SLBM_EINVAL;
         if (slbm_status s = c->require_bound(true)) return s;
+        if (int e = c->refresh_lap()) return c->hip_check(e, "Laplacian refresh");
         const int every = c->prm.ke_every;
         const double lim = c->prm.ke_limit > 0.0 ? c->prm.ke_limit : 1.0;
         int64_t done = 0;
@@ -914,6 +923,7 @@ extern "C" slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int
     return slbm_guard([&]() -> slbm_status {
         if (!c || n < 0 || !ms || !launches) return SLBM_EINVAL;
         if (slbm_status s = c->require_bound(true)) return s;
+        if (int e = c->refresh_lap()) return c->hip_check(e, "Laplacian refresh");
         hipStream_t st = (hipStream_t)c->stream;
         constexpr int kPerStep = 14;
         hipEvent_t ev[2 * kPerStep];
@@ -1000,6 +1010,7 @@ extern "C" slbm_status slbm_time_kernel(slbm_ctx *c, int kind, int64_t reps, dou
             return SLBM_EINVAL;
         if (slbm_status s = c->require_bound(true)) return s;
         if ((kind >= 6) != c->fused) return c->fail(SLBM_EINVAL, "kernel kind is not on this context's path");
+        if (int e = c->refresh_lap()) return c->hip_check(e, "Laplacian refresh");
         hipStream_t st = (hipStream_t)c->stream;
         // the launches overwrite stage buffers and the state's density: keep f-bar to restore
         std::vector<double> f((size_t)c->Q * c->Ng);

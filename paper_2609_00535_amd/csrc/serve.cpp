@@ -271,8 +271,9 @@ struct slbm_batch {
     slbm_status rebuild() {
         drop_graphs();
         groups.clear();
-        // groups by (d, N, path): a member keeps the path (fused or not) it steps alone
-        // with, so its state buffers always carry what that path expects between steps
+        // groups by (d, N, path): members start from the path they step alone with; a
+        // fused group whose members together exceed kUnfusedAboveLocalNodes local nodes then
+        // steps with the unfused kernels, as a single mesh of that size would
         for (int i = 0; i < (int)members.size(); ++i) {
             slbm_ctx *c = members[i];
             Group *g = nullptr;
@@ -288,6 +289,22 @@ struct slbm_batch {
             g->idx.push_back(i);
             g->elements += c->E;
         }
+        for (auto &g : groups) {
+            if (!g.fused) continue;
+            int64_t nl = 0;
+            for (int i : g.idx) nl += members[i]->Nl;
+            if (nl > kUnfusedAboveLocalNodes) g.fused = false;
+        }
+        // the unfused kernels leave Laplacian partials of the last stage's input behind: a
+        // fused-path member of an unfused group needs them recomputed before it steps fused
+        // again (here, or at slbm_step once it leaves the batch); members of fused groups
+        // that were stepped unfused get them now, ahead of any step on the batch stream
+        for (auto &g : groups)
+            for (int i : g.idx) {
+                slbm_ctx *c = members[i];
+                if (!g.fused && c->fused) c->rl_stale = true;
+                if (g.fused && c->refresh_lap() != 0) return SLBM_EDEVICE;
+            }
         // candidate shapes per group: one element per block and (where more than one
         // element fits) wide blocks, each in XCD-aware and plain block order
         for (auto &g : groups) {

@@ -642,3 +642,47 @@ def test_paper_isolated_decay(P):
         del b
         print(f"[parity] paper isolated KE after 300k steps {ke}", flush=True)
         assert np.all(ke < 1e-21)
+
+
+def test_batch_large_group_steps_unfused_same_bits(P):
+    """A batch group of fused-path members together over 2^20 local nodes steps with the
+    unfused kernels, as one mesh of that size would.  Its members equal the same solves
+    stepped alone (fused) bit for bit; so does a member that then leaves and steps alone,
+    and the rest once the shrunken group is back on the fused path (both need the Laplacian
+    partials the unfused steps leave stale)."""
+    import torch
+    mk = lambda seed: cases.small_flat(60.0, nx=96, ny=96, N=6, jitter=0.2, seed=seed,
+                                       Lx=384.0, Ly=384.0, R=60.0)
+    cs = [mk(sd) for sd in (41, 42, 43)]
+    assert all(c.mesh.n_local <= 1 << 20 for c in cs)
+    assert sum(c.mesh.n_local for c in cs) > 1 << 20 >= cs[1].mesh.n_local + cs[2].mesh.n_local
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ref30, ref40 = [], []
+        for c in cs:
+            s = P.Solve(c, stream=stream)
+            s.init_tanh()
+            s.step(30)
+            ref30.append(s.get_state()[0])
+            s.step(10)
+            ref40.append(s.get_state()[0])
+            del s
+        solves = []
+        b = P.Batch(stream)
+        for c in cs:
+            s = P.Solve(c, stream=stream)
+            s.init_tanh()
+            solves.append(s)
+            b.add(s)
+        b.step(30)
+        assert [g["fused"] for g in b.shapes()] == [False]
+        for s, r in zip(solves, ref30):
+            assert np.array_equal(s.get_state()[0], r)
+        b.remove(solves[0])
+        solves[0].step(10)  # alone again: fused, from refreshed partials
+        assert np.array_equal(solves[0].get_state()[0], ref40[0])
+        b.step(10)
+        assert [g["fused"] for g in b.shapes()] == [True]
+        for s, r in zip(solves[1:], ref40[1:]):
+            assert np.array_equal(s.get_state()[0], r)
+        del b
