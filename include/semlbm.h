@@ -33,7 +33,8 @@
  *   SLBM_UNFUSED=1        slbm_set_mesh: step with the separate element and node kernels
  *   SLBM_FUSED=1          slbm_set_mesh: step with the fused element kernels wherever the
  *                         mesh allows them (by default not for meshes over 2^20 local
- *                         nodes)
+ *                         nodes); a batch still steps a group over 2^20 local nodes with
+ *                         the unfused kernels
  *   SLBM_NO_GRAPH=1       slbm_bind / slbm_batch_create: plain launches, no HIP graphs
  *   SLBM_SERIAL_GROUPS=1  slbm_batch_create: a batch's groups one after another on its
  *                         stream instead of on concurrent streams
