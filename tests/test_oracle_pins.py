@@ -409,17 +409,22 @@ def test_young_cap_keeps_its_angle(theta):
     assert abs(a1 - theta) < 2.0
 
 
-@pytest.mark.parametrize("nu,tau,N,nel", [(0.05, 0.5, 6, 2), (0.01, 0.5, 8, 2), (0.0, 1.5, 8, 2),
-                                           (0.05, 0.5, 4, 4)])
-def test_shear_wave_decays_at_the_set_viscosity(nu, tau, N, nel):
+@pytest.mark.parametrize("dim,nu,tau,N,nel", [(2, 0.05, 0.5, 6, 2), (2, 0.01, 0.5, 8, 2),
+                                               (2, 0.0, 1.5, 8, 2), (2, 0.05, 0.5, 4, 4),
+                                               (3, 0.05, 0.5, 6, 2), (3, 0.0, 1.5, 6, 2)])
+def test_shear_wave_decays_at_the_set_viscosity(dim, nu, tau, N, nel):
     """R12 against the Navier-Stokes limit: at the uniform liquid density mu and the force
-    vanish, and a shear wave u_x = U sin(k y) in a periodic box decays as exp(-nu k^2 t)
-    with nu = tau cs^2 dt.  The measured rate matches the viscosity asked for (nu > 0) or
+    vanish, and a shear wave u_x = U sin(k y) in a periodic box (D2Q9 or D3Q19) decays as
+    exp(-nu k^2 t) with nu = tau cs^2 dt.  The measured rate matches the viscosity asked for (nu > 0) or
     the one tau gives (nu = 0) to 1%; reading omega as 1/tau, or nu as (tau + 1/2) cs^2 dt,
     is off by tens of percent here."""
     L, U = 32.0, 1e-3
-    m = meshes.box2d(nel, nel, N, L, L, periodic=(True, True), name="shear")
-    c = cases.Case("shear", m, cases.LATTICE_D2Q9, x0=(0.0, 0.0), R=1.0, steps=0, nu=nu, tau=tau)
+    if dim == 2:
+        m = meshes.box2d(nel, nel, N, L, L, periodic=(True, True), name="shear")
+    else:
+        m = meshes.box3d(nel, nel, nel, N, (L, L, L), periodic=(True, True, True), name="shear")
+    c = cases.Case("shear", m, cases.LATTICE_D2Q9 if dim == 2 else cases.LATTICE_D3Q19,
+                   x0=(0.0,) * dim, R=1.0, steps=0, nu=nu, tau=tau)
     o = Oracle(c)
     ev, tw, _ = o.lattice()
     y = m.first_copy_coords()[:, 1]
@@ -431,11 +436,12 @@ def test_shear_wave_decays_at_the_set_viscosity(nu, tau, N, nel):
     o.set_f(tw[:, None] * (1.0 + eu / cs2 + eu * eu / (2.0 * cs2 * cs2) - (ux * ux)[None, :] / (2.0 * cs2)))
     sk = np.sin(k * y)
     amp = lambda: float((o.u()[0] * sk).sum() / (sk * sk).sum())
-    o.step(50)
+    n0, n1 = (50, 450) if dim == 2 else (30, 300)
+    o.step(n0)
     a1 = amp()
-    o.step(400)
+    o.step(n1 - n0)
     a2 = amp()
-    measured = -math.log(a2 / a1) / (k * k * 400 * o.dt)
+    measured = -math.log(a2 / a1) / (k * k * (n1 - n0) * o.dt)
     expect = nu if nu > 0.0 else tau * o.dt / 3.0
     assert abs(measured / expect - 1.0) < 1e-2
 
