@@ -273,6 +273,8 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
       flat:     Sec. 3.1, N = 16, 16x8 elements, La = 122, equilibrium caps at 30-150 deg;
       curved:   Sec. 3.2, N = 11, circular wall on a 256-element O-grid, La = 341, equilibrium
                 caps at 30-150 deg;
+      flat-orders: the 60-degree flat-wall cap at N = 16 on 16x8 elements and at N = 8 on
+                32x16 (the same node count), one time step;
       isolated: Sec. 3.3, droplet in a 64x64 box, N = 16 on 4x4 elements and N = 4 on
                 16x16, La = 3.07, 15, 61.5."""
     from synth import cases
@@ -280,13 +282,16 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
         mk = cases.paper_flat if kind == "flat" else cases.paper_curved
         labels = [f"theta {t:g}" for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
         cs = [mk(t) for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
+    elif kind == "flat-orders":
+        labels = ["theta 60 N 16 16x8", "theta 60 N 8 32x16"]
+        cs = [cases.paper_flat(60.0, N=16, nx=16, ny=8), cases.paper_flat(60.0, N=8, nx=32, ny=16)]
     else:
         runs = [(La, N, nel) for N, nel in ((16, 4), (4, 16)) for La in (3.07, 15.0, 61.5)]
         labels = [f"La {La:g} N {N} {nel}x{nel}" for La, N, nel in runs]
         cs = [cases.paper_isolated(La, N, nel) for La, N, nel in runs]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        if kind == "isolated":
+        if kind in ("isolated", "flat-orders"):
             # one time step for the whole set (the smallest automatic one), so that every
             # run reaches the same T / t_eta at its Laplace number, at both orders
             dts = []
@@ -360,7 +365,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=700)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paper", choices=["flat", "curved", "isolated"],
+    ap.add_argument("--paper", choices=["flat", "flat-orders", "curved", "isolated"],
                     help="only the paper's parasitic-current runs of that test (see paper_runs)")
     ap.add_argument("--paper-steps", type=int, default=4300000)
     ap.add_argument("--paper-every", type=int, default=100000)
