@@ -273,13 +273,15 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
       flat:     Sec. 3.1, N = 16, 16x8 elements, La = 122, equilibrium caps at 30-150 deg;
       curved:   Sec. 3.2, N = 11, circular wall on a 256-element O-grid, La = 341, equilibrium
                 caps at 30-150 deg;
+      curved-fine: the same on a 4x finer O-grid (1,024 elements);
       flat-orders: the 60-degree flat-wall cap at N = 16 on 16x8 elements and at N = 8 on
                 32x16 (the same node count), one time step;
       isolated: Sec. 3.3, droplet in a 64x64 box, N = 16 on 4x4 elements and N = 4 on
                 16x16, La = 3.07, 15, 61.5."""
     from synth import cases
-    if kind in ("flat", "curved"):
-        mk = cases.paper_flat if kind == "flat" else cases.paper_curved
+    if kind in ("flat", "curved", "curved-fine"):
+        mk = {"flat": cases.paper_flat, "curved": cases.paper_curved,
+              "curved-fine": lambda t: cases.paper_curved(t, n_az=64, n_rad=16)}[kind]
         labels = [f"theta {t:g}" for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
         cs = [mk(t) for t in (30.0, 60.0, 90.0, 120.0, 150.0)]
     elif kind == "flat-orders":
@@ -309,7 +311,7 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
             solves.append(s)
             dt = s.info().dt
             c.tau = s.info().tau
-            D = 25.6 if kind == "curved" else 32.0
+            D = 25.6 if kind.startswith("curved") else 32.0
             t_eta = c.rho_l * c.nu * D / c.sigma
             meta.append({"N": c.N, "elements": c.mesh.E, "nu": c.nu, "dt": dt, "tau": c.tau,
                          "t_eta": t_eta, "La": c.sigma * D / (c.rho_l * c.nu ** 2)})
@@ -365,7 +367,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=700)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paper", choices=["flat", "flat-orders", "curved", "isolated"],
+    ap.add_argument("--paper", choices=["flat", "flat-orders", "curved", "curved-fine", "isolated"],
                     help="only the paper's parasitic-current runs of that test (see paper_runs)")
     ap.add_argument("--paper-steps", type=int, default=4300000)
     ap.add_argument("--paper-every", type=int, default=100000)
