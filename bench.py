@@ -349,6 +349,56 @@ def paper_runs(P, torch, kind: str, steps: int, every: int):
             "data": "synthetic", "n_gpus": 1, "dtype": "f64"}
 
 
+def measure_workload(P, torch, name: str, steps: int, warmup: int, profile_steps: int,
+                     kernel_reps: int) -> dict:
+    """Node-updates/s of one workload (inputs resident, graph-replayed steps between HIP
+    events) and the roofline point of its dominant kernel: per-kernel shares of a step from
+    HIP events around every launch, then that kernel's launch duration from back-to-back
+    launches replayed from one graph on the solve's stream."""
+    case = make_case(name)
+    m = case.mesh
+    Q, d, Ng, Nl = case.lattice, m.dim, m.n_global, m.n_local
+    stream = torch.cuda.Stream()  # default priority; capturable (not the null stream)
+    with torch.cuda.stream(stream):
+        s = P.Solve(case, stream=stream)
+        s.init_tanh()
+        s.step(warmup)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        s.step(steps)
+        end.record(stream)
+        end.synchronize()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        ke, mass = s.kinetic_energy()
+        prof = s.step_profile(profile_steps)
+        dom = max(prof, key=lambda k: prof[k][0])
+        avg_ms = s.time_kernel(dom, kernel_reps)
+        del s
+    ms_per_step = ms / steps
+    tot, nl = prof[dom]
+    alg = algorithmic_bytes(dom, Q, d, Ng, Nl)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    return {
+        "value": Ng * steps / (ms / 1e3),
+        "ms_per_step": ms_per_step,
+        "config": {"workload": f"{case.name}: " + (case.mesh.name or ""),
+                   "lattice": f"D{d}Q{Q}", "N": m.N, "elements": m.E, "n_global": Ng,
+                   "n_local": Nl, "local_node_updates_per_s": Nl * steps / (ms / 1e3),
+                   "model_bytes_per_step": step_model_bytes(Q, d, Ng, Nl),
+                   "model_GBps": step_model_bytes(Q, d, Ng, Nl) / (ms_per_step * 1e-3) / 1e9,
+                   "ke_max_end": ke, "mass_end": mass, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profiles(name, dom), "avg_launch_us": avg_ms * 1e3,
+                     "launches_timed": kernel_reps,
+                     "avg_launch_us_in_step": tot / max(nl, 1) * 1e3,
+                     "algorithmic_bytes_per_launch": alg,
+                     "kernel_ms_per_step": {k: v[0] / profile_steps for k, v in prof.items()}},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,6 +417,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=700)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-scale", action="store_true",
+                    help="skip the c2-XL roofline point of the default (c2, with serving) line")
     ap.add_argument("--paper", choices=["flat", "flat-orders", "curved", "curved-fine", "isolated"],
                     help="only the paper's parasitic-current runs of that test (see paper_runs)")
     ap.add_argument("--paper-steps", type=int, default=4300000)
@@ -406,62 +458,33 @@ def main():
                     "config": {"workload": "c5 (reduced request count and step cap)"}})
         print(json.dumps(out))
         return
-    case = make_case(args.workload)
-    m = case.mesh
-    Q, d, Ng, Nl = case.lattice, m.dim, m.n_global, m.n_local
-    stream = torch.cuda.Stream()  # default priority; capturable (not the null stream)
-    with torch.cuda.stream(stream):
-        s = P.Solve(case, stream=stream)
-        s.init_tanh()
-        s.step(args.warmup)
-        torch.cuda.synchronize()
-        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        s.step(args.steps)
-        end.record(stream)
-        end.synchronize()
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(end)
-        ke, mass = s.kinetic_energy()
-        # per-kernel shares of a step: HIP events around every launch of the step sequence
-        prof = s.step_profile(args.profile_steps)
-        dom = max(prof, key=lambda k: prof[k][0])
-        # the dominant kernel's launch duration: back-to-back launches replayed from one
-        # graph on the solve's stream, bracketed by a HIP event pair
-        avg_ms = s.time_kernel(dom, args.kernel_reps)
-    ms_per_step = ms / args.steps
-    value = Ng * args.steps / (ms / 1e3)
-    tot, nl = prof[dom]
-    alg = algorithmic_bytes(dom, Q, d, Ng, Nl)
-    achieved = alg / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(args.workload, dom)
+    r = measure_workload(P, torch, args.workload, args.steps, args.warmup, args.profile_steps,
+                         args.kernel_reps)
     out = {
         "metric": "FP64 node-updates/s per step",
-        "value": value,
+        "value": r["value"],
         "unit": "node-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{case.name}: " + (case.mesh.name or ""),
-                   "lattice": f"D{d}Q{Q}", "N": m.N, "elements": m.E, "n_global": Ng,
-                   "n_local": Nl, "local_node_updates_per_s": Nl * args.steps / (ms / 1e3),
-                   "model_bytes_per_step": step_model_bytes(Q, d, Ng, Nl),
-                   "model_GBps": step_model_bytes(Q, d, Ng, Nl) / (ms_per_step * 1e-3) / 1e9,
-                   "ke_max_end": ke, "mass_end": mass, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_us": avg_ms * 1e3,
-                     "launches_timed": args.kernel_reps,
-                     "avg_launch_us_in_step": tot / max(nl, 1) * 1e3,
-                     "algorithmic_bytes_per_launch": alg,
-                     "kernel_ms_per_step": {k: v[0] / args.profile_steps for k, v in prof.items()}},
+        "config": r["config"],
+        "roofline": r["roofline"],
     }
+    if args.workload == "c2" and not args.no_serving and not args.no_hbm_scale:
+        # the same measurement on c2-XL, whose working set is HBM-resident (c2 is latency
+        # bound): the HBM roofline point of the step kernels
+        x = measure_workload(P, torch, "c2xl", 100, 10, 3, 20)
+        out["hbm_scale"] = {"workload": x["config"]["workload"], "node_updates_per_s": x["value"],
+                            "ms_per_step": x["ms_per_step"], "n_global": x["config"]["n_global"],
+                            "roofline": {k: x["roofline"][k] for k in
+                                         ("bound", "kernel", "achieved", "peak", "unit", "frac",
+                                          "traffic", "avg_launch_us", "algorithmic_bytes_per_launch")}}
     if not args.no_serving and args.workload == "c2":
         if args.batch_members > 0:
             out["batch"] = batch_bench(P, torch, args.batch_members, args.batch_steps)
