@@ -497,6 +497,12 @@ extern "C" slbm_status slbm_batch_step(slbm_batch *b, int64_t n) {
         if (b->autotune && (done = b->tune_pending(n)) < 0) return SLBM_EDEVICE;
         if (b->run(n - done)) return SLBM_EDEVICE;
         for (slbm_ctx *c : b->members) c->step += n;
+        // every unfused step leaves the Laplacian partials of its last stage's input behind,
+        // also after a state upload cleared the flag since the rebuild
+        for (auto &g : b->groups)
+            if (!g.fused)
+                for (int i : g.idx)
+                    if (b->members[i]->fused) b->members[i]->rl_stale = true;
         return SLBM_OK;
     });
 }

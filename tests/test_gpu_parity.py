@@ -686,3 +686,43 @@ def test_batch_large_group_steps_unfused_same_bits(P):
         for s, r in zip(solves[1:], ref40[1:]):
             assert np.array_equal(s.get_state()[0], r)
         del b
+
+
+def test_batch_unfused_group_after_state_upload_keeps_partials_fresh(P):
+    """A fused-path member of an unfused batch group whose state is uploaded while it is in
+    the batch (set_state clears the stale-partials mark): the batched steps after the upload
+    leave the Laplacian partials of their last stage's input again, so the member must still
+    recompute them before it steps alone.  Checked bit for bit against the solve stepped
+    alone from the same uploaded state."""
+    import torch
+    mk = lambda seed: cases.small_flat(60.0, nx=96, ny=96, N=6, jitter=0.2, seed=seed,
+                                       Lx=384.0, Ly=384.0, R=60.0)
+    cs = [mk(sd) for sd in (51, 52, 53)]
+    assert sum(c.mesh.n_local for c in cs) > 1 << 20 >= cs[0].mesh.n_local
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        a = P.Solve(cs[0], stream=stream)
+        a.init_tanh()
+        a.step(7)
+        f7, _ = a.get_state()
+        a.step(5)
+        ref12 = a.get_state()[0]
+        a.step(6)
+        ref18 = a.get_state()[0]
+        del a
+        solves = []
+        b = P.Batch(stream)
+        for c in cs:
+            s = P.Solve(c, stream=stream)
+            s.init_tanh()
+            solves.append(s)
+            b.add(s)
+        b.step(3)
+        assert [g["fused"] for g in b.shapes()] == [False]
+        solves[0].set_state(f7, 7)  # upload while a member of the unfused group
+        b.step(5)
+        assert np.array_equal(solves[0].get_state()[0], ref12)
+        b.remove(solves[0])
+        solves[0].step(6)  # alone: fused, from recomputed partials
+        assert np.array_equal(solves[0].get_state()[0], ref18)
+        del b

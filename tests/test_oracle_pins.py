@@ -164,6 +164,33 @@ def test_collision_conserves_mass_and_momentum(mk):
     assert np.abs(Pi - Pi_eq - corr).max() < 1e-14
 
 
+@pytest.mark.parametrize("mk", [cases.small_flat, cases.small_box3d])
+def test_kinetic_energy_and_mass_of_a_known_equilibrium(mk):
+    # Sec. 3.3 defines KE_max = 0.5 rho |u|^2 (largest over the nodes).  An equilibrium
+    # state (A.2) at a known non-uniform rho0(x), u0(x) has exactly the moments rho0 and
+    # rho0 u0 (Eqs. 10-11) on a lattice whose moments are pinned above, so the query must
+    # return max 0.5 rho0 |u0|^2 and the mass sum M_A rho0 (M_A pinned against the area).
+    c = mk()
+    o = Oracle(c)
+    ev, tw, _ = o.lattice()
+    d = c.dim
+    e = ev[:, :d]
+    k = np.arange(o.Ng)
+    rho0 = 0.6 + 0.3 * np.sin(0.37 * k)
+    u0 = np.stack([0.02 * np.cos(0.11 * k + 0.3 * a) + 0.01 * a for a in range(d)])
+    eu = e @ u0
+    f = rho0 * tw[:, None] * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (u0 * u0).sum(0))
+    o.set_f(f)
+    ke, mass = o.diag()
+    ke_want = (0.5 * rho0 * (u0 * u0).sum(0)).max()
+    assert abs(ke - ke_want) <= 1e-14 * ke_want
+    MA = o.mass_matrix()
+    assert abs(mass - (MA * rho0).sum()) <= 1e-13 * mass
+    # the node that holds the maximum: rho and u there are rho0 and u0
+    g = int(np.argmax(0.5 * rho0 * (u0 * u0).sum(0)))
+    assert abs(o.rho()[g] - rho0[g]) < 1e-15 and np.abs(o.u()[:, g] - u0[:, g]).max() < 1e-15
+
+
 def test_collision_rest_state_is_fixed_point():
     o = Oracle(cases.c1())
     ev, tw, _ = o.lattice()
