@@ -3,9 +3,11 @@
 
 Metric: FP64 node-updates/s.  One node-update advances one unique global GLL node by
 one full time step (collision + three SSP-RK3 streaming stages, all populations).
-Default workload: c2, the D2Q9 sessile droplet on a 60-degree wetting wall (128x64
-domain, 32x16 jittered quads, N=6).  All inputs are seeded and synthetic and resident
-in device memory before the timed region.
+Default workload: c4, the D3Q19 droplet on a sphere (cubed-sphere shell of 24,000 curved
+hexes in a 128^3 box, N=5, about 3.06 M global nodes), the largest single-GPU
+configuration; the default line also carries c2, c2-XL, batched-stepping and serving
+objects and the oracle's CPU rate on c4.  All inputs are seeded and synthetic and
+resident in device memory before the timed region.
 
 Prints one JSON line (see the "value", "roofline" and "cpu_baseline" keys).
 """
@@ -69,17 +71,50 @@ def make_case(name: str):
     return cases.CASES[name]()
 
 
-def cpu_baseline(case, steps: int):
-    from oracle import Oracle
+def host_threads() -> int:
+    """Host threads the oracle may use: this process's CPU share (affinity mask), capped by
+    OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(case, budget_1: float = 15.0, budget_all: float = 6.0):
+    """The C oracle timed on this host on a bounded sample of the workload: whole time
+    steps at one thread until about budget_1 seconds have passed (at least one), then at
+    every host thread this process may use (its OpenMP element and node loops; the sums
+    stay sequential, so the results do not depend on the thread count) for about
+    budget_all seconds.  `value` is the all-thread rate."""
+    from oracle import Oracle, set_threads
     o = Oracle(case)
     o.init_tanh()
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    return dict(value=case.mesh.n_global * steps / dt, unit="node-updates/s", cores=1,
-                kind="oracle",
-                sample=f"{case.name}: {steps} full time steps of the single-threaded C oracle "
-                       f"({dt:.1f} s wall)")
+
+    def timed(budget):
+        n, t0 = 0, time.perf_counter()
+        chunk = 1
+        while True:
+            o.step(chunk)
+            n += chunk
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return n, el
+            # the next chunk ends near the budget (steps cost the same)
+            chunk = max(1, min(4 * chunk, int((budget - el) / (el / n))))
+
+    set_threads(1)
+    n1, dt1 = timed(budget_1)
+    nth = set_threads(host_threads())
+    nn, dtn = timed(budget_all)
+    set_threads(1)
+    ng = case.mesh.n_global
+    return dict(value=ng * nn / dtn, unit="node-updates/s", cores=nth, kind="oracle",
+                sample=f"{case.name}: {n1} full time step(s) of the C oracle at 1 thread "
+                       f"({dt1:.1f} s wall), then {nn} at {nth} threads ({dtn:.1f} s wall)",
+                seconds_per_step=dtn / nn,
+                single_core={"value": ng * n1 / dt1, "cores": 1, "seconds_per_step": dt1 / n1},
+                host_nproc=os.cpu_count(), host_cpu_share=host_threads())
 
 
 def kernels_sha256(csrc: str | None = None) -> str:
@@ -380,6 +415,7 @@ def measure_workload(P, torch, name: str, steps: int, warmup: int, profile_steps
     tot, nl = prof[dom]
     alg = algorithmic_bytes(dom, Q, d, Ng, Nl)
     achieved = alg / (avg_ms * 1e-3) / 1e9
+    step_gbs = step_model_bytes(Q, d, Ng, Nl) / (ms_per_step * 1e-3) / 1e9
     return {
         "value": Ng * steps / (ms / 1e3),
         "ms_per_step": ms_per_step,
@@ -387,10 +423,12 @@ def measure_workload(P, torch, name: str, steps: int, warmup: int, profile_steps
                    "lattice": f"D{d}Q{Q}", "N": m.N, "elements": m.E, "n_global": Ng,
                    "n_local": Nl, "local_node_updates_per_s": Nl * steps / (ms / 1e3),
                    "model_bytes_per_step": step_model_bytes(Q, d, Ng, Nl),
-                   "model_GBps": step_model_bytes(Q, d, Ng, Nl) / (ms_per_step * 1e-3) / 1e9,
+                   "model_GBps": step_gbs,
                    "ke_max_end": ke, "mass_end": mass, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     # the whole step against the step model (model bytes / step time / peak)
+                     "step_achieved": step_gbs, "step_frac": step_gbs / HBM_PEAK_GBS,
                      "traffic": traffic_from_profiles(name, dom), "avg_launch_us": avg_ms * 1e3,
                      "launches_timed": kernel_reps,
                      "avg_launch_us_in_step": tot / max(nl, 1) * 1e3,
@@ -402,9 +440,9 @@ def measure_workload(P, torch, name: str, steps: int, warmup: int, profile_steps
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c2xl"])
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "c2xl"])
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-steps", type=int, default=2000)
     ap.add_argument("--no-serving", action="store_true")
@@ -415,10 +453,11 @@ def main():
                     help="only the batched-stepping measurement (one JSON line)")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--kernel-reps", type=int, default=300)
-    ap.add_argument("--cpu-steps", type=int, default=700)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="oracle time budget at one thread (then 6 s at every host thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-hbm-scale", action="store_true",
-                    help="skip the c2-XL roofline point of the default (c2, with serving) line")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the chosen workload: no c2, c2-XL, batch or serving objects")
     ap.add_argument("--paper", choices=["flat", "flat-orders", "curved", "curved-fine", "isolated"],
                     help="only the paper's parasitic-current runs of that test (see paper_runs)")
     ap.add_argument("--paper-steps", type=int, default=4300000)
@@ -476,21 +515,25 @@ def main():
         "config": r["config"],
         "roofline": r["roofline"],
     }
-    if args.workload == "c2" and not args.no_serving and not args.no_hbm_scale:
-        # the same measurement on c2-XL, whose working set is HBM-resident (c2 is latency
-        # bound): the HBM roofline point of the step kernels
-        x = measure_workload(P, torch, "c2xl", 100, 10, 3, 20)
-        out["hbm_scale"] = {"workload": x["config"]["workload"], "node_updates_per_s": x["value"],
-                            "ms_per_step": x["ms_per_step"], "n_global": x["config"]["n_global"],
-                            "roofline": {k: x["roofline"][k] for k in
-                                         ("bound", "kernel", "achieved", "peak", "unit", "frac",
-                                          "traffic", "avg_launch_us", "algorithmic_bytes_per_launch")}}
-    if not args.no_serving and args.workload == "c2":
-        if args.batch_members > 0:
-            out["batch"] = batch_bench(P, torch, args.batch_members, args.batch_steps)
-        out["serving"] = serving_bench(P, torch, args.serve_requests, args.serve_max_steps)
+    if args.workload == "c4" and not args.no_extras:
+        # extra points beside the headline: c2 (a cache-resident, latency-bound 2-D step) and
+        # c2-XL (a 2-D step whose working set is HBM-resident)
+        for key, name, st, wu, ps, kr in (("c2", "c2", 2000, 100, 100, 300),
+                                          ("hbm_scale", "c2xl", 100, 10, 3, 20)):
+            x = measure_workload(P, torch, name, st, wu, ps, kr)
+            out[key] = {"workload": x["config"]["workload"], "node_updates_per_s": x["value"],
+                        "ms_per_step": x["ms_per_step"], "n_global": x["config"]["n_global"],
+                        "model_bytes_per_step": x["config"]["model_bytes_per_step"],
+                        "roofline": {k: x["roofline"][k] for k in
+                                     ("bound", "kernel", "achieved", "peak", "unit", "frac",
+                                      "step_achieved", "step_frac", "traffic", "avg_launch_us",
+                                      "algorithmic_bytes_per_launch")}}
+        if not args.no_serving:
+            if args.batch_members > 0:
+                out["batch"] = batch_bench(P, torch, args.batch_members, args.batch_steps)
+            out["serving"] = serving_bench(P, torch, args.serve_requests, args.serve_max_steps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(make_case(args.workload), args.cpu_seconds)
     print(json.dumps(out))
 
 

@@ -284,6 +284,11 @@ typedef struct slbm_request {
     double R;
     double noise_amp;
     slbm_wall_geom wall;     /* for the contact angle at retirement */
+    double *state_out;       /* NULL, or a caller-owned host buffer of Q * n_global doubles:
+                              * a request that completes with SLBM_OK copies its final
+                              * f-bar there ([Q][n_global], the caller's global numbering, as
+                              * slbm_get_state) before its result is published.  The caller
+                              * keeps the buffer alive until poll reports the result. */
 } slbm_request;
 
 typedef struct slbm_result {

@@ -49,8 +49,19 @@ def load():
         lib.orc_diag.argtypes = [C.c_void_p, _dp, _dp]
         lib.orc_splitmix64.argtypes = [C.c_uint64]
         lib.orc_splitmix64.restype = C.c_uint64
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_get_threads.restype = C.c_int
+        lib.orc_set_threads(1)
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the oracle's element and node loops (results do not depend on it);
+    returns the count in use."""
+    lib = load()
+    lib.orc_set_threads(int(n))
+    return lib.orc_get_threads()
 
 
 def _d(a):

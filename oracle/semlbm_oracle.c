@@ -44,6 +44,11 @@
  *       tau cs^2 dt; given a viscosity nu > 0, tau = 3 nu / dt.
  *   R16 seeded density noise: rho += a (2U - 1), U from SplitMix64 of (seed xor gid).
  *
+ * Threads: the element loops and the pointwise node loops may run on several host
+ * threads (OpenMP, orc_set_threads; one thread unless set).  Their iterations write
+ * disjoint entries, and every sum over nodes (the direct stiffness summation, the mass)
+ * stays a sequential loop, so the results do not depend on the thread count.
+ *
  * Arithmetic conventions (so that a separately written implementation can follow the
  * same expression trees): sums run in ascending index order starting from 0; the
  * tensor-product contractions with the GLL differentiation matrix use fused
@@ -54,6 +59,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OQ_MAX 19
 
@@ -91,6 +99,23 @@ typedef struct {
     double *rl;  /* [Q*Nl] */
     double *tmp; /* [Q*Ng] */
 } orc;
+
+/* host threads of the parallel loops (1 by default, see the header note) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------------------ */
 /* GLL nodes, weights and differentiation matrix (Deville, Fischer & Mund, ch. 2)       */
@@ -446,9 +471,10 @@ static void dss(const orc *o, const double *r, double *R) {
 void orc_lap(orc *o, const double *rho, double *lap, int with_wall) {
     int nloc = o->nloc, dim = o->dim;
     double *r = o->rl;
-    double re[4096], d[3][4096], v[3][4096];
     double sq = sqrt(2.0 * o->beta / o->kappa);
+#pragma omp parallel for schedule(static)
     for (long e = 0; e < o->E; ++e) {
+        double re[4096], d[3][4096], v[3][4096];
         for (int n = 0; n < nloc; ++n) re[n] = rho[o->gid[e * nloc + n]];
         for (int a = 0; a < dim; ++a)
             for (int n = 0; n < nloc; ++n) d[a][n] = dref(o, re, n, a);
@@ -474,6 +500,7 @@ void orc_lap(orc *o, const double *rho, double *lap, int with_wall) {
             r[l] += wsc * fabs((rh - o->rho_l) * (rh - o->rho_v));
         }
     dss(o, r, lap);
+#pragma omp parallel for schedule(static)
     for (long g = 0; g < o->Ng; ++g) lap[g] = lap[g] * o->Minv[g];
 }
 
@@ -481,6 +508,7 @@ void orc_lap(orc *o, const double *rho, double *lap, int with_wall) {
 void orc_mu(orc *o, const double *rho, double *mu) {
     orc_lap(o, rho, mu, 1);
     double rl = o->rho_l, rv = o->rho_v;
+#pragma omp parallel for schedule(static)
     for (long g = 0; g < o->Ng; ++g) {
         double p = rho[g];
         double mu0 = 2.0 * o->beta * (p - rl) * (p - rv) * (2.0 * p - rl - rv);
@@ -491,9 +519,10 @@ void orc_mu(orc *o, const double *rho, double *mu) {
 /* mass-weighted average of element gradients (R8): grad[c*Ng + g] */
 void orc_avg_grad(orc *o, const double *phi, double *grad) {
     int nloc = o->nloc, dim = o->dim;
-    double pe[4096], d[3][4096];
     for (int c = 0; c < dim; ++c) {
+#pragma omp parallel for schedule(static)
         for (long e = 0; e < o->E; ++e) {
+            double pe[4096], d[3][4096];
             for (int n = 0; n < nloc; ++n) pe[n] = phi[o->gid[e * nloc + n]];
             for (int a = 0; a < dim; ++a)
                 for (int n = 0; n < nloc; ++n) d[a][n] = dref(o, pe, n, a);
@@ -505,6 +534,7 @@ void orc_avg_grad(orc *o, const double *phi, double *grad) {
             }
         }
         dss(o, o->rl, grad + c * o->Ng);
+#pragma omp parallel for schedule(static)
         for (long g = 0; g < o->Ng; ++g) grad[c * o->Ng + g] = grad[c * o->Ng + g] * o->Minv[g];
     }
 }
@@ -514,8 +544,9 @@ void orc_avg_grad(orc *o, const double *phi, double *grad) {
 void orc_stream_op(orc *o, const double *g, const double *rho, const double *mu, double *L) {
     int nloc = o->nloc, dim = o->dim, Q = o->Q;
     long Ng = o->Ng, Nl = o->Nl;
-    double he[4096], me[4096], dh[3][4096], dm[3][4096];
+#pragma omp parallel for schedule(static)
     for (long e = 0; e < o->E; ++e) {
+        double he[4096], me[4096], dh[3][4096], dm[3][4096];
         const int *gd = o->gid + e * nloc;
         if (o->mode == 0) {
             for (int n = 0; n < nloc; ++n) me[n] = mu[gd[n]];
@@ -561,12 +592,14 @@ void orc_stream_op(orc *o, const double *g, const double *rho, const double *mu,
     memset(L, 0, sizeof(double) * Ng); /* rest population does not stream */
     for (int q = 1; q < Q; ++q) {
         dss(o, o->rl + (size_t)q * Nl, L + q * Ng);
+#pragma omp parallel for schedule(static)
         for (long gg = 0; gg < Ng; ++gg) L[q * Ng + gg] = L[q * Ng + gg] * o->Minv[gg];
     }
 }
 
 /* density, Eq. (10) */
 void orc_density(const orc *o, const double *f, double *rho) {
+#pragma omp parallel for schedule(static)
     for (long g = 0; g < o->Ng; ++g) {
         double s = 0.0;
         for (int q = 0; q < o->Q; ++q) s += f[q * o->Ng + g];
@@ -581,6 +614,7 @@ void orc_collide(const orc *o, const double *f, const double *rho, const double 
     int dim = o->dim, Q = o->Q;
     long Ng = o->Ng;
     double cs2 = 1.0 / 3.0, dt = o->dt, om = o->omega;
+#pragma omp parallel for schedule(static)
     for (long g = 0; g < Ng; ++g) {
         double p = rho[g], u[3] = {0, 0, 0}, F[3] = {0, 0, 0};
         for (int c = 0; c < dim; ++c) {
@@ -613,6 +647,7 @@ static void rk_combine(const orc *o, int stage, const double *g0, const double *
                        const double *L, double *gout) {
     long n = (long)o->Q * o->Ng;
     double dt = o->dt;
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
         double x = g[i] + dt * L[i];
         if (stage == 1) gout[i] = x;

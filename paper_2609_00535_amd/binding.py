@@ -65,7 +65,8 @@ class Request(C.Structure):
     _fields_ = [("params", Params), ("E", C.c_int64), ("xyz", C.c_void_p), ("gid", C.c_void_p),
                 ("n_global", C.c_int64), ("n_wall_faces", C.c_int64), ("wall_face", C.c_void_p),
                 ("wall_cos", C.c_void_p), ("wall_ub", C.c_void_p), ("x0", C.c_double * 3),
-                ("R", C.c_double), ("noise_amp", C.c_double), ("wall", WallGeom)]
+                ("R", C.c_double), ("noise_amp", C.c_double), ("wall", WallGeom),
+                ("state_out", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -416,9 +417,11 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, case, noise: float | None = None, ke_limit: float = 0.0) -> int:
+    def submit(self, case, noise: float | None = None, ke_limit: float = 0.0,
+               keep_state: bool = False) -> int:
         """Queue a solve of ``case``; ``ke_limit`` > 0 marks it diverged (SLBM_EDIVERGED)
-        at the first check with KE_max above it (default limit 1)."""
+        at the first check with KE_max above it (default limit 1).  With ``keep_state`` the
+        final f-bar of a completed request is returned by :meth:`state` ([Q][n_global])."""
         m = case.mesh
         r = Request()
         r.params = make_params(case, 0, ke_limit)
@@ -440,11 +443,19 @@ class Server:
         r.R = float(case.R)
         r.noise_amp = float(case.noise if noise is None else noise)
         r.wall = wall_geom(case.wall_geom)
+        out = np.zeros((case.lattice, m.n_global)) if keep_state else None
+        r.state_out = out.ctypes.data if keep_state else None
         rid = C.c_uint64()
         st = lib().slbm_server_submit(self._h, C.byref(r), C.byref(rid))
         if st != SLBM_OK:
             raise SLBMError(st, "server_submit")
+        if keep_state:
+            self._keep[rid.value] = out
         return rid.value
+
+    def state(self, rid):
+        """Final f-bar of a request submitted with ``keep_state`` (valid once polled done)."""
+        return self._keep[int(rid)]
 
     def tick(self) -> int:
         pend = C.c_int()

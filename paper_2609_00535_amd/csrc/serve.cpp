@@ -817,6 +817,11 @@ struct slbm_server {
             double th = NAN;
             r->job_status = slbm_contact_angle(r->ctx, &r->r.wall, &th);
             r->res.theta_deg = r->job_status == SLBM_OK ? th : NAN;
+            if (r->r.state_out) {
+                int64_t st = 0;
+                const slbm_status s2 = slbm_get_state(r->ctx, r->r.state_out, &st);
+                if (r->job_status == SLBM_OK) r->job_status = s2;
+            }
         }
     }
 

@@ -171,6 +171,26 @@ def small_box3d(N: int = 3, n: int = 3, periodic=(True, True, True), jitter: flo
                 seed=15, steps=20)
 
 
+def moving_walls(dim: int = 2) -> Case:
+    """Droplet cap on a wetting wall that slides, under a lid that slides the other way
+    (tangential wall velocities u_b of Eq. (9)): 2-D, a jittered 64x32 box of 8x4 quads at
+    N = 5; 3-D, a jittered 24^3 box of 3^3 hexes at N = 3, periodic in x and y."""
+    cb = math.cos(math.radians(70.0))
+    if dim == 2:
+        m = meshes.box2d(8, 4, 5, 64.0, 32.0, periodic=(False, False), jitter=0.2, seed=16,
+                         cos_theta={"bottom": cb}, ub={"bottom": (-0.004, 0.0), "top": (0.01, 0.0)},
+                         name="moving_walls")
+        return Case("moving_walls", m, LATTICE_D2Q9, x0=(32.0, -12.0 * cb), R=12.0, seed=16,
+                    steps=200, wall_geom=dict(kind="plane", point=(0.0, 0.0), normal=(0.0, -1.0)),
+                    theta_deg=70.0)
+    m = meshes.box3d(3, 3, 3, 3, (24.0, 24.0, 24.0), periodic=(True, True, False), jitter=0.1,
+                     seed=17, cos_theta={"z-": cb},
+                     ub={"z-": (-0.004, 0.002, 0.0), "z+": (0.01, 0.005, 0.0)}, name="moving_walls3d")
+    return Case("moving_walls3d", m, LATTICE_D3Q19, x0=(12.0, 12.0, -8.0 * cb), R=8.0, seed=17,
+                steps=20, wall_geom=dict(kind="plane", point=(0.0, 0.0, 0.0), normal=(0.0, 0.0, -1.0)),
+                theta_deg=70.0)
+
+
 def walled_droplet(nx: int = 8, N: int = 4, L: float = 64.0, R: float = 16.0,
                    delta: float = 6.0) -> Case:
     """Isolated droplet in a closed square box (non-wetting outer walls): the

@@ -325,12 +325,13 @@ def _trilinear(v, s, t, u):
 
 def box3d(nx: int, ny: int, nz: int, N: int, L=(1.0, 1.0, 1.0), *,
           periodic=(True, True, True), jitter: float = 0.0, seed: int = 0,
-          cos_theta=None, origin=(0.0, 0.0, 0.0), name: str = "") -> Mesh:
+          cos_theta=None, ub=None, origin=(0.0, 0.0, 0.0), name: str = "") -> Mesh:
     """Cuboid of nx x ny x nz trilinear hexes; walls on non-periodic sides.
 
-    ``cos_theta`` keys: 'x-', 'x+', 'y-', 'y+', 'z-', 'z+'.
+    ``cos_theta`` and ``ub`` (wall velocity) keys: 'x-', 'x+', 'y-', 'y+', 'z-', 'z+'.
     """
     cos_theta = dict(cos_theta or {})
+    ub = dict(ub or {})
     nel = (nx, ny, nz)
     h = [L[a] / nel[a] for a in range(3)]
     shape = (nx + 1, ny + 1, nz + 1)
@@ -383,7 +384,7 @@ def box3d(nx: int, ny: int, nz: int, N: int, L=(1.0, 1.0, 1.0), *,
                 Ig, Jg, Kg = ex * N + li, ey * N + lj, ez * N + lk
                 xyz[e] = X[Ig, Jg, Kg]
                 gid[e] = (Ig % nG[0]) + nG[0] * ((Jg % nG[1]) + nG[1] * (Kg % nG[2]))
-    faces, cth = [], []
+    faces, cth, ubs = [], [], []
     for a, (lo, hi) in enumerate((("x-", "x+"), ("y-", "y+"), ("z-", "z+"))):
         if periodic[a]:
             continue
@@ -395,12 +396,15 @@ def box3d(nx: int, ny: int, nz: int, N: int, L=(1.0, 1.0, 1.0), *,
                     if ec == 0:
                         faces.append((e, 2 * a))
                         cth.append(float(cos_theta.get(lo, 0.0)))
+                        ubs.append(tuple(ub.get(lo, (0.0, 0.0, 0.0))))
                     if ec == nel[a] - 1:
                         faces.append((e, 2 * a + 1))
                         cth.append(float(cos_theta.get(hi, 0.0)))
+                        ubs.append(tuple(ub.get(hi, (0.0, 0.0, 0.0))))
     m = Mesh(3, N, xyz, gid.astype(np.int32), int(np.prod(nG)),
              np.array(faces, dtype=np.int32).reshape(-1, 2),
-             np.array(cth, dtype=np.float64), np.zeros((len(faces), 3)), name=name,
+             np.array(cth, dtype=np.float64), np.array(ubs, dtype=np.float64).reshape(-1, 3),
+             name=name,
              meta=dict(kind="box3d", nel=nel, L=L, periodic=periodic, origin=origin,
                        jitter=jitter))
     m.check()

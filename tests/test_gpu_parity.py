@@ -71,6 +71,38 @@ def test_operator_parity(P, mk):
     assert rel(L_g, L_o) <= 1e-13, rel(L_g, L_o)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_moving_wall_operator_and_step_parity(P, dim):
+    """Eq. (9) with wall velocities u_b != 0 (a sliding wetting wall and a lid sliding the
+    other way, tangential components in every direction): the streaming operator alone,
+    then full steps (100 in 2-D, 20 in 3-D) against the oracle."""
+    c = cases.moving_walls(dim)
+    assert np.abs(c.mesh.wall_ub).max() > 0.0
+    s, o = _pair(c, P)
+    rng = np.random.default_rng(12)
+    X = c.mesh.first_copy_coords()
+    r = np.linalg.norm(X - np.asarray(c.x0)[None, : c.dim], axis=1)
+    rho = 0.55 - 0.45 * np.tanh(2 * (r - c.R) / c.delta) + 1e-3 * rng.standard_normal(o.Ng)
+    ev, tw, _ = o.lattice()
+    e = ev[:, : c.dim]
+    u = 0.01 * rng.standard_normal((c.dim, o.Ng))
+    eu = e @ u
+    f = rho * tw[:, None] * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (u * u).sum(0))
+    mu = o.mu(rho)
+    L_o, L_g = o.stream_op(f, rho, mu), s.op_stream(f, rho, mu)
+    assert rel(L_g, L_o) <= 1e-13, rel(L_g, L_o)
+    # the wall velocity terms alone: the same operator with resting walls differs
+    c0 = cases.moving_walls(dim)
+    c0.mesh.wall_ub[:] = 0.0
+    from oracle import Oracle
+    assert rel(Oracle(c0).stream_op(f, rho, mu), L_o) > 1e-6
+    steps = 100 if dim == 2 else 20
+    s, o = _run_pair(c, P, steps)
+    er, eu_ = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] {c.name} {steps} steps: rel rho {er:.3e} rel u {eu_:.3e}", flush=True)
+    assert er <= TOL and eu_ <= TOL
+
+
 def _run_pair(c, P, steps):
     s, o = _pair(c, P)
     s.init_tanh()
@@ -105,11 +137,12 @@ def test_walls_and_3d_parity(P, mk, steps):
 
 
 def test_c2_full_size(P):
-    """c2 at full size (32x16 jittered quads, N=6, 60 deg wetting wall), 200 steps."""
+    """c2 at full size (32x16 jittered quads, N=6, 60 deg wetting wall), 1000 steps (the
+    step count of the parity target; about 20 s of oracle time)."""
     c = cases.c2()
-    s, o = _run_pair(c, P, 200)
+    s, o = _run_pair(c, P, 1000)
     er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
-    print(f"[parity] c2 200 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    print(f"[parity] c2 1000 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
     assert er <= TOL and eu <= TOL
 
 
@@ -124,11 +157,12 @@ def test_c2xl_full_size(P):
 
 
 def test_c3_full_size(P):
-    """c3 at full size (O-grid of 2048 curved quads, N=8, cylinder wall), 10 steps."""
+    """c3 at full size (O-grid of 2048 curved quads, N=8, cylinder wall), 200 steps
+    (about 40 s of oracle time)."""
     c = cases.c3()
-    s, o = _run_pair(c, P, 10)
+    s, o = _run_pair(c, P, 200)
     er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
-    print(f"[parity] c3 10 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    print(f"[parity] c3 200 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
     assert er <= TOL and eu <= TOL
 
 
@@ -240,6 +274,47 @@ def test_contact_angle_gpu_matches_oracle(P):
     s = P.Solve(c)
     s.init_tanh()
     assert abs(s.contact_angle() - 135.0) < 0.1
+
+
+def test_served_results_match_oracle(P):
+    """Served requests against the oracle: the smallest requests of the serving mix of each
+    geometry and order (flat and cylinder walls, N = 4, 6, 8), served with fewer slots than
+    requests so that admissions happen while others run.  Each completed request's final
+    state (rho, u), KE_max and contact angle equal the oracle's after the same number of
+    steps (1e-11 on rho and u)."""
+    from oracle import Oracle, contact_angle
+    reqs = cases.request_stream(256, seed=5)
+    pick, seen = [], set()
+    for r in sorted(reqs, key=lambda r: (r["nx"] * r["ny"], r["id"])):
+        key = (r["geom"], r["N"])
+        if r["nx"] * r["ny"] == 64 and key not in seen:
+            seen.add(key)
+            pick.append(r)
+    assert len(pick) == 6, [(r["geom"], r["N"]) for r in pick]
+    cs = [cases.request_case(r) for r in pick]
+    srv = P.Server(arena_bytes=256 << 20, max_slots=3, check_every=100, ke_stop=1e-30,
+                   max_steps=300)
+    ids = [srv.submit(c, keep_state=True) for c in cs]
+    srv.drain()
+    for rid, c in zip(ids, cs):
+        res = srv.poll(rid)
+        assert res.status == 0 and res.steps == 300
+        o = Oracle(c)
+        o.init_tanh()
+        o.step(res.steps)
+        f = srv.state(rid)
+        rho_g = f.sum(0)
+        ev, _, _ = o.lattice()
+        u_g = (ev[:, : c.dim].T @ f) / rho_g
+        er, eu = rel(rho_g, o.rho()), rel(u_g, o.u())
+        ko, _ = o.diag()
+        a_o, _, _ = contact_angle(c.mesh, o.rho(), c.rho_l, c.rho_v, c.delta, c.wall_geom)
+        print(f"[serve-parity] {c.name} {c.mesh.meta.get('kind', '')} N={c.N}: rel rho {er:.3e} "
+              f"rel u {eu:.3e} KE {res.ke_max:.6e}/{ko:.6e} angle {res.theta_deg:.6f}/{a_o:.6f}",
+              flush=True)
+        assert er <= TOL and eu <= TOL
+        assert abs(res.ke_max - ko) <= 1e-9 * ko
+        assert abs(res.theta_deg - a_o) < 1e-6
 
 
 def test_server_results_equal_alone(P):

@@ -534,3 +534,20 @@ def test_walled_droplet_reaches_residual_floor():
     assert kes[-1] < 1e-20, kes
     assert kes[-1] < 1e-10 * kes[0]
     assert abs(m1 - m0) < 1e-13 * m0
+
+
+def test_oracle_threads_change_no_bit():
+    """The oracle's OpenMP loops write disjoint entries and its sums stay sequential, so the
+    state after a few steps is the same bit for bit at 1 and 4 host threads (2-D walls and
+    3-D curved hexes)."""
+    from oracle import set_threads
+    for mk, n in ((cases.small_flat, 20), (cases.small_sphere, 3)):
+        out = []
+        for th in (1, 4):
+            set_threads(th)
+            o = Oracle(mk())
+            o.init_tanh()
+            o.step(n)
+            out.append(o.get_f())
+        set_threads(1)
+        assert np.array_equal(out[0], out[1])
