@@ -308,13 +308,19 @@ def test_served_results_match_oracle(P):
         u_g = (ev[:, : c.dim].T @ f) / rho_g
         er, eu = rel(rho_g, o.rho()), rel(u_g, o.u())
         ko, _ = o.diag()
-        a_o, _, _ = contact_angle(c.mesh, o.rho(), c.rho_l, c.rho_v, c.delta, c.wall_geom)
+        try:
+            a_o, _, _ = contact_angle(c.mesh, o.rho(), c.rho_l, c.rho_v, c.delta, c.wall_geom)
+        except ValueError:  # a cap too low for the fit (every crossing within 2 delta of the wall)
+            a_o = float("nan")
         print(f"[serve-parity] {c.name} {c.mesh.meta.get('kind', '')} N={c.N}: rel rho {er:.3e} "
               f"rel u {eu:.3e} KE {res.ke_max:.6e}/{ko:.6e} angle {res.theta_deg:.6f}/{a_o:.6f}",
               flush=True)
         assert er <= TOL and eu <= TOL
         assert abs(res.ke_max - ko) <= 1e-9 * ko
-        assert abs(res.theta_deg - a_o) < 1e-6
+        if np.isnan(a_o):  # the library's measurement fails the same way: no angle
+            assert np.isnan(res.theta_deg)
+        else:
+            assert abs(res.theta_deg - a_o) < 1e-6
 
 
 def test_server_results_equal_alone(P):
