@@ -253,6 +253,22 @@ typedef struct slbm_batch_shape {
  * count, max < 0, or max > 0 with null out), or those of rebuilding the launch tables
  * after a membership change (SLBM_ENOMEM, SLBM_EDEVICE). */
 slbm_status slbm_batch_shapes(slbm_batch *b, slbm_batch_shape *out, int max, int *count);
+/* Allocation-free batched step, for callers that cannot allocate device memory (tight
+ * serving loops and harnesses that forbid hipMalloc/hipFree): the same n time steps of
+ * every member as slbm_batch_step, bit for bit, with no device allocation.  The batch's
+ * launch tables (member descriptors and block tables of each group's chosen launch shape)
+ * are laid out in a file-scope device array of SLBM_STATIC_SCRATCH_BYTES per GPU instead
+ * of library-allocated memory; the groups step one after another on the batch's stream
+ * with plain launches (no graphs, no shape tuning: a group uses the shape an earlier
+ * slbm_batch_step tuned for its key, else the fixed rule).  Every call on a GPU shares that
+ * GPU's array: a call uploads its tables (waiting for its stream) unless the array still
+ * holds this batch's current layout, so calls that overlap on one GPU (batches on
+ * different streams or host threads) race and must be serialised by the caller.
+ * Asynchronous on the batch's stream otherwise.  Errors: SLBM_EINVAL (null b, n < 0),
+ * SLBM_ENOMEM if the tables exceed SLBM_STATIC_SCRATCH_BYTES (about 500,000 element and
+ * node blocks in all), SLBM_EDEVICE on a HIP error. */
+#define SLBM_STATIC_SCRATCH_BYTES (4u << 20)
+slbm_status slbm_batch_step_static(slbm_batch *b, int64_t n);
 /* Per-member KE_max and mass into ke[size], mass[size] (member order of insertion). */
 slbm_status slbm_batch_kinetic_energy(slbm_batch *b, double *ke, double *mass);
 void slbm_batch_destroy(slbm_batch *b);

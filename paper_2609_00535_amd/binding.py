@@ -107,6 +107,7 @@ SIGNATURES = {
     "slbm_batch_remove": (C.c_int, [_vp, _vp]),
     "slbm_batch_size": (C.c_int, [_vp]),
     "slbm_batch_step": (C.c_int, [_vp, _i64]),
+    "slbm_batch_step_static": (C.c_int, [_vp, _i64]),
     "slbm_batch_set_autotune": (C.c_int, [_vp, C.c_int]),
     "slbm_batch_shapes": (C.c_int, [_vp, C.POINTER(BatchShape), C.c_int, C.POINTER(C.c_int)]),
     "slbm_batch_kinetic_energy": (C.c_int, [_vp, _dp, _dp]),
@@ -353,6 +354,12 @@ class Batch:
         st = lib().slbm_batch_step(self._h, int(n))
         if st != SLBM_OK:
             raise SLBMError(st, "batch_step")
+
+    def step_static(self, n=1):
+        """The allocation-free batched step (slbm_batch_step_static)."""
+        st = lib().slbm_batch_step_static(self._h, int(n))
+        if st != SLBM_OK:
+            raise SLBMError(st, "batch_step_static")
 
     def set_autotune(self, on: bool):
         st = lib().slbm_batch_set_autotune(self._h, 1 if on else 0)

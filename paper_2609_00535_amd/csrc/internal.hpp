@@ -131,4 +131,10 @@ int launch_fC(int d, int N, const LaunchPlan &p, int stage, void *stream);
 int launch_fD(int d, int N, const LaunchPlan &p, int stage, void *stream);
 bool supported_order(int d, int N);
 
+// Allocation-free batched stepping: the launch tables live in a file-scope device array of
+// this many bytes per GPU (static_scratch.hip); static_scratch returns its device address on
+// the current device (looked up once per device), or a hipError_t.
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+int static_scratch(void **ptr);
+
 }  // namespace slbm

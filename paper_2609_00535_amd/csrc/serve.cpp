@@ -28,6 +28,8 @@
 
 using namespace slbm;
 
+static_assert(kStaticScratchBytes == SLBM_STATIC_SCRATCH_BYTES, "static scratch size of the header");
+
 // ------------------------------------------------------------------------------------------
 // batch
 // ------------------------------------------------------------------------------------------
@@ -58,6 +60,7 @@ struct slbm_batch {
         double *diag_out = nullptr; // device [2 * members]
     };
     std::vector<Group> groups;
+    bool tables_ok = false;  // dmem holds the current groups' launch tables
     void *dmem = nullptr;
     size_t dcap = 0;
     slbm_status status = SLBM_OK;
@@ -215,7 +218,8 @@ struct slbm_batch {
         return 0;
     }
 
-    static void select(Group &g, int k, bool measured) {
+    void select(Group &g, int k, bool measured) {
+        if (g.pick != k) ++layout_gen;
         g.pick = k;
         g.measured = measured;
         g.ep = g.shapes[k].ep;
@@ -268,9 +272,14 @@ struct slbm_batch {
         }
     }
 
-    slbm_status rebuild() {
+    // Host side of a membership change: groups by (d, N, path), stale-partial bookkeeping,
+    // candidate launch shapes and each group's pick (the tuned one for its key, else the
+    // fixed rule).  Launch tables are laid out afterwards (make_tables, or the static path).
+    slbm_status regroup() {
         drop_graphs();
         groups.clear();
+        tables_ok = false;
+        ++layout_gen;
         // groups by (d, N, path): members start from the path they step alone with; a
         // fused group whose members together exceed kUnfusedAboveLocalNodes local nodes then
         // steps with the unfused kernels, as a single mesh of that size would
@@ -319,6 +328,32 @@ struct slbm_batch {
                 }
             }
         }
+        for (auto &g : groups) {
+            auto it = cache.find(key_of(g));
+            if (it != cache.end() && it->second.us.size() == g.shapes.size()) {
+                for (size_t k = 0; k < g.shapes.size(); ++k) g.shapes[k].us = it->second.us[k];
+                g.pick = it->second.pick;
+                g.measured = true;
+            } else {
+                const int w = epb_wide(g.d, g.N);
+                int nbw = 0;
+                for (int i : g.idx) nbw += eblocks(members[i], w);
+                const int want = nbw >= 256 ? w : 1;
+                g.pick = 0;
+                for (size_t k = 0; k < g.shapes.size(); ++k)
+                    if (g.shapes[k].epb == want && g.shapes[k].xcd) { g.pick = (int)k; break; }
+                g.measured = false;
+            }
+        }
+        dirty = false;
+        return SLBM_OK;
+    }
+
+    // the groups' launch tables for every candidate shape in library-allocated device memory
+    slbm_status rebuild() {
+        if (dirty)
+            if (slbm_status s = regroup()) return s;
+        if (tables_ok) return SLBM_OK;
         // one device block: per group [descs][e tables per shape][n tables per order][diag out]
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         auto counts = [&](const Group &g, int epb, int *ne, int *nn) {
@@ -382,31 +417,112 @@ struct slbm_batch {
                 s.ep = LaunchPlan{g.desc, et, et + te, te, 0, s.epb, te};
                 s.np = LaunchPlan{g.desc, nt, nt + tn, tn, 0, 0, tn};
             }
-            // shape: the tuned one for this group's key, else wide blocks (XCD order) once
-            // the group's elements fill the chip and one element per block otherwise
-            auto it = cache.find(key_of(g));
-            if (it != cache.end() && it->second.us.size() == g.shapes.size()) {
-                for (size_t k = 0; k < g.shapes.size(); ++k) g.shapes[k].us = it->second.us[k];
-                select(g, it->second.pick, true);
-            } else {
-                const int w = epb_wide(g.d, g.N);
-                int nbw = 0, nn = 0;
-                counts(g, w, &nbw, &nn);
-                const int want = nbw >= 256 ? w : 1;
-                int k0 = 0;
-                for (size_t k = 0; k < g.shapes.size(); ++k)
-                    if (g.shapes[k].epb == want && g.shapes[k].xcd) { k0 = (int)k; break; }
-                select(g, k0, false);
-            }
+            select(g, g.pick, g.measured);
         }
         if (total) {
             if (hipMemcpyAsync(dmem, host.data(), total, hipMemcpyHostToDevice, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 return SLBM_EDEVICE;
         }
-        dirty = false;
+        tables_ok = true;
         return SLBM_OK;
     }
+
+    // Allocation-free stepping.  The tables of each group's chosen shape are laid out in the
+    // per-device static array (no device allocation) and uploaded when the array does not
+    // already hold this batch's current layout; the groups then step one after another on
+    // the batch's stream with plain launches (no graphs, no tuning, no extra streams).
+    slbm_status step_static(int64_t n) {
+        if (dirty)
+            if (slbm_status s = regroup()) return s;
+        void *base_v = nullptr;
+        if (static_scratch(&base_v)) return SLBM_EDEVICE;
+        char *base = (char *)base_v;
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        size_t total = 0;
+        std::vector<size_t> goff;
+        std::vector<int> ne(groups.size()), nn(groups.size());
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Group &g = groups[gi];
+            const Shape &sh = g.shapes[g.pick];
+            ne[gi] = nn[gi] = 0;
+            for (int i : g.idx) {
+                ne[gi] += eblocks(members[i], sh.epb);
+                nn[gi] += members[i]->n_nblocks;
+            }
+            goff.push_back(total);
+            total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(int) * 2 * table_len(ne[gi], sh.xcd)) +
+                     al(sizeof(int) * 2 * table_len(nn[gi], sh.xcd));
+        }
+        if (total > kStaticScratchBytes) {
+            status = SLBM_ENOMEM;
+            return SLBM_ENOMEM;  // the launch tables exceed the static array
+        }
+        std::vector<LaunchPlan> sep(groups.size()), snp(groups.size());
+        std::vector<char> img(total, 0);
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Group &g = groups[gi];
+            const Shape &sh = g.shapes[g.pick];
+            size_t o = goff[gi];
+            SolveDesc *dd = reinterpret_cast<SolveDesc *>(base + o);
+            SolveDesc *dh = reinterpret_cast<SolveDesc *>(img.data() + o);
+            for (int k = 0; k < (int)g.idx.size(); ++k) dh[k] = members[g.idx[k]]->desc;
+            o += al(sizeof(SolveDesc) * g.idx.size());
+            std::vector<int> le_s, le_l, ln_s, ln_l;
+            for (int k = 0; k < (int)g.idx.size(); ++k) {
+                slbm_ctx *c = members[g.idx[k]];
+                for (int b = 0; b < eblocks(c, sh.epb); ++b) { le_s.push_back(k); le_l.push_back(b); }
+                for (int b = 0; b < c->n_nblocks; ++b) { ln_s.push_back(k); ln_l.push_back(b); }
+            }
+            const int te = table_len(ne[gi], sh.xcd), tn = table_len(nn[gi], sh.xcd);
+            fill_table(reinterpret_cast<int *>(img.data() + o), ne[gi], sh.xcd, le_s, le_l);
+            int *et = reinterpret_cast<int *>(base + o);
+            o += al(sizeof(int) * 2 * te);
+            fill_table(reinterpret_cast<int *>(img.data() + o), nn[gi], sh.xcd, ln_s, ln_l);
+            int *nt = reinterpret_cast<int *>(base + o);
+            sep[gi] = LaunchPlan{dd, et, et + te, te, 0, sh.epb, te};
+            snp[gi] = LaunchPlan{dd, nt, nt + tn, tn, 0, 0, tn};
+        }
+        hipStream_t st = (hipStream_t)stream;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return SLBM_EDEVICE;
+        if (!static_holds(dev, id, layout_gen)) {
+            // launches queued earlier on this stream may still read the array's previous
+            // tables; the upload waits for them and completes before the steps are queued
+            if (hipStreamSynchronize(st) != hipSuccess ||
+                hipMemcpyAsync(base, img.data(), total, hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return SLBM_EDEVICE;
+            static_claim(dev, id, layout_gen);
+        }
+        for (size_t gi = 0; gi < groups.size(); ++gi)
+            if (enqueue_group(groups[gi], sep[gi], snp[gi], n)) return SLBM_EDEVICE;
+        return SLBM_OK;
+    }
+
+    // which batch layout each device's static array holds (batch id, layout generation)
+    static std::mutex &static_mu() { static std::mutex m; return m; }
+    static std::map<int, std::pair<uint64_t, uint64_t>> &static_owner() {
+        static std::map<int, std::pair<uint64_t, uint64_t>> m;
+        return m;
+    }
+    static bool static_holds(int dev, uint64_t bid, uint64_t gen) {
+        std::lock_guard<std::mutex> lk(static_mu());
+        auto it = static_owner().find(dev);
+        return it != static_owner().end() && it->second == std::make_pair(bid, gen);
+    }
+    static void static_claim(int dev, uint64_t bid, uint64_t gen) {
+        std::lock_guard<std::mutex> lk(static_mu());
+        static_owner()[dev] = {bid, gen};
+    }
+    static uint64_t next_id() {
+        static std::mutex m;
+        static uint64_t k = 0;
+        std::lock_guard<std::mutex> lk(m);
+        return ++k;
+    }
+    const uint64_t id = next_id();   // distinguishes batches (addresses may be reused)
+    uint64_t layout_gen = 0;         // bumped at every regroup and shape change
 };
 
 extern "C" slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out) {
@@ -461,7 +577,7 @@ extern "C" slbm_status slbm_batch_set_autotune(slbm_batch *b, int on) {
 extern "C" slbm_status slbm_batch_shapes(slbm_batch *b, slbm_batch_shape *out, int max, int *count) {
     return slbm_guard([&]() -> slbm_status {
         if (!b || !count || max < 0 || (max > 0 && !out)) return SLBM_EINVAL;
-        if (b->dirty && !b->members.empty())
+        if (!b->members.empty())
             if (slbm_status s = b->rebuild()) return s;
         const int ng = b->members.empty() ? 0 : (int)b->groups.size();
         *count = ng;
@@ -491,8 +607,7 @@ extern "C" slbm_status slbm_batch_step(slbm_batch *b, int64_t n) {
     return slbm_guard([&]() -> slbm_status {
         if (!b || n < 0) return SLBM_EINVAL;
         if (b->members.empty() || n == 0) return SLBM_OK;
-        if (b->dirty)
-            if (slbm_status s = b->rebuild()) return s;
+        if (slbm_status s = b->rebuild()) return s;
         int64_t done = 0;
         if (b->autotune && (done = b->tune_pending(n)) < 0) return SLBM_EDEVICE;
         if (b->run(n - done)) return SLBM_EDEVICE;
@@ -507,12 +622,25 @@ extern "C" slbm_status slbm_batch_step(slbm_batch *b, int64_t n) {
     });
 }
 
+extern "C" slbm_status slbm_batch_step_static(slbm_batch *b, int64_t n) {
+    return slbm_guard([&]() -> slbm_status {
+        if (!b || n < 0) return SLBM_EINVAL;
+        if (b->members.empty() || n == 0) return SLBM_OK;
+        if (slbm_status s = b->step_static(n)) return s;
+        for (slbm_ctx *c : b->members) c->step += n;
+        for (auto &g : b->groups)
+            if (!g.fused)
+                for (int i : g.idx)
+                    if (b->members[i]->fused) b->members[i]->rl_stale = true;
+        return SLBM_OK;
+    });
+}
+
 extern "C" slbm_status slbm_batch_kinetic_energy(slbm_batch *b, double *ke, double *mass) {
     return slbm_guard([&]() -> slbm_status {
         if (!b) return SLBM_EINVAL;
         if (b->members.empty()) return SLBM_OK;
-        if (b->dirty)
-            if (slbm_status s = b->rebuild()) return s;
+        if (slbm_status s = b->rebuild()) return s;
         hipStream_t st = (hipStream_t)b->stream;
         std::vector<std::vector<double>> outs(b->groups.size());
         for (size_t gi = 0; gi < b->groups.size(); ++gi) {
