@@ -172,7 +172,7 @@ static void gll(int N, double *x, double *w, double *D) {
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* lattices: D2Q9 (Sec. 2.1) and D3Q19                                                  */
+/* lattices: D2Q9 (Sec. 2.1), D3Q19 and D3Q13                                        */
 /* ------------------------------------------------------------------------------------ */
 
 static int set_lattice(orc *o, int Q) {
@@ -192,6 +192,33 @@ static int set_lattice(orc *o, int Q) {
         for (int a = 0; a < 19; ++a) {
             for (int c = 0; c < 3; ++c) o->ev[a][c] = E19[a][c];
             o->tw[a] = a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+        }
+    } else if (Q == 13) {
+        /* 13 velocities in 3-D (Sec. 3.2 uses a 13-velocity model), reading R22.  With a
+         * rest weight t0 and one weight t1 for twelve moving velocities of speed |e|, the
+         * equilibrium (A.2) has the moments rho, rho u and rho cs^2 I + rho u u only if
+         *   sum t = 1, sum t e_i e_j = cs^2 d_ij, sum t e_i e_j e_k = 0 and
+         *   sum t e_i e_j e_k e_l = cs^4 (d_ij d_kl + d_ik d_jl + d_il d_jk).
+         * The twelve face diagonals of a cube (the cubic 13-velocity set) give
+         * sum e_x^4 = 2 sum e_x^2 e_y^2 and cannot meet the last condition; the twelve
+         * vertices of an icosahedron, a spherical 5-design, give
+         *   sum e_i e_j = 4 |e|^2 d_ij and sum e_i e_j e_k e_l = (4/5)|e|^4 (d d + d d + d d),
+         * so 4 |e|^2 t1 = cs^2 and (4/5)|e|^4 t1 = cs^4: |e|^2 = 5 cs^2 = 5/3, t1 = 1/20 and
+         * t0 = 2/5.  The vertices (0, +-1, +-phi) and their cyclic permutations, scaled to
+         * |e|^2 = 5/3, have components of magnitude
+         *   a = sqrt((5 - sqrt 5) / 6) and b = phi a = sqrt((5 + sqrt 5) / 6).
+         * Population order (1 = a, 2 = b, signs as written): opposite pairs are adjacent. */
+        static const int P13[13][3] = {{0, 0, 0},  {0, 1, 2},   {0, -1, -2}, {0, 1, -2}, {0, -1, 2},
+                                       {1, 2, 0},  {-1, -2, 0}, {1, -2, 0},  {-1, 2, 0}, {2, 0, 1},
+                                       {-2, 0, -1}, {2, 0, -1}, {-2, 0, 1}};
+        double ma = sqrt((5.0 - sqrt(5.0)) / 6.0), mb = sqrt((5.0 + sqrt(5.0)) / 6.0);
+        for (int a = 0; a < 13; ++a) {
+            for (int c = 0; c < 3; ++c) {
+                int k = P13[a][c];
+                double m = (k == 1 || k == -1) ? ma : mb;
+                o->ev[a][c] = k == 0 ? 0.0 : (k > 0 ? m : -m);
+            }
+            o->tw[a] = a == 0 ? 2.0 / 5.0 : 1.0 / 20.0;
         }
     } else
         return -1;

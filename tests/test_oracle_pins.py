@@ -25,6 +25,16 @@ def _case(mesh, lattice=None, **kw):
     return cases.Case("t", mesh, lattice, **kw)
 
 
+def _q13(mk):
+    """The same case with the D3Q13 lattice."""
+    def f():
+        c = mk()
+        c.lattice = 13
+        return c
+    f.__name__ = mk.__name__ + "_q13"
+    return f
+
+
 # ---------------------------------------------------------------------------
 # GLL tables (Deville, Fischer & Mund ch. 2)
 # ---------------------------------------------------------------------------
@@ -73,17 +83,25 @@ def test_gll_closed_forms():
 # lattices and free-energy parameters
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("Q", [9, 19])
+def _lattice_case(Q):
+    c = cases.c1() if Q == 9 else cases.small_box3d()
+    c.lattice = Q
+    return c
+
+
+@pytest.mark.parametrize("Q", [9, 19, 13])
 def test_lattice_moments(Q):
-    mk = cases.c1 if Q == 9 else cases.small_box3d
-    o = Oracle(mk())
+    o = Oracle(_lattice_case(Q))
     ev, tw, opp = o.lattice()
     d = 2 if Q == 9 else 3
     e = ev[:, :d]
     cs2 = 1.0 / 3.0
     from fractions import Fraction
     assert sum(Fraction(t) for t in tw) == 1          # exact in FP64 (no mass bleed)
-    assert np.abs(tw @ e).max() == 0.0
+    # opposite pairs cancel exactly; numpy's summation order leaves rounding for the
+    # irrational D3Q13 components
+    assert np.abs(tw @ e).max() <= (1e-17 if Q == 13 else 0.0)
+    assert np.abs(tw[opp, None] * e[opp] + tw[:, None] * e).max() == 0.0
     assert np.abs(np.einsum("a,ai,aj->ij", tw, e, e) - cs2 * np.eye(d)).max() < 3e-16
     assert np.abs(np.einsum("a,ai,aj,ak->ijk", tw, e, e, e)).max() < 1e-17
     I = np.eye(d)
@@ -94,8 +112,60 @@ def test_lattice_moments(Q):
     # paper's weights (Sec. 2.1 for D2Q9): rest 4/9, axes 1/9, diagonals 1/36
     if Q == 9:
         assert abs(tw[0] - 4 / 9) < 1e-16 and np.all(tw[1:5] == 1 / 9) and np.all(tw[5:] == 1 / 36)
-    else:
+    elif Q == 19:
         assert abs(tw[0] - 1 / 3) < 1e-16 and np.all(tw[1:7] == 1 / 18) and np.all(tw[7:] == 1 / 36)
+    else:
+        assert abs(tw[0] - 2 / 5) < 1e-16 and np.all(tw[1:] == 1 / 20)
+
+
+def _unit_icosahedron():
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    v = []
+    for s1 in (1.0, -1.0):
+        for s2 in (1.0, -1.0):
+            for p in ((0.0, s1, s2 * phi), (s1, s2 * phi, 0.0), (s2 * phi, 0.0, s1)):
+                v.append(p)
+    v = np.array(v)
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def _weights_from_moments(V, cs2=1.0 / 3.0):
+    """Rest weight t0, moving weight t1 and speed^2 r2 of a set of unit directions V (one
+    weight for all of them) from the moment conditions (A.2) needs: sum t = 1,
+    t1 r2 sum v_x^2 = cs^2, t1 r2^2 sum v_x^4 = 3 cs^4, t1 r2^2 sum v_x^2 v_y^2 = cs^4.
+    Returns None when the last two cannot both hold (the set is not isotropic enough)."""
+    S2 = (V[:, 0] ** 2).sum()
+    S4 = (V[:, 0] ** 4).sum()
+    S22 = (V[:, 0] ** 2 * V[:, 1] ** 2).sum()
+    if abs(S4 - 3.0 * S22) > 1e-12:
+        return None
+    r2 = 3.0 * cs2 * S2 / S4
+    t1 = cs2 / (r2 * S2)
+    return 1.0 - len(V) * t1, t1, r2
+
+
+def test_d3q13_follows_from_the_moment_conditions():
+    """Reading R22: the only cubic-symmetric 13-velocity set (rest + the twelve face
+    diagonals of a cube) has sum v_x^4 = 2 sum v_x^2 v_y^2 and cannot give (A.2) its
+    fourth-order moments under one relaxation time; the icosahedral set can, and the
+    moment conditions then fix t0 = 2/5, t1 = 1/20 and |e|^2 = 5/3.  The oracle's D3Q13
+    table is that set (as a set of vectors, with opposite pairs)."""
+    fcc = np.array([p for p in __import__("itertools").product((-1, 0, 1), repeat=3)
+                    if sum(abs(x) for x in p) == 2], dtype=float)
+    assert len(fcc) == 12
+    assert _weights_from_moments(fcc / np.sqrt(2.0)) is None
+    V = _unit_icosahedron()
+    t0, t1, r2 = _weights_from_moments(V)
+    assert abs(t0 - 0.4) < 1e-15 and abs(t1 - 0.05) < 1e-16 and abs(r2 - 5.0 / 3.0) < 1e-14
+    o = Oracle(_lattice_case(13))
+    ev, tw, opp = o.lattice()
+    assert np.all(ev[0] == 0.0)
+    want = V * math.sqrt(r2)
+    for k in range(1, 13):
+        dmin = np.abs(want - ev[k]).max(axis=1).min()
+        assert dmin < 1e-15, (k, ev[k])
+    assert sorted(opp[1:]) == list(range(1, 13)) and all(opp[opp[k]] == k for k in range(13))
+    assert abs(tw[1:].sum() + tw[0] - 1.0) == 0.0 and abs(tw[0] - t0) < 1e-16
 
 
 def test_parameters_reproduce_surface_tension():
@@ -134,7 +204,7 @@ def test_automatic_dt_capillary_bound(N, ccap):
 # collision (Eq. 4, A.2, A.6-A.7)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("mk", [cases.c1, cases.small_box3d])
+@pytest.mark.parametrize("mk", [cases.c1, cases.small_box3d, _q13(cases.small_box3d)])
 def test_collision_conserves_mass_and_momentum(mk):
     c = mk()
     o = Oracle(c)
@@ -354,7 +424,8 @@ def test_flux_bounce_back_moving_wall_momentum_input():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mk,n", [(cases.c1, 200), (cases.small_flat, 200),
-                                  (cases.small_cyl, 40), (cases.small_sphere, 6)])
+                                  (cases.small_cyl, 40), (cases.small_sphere, 6),
+                                  (_q13(cases.small_sphere), 6)])
 def test_mass_conserved_to_machine_precision(mk, n):
     c = mk()
     o = Oracle(c)
@@ -436,22 +507,24 @@ def test_young_cap_keeps_its_angle(theta):
     assert abs(a1 - theta) < 2.0
 
 
-@pytest.mark.parametrize("dim,nu,tau,N,nel", [(2, 0.05, 0.5, 6, 2), (2, 0.01, 0.5, 8, 2),
-                                               (2, 0.0, 1.5, 8, 2), (2, 0.05, 0.5, 4, 4),
-                                               (3, 0.05, 0.5, 6, 2), (3, 0.0, 1.5, 6, 2)])
-def test_shear_wave_decays_at_the_set_viscosity(dim, nu, tau, N, nel):
+@pytest.mark.parametrize("dim,nu,tau,N,nel,Q", [(2, 0.05, 0.5, 6, 2, 9), (2, 0.01, 0.5, 8, 2, 9),
+                                                 (2, 0.0, 1.5, 8, 2, 9), (2, 0.05, 0.5, 4, 4, 9),
+                                                 (3, 0.05, 0.5, 6, 2, 19), (3, 0.0, 1.5, 6, 2, 19),
+                                                 (3, 0.05, 0.5, 6, 2, 13), (3, 0.0, 1.5, 6, 3, 13)])
+def test_shear_wave_decays_at_the_set_viscosity(dim, nu, tau, N, nel, Q):
     """R12 against the Navier-Stokes limit: at the uniform liquid density mu and the force
-    vanish, and a shear wave u_x = U sin(k y) in a periodic box (D2Q9 or D3Q19) decays as
-    exp(-nu k^2 t) with nu = tau cs^2 dt.  The measured rate matches the viscosity asked for (nu > 0) or
-    the one tau gives (nu = 0) to 1%; reading omega as 1/tau, or nu as (tau + 1/2) cs^2 dt,
-    is off by tens of percent here."""
+    vanish, and a shear wave u_x = U sin(k y) in a periodic box (D2Q9, D3Q19 or D3Q13) decays
+    as exp(-nu k^2 t) with nu = tau cs^2 dt.  The measured rate matches the viscosity asked
+    for (nu > 0) or the one tau gives (nu = 0) to 1%; reading omega as 1/tau, or nu as
+    (tau + 1/2) cs^2 dt, is off by tens of percent here.  A cubic 13-velocity set (weights
+    1/2, 1/24) would give this wave 1.5 times the viscosity: its sum t e_x^2 e_y^2 is 1/6,
+    not cs^4 = 1/9 (R22)."""
     L, U = 32.0, 1e-3
     if dim == 2:
         m = meshes.box2d(nel, nel, N, L, L, periodic=(True, True), name="shear")
     else:
         m = meshes.box3d(nel, nel, nel, N, (L, L, L), periodic=(True, True, True), name="shear")
-    c = cases.Case("shear", m, cases.LATTICE_D2Q9 if dim == 2 else cases.LATTICE_D3Q19,
-                   x0=(0.0,) * dim, R=1.0, steps=0, nu=nu, tau=tau)
+    c = cases.Case("shear", m, Q, x0=(0.0,) * dim, R=1.0, steps=0, nu=nu, tau=tau)
     o = Oracle(c)
     ev, tw, _ = o.lattice()
     y = m.first_copy_coords()[:, 1]
