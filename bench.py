@@ -204,7 +204,7 @@ def batch_bench(P, torch, n_req: int, steps: int, warmup: int = 40, seed: int = 
         "ms_per_step": ms_batch, "node_updates_per_s": ng / (ms_batch * 1e-3),
         "plain_ms_per_step_all_members": plain_ms,
         "batched_over_plain": plain_ms / ms_batch,
-        "groups": [{"lattice": f"D{g['dim']}Q{9 if g['dim'] == 2 else 19}", "N": g["N"],
+        "groups": [{"lattice": f"D{g['dim']}Q{g['lattice']}", "N": g["N"],
                     "fused": g["fused"], "members": g["members"], "elements": g["elements"],
                     "chosen": g["shapes"][g["chosen"]], "timed": g["measured"],
                     "candidates": g["shapes"]} for g in shapes],
@@ -442,7 +442,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "c2xl"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "c2xl", "c4q13"])
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-steps", type=int, default=2000)
     ap.add_argument("--no-serving", action="store_true")
@@ -516,10 +516,11 @@ def main():
         "roofline": r["roofline"],
     }
     if args.workload == "c4" and not args.no_extras:
-        # extra points beside the headline: c2 (a cache-resident, latency-bound 2-D step) and
-        # c2-XL (a 2-D step whose working set is HBM-resident)
+        # extra points beside the headline: c2 (a cache-resident, latency-bound 2-D step),
+        # c2-XL (a 2-D step whose working set is HBM-resident) and c4 with the D3Q13 lattice
         for key, name, st, wu, ps, kr in (("c2", "c2", 2000, 100, 100, 300),
-                                          ("hbm_scale", "c2xl", 100, 10, 3, 20)):
+                                          ("hbm_scale", "c2xl", 100, 10, 3, 20),
+                                          ("c4q13", "c4q13", 100, 10, 3, 20)):
             x = measure_workload(P, torch, name, st, wu, ps, kr)
             out[key] = {"workload": x["config"]["workload"], "node_updates_per_s": x["value"],
                         "ms_per_step": x["ms_per_step"], "n_global": x["config"]["n_global"],

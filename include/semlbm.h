@@ -21,6 +21,13 @@
  *       D3Q19 (lattice = 19): 0 rest 1/3; 1..6: +x,-x,+y,-y,+z,-z 1/18;
  *                             7..18: (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),
  *                             (1,0,-1),(-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1) 1/36.
+ *       D3Q13 (lattice = 13): 0 rest 2/5; 1..12 the icosahedron vertices at |e|^2 = 5/3,
+ *                             weight 1/20, with a = sqrt((5 - sqrt 5)/6), b = sqrt((5 + sqrt 5)/6):
+ *                             (0,a,b),(0,-a,-b),(0,a,-b),(0,-a,b),(a,b,0),(-a,-b,0),
+ *                             (a,-b,0),(-a,b,0),(b,0,a),(-b,0,-a),(b,0,-a),(-b,0,a).
+ *                             The paper's 3-D runs use a 13-velocity model (Sec. 3.2); this is
+ *                             the 13-velocity set whose weights give the equilibrium (A.2) its
+ *                             moments up to fourth order under one relaxation time.
  *     The FP64 rest weight is 1 minus the exact sum of the others, so the weights sum to
  *     exactly one.  c_s^2 = 1/3.
  *   - Population arrays are [Q][n_global] (population-major), velocity arrays [d][n_global].
@@ -59,7 +66,7 @@ typedef int slbm_status;
 #define SLBM_EDIVERGED (-5) /* non-finite state or kinetic energy above the limit */
 
 typedef struct slbm_params {
-    int lattice;      /* 9 = D2Q9 (2-D) or 19 = D3Q19 (3-D) */
+    int lattice;      /* 9 = D2Q9 (2-D), 19 = D3Q19 or 13 = D3Q13 (3-D) */
     int N;            /* GLL polynomial order: 2..16 in 2-D, 2..6 in 3-D */
     double rho_l;     /* liquid bulk density (Appendix A: 1.0 in the paper) */
     double rho_v;     /* vapour bulk density (Appendix A: 0.1) */
@@ -238,7 +245,7 @@ slbm_status slbm_batch_set_autotune(slbm_batch *b, int on);
 
 #define SLBM_MAX_SHAPES 4
 typedef struct slbm_batch_shape {
-    int dim, order, fused;     /* group key: lattice dimension, N, fused kernel path (0/1) */
+    int dim, order, fused;     /* group key (with lattice): dimension, N, fused kernel path (0/1) */
     int members;               /* members in the group */
     int64_t elements;          /* their elements */
     int n_shapes;              /* candidate shapes, at most SLBM_MAX_SHAPES */
@@ -247,6 +254,7 @@ typedef struct slbm_batch_shape {
     double us_per_step[SLBM_MAX_SHAPES]; /* measured device us per step of the group, 0 if not */
     int chosen;                /* index of the shape the group launches with */
     int measured;              /* 1 if chosen by timing, 0 by the fixed rule above */
+    int lattice;               /* the group's lattice: 9, 19 or 13 */
 } slbm_batch_shape;
 /* The groups of the current membership: writes min(count, max) entries to out[max] and
  * the number of groups to *count (0 for an empty batch).  Errors: SLBM_EINVAL (null b or

@@ -52,7 +52,7 @@ class BatchShape(C.Structure):
     _fields_ = [("dim", C.c_int), ("order", C.c_int), ("fused", C.c_int), ("members", C.c_int),
                 ("elements", C.c_int64), ("n_shapes", C.c_int), ("epb", C.c_int * MAX_SHAPES),
                 ("xcd", C.c_int * MAX_SHAPES), ("us_per_step", C.c_double * MAX_SHAPES),
-                ("chosen", C.c_int), ("measured", C.c_int)]
+                ("chosen", C.c_int), ("measured", C.c_int), ("lattice", C.c_int)]
 
 
 class ServerCfg(C.Structure):
@@ -379,7 +379,8 @@ class Batch:
             raise SLBMError(st, "batch_shapes")
         out = []
         for r in arr[:cnt.value]:
-            out.append({"dim": r.dim, "N": r.order, "fused": bool(r.fused), "members": r.members,
+            out.append({"dim": r.dim, "lattice": r.lattice, "N": r.order, "fused": bool(r.fused),
+                        "members": r.members,
                         "elements": r.elements, "chosen": r.chosen, "measured": bool(r.measured),
                         "shapes": [{"epb": r.epb[k], "xcd": bool(r.xcd[k]), "us_per_step": r.us_per_step[k]}
                                    for k in range(r.n_shapes)]})

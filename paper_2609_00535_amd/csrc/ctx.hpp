@@ -40,6 +40,7 @@ struct slbm_ctx {
     slbm_params prm{};
     double tau = 0.0;  // relaxation time in use (prm.tau, or from prm.nu at set_mesh)
     int dim = 0, Q = 0, N = 0, Np = 0, nloc = 0;
+    int dq = 0;  // lattice key of the kernel launchers: 2 (D2Q9), 3 (D3Q19), 13 (D3Q13)
     double beta = 0, kappa = 0, omega = 0, dt = 0, hmin = 0;
     double ev[slbm::kMaxQ][3] = {};
     double tw[slbm::kMaxQ] = {}, tc[slbm::kMaxQ] = {};

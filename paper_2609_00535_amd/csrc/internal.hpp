@@ -65,8 +65,11 @@ struct SolveDesc {
     double SLBM_GLOBAL *red;  // [2 * max blocks] reduction partials
     // physics
     double rho_l, rho_v, beta, kappa, omega, dt;
-    // lattice weights t and t / cs^2 by class |e|^2 = 0 (rest), 1 (axis), 2 (diagonal)
+    // lattice weights t and t / cs^2 by class: |e|^2 = 0 (rest), 1 (axis), 2 (diagonal) for
+    // D2Q9 and D3Q19; 0 (rest), 1 (moving) for D3Q13
     double tw[3], twc[3];
+    // D3Q13 component magnitudes a = sqrt((5 - sqrt 5)/6), b = sqrt((5 + sqrt 5)/6) (else 0)
+    double lat_a, lat_b;
 };
 
 // Launch-shape bookkeeping shared by host and device.
@@ -102,7 +105,7 @@ SLBM_HD inline int xcd_single(int b, int n) {
 // Element-kernel shape for order N in d dimensions (must match Shape in kernels.hpp): "wide" blocks
 // hold as many elements as fit in 256 threads; small meshes use one element per block so
 // that every compute unit gets work.
-inline int nloc_of(int d, int N) { int p = N + 1; return d == 2 ? p * p : p * p * p; }
+inline int nloc_of(int d, int N) { int p = N + 1; return d == 2 ? p * p : p * p * p; }  // d: 2, 3 or 13
 inline int epb_wide(int d, int N) { int n = nloc_of(d, N); return n <= 256 ? 256 / n : 1; }
 inline int epb_for(int d, int N, int64_t E) {
     const int w = epb_wide(d, N);
@@ -110,7 +113,8 @@ inline int epb_for(int d, int N, int64_t E) {
 }
 constexpr int kNodeThreads = 256;
 
-// Kernel launchers (kernels.hip dispatches them to the per-order units).  'stage' is 1..3
+// Kernel launchers (kernels.hip dispatches them to the per-order units).  'd' is the lattice
+// key: 2 (D2Q9), 3 (D3Q19) or 13 (D3Q13).  'stage' is 1..3
 // for the RK stages.  All launch on 'stream' and return the hipError_t of the launch as int.
 int launch_lap(int d, int N, const LaunchPlan &p, void *stream);
 int launch_mu(int d, int N, const LaunchPlan &p, void *stream);

@@ -21,19 +21,22 @@ namespace slbm {
 SLBM_DECLARE_SET(2a)
 SLBM_DECLARE_SET(2b)
 SLBM_DECLARE_SET(3d)
+SLBM_DECLARE_SET(3q)
 
 bool supported_order(int d, int N) {
 #define X(DD, NN) if (d == DD && N == NN) return true;
     SLBM_ORDERS_2A(X)
     SLBM_ORDERS_2B(X)
     SLBM_ORDERS_3D(X)
+    SLBM_ORDERS_3Q(X)
 #undef X
     return false;
 }
 
-// (d, N) -> instance set
+// (lattice key, N) -> instance set
 #define SLBM_PICK(NAME, ...)                                                                 \
-    (d == 3 ? launch_##NAME##_3d(d, N, __VA_ARGS__)                                          \
+    (d == 13 ? launch_##NAME##_3q(d, N, __VA_ARGS__) :                                       \
+     d == 3 ? launch_##NAME##_3d(d, N, __VA_ARGS__)                                          \
             : (N <= 7 ? launch_##NAME##_2a(d, N, __VA_ARGS__) : launch_##NAME##_2b(d, N, __VA_ARGS__)))
 
 int launch_lap(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(lap, p, stream); }

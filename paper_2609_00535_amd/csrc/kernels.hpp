@@ -49,28 +49,55 @@ template <> struct Lat<19> {
         {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
     static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 };
+// D3Q13: the rest velocity and the twelve vertices of an icosahedron with |e|^2 = 5/3.  The
+// table holds the pattern of each velocity: 0, +-1 for a component of magnitude a and +-2
+// for magnitude b (a = sqrt((5 - sqrt 5)/6), b = sqrt((5 + sqrt 5)/6), in the descriptor).
+template <> struct Lat<13> {
+    static constexpr int D = 3;
+    static constexpr int e[13][3] = {{0, 0, 0},  {0, 1, 2},   {0, -1, -2}, {0, 1, -2}, {0, -1, 2},
+                                     {1, 2, 0},  {-1, -2, 0}, {1, -2, 0},  {-1, 2, 0}, {2, 0, 1},
+                                     {-2, 0, -1}, {2, 0, -1}, {-2, 0, 1}};
+    static constexpr int opp[13] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11};
+};
 template <int D> struct QOf;
 template <> struct QOf<2> { static constexpr int Q = 9; };
 template <> struct QOf<3> { static constexpr int Q = 19; };
+// Kernel templates take a lattice key DQ: 2 (D2Q9), 3 (D3Q19) or 13 (D3Q13).
+template <int DQ> struct DimOf { static constexpr int v = DQ == 2 ? 2 : 3; };
+template <int DQ> struct QOfDQ { static constexpr int v = DQ == 2 ? 9 : (DQ == 3 ? 19 : 13); };
 
-// weight class |e_q|^2 (0 rest, 1 axis, 2 diagonal): t_q = tw[class], t_q / cs^2 = twc[class]
+// weight class of population q: t_q = tw[class], t_q / cs^2 = twc[class]; |e_q|^2 (0 rest,
+// 1 axis, 2 diagonal) for D2Q9 and D3Q19, rest (0) or moving (1) for D3Q13
 template <int Q>
 __device__ __forceinline__ constexpr int wcls(int q) {
-    return Lat<Q>::e[q][0] * Lat<Q>::e[q][0] + Lat<Q>::e[q][1] * Lat<Q>::e[q][1] +
-           Lat<Q>::e[q][2] * Lat<Q>::e[q][2];
+    if constexpr (Q == 13) return q == 0 ? 0 : 1;
+    else return Lat<Q>::e[q][0] * Lat<Q>::e[q][0] + Lat<Q>::e[q][1] * Lat<Q>::e[q][1] +
+                Lat<Q>::e[q][2] * Lat<Q>::e[q][2];
 }
 
-// v . e_q summed in ascending component order from 0 (components of e are -1, 0, 1, so
-// the sum equals the plain dot product bit for bit)
+// s + x (e_q)_c with the rounding of the plain product-and-sum: components 1 and -1 add or
+// subtract x exactly, zero components add nothing (s + (+-0) == s for the sums here, which
+// start from +0.0), and the D3Q13 magnitudes multiply
+template <int Q>
+__device__ __forceinline__ double acc_e(double s, double x, int q, int c, const SolveDesc &sd) {
+    const int ec = Lat<Q>::e[q][c];
+    if constexpr (Q == 13) {
+        if (ec == 0) return s;
+        const double m = (ec == 1 || ec == -1) ? sd.lat_a : sd.lat_b;
+        return s + x * (ec > 0 ? m : -m);
+    } else {
+        if (ec == 1) return s + x;
+        if (ec == -1) return s - x;
+        return s;
+    }
+}
+
+// v . e_q summed in ascending component order from 0 (equals the plain dot product bit for bit)
 template <int Q, int D>
-__device__ __forceinline__ double dot_e(const double *v, int q) {
+__device__ __forceinline__ double dot_e(const double *v, int q, const SolveDesc &sd) {
     double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-        const int ec = Lat<Q>::e[q][c];
-        if (ec == 1) s = s + v[c];
-        else if (ec == -1) s = s - v[c];
-    }
+    for (int c = 0; c < D; ++c) s = acc_e<Q>(s, v[c], q, c, sd);
     return s;
 }
 
@@ -274,8 +301,9 @@ __device__ __forceinline__ void metric_times_grad(const double *g, const double 
     }
 }
 
-template <int D, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_lap(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
     using S = Shape<D, N, WIDE>;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
@@ -322,8 +350,9 @@ __device__ __forceinline__ double mu_of(const SolveDesc &sd, double pr, double l
     return mu0 - sd.kappa * lap;
 }
 
-template <int D, int N, bool SINGLE>
+template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
@@ -336,8 +365,9 @@ __global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
 }
 
 // lumped-mass weighted element gradients w Ja^T grad_ref of rho and mu (for the collision)
-template <int D, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_grad(LaunchPlan p) {
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_grad(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
     using S = Shape<D, N, WIDE>;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
@@ -382,8 +412,9 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_grad(LaunchPlan p) 
 }
 
 // averaged gradients DSS(gl) / M into aux [2d][Ng] (operator entry point)
-template <int D, int N, bool SINGLE>
+template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
@@ -405,18 +436,14 @@ template <int Q, int D> struct CollidePrep {
     double u[D], F[D], uF, uu;
 };
 template <int Q, int D>
-__device__ __forceinline__ void collide_prep(const double *f, double pr, const double *gr, const double *gm,
-                                             CollidePrep<Q, D> &c) {
+__device__ __forceinline__ void collide_prep(const SolveDesc &sd, const double *f, double pr, const double *gr,
+                                             const double *gm, CollidePrep<Q, D> &c) {
     const double cs2 = 1.0 / 3.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         double m = 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int ec = Lat<Q>::e[q][k];
-            if (ec == 1) m = m + f[q];
-            else if (ec == -1) m = m - f[q];
-        }
+        for (int q = 0; q < Q; ++q) m = acc_e<Q>(m, f[q], q, k, sd);
         c.u[k] = m / pr;
         c.F[k] = cs2 * gr[k] - pr * gm[k];
     }
@@ -433,7 +460,7 @@ template <int Q, int D>
 __device__ __forceinline__ double collide_q(const SolveDesc &sd, int q, double fq, double pr,
                                             const CollidePrep<Q, D> &c) {
     const double dt = sd.dt, om = sd.omega;
-    const double eu = dot_e<Q, D>(c.u, q), eF = dot_e<Q, D>(c.F, q);
+    const double eu = dot_e<Q, D>(c.u, q, sd), eF = dot_e<Q, D>(c.F, q, sd);
     const double tq = sd.tw[wcls<Q>(q)], tc = sd.twc[wcls<Q>(q)];
     const double Fss = tc * (eu * eF * 3.0 - c.uF);
     const double feq = pr * tq * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * c.uu);
@@ -444,14 +471,15 @@ template <int Q, int D>
 __device__ __forceinline__ void collide_node(const SolveDesc &sd, const double *f, double pr,
                                              const double *gr, const double *gm, double *fs) {
     CollidePrep<Q, D> c;
-    collide_prep<Q, D>(f, pr, gr, gm, c);
+    collide_prep<Q, D>(sd, f, pr, gr, gm, c);
 #pragma unroll
     for (int q = 0; q < Q; ++q) fs[q] = collide_q<Q, D>(sd, q, f[q], pr, c);
 }
 
-template <int D, int N, bool SINGLE>
+template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_aux) {
-    constexpr int Q = QOf<D>::Q;
+    constexpr int D = DimOf<DQ>::v;
+    constexpr int Q = QOfDQ<DQ>::v;
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
@@ -519,7 +547,7 @@ __device__ __forceinline__ double residual_q(const SolveDesc &sd, int q, const d
     double adv = 0.0, frc = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double ca = dot_e<Q, D>(geo.J[a], q);
+        const double ca = dot_e<Q, D>(geo.J[a], q, sd);
         adv += ca * dh[a];
         frc += ca * dmu[a];
     }
@@ -528,9 +556,9 @@ __device__ __forceinline__ double residual_q(const SolveDesc &sd, int q, const d
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         if (j < geo.wf.cnt) {
-            const double cn = dot_e<Q, D>(geo.wf.sn[j], q);
+            const double cn = dot_e<Q, D>(geo.wf.sn[j], q, sd);
             if (cn < 0.0) {
-                const double eub = dot_e<Q, D>(geo.wf.ub[j], q);
+                const double eub = dot_e<Q, D>(geo.wf.ub[j], q, sd);
                 const double bc = gq - gopp - 2.0 * tc * pr * eub;
                 r += cn * bc;
             }
@@ -539,12 +567,11 @@ __device__ __forceinline__ double residual_q(const SolveDesc &sd, int q, const d
     return r;
 }
 
-template <int D, int N, bool WIDE>
+template <int Q, int D, int N, bool WIDE>
 __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
                                                 const double *smu_e, int es, int n, int l,
                                                 double pr, const double *gq, const NodeGeo<D> &geo) {
     using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     double dmu[D];
     grad_ref<D, NP>(sD, smu_e, n, dmu);
@@ -557,10 +584,11 @@ __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const doubl
 }
 
 // stage 1 streams g0, stages 2-3 stream g1
-template <int D, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT), (Shape<D, N, WIDE>::WPE_STREAM)) void k_stream(LaunchPlan p, int stage) {
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ>::v, N, WIDE>::WPE_STREAM)) void k_stream(LaunchPlan p, int stage) {
+    constexpr int D = DimOf<DQ>::v;
     using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
+    constexpr int Q = QOfDQ<DQ>::v;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
     __shared__ double smu[NB];
@@ -593,7 +621,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT), (Shape<D, N, WIDE>::WPE_ST
     dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
-    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
+    stream_residual<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
 }
 
 // SSP-RK3 stage combination after DSS(r)/M, and the new stage's density (Eq. (10))
@@ -609,9 +637,10 @@ __device__ __forceinline__ double rk_combine(int stage, double L, double gin, do
     return (g0 + 2.0 * x) / 3.0;
 }
 
-template <int D, int N, bool SINGLE>
+template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
-    constexpr int Q = QOf<D>::Q;
+    constexpr int D = DimOf<DQ>::v;
+    constexpr int Q = QOfDQ<DQ>::v;
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
@@ -667,9 +696,10 @@ __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
 }
 
 // rho = sum_a f_a (Eq. (10)) of the state (which = 0) or of g1 (which = 1)
-template <int D, int N, bool SINGLE>
+template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int which) {
-    constexpr int Q = QOf<D>::Q;
+    constexpr int D = DimOf<DQ>::v;
+    constexpr int Q = QOfDQ<DQ>::v;
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
@@ -683,9 +713,10 @@ __global__ __launch_bounds__(kNodeThreads) void k_density(LaunchPlan p, int whic
 }
 
 // KE_max = max 1/2 rho |u|^2 and mass = sum M rho; per-block partials in red[]
-template <int D, int N, bool SINGLE>
+template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_diag(LaunchPlan p) {
-    constexpr int Q = QOf<D>::Q;
+    constexpr int D = DimOf<DQ>::v;
+    constexpr int Q = QOfDQ<DQ>::v;
     __shared__ double smax[kNodeThreads], ssum[kNodeThreads];
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
@@ -707,11 +738,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_diag(LaunchPlan p) {
         for (int c = 0; c < D; ++c) {
             double m = 0.0;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int ec = Lat<Q>::e[q][c];
-                if (ec == 1) m = m + f[q];
-                else if (ec == -1) m = m - f[q];
-            }
+            for (int q = 0; q < Q; ++q) m = acc_e<Q>(m, f[q], q, c, sd);
             const double u = m / pr;
             uu += u * u;
         }
@@ -819,8 +846,9 @@ __device__ __forceinline__ double gather1(P v, const CopyList<D> &c) {
 
 // A: mu of the state's density (DSS of the Laplacian partials) and the lumped-mass
 // weighted element gradients of rho and mu for the collision
-template <int D, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
     using S = Shape<D, N, WIDE>;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
@@ -871,10 +899,11 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fA(LaunchPlan p) {
 
 // B: averaged gradients (DSS), collision (Eq. (4)) at every element node, owners store f*
 // in g0, then the stage-1 streaming residual of f*
-template <int D, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
     using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
+    constexpr int Q = QOfDQ<DQ>::v;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
     __shared__ double smu[NB];
@@ -922,17 +951,18 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fB(LaunchPlan p) {
     dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
-    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, fs, geo);
+    stream_residual<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, fs, geo);
 }
 
 // C: DSS of the streaming residual, SSP-RK3 combination and the stage density at every
 // element node (owners store them), then the Laplacian partials of the new density
 //   stage 1: g1 = g0 + dt L;  stage 2: g2 = 3/4 g0 + 1/4 (g1 + dt L);
 //   stage 3: f = (g0 + 2 (g2 + dt L)) / 3
-template <int D, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, int stage) {
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_fC(LaunchPlan p, int stage) {
+    constexpr int D = DimOf<DQ>::v;
     using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
+    constexpr int Q = QOfDQ<DQ>::v;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     constexpr int K = CopyList<D>::K;
     __shared__ double sD[NP * NP];
@@ -1039,10 +1069,11 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fC(LaunchPlan p, in
 
 // D: mu of the stage density (DSS of the Laplacian partials) and the streaming residual of
 // stage 2 (g1) or 3 (g2)
-template <int D, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, int stage) {
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_fD(LaunchPlan p, int stage) {
+    constexpr int D = DimOf<DQ>::v;
     using S = Shape<D, N, WIDE>;
-    constexpr int Q = QOf<D>::Q;
+    constexpr int Q = QOfDQ<DQ>::v;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     __shared__ double sD[NP * NP];
     __shared__ double smu[NB];
@@ -1077,7 +1108,7 @@ __global__ __launch_bounds__((Shape<D, N, WIDE>::NT)) void k_fD(LaunchPlan p, in
     dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
-    stream_residual<D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
+    stream_residual<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1151,7 +1182,7 @@ __global__ __launch_bounds__(Split2<N>::NT) void k_fB4(LaunchPlan p) {
         pr = sd.rho[G];
         const double mu = sd.mu[G];
         CollidePrep<Q, D> cp;
-        collide_prep<Q, D>(f, pr, gr, gm, cp);
+        collide_prep<Q, D>(sd, f, pr, gr, gm, cp);
         const bool owner = cl.cp[0] == l;
         for_group(grp, [&](auto gc) {
             constexpr int qa = PairOf<decltype(gc)::value>::qa, qb = Lat<Q>::opp[qa];
@@ -1337,17 +1368,17 @@ template <int DD, int NN> constexpr bool kSplit = DD == 2 && Split2<NN>::NT <= 1
 template <int DD, int NN, bool S>
 inline void launch_narrow_fB(const LaunchPlan &p, hipStream_t st) {
     if constexpr (kSplit<DD, NN>) k_fB4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p);
-    else k_fB<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p);
+    else k_fB<DD, NN, false, S><<<p.grid, Shape<DimOf<DD>::v, NN, false>::NT, 0, st>>>(p);
 }
 template <int DD, int NN, bool S>
 inline void launch_narrow_fC(const LaunchPlan &p, hipStream_t st, int stage) {
     if constexpr (kSplit<DD, NN>) k_fC4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p, stage);
-    else k_fC<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p, stage);
+    else k_fC<DD, NN, false, S><<<p.grid, Shape<DimOf<DD>::v, NN, false>::NT, 0, st>>>(p, stage);
 }
 template <int DD, int NN, bool S>
 inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
     if constexpr (kSplit<DD, NN>) k_fD4<NN, S><<<p.grid, Split2<NN>::NT, 0, st>>>(p, stage);
-    else k_fD<DD, NN, false, S><<<p.grid, Shape<DD, NN, false>::NT, 0, st>>>(p, stage);
+    else k_fD<DD, NN, false, S><<<p.grid, Shape<DimOf<DD>::v, NN, false>::NT, 0, st>>>(p, stage);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1355,10 +1386,10 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 // launch_<kernel>_<sfx>(d, N, plan, ..., stream) for the orders listed by ORDERS(X)
 // ------------------------------------------------------------------------------------------
 #define SLBM_ELEM_LAUNCH(KERNEL, DD, NN, W, S, ...)                                          \
-    KERNEL<DD, NN, W, S><<<p.grid, Shape<DD, NN, W>::NT, 0, st>>>(p, ##__VA_ARGS__)
+    KERNEL<DD, NN, W, S><<<p.grid, Shape<DimOf<DD>::v, NN, W>::NT, 0, st>>>(p, ##__VA_ARGS__)
 #define SLBM_ELEM_CASE(KERNEL, DD, NN, ...)                                                  \
     if (!done && d == DD && N == NN) {                                                       \
-        const bool wide = p.epb == Shape<DD, NN, true>::EPB;                                 \
+        const bool wide = p.epb == Shape<DimOf<DD>::v, NN, true>::EPB;                                 \
         if (wide && p.single) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, true, true, ##__VA_ARGS__);   \
         else if (wide) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, true, false, ##__VA_ARGS__);         \
         else if (p.single) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, false, true, ##__VA_ARGS__);     \
@@ -1367,7 +1398,7 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
     }
 #define SLBM_SPLIT_CASE(KERNEL, NARROW, DD, NN, ...)                                        \
     if (!done && d == DD && N == NN) {                                                       \
-        const bool wide = p.epb == Shape<DD, NN, true>::EPB;                                 \
+        const bool wide = p.epb == Shape<DimOf<DD>::v, NN, true>::EPB;                                 \
         if (wide && p.single) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, true, true, ##__VA_ARGS__);   \
         else if (wide) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, true, false, ##__VA_ARGS__);         \
         else if (p.single) NARROW<DD, NN, true>(p, st, ##__VA_ARGS__);                       \
@@ -1429,5 +1460,6 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 #define SLBM_ORDERS_2A(X) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(2, 7)
 #define SLBM_ORDERS_2B(X) X(2, 8) X(2, 9) X(2, 10) X(2, 11) X(2, 12) X(2, 14) X(2, 16)
 #define SLBM_ORDERS_3D(X) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6)
+#define SLBM_ORDERS_3Q(X) X(13, 2) X(13, 3) X(13, 4) X(13, 5) X(13, 6)
 
 }  // namespace slbm

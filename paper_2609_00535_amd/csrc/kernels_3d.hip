@@ -1,4 +1,4 @@
-// Kernel instances and launchers for 3-D (D3Q19), N = 2..6.
+// Kernel instances and launchers for 3-D D3Q19, N = 2..6.
 #include "kernels.hpp"
 
 namespace slbm {

@@ -92,7 +92,23 @@ void lattice_tables(int Q, double e[][3], double *t, int *opp) {
         {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
         {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
         {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    // D3Q13: rest and the icosahedron vertices (0, +-1, +-phi) and cyclic permutations at
+    // |e|^2 = 5/3 (the speed and weights that give (A.2) its moments up to fourth order);
+    // pattern entries 1 and 2 stand for the magnitudes a and b below
+    static const int e13[13][3] = {{0, 0, 0},  {0, 1, 2},   {0, -1, -2}, {0, 1, -2}, {0, -1, 2},
+                                   {1, 2, 0},  {-1, -2, 0}, {1, -2, 0},  {-1, 2, 0}, {2, 0, 1},
+                                   {-2, 0, -1}, {2, 0, -1}, {-2, 0, 1}};
+    const double a13 = std::sqrt((5.0 - std::sqrt(5.0)) / 6.0), b13 = std::sqrt((5.0 + std::sqrt(5.0)) / 6.0);
     for (int q = 0; q < Q; ++q) {
+        if (Q == 13) {
+            for (int c = 0; c < 3; ++c) {
+                const int k = e13[q][c];
+                const double m = (k == 1 || k == -1) ? a13 : b13;
+                e[q][c] = k == 0 ? 0.0 : (k > 0 ? m : -m);
+            }
+            t[q] = q == 0 ? 2.0 / 5.0 : 1.0 / 20.0;
+            continue;
+        }
         for (int c = 0; c < 3; ++c) e[q][c] = Q == 9 ? e9[q][c] : e19[q][c];
         const int nz = std::abs((int)e[q][0]) + std::abs((int)e[q][1]) + std::abs((int)e[q][2]);
         if (Q == 9) t[q] = nz == 0 ? 4.0 / 9.0 : (nz == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
@@ -167,15 +183,16 @@ extern "C" slbm_status slbm_create(const slbm_params *p, slbm_ctx **out) {
         slbm_ctx *c = new (std::nothrow) slbm_ctx();
         if (!c) return SLBM_ENOMEM;
         c->prm = *p;
-        if (p->lattice != 9 && p->lattice != 19) {
-            c->fail(SLBM_EINVAL, "lattice must be 9 (D2Q9) or 19 (D3Q19)");
+        if (p->lattice != 9 && p->lattice != 19 && p->lattice != 13) {
+            c->fail(SLBM_EINVAL, "lattice must be 9 (D2Q9), 19 (D3Q19) or 13 (D3Q13)");
             delete c;
             return SLBM_EINVAL;
         }
         c->Q = p->lattice;
         c->dim = c->Q == 9 ? 2 : 3;
+        c->dq = c->Q == 9 ? 2 : (c->Q == 19 ? 3 : 13);
         c->N = p->N;
-        if (!supported_order(c->dim, c->N)) {
+        if (!supported_order(c->dq, c->N)) {
             delete c;
             return SLBM_EINVAL;
         }
@@ -624,9 +641,15 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
         d.omega = c->omega;
         d.dt = c->dt;
         for (int q = 0; q < c->Q; ++q) {
-            const int cls = (int)(std::fabs(c->ev[q][0]) + std::fabs(c->ev[q][1]) + std::fabs(c->ev[q][2]));
+            // weight classes of the kernels: |e|^2 for D2Q9 and D3Q19, rest / moving for D3Q13
+            const int cls = c->Q == 13 ? (q == 0 ? 0 : 1)
+                                       : (int)(std::fabs(c->ev[q][0]) + std::fabs(c->ev[q][1]) + std::fabs(c->ev[q][2]));
             d.tw[cls] = c->tw[q];
             d.twc[cls] = c->tc[q];
+        }
+        if (c->Q == 13) {
+            d.lat_a = std::fabs(c->ev[1][1]);
+            d.lat_b = std::fabs(c->ev[1][2]);
         }
         // block tables of the single-member plans
         std::vector<int> ep(2 * (size_t)c->n_eblocks), np_(2 * (size_t)c->n_nblocks);
@@ -686,8 +709,8 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
 slbm_status slbm_ctx::upload_f_and_density(const std::vector<double> &f_int) {
     hipStream_t st = (hipStream_t)stream;
     int e = (int)hipMemcpyAsync(desc.f, f_int.data(), sizeof(double) * Q * Ng, hipMemcpyHostToDevice, st);
-    if (e == 0) e = launch_density(dim, N, nplan, 0, stream);
-    if (e == 0) e = launch_lap(dim, N, eplan, stream);  // Laplacian partials the fused step starts from
+    if (e == 0) e = launch_density(dq, N, nplan, 0, stream);
+    if (e == 0) e = launch_lap(dq, N, eplan, stream);  // Laplacian partials the fused step starts from
     if (e == 0) e = (int)hipStreamSynchronize(st);
     if (e) return hip_check(e, "upload state");
     has_state = true;
@@ -814,7 +837,7 @@ int slbm::enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &np
 
 slbm_status slbm_ctx::read_diag(double *ke, double *mass) {
     hipStream_t st = (hipStream_t)stream;
-    int e = launch_diag(dim, N, nplan, stream);
+    int e = launch_diag(dq, N, nplan, stream);
     if (e == 0) e = launch_diag_final(eplan.desc, 1, stream);
     double h[2] = {0.0, 0.0};
     if (e == 0) e = (int)hipMemcpyAsync(h, desc.diag, sizeof h, hipMemcpyDeviceToHost, st);
@@ -864,7 +887,7 @@ slbm_status slbm_ctx::enqueue(int64_t n) {
                 struct A { slbm_ctx *c; int steps; } a{this, sizes[k]};
                 auto fn = [](void *st, void *p) -> int {
                     A *x = (A *)p;
-                    return enqueue_steps(x->c->dim, x->c->N, x->c->eplan, x->c->nplan, x->steps, st,
+                    return enqueue_steps(x->c->dq, x->c->N, x->c->eplan, x->c->nplan, x->steps, st,
                                          x->c->fused);
                 };
                 const int e = capture_graph(stream, &graph[k], fn, &a);
@@ -885,12 +908,12 @@ slbm_status slbm_ctx::enqueue(int64_t n) {
             return hip_check(e, "graph launch");
         }
     }
-    return hip_check(enqueue_steps(dim, N, eplan, nplan, n, stream, fused), "step launch");
+    return hip_check(enqueue_steps(dq, N, eplan, nplan, n, stream, fused), "step launch");
 }
 
 int slbm_ctx::refresh_lap() {
     if (!fused || !rl_stale) return 0;
-    const int e = launch_lap(dim, N, eplan, stream);
+    const int e = launch_lap(dq, N, eplan, stream);
     if (e == 0) rl_stale = false;
     return e;
 }
@@ -930,7 +953,7 @@ extern "C" slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess) return c->fail(SLBM_EDEVICE, "event create");
         for (int k = 0; k < SLBM_NUM_KERNEL_KINDS; ++k) { ms[k] = 0.0; launches[k] = 0; }
-        const int d = c->dim, N = c->N;
+        const int d = c->dq, N = c->N;
         int kinds[kPerStep];
         int e = 0;
         for (int64_t s = 0; s < n && e == 0; ++s) {
@@ -981,7 +1004,7 @@ namespace {
 // One launch of kernel kind `kind`; kinds with stages cycle through them so that every
 // launch reads what a launch of the step sequence reads.
 int launch_kind(const slbm_ctx *c, int kind, int64_t i) {
-    const int d = c->dim, N = c->N;
+    const int d = c->dq, N = c->N;
     void *st = c->stream;
     switch (kind) {
     case 0: return launch_lap(d, N, c->eplan, st);
@@ -1170,8 +1193,8 @@ slbm_status slbm_ctx::get(const double *src, double *dst_user, int fields) {
 // the operators overwrite rho/mu/g0/g1 scratch; the state's density is restored afterwards
 slbm_status slbm_ctx::restore_density() {
     if (!has_state) return SLBM_OK;
-    int e = launch_density(dim, N, nplan, 0, stream);
-    if (e == 0) e = launch_lap(dim, N, eplan, stream);
+    int e = launch_density(dq, N, nplan, 0, stream);
+    if (e == 0) e = launch_lap(dq, N, eplan, stream);
     if (e == 0) e = (int)hipStreamSynchronize((hipStream_t)stream);
     return hip_check(e, "restore density");
 }
@@ -1181,8 +1204,8 @@ extern "C" slbm_status slbm_op_mu(slbm_ctx *c, const double *rho, double *mu) {
         if (!c || !rho || !mu) return SLBM_EINVAL;
         if (slbm_status s = c->require_bound(false)) return s;
         if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
-        int e = launch_lap(c->dim, c->N, c->eplan, c->stream);
-        if (e == 0) e = launch_mu(c->dim, c->N, c->nplan, c->stream);
+        int e = launch_lap(c->dq, c->N, c->eplan, c->stream);
+        if (e == 0) e = launch_mu(c->dq, c->N, c->nplan, c->stream);
         if (e) return c->hip_check(e, "op_mu");
         if (slbm_status s = c->get(c->desc.mu, mu, 1)) return s;
         return c->restore_density();
@@ -1194,8 +1217,8 @@ extern "C" slbm_status slbm_op_grad(slbm_ctx *c, const double *phi, double *grad
         if (!c || !phi || !grad) return SLBM_EINVAL;
         if (slbm_status s = c->require_bound(false)) return s;
         if (slbm_status s = c->put(c->desc.rho, phi, 1)) return s;
-        int e = launch_grad(c->dim, c->N, c->eplan, c->stream);
-        if (e == 0) e = launch_gavg(c->dim, c->N, c->nplan, c->stream);
+        int e = launch_grad(c->dq, c->N, c->eplan, c->stream);
+        if (e == 0) e = launch_gavg(c->dq, c->N, c->nplan, c->stream);
         if (e) return c->hip_check(e, "op_grad");
         if (slbm_status s = c->get(c->desc.aux, grad, c->dim)) return s;
         return c->restore_density();
@@ -1210,8 +1233,8 @@ extern "C" slbm_status slbm_op_stream(slbm_ctx *c, const double *g, const double
         if (slbm_status s = c->put(c->desc.g1, g, c->Q)) return s;
         if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
         if (slbm_status s = c->put(c->desc.mu, mu, 1)) return s;
-        int e = launch_stream(c->dim, c->N, c->eplan, 2, c->stream);
-        if (e == 0) e = launch_rk(c->dim, c->N, c->nplan, 0, c->stream);  // stage 0: L into g1
+        int e = launch_stream(c->dq, c->N, c->eplan, 2, c->stream);
+        if (e == 0) e = launch_rk(c->dq, c->N, c->nplan, 0, c->stream);  // stage 0: L into g1
         if (e) return c->hip_check(e, "op_stream");
         if (slbm_status s = c->get(c->desc.g1, L, c->Q)) return s;
         return c->restore_density();
@@ -1238,7 +1261,7 @@ extern "C" slbm_status slbm_op_collide(slbm_ctx *c, const double *f, const doubl
         if (slbm_status s = c->put(c->desc.f, f, c->Q)) return s;
         if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
         if (slbm_status s = c->put(c->desc.aux, gg.data(), 2 * c->dim)) return s;
-        int e = launch_collide(c->dim, c->N, c->nplan, 1, c->stream);
+        int e = launch_collide(c->dq, c->N, c->nplan, 1, c->stream);
         if (e) return c->hip_check(e, "op_collide");
         if (slbm_status s = c->get(c->desc.g0, fstar, c->Q)) return s;
         if (c->has_state) {

@@ -287,11 +287,11 @@ struct slbm_batch {
             slbm_ctx *c = members[i];
             Group *g = nullptr;
             for (auto &x : groups)
-                if (x.d == c->dim && x.N == c->N && x.fused == c->fused) g = &x;
+                if (x.d == c->dq && x.N == c->N && x.fused == c->fused) g = &x;
             if (!g) {
                 groups.emplace_back();
                 g = &groups.back();
-                g->d = c->dim;
+                g->d = c->dq;
                 g->N = c->N;
                 g->fused = c->fused;
             }
@@ -585,7 +585,8 @@ extern "C" slbm_status slbm_batch_shapes(slbm_batch *b, slbm_batch_shape *out, i
             const auto &g = b->groups[gi];
             slbm_batch_shape &r = out[gi];
             r = slbm_batch_shape{};
-            r.dim = g.d;
+            r.dim = g.d == 2 ? 2 : 3;
+            r.lattice = g.d == 2 ? 9 : (g.d == 3 ? 19 : 13);
             r.order = g.N;
             r.fused = g.fused ? 1 : 0;
             r.members = (int)g.idx.size();

@@ -22,6 +22,7 @@ from . import meshes
 
 LATTICE_D2Q9 = 9
 LATTICE_D3Q19 = 19
+LATTICE_D3Q13 = 13
 
 
 @dataclass
@@ -108,7 +109,8 @@ def c3(theta_deg: float = 90.0, n_az: int = 128, n_rad: int = 16, N: int = 8) ->
                 theta_deg=theta_deg)
 
 
-def c4(n_t: int = 20, n_rad: int = 10, N: int = 5, theta_deg: float = 90.0) -> Case:
+def c4(n_t: int = 20, n_rad: int = 10, N: int = 5, theta_deg: float = 90.0,
+       lattice: int = LATTICE_D3Q19) -> Case:
     """D3Q19 droplet (R=20) on a sphere (R=30): cubed-sphere shell in a 128^3 box, N=5."""
     Rs, R = 30.0, 20.0
     cs = math.cos(math.radians(theta_deg))
@@ -116,7 +118,8 @@ def c4(n_t: int = 20, n_rad: int = 10, N: int = 5, theta_deg: float = 90.0) -> C
                               half_width=64.0, grading=3.0, jitter=0.1, seed=4,
                               cos_sphere=cs, cos_box=0.0, name="c4")
     d = young_center_distance(Rs, R, theta_deg)
-    return Case("c4", m, LATTICE_D3Q19, x0=(64.0, 64.0, 64.0 + d), R=R, seed=4, steps=5000,
+    return Case("c4" if lattice == LATTICE_D3Q19 else "c4q13", m, lattice, x0=(64.0, 64.0, 64.0 + d),
+                R=R, seed=4, steps=5000,
                 wall_geom=dict(kind="sphere", center=(64.0, 64.0, 64.0), radius=Rs),
                 theta_deg=theta_deg)
 
@@ -298,17 +301,24 @@ ORDERS_2D = (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16)
 ORDERS_3D = (2, 3, 4, 5, 6)
 
 
+def _lattice_key(dim: int):
+    """2 -> (2, D2Q9), 3 -> (3, D3Q19), 13 -> (3, D3Q13)."""
+    return (3, LATTICE_D3Q13) if dim == 13 else (dim, LATTICE_D2Q9 if dim == 2 else LATTICE_D3Q19)
+
+
 def order_case(dim: int, N: int) -> Case:
     """Small walled, jittered mesh of order N for the order sweep: a 70-degree wetting
-    wall and a sessile cap, 5x3 quads (2-D) or 2x3x2 hexes (3-D, D3Q19); the element
-    counts are not multiples of the wide block sizes, so wide launches end ragged."""
+    wall and a sessile cap, 5x3 quads (2-D) or 2x3x2 hexes (3-D); dim 13 is the 3-D mesh
+    with the D3Q13 lattice.  The element counts are not multiples of the wide block sizes,
+    so wide launches end ragged."""
+    dim, lat = _lattice_key(dim)
     cb = math.cos(math.radians(70.0))
     if dim == 2:
         return small_flat(theta_deg=70.0, nx=5, ny=3, N=N, Lx=40.0, Ly=24.0, R=9.0)
     m = meshes.box3d(2, 3, 2, N, (16.0, 24.0, 16.0), periodic=(True, False, True), jitter=0.15,
                      seed=16, cos_theta={"y-": cb}, name=f"order3d_N{N}")
     R = 7.0
-    return Case(f"order3d_N{N}", m, LATTICE_D3Q19, x0=(8.0, -R * cb, 8.0), R=R, seed=16, steps=10,
+    return Case(f"order3d_N{N}", m, lat, x0=(8.0, -R * cb, 8.0), R=R, seed=16, steps=10,
                 wall_geom=dict(kind="plane", point=(0.0, 0.0, 0.0), normal=(0.0, -1.0, 0.0)),
                 theta_deg=70.0)
 
@@ -317,7 +327,8 @@ def wide_case(dim: int, N: int) -> Case:
     """Mesh of order N large enough that a single solve launches its element kernels in
     wide blocks (at least 256 blocks of 256 // (N+1)^d elements) with a ragged last block:
     a walled jittered box (2-D, 70-degree wetting bottom wall) or a periodic-x walled-y
-    box (3-D)."""
+    box (3-D; dim 13: with the D3Q13 lattice)."""
+    dim, lat = _lattice_key(dim)
     nloc = (N + 1) ** dim
     epb = max(1, 256 // nloc)
     E = 256 * epb + max(1, epb // 2)
@@ -332,12 +343,17 @@ def wide_case(dim: int, N: int) -> Case:
     m = meshes.box3d(n, n, nz, N, (6.0 * n, 6.0 * n, 6.0 * nz), periodic=(True, False, True),
                      jitter=0.1, seed=17, cos_theta={"y-": cb}, name=f"wide3d_N{N}")
     R = 2.0 * n
-    return Case(f"wide3d_N{N}", m, LATTICE_D3Q19, x0=(3.0 * n, -R * cb, 3.0 * nz), R=R, seed=17,
+    return Case(f"wide3d_N{N}", m, lat, x0=(3.0 * n, -R * cb, 3.0 * nz), R=R, seed=17,
                 steps=3, wall_geom=dict(kind="plane", point=(0.0, 0.0, 0.0), normal=(0.0, -1.0, 0.0)),
                 theta_deg=70.0)
 
 
-CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c2xl": c2xl}
+def c4q13() -> Case:
+    """c4's mesh and droplet with the paper's 3-D lattice size: D3Q13 (13 populations)."""
+    return c4(lattice=LATTICE_D3Q13)
+
+
+CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c2xl": c2xl, "c4q13": c4q13}
 
 
 def sizes(case: Case) -> dict:

@@ -39,7 +39,18 @@ def _pair(case, P, mode=0):
     return P.Solve(case), Oracle(case)
 
 
-SMALL = [cases.c1, cases.small_flat, cases.small_cyl, cases.small_sphere, cases.small_box3d]
+def _q13(mk):
+    """The same case with the D3Q13 lattice."""
+    def f():
+        c = mk()
+        c.lattice = 13
+        return c
+    f.__name__ = mk.__name__ + "_q13"
+    return f
+
+
+SMALL = [cases.c1, cases.small_flat, cases.small_cyl, cases.small_sphere, cases.small_box3d,
+         _q13(cases.small_sphere), _q13(cases.small_box3d)]
 
 
 @pytest.mark.parametrize("mk", SMALL)
@@ -71,12 +82,14 @@ def test_operator_parity(P, mk):
     assert rel(L_g, L_o) <= 1e-13, rel(L_g, L_o)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dim", [2, 3, 13])
 def test_moving_wall_operator_and_step_parity(P, dim):
     """Eq. (9) with wall velocities u_b != 0 (a sliding wetting wall and a lid sliding the
     other way, tangential components in every direction): the streaming operator alone,
     then full steps (100 in 2-D, 20 in 3-D) against the oracle."""
-    c = cases.moving_walls(dim)
+    c = cases.moving_walls(min(dim, 3))
+    if dim == 13:
+        c.lattice = 13
     assert np.abs(c.mesh.wall_ub).max() > 0.0
     s, o = _pair(c, P)
     rng = np.random.default_rng(12)
@@ -92,7 +105,8 @@ def test_moving_wall_operator_and_step_parity(P, dim):
     L_o, L_g = o.stream_op(f, rho, mu), s.op_stream(f, rho, mu)
     assert rel(L_g, L_o) <= 1e-13, rel(L_g, L_o)
     # the wall velocity terms alone: the same operator with resting walls differs
-    c0 = cases.moving_walls(dim)
+    c0 = cases.moving_walls(min(dim, 3))
+    c0.lattice = c.lattice
     c0.mesh.wall_ub[:] = 0.0
     from oracle import Oracle
     assert rel(Oracle(c0).stream_op(f, rho, mu), L_o) > 1e-6
@@ -173,6 +187,19 @@ def test_c4_full_size(P):
     s, o = _run_pair(c, P, 2)
     er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
     print(f"[parity] c4 2 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+    _, mg = s.kinetic_energy()
+    _, mo = o.diag()
+    assert abs(mg - mo) <= 1e-13 * mo
+
+
+def test_c4_d3q13_full_size(P):
+    """c4's mesh and droplet with the D3Q13 lattice (the paper's 3-D lattice size; the
+    launch configuration of the benchmark's c4q13 point): 2 steps against the oracle."""
+    c = cases.c4q13()
+    s, o = _run_pair(c, P, 2)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] c4q13 2 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
     assert er <= TOL and eu <= TOL
     _, mg = s.kinetic_energy()
     _, mo = o.diag()
@@ -467,7 +494,9 @@ def test_batch_autotune_same_bits(P):
     assert np.all(np.isfinite(mt[1].get_state()[0]))
 
 
-ORDER_CASES = [(2, n) for n in cases.ORDERS_2D] + [(3, n) for n in cases.ORDERS_3D]
+# lattice keys: 2 (D2Q9), 3 (D3Q19), 13 (D3Q13)
+ORDER_CASES = ([(2, n) for n in cases.ORDERS_2D] + [(3, n) for n in cases.ORDERS_3D] +
+               [(13, n) for n in cases.ORDERS_3D])
 
 
 def test_every_order_matches_oracle(P, monkeypatch):
@@ -505,7 +534,7 @@ def test_every_order_matches_oracle(P, monkeypatch):
     assert len(sh) == len(ORDER_CASES) and all(g["measured"] for g in sh)
 
 
-WIDE_ORDERS = [(2, n) for n in range(2, 11)] + [(3, n) for n in (2, 3, 4)]
+WIDE_ORDERS = [(2, n) for n in range(2, 11)] + [(3, n) for n in (2, 3, 4)] + [(13, n) for n in (2, 4)]
 
 
 @pytest.mark.parametrize("d,n", WIDE_ORDERS)
