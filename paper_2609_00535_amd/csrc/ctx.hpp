@@ -22,8 +22,9 @@ inline slbm_status slbm_guard(F &&f) noexcept {
         return SLBM_EINVAL;
     }
 }
-// enqueue n full time steps for one (d, N) group of solves
-int enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &np, int64_t n, void *stream,
+// enqueue n full time steps for one (lattice key, N) group of solves: element plan ep, and
+// sp for the node kernels of the unfused step (nodes past each member's interior range)
+int enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &sp, int64_t n, void *stream,
                   bool fused);
 // capture 'steps' calls of fn(stream) into an instantiated graph (hipGraphExec_t)
 int capture_graph(void *stream, void **exec, int (*fn)(void *, void *), void *arg);
@@ -53,6 +54,7 @@ struct slbm_ctx {
     std::vector<int32_t> lgid, ig2ug, csr_ptr, csr_idx, gcopy, lwall, lcp;
     int vmax = 0;
     bool fused = true;  // fused element-kernel path (needs vmax <= the fused copy slots)
+    int64_t Nint = 0;   // element-interior nodes numbered first (unfused path; see SolveDesc)
     std::vector<double> Ja, Gm, MA, Minv, w_dat;
     // device
     struct Offsets {
@@ -60,7 +62,7 @@ struct slbm_ctx {
             g2, rho, mu, rl, gl, rs, aux, diag, red;
     } off{};
     size_t ws_bytes = 0;
-    int n_eblocks = 0, n_nblocks = 0, epb = 1;
+    int n_eblocks = 0, n_nblocks = 0, n_sblocks = 0, epb = 1;
     bool bound = false, has_state = false;
     // the Laplacian partials no longer belong to the state: a fused-path context stepped by
     // the unfused kernels in a batch (their last stage leaves the partials of its input)
@@ -68,7 +70,8 @@ struct slbm_ctx {
     void *dev = nullptr;
     void *stream = nullptr;
     slbm::SolveDesc desc{};
-    slbm::LaunchPlan eplan{}, nplan{};
+    // element blocks, node blocks over every node, node blocks over nodes Nint .. Ng-1
+    slbm::LaunchPlan eplan{}, nplan{}, splan{};
     int64_t step = 0;
     std::string err;
     // HIP graphs of 1 and kGraphSteps time steps (captured lazily on a non-null stream)

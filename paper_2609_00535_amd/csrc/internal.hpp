@@ -36,6 +36,11 @@ struct alignas(16) NodeCopies {
 // member).  Index arrays are int32: a solve holds < 2^31 local nodes.
 struct SolveDesc {
     int E, Nl, Ng, vmax;
+    // element-interior split (unfused path): global nodes 0 .. Nint-1 are the nodes strictly
+    // inside an element, numbered first (element by element).  The element kernels finish
+    // them (mu in k_lap, the collision in k_grad, the Runge-Kutta stage in k_stream) and the
+    // node kernels mu, collide and rk run over nodes Nint .. Ng-1 only.  0: no split.
+    int Nint;
     // mesh tables (device)
     const int SLBM_GLOBAL *lgid;      // [Nl] local node -> internal global node
     const double SLBM_GLOBAL *Ja;     // [d*d][Nl] J * d xi_a / d x_c, index (a*d + c)
@@ -118,9 +123,14 @@ constexpr int kNodeThreads = 256;
 // for the RK stages.  All launch on 'stream' and return the hipError_t of the launch as int.
 int launch_lap(int d, int N, const LaunchPlan &p, void *stream);
 int launch_mu(int d, int N, const LaunchPlan &p, void *stream);
-int launch_grad(int d, int N, const LaunchPlan &p, void *stream);
+// collide != 0 (in-step): element-interior nodes are collided here (see SolveDesc::Nint)
+int launch_grad(int d, int N, const LaunchPlan &p, int collide, void *stream);
 int launch_gavg(int d, int N, const LaunchPlan &p, void *stream);
+// use_aux: operator entry point (averaged gradients from aux, every node); else in-step
 int launch_collide(int d, int N, const LaunchPlan &p, int use_aux, void *stream);
+
+// stage 1..3: streams g0 (1) or g1 (2, 3) and finishes element-interior nodes with that
+// Runge-Kutta stage; stage 0 (operator entry point): streams g1, interior nodes get L
 int launch_stream(int d, int N, const LaunchPlan &p, int stage, void *stream);
 int launch_rk(int d, int N, const LaunchPlan &p, int stage, void *stream);
 int launch_density(int d, int N, const LaunchPlan &p, int which, void *stream);

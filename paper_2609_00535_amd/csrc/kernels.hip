@@ -7,7 +7,7 @@ namespace slbm {
 #define SLBM_DECLARE_SET(SFX)                                                                \
     int launch_lap_##SFX(int, int, const LaunchPlan &, void *);                              \
     int launch_mu_##SFX(int, int, const LaunchPlan &, void *);                               \
-    int launch_grad_##SFX(int, int, const LaunchPlan &, void *);                             \
+    int launch_grad_##SFX(int, int, const LaunchPlan &, int, void *);                        \
     int launch_gavg_##SFX(int, int, const LaunchPlan &, void *);                             \
     int launch_collide_##SFX(int, int, const LaunchPlan &, int, void *);                     \
     int launch_stream_##SFX(int, int, const LaunchPlan &, int, void *);                      \
@@ -41,7 +41,9 @@ bool supported_order(int d, int N) {
 
 int launch_lap(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(lap, p, stream); }
 int launch_mu(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(mu, p, stream); }
-int launch_grad(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(grad, p, stream); }
+int launch_grad(int d, int N, const LaunchPlan &p, int collide, void *stream) {
+    return SLBM_PICK(grad, p, collide, stream);
+}
 int launch_gavg(int d, int N, const LaunchPlan &p, void *stream) { return SLBM_PICK(gavg, p, stream); }
 int launch_collide(int d, int N, const LaunchPlan &p, int use_aux, void *stream) {
     return SLBM_PICK(collide, p, use_aux, stream);

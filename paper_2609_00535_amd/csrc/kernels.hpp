@@ -111,6 +111,7 @@ template <int D, int N, bool WIDE = true> struct Shape {
     static constexpr int NB = EPB * NLOC;  // nodes of one block
     static constexpr int NT = ((NB + 63) / 64) * 64;
     static constexpr int NG = D * (D + 1) / 2;
+    static constexpr int NINT = D == 2 ? (NP - 2) * (NP - 2) : (NP - 2) * (NP - 2) * (NP - 2);  // interior nodes
     // minimum waves per SIMD asked of the 3-D streaming kernels (caps their registers so
     // that three 256-thread blocks share a compute unit)
     static constexpr int WPE_STREAM = D == 3 ? 3 : 1;
@@ -284,6 +285,61 @@ __device__ __forceinline__ double dss_sum(P v, const NodeCopies &c, const int SL
 // Eq. (8): element part of the weak Laplacian, r = -sum_a D_a^T (G^{ab} D_b rho), plus the
 // wetting boundary integral s n.grad(rho) = s cos(theta) sqrt(2 beta/kappa) |(rho-rl)(rho-rv)|
 // ------------------------------------------------------------------------------------------
+// Eq. (2): mu = mu0(rho) - kappa lap, lap = DSS(r) / M (reading: mu0 = 2 beta (rho-rl)(rho-rv)(2rho-rl-rv))
+__device__ __forceinline__ double mu_of(const SolveDesc &sd, double pr, double lap) {
+    const double rl = sd.rho_l, rv = sd.rho_v;
+    const double mu0 = 2.0 * sd.beta * (pr - rl) * (pr - rv) * (2.0 * pr - rl - rv);
+    return mu0 - sd.kappa * lap;
+}
+
+// element node n (i fastest) on the element's boundary?  Nodes inside an element belong to
+// it alone (the fused path is selected only for meshes where that holds).
+// (bitwise, not short-circuit: a chain of || becomes a chain of divergent branches, and
+// hipcc has been seen to reuse a live register inside such a chain at N = 3 in 2-D)
+template <int D, int NP>
+__device__ __forceinline__ bool on_elem_boundary(int n) {
+    const int i = n % NP, j = (n / NP) % NP;
+    int b = (int)(i == 0) | (int)(i == NP - 1) | (int)(j == 0) | (int)(j == NP - 1);
+    if constexpr (D == 3) {
+        const int k = n / (NP * NP);
+        b |= (int)(k == 0) | (int)(k == NP - 1);
+    }
+    return b != 0;
+}
+
+// Element-interior split: the local nodes of an element are stored interior-first (the
+// (N-1)^d interior nodes in natural order, then the boundary nodes in natural order), so
+// that lanes of an element take interior and boundary nodes in separate runs (3-D N = 5:
+// the first wave is exactly the 64 interior nodes).  split_node maps the storage position
+// m within the element to the element node n = i + (N+1) j (+ (N+1)^2 k).
+template <int NP>
+__device__ __forceinline__ int ring_node(int b) {  // b-th boundary node of an NP x NP face, natural order
+    constexpr int NI = NP - 2;
+    if (b < NP) return b;  // row j = 0
+    b -= NP;
+    if (b < 2 * NI) return (1 + b / 2) * NP + ((b & 1) ? NP - 1 : 0);
+    return (NP - 1) * NP + (b - 2 * NI);  // row j = N
+}
+template <int D, int NP>
+__device__ __forceinline__ int split_node(int m) {
+    constexpr int NI = NP - 2;
+    constexpr int NINT = D == 2 ? NI * NI : NI * NI * NI;
+    if (m < NINT) {
+        const int i = 1 + m % NI, j = 1 + (m / NI) % NI;
+        return D == 2 ? i + NP * j : i + NP * j + NP * NP * (1 + m / (NI * NI));
+    }
+    const int b = m - NINT;
+    if constexpr (D == 2) {
+        return ring_node<NP>(b);
+    } else {
+        constexpr int P2 = NP * NP, RING = 4 * (NP - 1);
+        if (b < P2) return b;  // face k = 0
+        const int r = b - P2;
+        if (r < NI * RING) return (1 + r / RING) * P2 + ring_node<NP>(r % RING);
+        return (NP - 1) * P2 + (r - NI * RING);  // face k = N
+    }
+}
+
 template <int D, int NB, int NG>
 __device__ __forceinline__ void metric_times_grad(const double *g, const double *d, double *sv, int tid) {
     // v_a = sum_b G_ab d_b (ascending b from 0)
@@ -314,40 +370,46 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_lap(Laun
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
     const int tid = threadIdx.x;
     double dmv = 0.0;  // fetched by the active lanes (every lane below (N+1)^2 is active)
-    const int es = tid / NLOC, n = tid - es * NLOC;
+    // storage position m of the lane's node within its element, element node n, and the
+    // node's LDS slot ln (natural order within the element)
+    const int es = tid / NLOC, m = tid - es * NLOC;
+    const int n = sd.Nint > 0 ? split_node<D, NP>(m) : m;
+    const int ln = es * NLOC + n;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    double rh = 0.0;
+    const int l = e * NLOC + m;
+    // element-interior node of a split mesh: its Laplacian has this copy alone, so mu is
+    // finished here (as k_mu would: the sum of one copy, times 1/M)
+    const bool own = sd.Nint > 0 && m < S::NINT;
+    double rh = 0.0, mi = 0.0;
+    int G = 0;
     double g[S::NG];
     WallLap<D> wl;
     if (act) {
         dmv = dm_fetch<NP>(sd, tid);
-        const int G = sd.lgid[l];
+        G = sd.lgid[l];
 #pragma unroll
         for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * sd.Nl + l];
         load_wall_lap<D>(sd, l, wl);
         rh = sd.rho[G];
-        srho[tid] = rh;
+        if (own) mi = sd.Minv[G];
+        srho[ln] = rh;
     }
     dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (act) {
         double d[D];
         grad_ref<D, NP>(sD, srho + es * NLOC, n, d);
-        metric_times_grad<D, NB, S::NG>(g, d, sv, tid);
+        metric_times_grad<D, NB, S::NG>(g, d, sv, ln);
     }
     __syncthreads();
     if (!act) return;
     const double r = -div_refT<D, NP>(sD, sv + es * NLOC, NB, n);
+    if (own) {
+        sd.mu[G] = mu_of(sd, rh, (0.0 + r) * mi);  // no wall faces pass through an interior node
+        return;
+    }
     sd.rl[l] = wall_lap_term<D>(sd, wl, rh, r);
-}
-
-// Eq. (2): mu = mu0(rho) - kappa lap, lap = DSS(r) / M (reading: mu0 = 2 beta (rho-rl)(rho-rv)(2rho-rl-rv))
-__device__ __forceinline__ double mu_of(const SolveDesc &sd, double pr, double lap) {
-    const double rl = sd.rho_l, rv = sd.rho_v;
-    const double mu0 = 2.0 * sd.beta * (pr - rl) * (pr - rv) * (2.0 * pr - rl - rv);
-    return mu0 - sd.kappa * lap;
 }
 
 template <int DQ, int N, bool SINGLE>
@@ -356,77 +418,12 @@ __global__ __launch_bounds__(kNodeThreads) void k_mu(LaunchPlan p) {
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
+    const int G = sd.Nint + bs.local * kNodeThreads + threadIdx.x;  // interior nodes: k_lap
     if (G >= sd.Ng) return;
     const NodeCopies c = sd.gcopy[G];
     const double mi = sd.Minv[G], pr = sd.rho[G];
     const double lap = dss_sum(sd.rl, c, sd.csr_idx) * mi;
     sd.mu[G] = mu_of(sd, pr, lap);
-}
-
-// lumped-mass weighted element gradients w Ja^T grad_ref of rho and mu (for the collision)
-template <int DQ, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_grad(LaunchPlan p) {
-    constexpr int D = DimOf<DQ>::v;
-    using S = Shape<D, N, WIDE>;
-    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
-    __shared__ double sD[NP * NP];
-    __shared__ double sf[2 * NB];
-    const BlockSlot bs = block_slot<SINGLE>(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of<SINGLE>(p, bs);
-    const int tid = threadIdx.x;
-    double dmv = 0.0;  // fetched by the active lanes (every lane below (N+1)^2 is active)
-    const int es = tid / NLOC, n = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
-    double J[D][D];
-    double w = 0.0;
-    if (act) {
-        dmv = dm_fetch<NP>(sd, tid);
-        const int G = sd.lgid[l];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
-        w = sd.wn[n];
-        sf[tid] = sd.rho[G];
-        sf[NB + tid] = sd.mu[G];
-    }
-    dm_store<NP>(sD, tid, dmv);
-    __syncthreads();
-    if (!act) return;
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-        double d[D];
-        grad_ref<D, NP>(sD, sf + f * NB + es * NLOC, n, d);
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) s += J[a][c] * d[a];
-            sd.gl[(size_t)(f * D + c) * sd.Nl + l] = w * s;
-        }
-    }
-}
-
-// averaged gradients DSS(gl) / M into aux [2d][Ng] (operator entry point)
-template <int DQ, int N, bool SINGLE>
-__global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
-    constexpr int D = DimOf<DQ>::v;
-    const BlockSlot bs = block_slot<SINGLE>(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of<SINGLE>(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
-    if (G >= sd.Ng) return;
-    const NodeCopies cp = sd.gcopy[G];
-    const double mi = sd.Minv[G];
-    double s[2 * D];
-#pragma unroll
-    for (int c = 0; c < 2 * D; ++c) s[c] = dss_sum(sd.gl + (size_t)c * sd.Nl, cp, sd.csr_idx);
-#pragma unroll
-    for (int c = 0; c < 2 * D; ++c) sd.aux[(size_t)c * sd.Ng + G] = s[c] * mi;
 }
 
 // Eq. (4) with (A.2), (A.6)-(A.7) and F** of Sec. 2.1 at one node:
@@ -476,6 +473,100 @@ __device__ __forceinline__ void collide_node(const SolveDesc &sd, const double *
     for (int q = 0; q < Q; ++q) fs[q] = collide_q<Q, D>(sd, q, f[q], pr, c);
 }
 
+// lumped-mass weighted element gradients w Ja^T grad_ref of rho and mu (for the collision);
+// with collide != 0 the element-interior nodes of a split mesh (one copy each, so their
+// averaged gradient is this copy's times 1/M) are collided here as k_collide would
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_grad(LaunchPlan p, int collide) {
+    constexpr int D = DimOf<DQ>::v;
+    constexpr int Q = QOfDQ<DQ>::v;
+    using S = Shape<D, N, WIDE>;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    __shared__ double sD[NP * NP];
+    __shared__ double sf[2 * NB];
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x;
+    double dmv = 0.0;  // fetched by the active lanes (every lane below (N+1)^2 is active)
+    // storage position m of the lane's node within its element, element node n, and the
+    // node's LDS slot ln (natural order within the element)
+    const int es = tid / NLOC, m = tid - es * NLOC;
+    const int n = sd.Nint > 0 ? split_node<D, NP>(m) : m;
+    const int ln = es * NLOC + n;
+    const int e = bs.local * S::EPB + es;
+    const bool act = tid < NB && e < sd.E;
+    const int l = e * NLOC + m;
+    const bool own = collide && sd.Nint > 0 && m < S::NINT;
+    const size_t Ng = sd.Ng;
+    double J[D][D];
+    double w = 0.0, pr = 0.0, mi = 0.0;
+    double f[Q];
+    int G = 0;
+    if (act) {
+        dmv = dm_fetch<NP>(sd, tid);
+        G = sd.lgid[l];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+        w = sd.wn[n];
+        pr = sd.rho[G];
+        sf[ln] = pr;
+        sf[NB + ln] = sd.mu[G];
+        if (own) {
+            mi = sd.Minv[G];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
+        }
+    }
+    dm_store<NP>(sD, tid, dmv);
+    __syncthreads();
+    if (!act) return;
+    double gs[2][D];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        double d[D];
+        grad_ref<D, NP>(sD, sf + k * NB + es * NLOC, n, d);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) s += J[a][c] * d[a];
+            gs[k][c] = w * s;
+            if (!own) sd.gl[(size_t)(k * D + c) * sd.Nl + l] = gs[k][c];
+        }
+    }
+    if (!own) return;
+    double gr[D], gm[D], fs[Q];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        gr[c] = (0.0 + gs[0][c]) * mi;
+        gm[c] = (0.0 + gs[1][c]) * mi;
+    }
+    collide_node<Q, D>(sd, f, pr, gr, gm, fs);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sd.g0[q * Ng + G] = fs[q];
+}
+
+// averaged gradients DSS(gl) / M into aux [2d][Ng] (operator entry point)
+template <int DQ, int N, bool SINGLE>
+__global__ __launch_bounds__(kNodeThreads) void k_gavg(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int G = bs.local * kNodeThreads + threadIdx.x;
+    if (G >= sd.Ng) return;
+    const NodeCopies cp = sd.gcopy[G];
+    const double mi = sd.Minv[G];
+    double s[2 * D];
+#pragma unroll
+    for (int c = 0; c < 2 * D; ++c) s[c] = dss_sum(sd.gl + (size_t)c * sd.Nl, cp, sd.csr_idx);
+#pragma unroll
+    for (int c = 0; c < 2 * D; ++c) sd.aux[(size_t)c * sd.Ng + G] = s[c] * mi;
+}
+
 template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_aux) {
     constexpr int D = DimOf<DQ>::v;
@@ -483,7 +574,8 @@ __global__ __launch_bounds__(kNodeThreads) void k_collide(LaunchPlan p, int use_
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
+    // in-step: element-interior nodes were collided by k_grad; the operator covers every node
+    const int G = (use_aux ? 0 : sd.Nint) + bs.local * kNodeThreads + threadIdx.x;
     if (G >= sd.Ng) return;
     const size_t Ng = sd.Ng;
     double gr[D], gm[D];
@@ -524,12 +616,16 @@ template <int D> struct NodeGeo {
     WallFlux<D> wf;
 };
 template <int D>
-__device__ __forceinline__ void load_geo(const SolveDesc &sd, int n, int l, NodeGeo<D> &g) {
+__device__ __forceinline__ void load_metric(const SolveDesc &sd, int n, int l, NodeGeo<D> &g) {
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int c = 0; c < D; ++c) g.J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
     g.w = sd.wn[n];
+}
+template <int D>
+__device__ __forceinline__ void load_geo(const SolveDesc &sd, int n, int l, NodeGeo<D> &g) {
+    load_metric<D>(sd, n, l, g);
     load_wall_flux<D>(sd, l, g.wf);
 }
 
@@ -583,7 +679,58 @@ __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const doubl
     }
 }
 
-// stage 1 streams g0, stages 2-3 stream g1
+// SSP-RK3 stage combination after DSS(r)/M, and the new stage's density (Eq. (10))
+//   stage 0 (operator entry point only): g1 = L(g1)
+//   stage 1: g1 = g0 + dt L(g0); stage 2: g1 = 3/4 g0 + 1/4 (g1 + dt L(g1));
+//   stage 3: f = (g0 + 2 (g1 + dt L(g1))) / 3
+template <int Q>
+__device__ __forceinline__ double rk_combine(int stage, double L, double gin, double g0, double dt) {
+    const double x = gin + dt * L;
+    if (stage == 0) return L;  // operator entry point: the assembled right-hand side
+    if (stage == 1) return x;
+    if (stage == 2) return 0.75 * g0 + 0.25 * x;
+    return (g0 + 2.0 * x) / 3.0;
+}
+
+// Element-interior node of a split mesh (one copy, no wall face): its residual needs no
+// summation, so the stage is finished here as k_rk would (L = (0 + r) / M, the stage
+// combination and the new density in ascending q); stage 0 stores L (operator entry point)
+template <int Q, int D, int N, bool WIDE>
+__device__ __forceinline__ void stream_finish(const SolveDesc &sd, const double *sD, const double *sh,
+                                              const double *smu_e, int es, int n, int G, double pr,
+                                              const double *gq, const NodeGeo<D> &geo, int stage) {
+    using S = Shape<D, N, WIDE>;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    const size_t Ng = sd.Ng;
+    double SLBM_GLOBAL *gout = stage == 3 ? sd.f : sd.g1;
+    // the loads go out before the first store
+    const double mi = sd.Minv[G], dt = sd.dt;
+    double g0v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g0v[q] = 0.0;
+    if (stage >= 2) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) g0v[q] = sd.g0[q * Ng + G];
+    }
+    double dmu[D];
+    grad_ref<D, NP>(sD, smu_e, n, dmu);
+    double rho = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double L = 0.0;
+        if (q > 0) {
+            const double r = residual_q<Q, D, NP>(sd, q, sD, sh + (q - 1) * NB + es * NLOC, n, dmu, pr, gq[q],
+                                                  gq[Lat<Q>::opp[q]], geo);
+            L = (0.0 + r) * mi;
+        }
+        const double out = rk_combine<Q>(stage, L, gq[q], g0v[q], dt);
+        gout[q * Ng + G] = out;
+        rho += out;
+    }
+    sd.rho[G] = rho;
+}
+
+// stage 1 streams g0, stages 2-3 stream g1 (stage 0, the operator entry point, streams g1)
 template <int DQ, int N, bool WIDE, bool SINGLE>
 __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ>::v, N, WIDE>::WPE_STREAM)) void k_stream(LaunchPlan p, int stage) {
     constexpr int D = DimOf<DQ>::v;
@@ -599,42 +746,45 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     const double SLBM_GLOBAL *g = stage == 1 ? sd.g0 : sd.g1;
     const int tid = threadIdx.x;
     double dmv = 0.0;  // fetched by the active lanes (every lane below (N+1)^2 is active)
-    const int es = tid / NLOC, n = tid - es * NLOC;
+    // storage position m of the lane's node within its element, element node n, and the
+    // node's LDS slot ln (natural order within the element)
+    const int es = tid / NLOC, m = tid - es * NLOC;
+    const int n = sd.Nint > 0 ? split_node<D, NP>(m) : m;
+    const int ln = es * NLOC + n;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + n;
+    const int l = e * NLOC + m;
     const size_t Ng = sd.Ng;
+    const bool own = sd.Nint > 0 && m < S::NINT;
     double pr = 0.0;
     double gq[Q];
     NodeGeo<D> geo;
+    int G = 0;
+    // the wall data of boundary nodes are loaded after the barrier (an interior node has
+    // none): they are not live across it, and not at all on the interior path
+    geo.wf.cnt = 0;
     if (act) {
         dmv = dm_fetch<NP>(sd, tid);
-        const int G = sd.lgid[l];
-        load_geo<D>(sd, n, l, geo);
+        G = sd.lgid[l];
+        load_metric<D>(sd, n, l, geo);
         pr = sd.rho[G];
-        smu[tid] = sd.mu[G];
+        smu[ln] = sd.mu[G];
+        gq[0] = 0.0;
+        if (own) gq[0] = g[G];
 #pragma unroll
         for (int q = 1; q < Q; ++q) gq[q] = g[q * Ng + G];
 #pragma unroll
-        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + tid] = gq[q] - sd.tw[wcls<Q>(q)] * pr;
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + ln] = gq[q] - sd.tw[wcls<Q>(q)] * pr;
     }
     dm_store<NP>(sD, tid, dmv);
     __syncthreads();
     if (!act) return;
+    if (own) {
+        stream_finish<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, G, pr, gq, geo, stage);
+        return;
+    }
+    load_wall_flux<D>(sd, l, geo.wf);
     stream_residual<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
-}
-
-// SSP-RK3 stage combination after DSS(r)/M, and the new stage's density (Eq. (10))
-//   stage 0 (operator entry point only): g1 = L(g1)
-//   stage 1: g1 = g0 + dt L(g0); stage 2: g1 = 3/4 g0 + 1/4 (g1 + dt L(g1));
-//   stage 3: f = (g0 + 2 (g1 + dt L(g1))) / 3
-template <int Q>
-__device__ __forceinline__ double rk_combine(int stage, double L, double gin, double g0, double dt) {
-    const double x = gin + dt * L;
-    if (stage == 0) return L;  // operator entry point: the assembled right-hand side
-    if (stage == 1) return x;
-    if (stage == 2) return 0.75 * g0 + 0.25 * x;
-    return (g0 + 2.0 * x) / 3.0;
 }
 
 template <int DQ, int N, bool SINGLE>
@@ -644,7 +794,7 @@ __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     const BlockSlot bs = block_slot<SINGLE>(p);
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
-    const int G = bs.local * kNodeThreads + threadIdx.x;
+    const int G = sd.Nint + bs.local * kNodeThreads + threadIdx.x;  // interior nodes: k_stream
     if (G >= sd.Ng) return;
     const size_t Ng = sd.Ng, Nl = sd.Nl;
     const double SLBM_GLOBAL *gin = stage == 1 ? sd.g0 : sd.g1;
@@ -784,21 +934,6 @@ template <int D> struct CopyList {
     int cp[K];
     int nc;
 };
-// element node n (i fastest) on the element's boundary?  Nodes inside an element belong to
-// it alone (the fused path is selected only for meshes where that holds).
-// (bitwise, not short-circuit: a chain of || becomes a chain of divergent branches, and
-// hipcc has been seen to reuse a live register inside such a chain at N = 3 in 2-D)
-template <int D, int NP>
-__device__ __forceinline__ bool on_elem_boundary(int n) {
-    const int i = n % NP, j = (n / NP) % NP;
-    int b = (int)(i == 0) | (int)(i == NP - 1) | (int)(j == 0) | (int)(j == NP - 1);
-    if constexpr (D == 3) {
-        const int k = n / (NP * NP);
-        b |= (int)(k == 0) | (int)(k == NP - 1);
-    }
-    return b != 0;
-}
-
 template <int D, int NP, bool PRED>
 __device__ __forceinline__ void load_copies(const SolveDesc &sd, int n, int l, CopyList<D> &c) {
     c.cp[0] = l;
@@ -1413,7 +1548,7 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
     }
 #define SLBM_CASE_lap(DD, NN) SLBM_ELEM_CASE(k_lap, DD, NN)
 #define SLBM_CASE_mu(DD, NN) SLBM_NODE_CASE(k_mu, DD, NN)
-#define SLBM_CASE_grad(DD, NN) SLBM_ELEM_CASE(k_grad, DD, NN)
+#define SLBM_CASE_grad(DD, NN) SLBM_ELEM_CASE(k_grad, DD, NN, collide)
 #define SLBM_CASE_gavg(DD, NN) SLBM_NODE_CASE(k_gavg, DD, NN)
 #define SLBM_CASE_collide(DD, NN) SLBM_NODE_CASE(k_collide, DD, NN, use_aux)
 #define SLBM_CASE_stream(DD, NN) SLBM_ELEM_CASE(k_stream, DD, NN, stage)
@@ -1438,7 +1573,9 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 #define SLBM_LAUNCHER_SET(SFX, ORDERS)                                                       \
     int launch_lap_##SFX(int d, int N, const LaunchPlan &p, void *stream) { SLBM_DISPATCH(ORDERS, lap); } \
     int launch_mu_##SFX(int d, int N, const LaunchPlan &p, void *stream) { SLBM_DISPATCH(ORDERS, mu); } \
-    int launch_grad_##SFX(int d, int N, const LaunchPlan &p, void *stream) { SLBM_DISPATCH(ORDERS, grad); } \
+    int launch_grad_##SFX(int d, int N, const LaunchPlan &p, int collide, void *stream) {                \
+        SLBM_DISPATCH(ORDERS, grad);                                                         \
+    }                                                                                        \
     int launch_gavg_##SFX(int d, int N, const LaunchPlan &p, void *stream) { SLBM_DISPATCH(ORDERS, gavg); } \
     int launch_collide_##SFX(int d, int N, const LaunchPlan &p, int use_aux, void *stream) {             \
         SLBM_DISPATCH(ORDERS, collide);                                                      \

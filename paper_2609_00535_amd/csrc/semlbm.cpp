@@ -257,27 +257,42 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
         c->E = E;
         c->Nl = Nl;
         c->Ng = n_global;
-        // DSS gather lists: local copies of each global node in ascending local order
-        c->csr_ptr.assign(n_global + 1, 0);
-        for (int64_t l = 0; l < Nl; ++l) c->csr_ptr[c->lgid[l] + 1]++;
-        for (int64_t g = 0; g < n_global; ++g) c->csr_ptr[g + 1] += c->csr_ptr[g];
-        c->csr_idx.assign(Nl, 0);
-        {
+        // DSS gather lists of the current numbering: local copies of each global node in
+        // ascending local order, and the first two copies of every node (read by the node
+        // kernels in one load)
+        auto build_copies = [&]() {
+            c->csr_ptr.assign(n_global + 1, 0);
+            for (int64_t l = 0; l < Nl; ++l) c->csr_ptr[c->lgid[l] + 1]++;
+            for (int64_t g = 0; g < n_global; ++g) c->csr_ptr[g + 1] += c->csr_ptr[g];
+            c->csr_idx.assign(Nl, 0);
             std::vector<int32_t> fill(c->csr_ptr.begin(), c->csr_ptr.end() - 1);
             for (int64_t l = 0; l < Nl; ++l) c->csr_idx[fill[c->lgid[l]]++] = (int32_t)l;
-        }
-        // first two copies of every global node, read by the node kernels in one load
-        c->gcopy.assign((size_t)4 * n_global, 0);
-        for (int64_t g = 0; g < n_global; ++g) {
-            const int k0 = c->csr_ptr[g], nc = c->csr_ptr[g + 1] - k0;
-            c->gcopy[4 * g] = k0;
-            c->gcopy[4 * g + 1] = nc;
-            c->gcopy[4 * g + 2] = c->csr_idx[k0];
-            c->gcopy[4 * g + 3] = c->csr_idx[nc > 1 ? k0 + 1 : k0];
-        }
+            c->gcopy.assign((size_t)4 * n_global, 0);
+            for (int64_t g = 0; g < n_global; ++g) {
+                const int k0 = c->csr_ptr[g], nc = c->csr_ptr[g + 1] - k0;
+                c->gcopy[4 * g] = k0;
+                c->gcopy[4 * g + 1] = nc;
+                c->gcopy[4 * g + 2] = c->csr_idx[k0];
+                c->gcopy[4 * g + 3] = c->csr_idx[nc > 1 ? k0 + 1 : k0];
+            }
+        };
+        build_copies();
         // most local copies of any global node
         c->vmax = 0;
         for (int64_t g = 0; g < n_global; ++g) c->vmax = std::max<int>(c->vmax, c->csr_ptr[g + 1] - c->csr_ptr[g]);
+        // nodes strictly inside an element (not on its boundary)
+        std::vector<char> on_bnd(nloc, 0);
+        for (int n = 0; n < nloc; ++n)
+            for (int a = 0; a < dim; ++a) {
+                const int i = c->along(n, a);
+                if (i == 0 || i == N) on_bnd[n] = 1;
+            }
+        bool interior_single = true;  // every such node belongs to its element alone
+        for (int64_t e = 0; e < E && interior_single; ++e)
+            for (int n = 0; n < nloc; ++n) {
+                const int g = c->lgid[e * nloc + n];
+                if (!on_bnd[n] && c->csr_ptr[g + 1] - c->csr_ptr[g] != 1) interior_single = false;
+            }
         {
             // fused kernels finish each summation by gathering all copies at every copy: the
             // right trade while the state stays in the device's caches; meshes over 2^20 local
@@ -286,24 +301,31 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
             const char *nf = std::getenv("SLBM_UNFUSED");
             const char *ff = std::getenv("SLBM_FUSED");
             const bool large = Nl > kUnfusedAboveLocalNodes;
-            // nodes inside an element must belong to it alone (the fused kernels skip their
-            // copy lists)
-            std::vector<char> on_bnd(nloc, 0);
-            for (int n = 0; n < nloc; ++n)
-                for (int a = 0; a < dim; ++a) {
-                    const int i = c->along(n, a);
-                    if (i == 0 || i == N) on_bnd[n] = 1;
-                }
-            bool interior_single = true;
-            for (int64_t e = 0; e < E && interior_single; ++e)
-                for (int n = 0; n < nloc; ++n) {
-                    const int g = c->lgid[e * nloc + n];
-                    if (!on_bnd[n] && c->csr_ptr[g + 1] - c->csr_ptr[g] != 1) interior_single = false;
-                }
+            // the fused kernels skip the copy lists of element-interior nodes
             const bool fits = c->vmax <= kCopySlots[dim - 2] && interior_single;
             c->fused = fits && !large;
             if (nf && nf[0] == '1') c->fused = false;
             if (ff && ff[0] == '1' && fits) c->fused = true;
+        }
+        // Element-interior split (unfused path): the element-interior nodes are numbered first,
+        // element by element in local order, then the others by first appearance; the element
+        // kernels finish the interior nodes and the node kernels run over the rest only.
+        c->Nint = 0;
+        const char *ns = std::getenv("SLBM_NO_SPLIT");
+        if (!c->fused && interior_single && !(ns && ns[0] == '1')) {
+            std::vector<int32_t> renum(n_global, -1);
+            int32_t next = 0;
+            for (int64_t e = 0; e < E; ++e)
+                for (int n = 0; n < nloc; ++n)
+                    if (!on_bnd[n]) renum[c->lgid[e * nloc + n]] = next++;
+            c->Nint = next;
+            for (int64_t l = 0; l < Nl; ++l)
+                if (renum[c->lgid[l]] < 0) renum[c->lgid[l]] = next++;
+            std::vector<int32_t> ig2ug(n_global);
+            for (int64_t g = 0; g < n_global; ++g) ig2ug[renum[g]] = c->ig2ug[g];
+            c->ig2ug.swap(ig2ug);
+            for (int64_t l = 0; l < Nl; ++l) c->lgid[l] = renum[c->lgid[l]];
+            build_copies();
         }
         // per-local-node copy lists (fused path only): the ascending local copies of its global
         // node in kCopySlots[dim-2] rows, -1 padded, so the fused kernels load every slot
@@ -560,6 +582,7 @@ void slbm_ctx::layout() {
     epb = epb_for(dim_, N, E);
     n_eblocks = (int)((E + epb - 1) / epb);
     n_nblocks = (int)((Ng + kNodeThreads - 1) / kNodeThreads);
+    n_sblocks = (int)((Ng - Nint + kNodeThreads - 1) / kNodeThreads);
     off.desc = take(sizeof(SolveDesc));
     off.eplan = take(sizeof(int) * 2 * (size_t)n_eblocks);
     off.nplan = take(sizeof(int) * 2 * (size_t)n_nblocks);
@@ -610,6 +633,7 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
         d.E = (int)c->E;
         d.Nl = (int)c->Nl;
         d.Ng = (int)c->Ng;
+        d.Nint = (int)c->Nint;
         d.lgid = at<int>(b, c->off.lgid);
         d.Ja = at<double>(b, c->off.Ja);
         d.G = at<double>(b, c->off.G);
@@ -671,23 +695,75 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
         c->nplan.one = d;
         c->nplan.epb = 0;
         c->nplan.grid = c->n_nblocks;
+        // the node kernels past the interior range: the same (unused, single-solve) tables,
+        // fewer blocks
+        c->splan = c->nplan;
+        c->splan.nblocks = c->n_sblocks;
+        c->splan.grid = c->n_sblocks;
         const int dim = c->dim;
         const size_t ng = (size_t)dim * (dim + 1) / 2;
         int e = 0;
         auto up = [&](size_t off, const void *src, size_t n) {
             if (e == 0 && n) e = (int)hipMemcpyAsync((char *)b + off, src, n, hipMemcpyHostToDevice, st);
         };
+        // Element-interior split: the device stores each element's local nodes interior-first
+        // (interior nodes, then boundary nodes, each in natural order; the kernels' lane map
+        // is the inverse).  Host tables stay in natural order; permuted copies are uploaded.
+        const int64_t Nl = c->Nl, nloc = c->nloc;
+        std::vector<int32_t> pos;  // natural element node -> storage position
+        if (c->Nint > 0) {
+            pos.assign(nloc, 0);
+            int m = 0;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int n = 0; n < nloc; ++n) {
+                    bool bnd = false;
+                    for (int a = 0; a < dim; ++a) {
+                        const int i = c->along(n, a);
+                        if (i == 0 || i == c->N) bnd = true;
+                    }
+                    if (bnd == (pass == 1)) pos[n] = m++;
+                }
+        }
+        auto lmap = [&](int64_t l) -> int64_t { return pos.empty() ? l : (l / nloc) * nloc + pos[l % nloc]; };
+        auto perm_int = [&](const std::vector<int32_t> &v, int fields) {
+            std::vector<int32_t> o(v.size());
+            for (int k = 0; k < fields; ++k)
+                for (int64_t l = 0; l < Nl; ++l) o[(size_t)k * Nl + lmap(l)] = v[(size_t)k * Nl + l];
+            return o;
+        };
+        auto perm_dbl = [&](const std::vector<double> &v, int fields) {
+            std::vector<double> o(v.size());
+            for (int k = 0; k < fields; ++k)
+                for (int64_t l = 0; l < Nl; ++l) o[(size_t)k * Nl + lmap(l)] = v[(size_t)k * Nl + l];
+            return o;
+        };
+        std::vector<int32_t> lgid_u, lwall_u, csr_u, gcopy_u;
+        std::vector<double> Ja_u, G_u;
+        const bool perm = !pos.empty();
+        if (perm) {
+            lgid_u = perm_int(c->lgid, 1);
+            lwall_u = perm_int(c->lwall, 1);
+            Ja_u = perm_dbl(c->Ja, dim * dim);
+            G_u = perm_dbl(c->Gm, (int)ng);
+            csr_u.resize(c->csr_idx.size());
+            for (size_t k = 0; k < csr_u.size(); ++k) csr_u[k] = (int32_t)lmap(c->csr_idx[k]);
+            gcopy_u = c->gcopy;
+            for (size_t g = 0; g < gcopy_u.size() / 4; ++g) {
+                gcopy_u[4 * g + 2] = (int32_t)lmap(gcopy_u[4 * g + 2]);
+                gcopy_u[4 * g + 3] = (int32_t)lmap(gcopy_u[4 * g + 3]);
+            }
+        }
         up(c->off.desc, &d, sizeof d);
         up(c->off.eplan, ep.data(), sizeof(int) * ep.size());
         up(c->off.nplan, np_.data(), sizeof(int) * np_.size());
-        up(c->off.lgid, c->lgid.data(), sizeof(int) * c->Nl);
-        up(c->off.gcopy, c->gcopy.data(), sizeof(int) * c->gcopy.size());
-        up(c->off.csr_idx, c->csr_idx.data(), sizeof(int) * c->Nl);
+        up(c->off.lgid, (perm ? lgid_u : c->lgid).data(), sizeof(int) * c->Nl);
+        up(c->off.gcopy, (perm ? gcopy_u : c->gcopy).data(), sizeof(int) * c->gcopy.size());
+        up(c->off.csr_idx, (perm ? csr_u : c->csr_idx).data(), sizeof(int) * c->Nl);
         up(c->off.lcp, c->lcp.data(), sizeof(int) * c->lcp.size());
-        up(c->off.lwall, c->lwall.data(), sizeof(int) * c->Nl);
+        up(c->off.lwall, (perm ? lwall_u : c->lwall).data(), sizeof(int) * c->Nl);
         up(c->off.w_dat, c->w_dat.data(), sizeof(double) * c->w_dat.size());
-        up(c->off.Ja, c->Ja.data(), sizeof(double) * dim * dim * c->Nl);
-        up(c->off.G, c->Gm.data(), sizeof(double) * ng * c->Nl);
+        up(c->off.Ja, (perm ? Ja_u : c->Ja).data(), sizeof(double) * dim * dim * c->Nl);
+        up(c->off.G, (perm ? G_u : c->Gm).data(), sizeof(double) * ng * c->Nl);
         up(c->off.Minv, c->Minv.data(), sizeof(double) * c->Ng);
         up(c->off.Dm, c->Dm.data(), sizeof(double) * c->Np * c->Np);
         up(c->off.wn, c->wn.data(), sizeof(double) * c->nloc);
@@ -798,7 +874,7 @@ extern "C" slbm_status slbm_set_state(slbm_ctx *c, const double *f, int64_t step
 // ------------------------------------------------------------------------------------------
 // time step
 // ------------------------------------------------------------------------------------------
-int slbm::enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &np, int64_t n,
+int slbm::enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &sp, int64_t n,
                         void *stream, bool fused) {
     int e = 0;
     if (fused) {
@@ -818,18 +894,18 @@ int slbm::enqueue_steps(int d, int N, const LaunchPlan &ep, const LaunchPlan &np
     for (int64_t s = 0; s < n && e == 0; ++s) {
         // chemical potential of the state's density (also stage 1's, R10)
         e = launch_lap(d, N, ep, stream);
-        if (!e) e = launch_mu(d, N, np, stream);
+        if (!e) e = launch_mu(d, N, sp, stream);
         // collision with averaged gradients
-        if (!e) e = launch_grad(d, N, ep, stream);
-        if (!e) e = launch_collide(d, N, np, 0, stream);
+        if (!e) e = launch_grad(d, N, ep, 1, stream);
+        if (!e) e = launch_collide(d, N, sp, 0, stream);
         // three SSP-RK3 streaming stages
         for (int stage = 1; stage <= 3 && !e; ++stage) {
             if (stage > 1) {
                 e = launch_lap(d, N, ep, stream);
-                if (!e) e = launch_mu(d, N, np, stream);
+                if (!e) e = launch_mu(d, N, sp, stream);
             }
             if (!e) e = launch_stream(d, N, ep, stage, stream);
-            if (!e) e = launch_rk(d, N, np, stage, stream);
+            if (!e) e = launch_rk(d, N, sp, stage, stream);
         }
     }
     return e;
@@ -887,7 +963,7 @@ slbm_status slbm_ctx::enqueue(int64_t n) {
                 struct A { slbm_ctx *c; int steps; } a{this, sizes[k]};
                 auto fn = [](void *st, void *p) -> int {
                     A *x = (A *)p;
-                    return enqueue_steps(x->c->dq, x->c->N, x->c->eplan, x->c->nplan, x->steps, st,
+                    return enqueue_steps(x->c->dq, x->c->N, x->c->eplan, x->c->splan, x->steps, st,
                                          x->c->fused);
                 };
                 const int e = capture_graph(stream, &graph[k], fn, &a);
@@ -908,7 +984,7 @@ slbm_status slbm_ctx::enqueue(int64_t n) {
             return hip_check(e, "graph launch");
         }
     }
-    return hip_check(enqueue_steps(dq, N, eplan, nplan, n, stream, fused), "step launch");
+    return hip_check(enqueue_steps(dq, N, eplan, splan, n, stream, fused), "step launch");
 }
 
 int slbm_ctx::refresh_lap() {
@@ -975,16 +1051,16 @@ extern "C" slbm_status slbm_step_profile(slbm_ctx *c, int64_t n, double *ms, int
                 rec(8, [&] { return launch_fC(d, N, c->eplan, 3, c->stream); });
             }
             if (!c->fused) rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
-            if (!c->fused) rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
-            if (!c->fused) rec(2, [&] { return launch_grad(d, N, c->eplan, c->stream); });
-            if (!c->fused) rec(3, [&] { return launch_collide(d, N, c->nplan, 0, c->stream); });
+            if (!c->fused) rec(1, [&] { return launch_mu(d, N, c->splan, c->stream); });
+            if (!c->fused) rec(2, [&] { return launch_grad(d, N, c->eplan, 1, c->stream); });
+            if (!c->fused) rec(3, [&] { return launch_collide(d, N, c->splan, 0, c->stream); });
             for (int stage = 1; stage <= 3 && !c->fused; ++stage) {
                 if (stage > 1) {
                     rec(0, [&] { return launch_lap(d, N, c->eplan, c->stream); });
-                    rec(1, [&] { return launch_mu(d, N, c->nplan, c->stream); });
+                    rec(1, [&] { return launch_mu(d, N, c->splan, c->stream); });
                 }
                 rec(4, [&] { return launch_stream(d, N, c->eplan, stage, c->stream); });
-                rec(5, [&] { return launch_rk(d, N, c->nplan, stage, c->stream); });
+                rec(5, [&] { return launch_rk(d, N, c->splan, stage, c->stream); });
             }
             if (!e) e = (int)hipEventSynchronize(ev[2 * i - 1]);
             for (int j = 0; j < i && !e; ++j) {
@@ -1008,11 +1084,11 @@ int launch_kind(const slbm_ctx *c, int kind, int64_t i) {
     void *st = c->stream;
     switch (kind) {
     case 0: return launch_lap(d, N, c->eplan, st);
-    case 1: return launch_mu(d, N, c->nplan, st);
-    case 2: return launch_grad(d, N, c->eplan, st);
-    case 3: return launch_collide(d, N, c->nplan, 0, st);
+    case 1: return launch_mu(d, N, c->splan, st);
+    case 2: return launch_grad(d, N, c->eplan, 1, st);
+    case 3: return launch_collide(d, N, c->splan, 0, st);
     case 4: return launch_stream(d, N, c->eplan, 1 + (int)(i % 3), st);
-    case 5: return launch_rk(d, N, c->nplan, 1 + (int)(i % 3), st);
+    case 5: return launch_rk(d, N, c->splan, 1 + (int)(i % 3), st);
     case 6: return launch_fA(d, N, c->eplan, st);
     case 7: return launch_fB(d, N, c->eplan, st);
     case 8: return launch_fC(d, N, c->eplan, 1 + (int)(i % 3), st);
@@ -1217,7 +1293,7 @@ extern "C" slbm_status slbm_op_grad(slbm_ctx *c, const double *phi, double *grad
         if (!c || !phi || !grad) return SLBM_EINVAL;
         if (slbm_status s = c->require_bound(false)) return s;
         if (slbm_status s = c->put(c->desc.rho, phi, 1)) return s;
-        int e = launch_grad(c->dq, c->N, c->eplan, c->stream);
+        int e = launch_grad(c->dq, c->N, c->eplan, 0, c->stream);
         if (e == 0) e = launch_gavg(c->dq, c->N, c->nplan, c->stream);
         if (e) return c->hip_check(e, "op_grad");
         if (slbm_status s = c->get(c->desc.aux, grad, c->dim)) return s;
@@ -1233,8 +1309,8 @@ extern "C" slbm_status slbm_op_stream(slbm_ctx *c, const double *g, const double
         if (slbm_status s = c->put(c->desc.g1, g, c->Q)) return s;
         if (slbm_status s = c->put(c->desc.rho, rho, 1)) return s;
         if (slbm_status s = c->put(c->desc.mu, mu, 1)) return s;
-        int e = launch_stream(c->dq, c->N, c->eplan, 2, c->stream);
-        if (e == 0) e = launch_rk(c->dq, c->N, c->nplan, 0, c->stream);  // stage 0: L into g1
+        int e = launch_stream(c->dq, c->N, c->eplan, 0, c->stream);  // stage 0: L into g1
+        if (e == 0) e = launch_rk(c->dq, c->N, c->splan, 0, c->stream);
         if (e) return c->hip_check(e, "op_stream");
         if (slbm_status s = c->get(c->desc.g1, L, c->Q)) return s;
         return c->restore_density();

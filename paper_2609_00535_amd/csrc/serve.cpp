@@ -44,7 +44,7 @@ struct slbm_batch {
     struct Shape {
         int epb = 1;       // elements per block (1, or as many as fit in 256 threads)
         bool xcd = true;   // XCD-aware block order (contiguous ranges per die), else plain order
-        LaunchPlan ep{}, np{};
+        LaunchPlan ep{}, np{}, sp{};  // element, every node, nodes past the interior range
         double us = 0.0;   // measured device time of one step of the group (0: not measured)
     };
     struct Group {
@@ -55,7 +55,7 @@ struct slbm_batch {
         std::vector<Shape> shapes;
         int pick = 0;          // index into shapes
         bool measured = false; // pick chosen by timing (here or earlier, from the tuning cache)
-        LaunchPlan ep{}, np{}; // shapes[pick]
+        LaunchPlan ep{}, np{}, sp{}; // shapes[pick]
         SolveDesc *desc = nullptr;  // device
         double *diag_out = nullptr; // device [2 * members]
     };
@@ -86,9 +86,9 @@ struct slbm_batch {
         graph[0] = graph[1] = nullptr;
     }
 
-    int enqueue_group(const Group &g, const LaunchPlan &ep, const LaunchPlan &np, int64_t n,
+    int enqueue_group(const Group &g, const LaunchPlan &ep, const LaunchPlan &sp, int64_t n,
                       void *on = nullptr) const {
-        return enqueue_steps(g.d, g.N, ep, np, n, on ? on : stream, g.fused);
+        return enqueue_steps(g.d, g.N, ep, sp, n, on ? on : stream, g.fused);
     }
 
     // Concurrent groups: the groups share no data, so each group's chain of steps runs on a
@@ -118,7 +118,7 @@ struct slbm_batch {
         if (!concurrent || groups.size() < 2) {
             for (int64_t s = 0; s < n; ++s)
                 for (auto &g : groups) {
-                    const int e = enqueue_group(g, g.ep, g.np, 1);
+                    const int e = enqueue_group(g, g.ep, g.sp, 1);
                     if (e) return e;
                 }
             return 0;
@@ -129,7 +129,7 @@ struct slbm_batch {
         for (size_t gi = 0; gi < groups.size() && !e; ++gi) {
             hipStream_t ss = (hipStream_t)side[gi];
             e = (int)hipStreamWaitEvent(ss, (hipEvent_t)fork_ev, 0);
-            if (!e) e = enqueue_group(groups[gi], groups[gi].ep, groups[gi].np, n, ss);
+            if (!e) e = enqueue_group(groups[gi], groups[gi].ep, groups[gi].sp, n, ss);
             if (!e) e = (int)hipEventRecord((hipEvent_t)join_ev[gi], ss);
             if (!e) e = (int)hipStreamWaitEvent(st, (hipEvent_t)join_ev[gi], 0);
         }
@@ -182,7 +182,7 @@ struct slbm_batch {
             struct A { const slbm_batch *b; const Group *g; const Shape *s; } a{this, &g, &g.shapes[k]};
             auto fn = [](void *, void *p) -> int {
                 const A *x = (const A *)p;
-                return x->b->enqueue_group(*x->g, x->s->ep, x->s->np, 1);
+                return x->b->enqueue_group(*x->g, x->s->ep, x->s->sp, 1);
             };
             void *gr = nullptr;
             if (use_graph && stream != nullptr && capture_graph(stream, &gr, fn, &a)) {
@@ -224,6 +224,7 @@ struct slbm_batch {
         g.measured = measured;
         g.ep = g.shapes[k].ep;
         g.np = g.shapes[k].np;
+        g.sp = g.shapes[k].sp;
     }
 
     // Tune the groups that have more than one shape and no timing yet, when this call's
@@ -242,7 +243,7 @@ struct slbm_batch {
         if (mx == 0) return 0;
         drop_graphs();  // captured with the previous shapes
         for (size_t gi = 0; gi < groups.size(); ++gi)
-            if (used[gi] < mx && enqueue_group(groups[gi], groups[gi].ep, groups[gi].np, mx - used[gi]))
+            if (used[gi] < mx && enqueue_group(groups[gi], groups[gi].ep, groups[gi].sp, mx - used[gi]))
                 return -1;
         return mx;
     }
@@ -356,11 +357,12 @@ struct slbm_batch {
         if (tables_ok) return SLBM_OK;
         // one device block: per group [descs][e tables per shape][n tables per order][diag out]
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-        auto counts = [&](const Group &g, int epb, int *ne, int *nn) {
-            *ne = *nn = 0;
+        auto counts = [&](const Group &g, int epb, int *ne, int *nn, int *ns) {
+            *ne = *nn = *ns = 0;
             for (int i : g.idx) {
                 *ne += eblocks(members[i], epb);
                 *nn += members[i]->n_nblocks;
+                *ns += members[i]->n_sblocks;
             }
         };
         size_t total = 0;
@@ -368,10 +370,11 @@ struct slbm_batch {
         for (auto &g : groups) {
             goff.push_back(total);
             total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(double) * 2 * g.idx.size());
-            int ne = 0, nn = 0;
+            int ne = 0, nn = 0, ns = 0;
             for (auto &s : g.shapes) {
-                counts(g, s.epb, &ne, &nn);
-                total += al(sizeof(int) * 2 * table_len(ne, s.xcd)) + al(sizeof(int) * 2 * table_len(nn, s.xcd));
+                counts(g, s.epb, &ne, &nn, &ns);
+                total += al(sizeof(int) * 2 * table_len(ne, s.xcd)) + al(sizeof(int) * 2 * table_len(nn, s.xcd)) +
+                         al(sizeof(int) * 2 * table_len(ns, s.xcd));
             }
         }
         hipStream_t st = (hipStream_t)stream;
@@ -400,22 +403,27 @@ struct slbm_batch {
             o += al(sizeof(double) * 2 * g.idx.size());
             for (int k = 0; k < (int)g.idx.size(); ++k) dh[k] = members[g.idx[k]]->desc;
             for (auto &s : g.shapes) {
-                std::vector<int> le_s, le_l, ln_s, ln_l;  // logical order
+                std::vector<int> le_s, le_l, ln_s, ln_l, ls_s, ls_l;  // logical order
                 for (int k = 0; k < (int)g.idx.size(); ++k) {
                     slbm_ctx *c = members[g.idx[k]];
                     for (int b = 0; b < eblocks(c, s.epb); ++b) { le_s.push_back(k); le_l.push_back(b); }
                     for (int b = 0; b < c->n_nblocks; ++b) { ln_s.push_back(k); ln_l.push_back(b); }
+                    for (int b = 0; b < c->n_sblocks; ++b) { ls_s.push_back(k); ls_l.push_back(b); }
                 }
-                const int ne = (int)le_s.size(), nn = (int)ln_s.size();
-                const int te = table_len(ne, s.xcd), tn = table_len(nn, s.xcd);
+                const int ne = (int)le_s.size(), nn = (int)ln_s.size(), ns = (int)ls_s.size();
+                const int te = table_len(ne, s.xcd), tn = table_len(nn, s.xcd), ts = table_len(ns, s.xcd);
                 fill_table(reinterpret_cast<int *>(host.data() + o), ne, s.xcd, le_s, le_l);
                 int *et = reinterpret_cast<int *>(base + o);
                 o += al(sizeof(int) * 2 * te);
                 fill_table(reinterpret_cast<int *>(host.data() + o), nn, s.xcd, ln_s, ln_l);
                 int *nt = reinterpret_cast<int *>(base + o);
                 o += al(sizeof(int) * 2 * tn);
+                fill_table(reinterpret_cast<int *>(host.data() + o), ns, s.xcd, ls_s, ls_l);
+                int *st_ = reinterpret_cast<int *>(base + o);
+                o += al(sizeof(int) * 2 * ts);
                 s.ep = LaunchPlan{g.desc, et, et + te, te, 0, s.epb, te};
                 s.np = LaunchPlan{g.desc, nt, nt + tn, tn, 0, 0, tn};
+                s.sp = LaunchPlan{g.desc, st_, st_ + ts, ts, 0, 0, ts};
             }
             select(g, g.pick, g.measured);
         }
@@ -448,7 +456,7 @@ struct slbm_batch {
             ne[gi] = nn[gi] = 0;
             for (int i : g.idx) {
                 ne[gi] += eblocks(members[i], sh.epb);
-                nn[gi] += members[i]->n_nblocks;
+                nn[gi] += members[i]->n_sblocks;
             }
             goff.push_back(total);
             total += al(sizeof(SolveDesc) * g.idx.size()) + al(sizeof(int) * 2 * table_len(ne[gi], sh.xcd)) +
@@ -472,7 +480,7 @@ struct slbm_batch {
             for (int k = 0; k < (int)g.idx.size(); ++k) {
                 slbm_ctx *c = members[g.idx[k]];
                 for (int b = 0; b < eblocks(c, sh.epb); ++b) { le_s.push_back(k); le_l.push_back(b); }
-                for (int b = 0; b < c->n_nblocks; ++b) { ln_s.push_back(k); ln_l.push_back(b); }
+                for (int b = 0; b < c->n_sblocks; ++b) { ln_s.push_back(k); ln_l.push_back(b); }
             }
             const int te = table_len(ne[gi], sh.xcd), tn = table_len(nn[gi], sh.xcd);
             fill_table(reinterpret_cast<int *>(img.data() + o), ne[gi], sh.xcd, le_s, le_l);

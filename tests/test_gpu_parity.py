@@ -410,6 +410,63 @@ def test_unfused_path_matches(P, monkeypatch):
     assert np.array_equal(f.get_state()[0], s.get_state()[0])
 
 
+@pytest.mark.parametrize("mk", [lambda: cases.small_flat(N=6), cases.small_sphere,
+                                _q13(cases.small_sphere), lambda: cases.wide_case(3, 4)])
+def test_interior_split_changes_no_bits(P, monkeypatch, mk):
+    """The unfused path with element-interior nodes finished by the element kernels (the
+    default) against the same path with every node summed by the node kernels
+    (SLBM_NO_SPLIT=1): the same bits after 30 steps, alone and as members of one batch with
+    solves of the other kind; and the operator entry points (mu, averaged gradients,
+    streaming right-hand side, collision) of a split mesh against the oracle."""
+    import torch
+    monkeypatch.setenv("SLBM_UNFUSED", "1")
+    out = {}
+    for split in (True, False):
+        if split:
+            monkeypatch.delenv("SLBM_NO_SPLIT", raising=False)
+        else:
+            monkeypatch.setenv("SLBM_NO_SPLIT", "1")
+        a = P.Solve(mk())
+        a.init_tanh()
+        a.step(30)
+        out[split] = a.get_state()[0]
+    assert np.array_equal(out[True], out[False])
+    b = P.Batch(torch.cuda.current_stream())
+    ms = []
+    for split in (True, False):
+        if split:
+            monkeypatch.delenv("SLBM_NO_SPLIT", raising=False)
+        else:
+            monkeypatch.setenv("SLBM_NO_SPLIT", "1")
+        m = P.Solve(mk())
+        m.init_tanh()
+        b.add(m)
+        ms.append(m)
+    b.step(30)
+    for m in ms:
+        assert np.array_equal(m.get_state()[0], out[True])
+    del b
+    monkeypatch.delenv("SLBM_NO_SPLIT", raising=False)
+    c = mk()
+    s, o = _pair(c, P)
+    rng = np.random.default_rng(13)
+    X = c.mesh.first_copy_coords()
+    r = np.linalg.norm(X - np.asarray(c.x0)[None, : c.dim], axis=1)
+    rho = 0.55 - 0.45 * np.tanh(2 * (r - c.R) / c.delta) + 1e-3 * rng.standard_normal(o.Ng)
+    mu_o = o.mu(rho)
+    assert rel(s.op_mu(rho), mu_o) <= 1e-13
+    gr_o = o.avg_grad(rho)
+    assert rel(s.op_grad(rho), gr_o) <= 1e-13
+    ev, tw, _ = o.lattice()
+    e = ev[:, : c.dim]
+    u = 0.01 * rng.standard_normal((c.dim, o.Ng))
+    eu = e @ u
+    f = rho * tw[:, None] * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (u * u).sum(0))
+    gm = o.avg_grad(mu_o)
+    assert rel(s.op_collide(f, rho, gr_o, gm), o.collide(f, rho, gr_o, gm)) <= 1e-14
+    assert rel(s.op_stream(f, rho, mu_o), o.stream_op(f, rho, mu_o)) <= 1e-13
+
+
 def test_batch_mixed_paths_and_wide_blocks(P, monkeypatch):
     """A batch whose members step on different kernel paths (fused / unfused, chosen at
     set_mesh) and a group large enough for wide blocks: every member evolves exactly as
