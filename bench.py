@@ -27,24 +27,34 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def algorithmic_bytes(kind: str, Q: int, d: int, Ng: int, Nl: int) -> float:
-    """Minimum bytes one launch of a kernel kind must move (FP64 values, assembled
-    sizes: the per-local-copy residual buffers are implementation overhead)."""
+def algorithmic_bytes(kind: str, Q: int, d: int, Ng: int, Nl: int, Ni: int = 0) -> float:
+    """Bytes one launch of a kernel kind reads and writes at their minimum size: each FP64
+    array it takes or produces counted once (arrays of global nodes at Ng, of local nodes at
+    Nl; index tables are not counted).  The per-local-copy partial sums that pass from an
+    element kernel to a node kernel are this kernel's inputs or outputs and are counted,
+    at one value per local copy; the whole-step model (step_model_bytes) does not count them.
+
+    Ni: global nodes strictly inside an element that the unfused element kernels finish
+    themselves (one local copy each); the node kernels mu, collide and rk then run over the
+    other Ns = Ng - Ni nodes, whose Nb = Nl - Ni local copies carry partial sums."""
     ng = d * (d + 1) // 2
+    Ns, Nb = Ng - Ni, Nl - Ni
     per = {
-        # reads rho (Ng), metric G (ng*Nl); writes the Laplacian residual (Ng)
-        "lap": 2 * Ng + ng * Nl,
-        # reads residual, rho, 1/M; writes mu
-        "mu": 4 * Ng,
-        # reads rho, mu, metric Ja; writes 2d gradient components
-        "grad": 2 * Ng + d * d * Nl + 2 * d * Ng,
-        # reads f (Q), rho, 2d averaged gradients, 1/M; writes f* (Q)
-        "collide": Q * Ng + Ng + 2 * d * Ng + Ng + Q * Ng,
-        # reads Q-1 populations, rho, mu, metric Ja; writes Q-1 residuals
-        "stream": (Q - 1) * Ng + 2 * Ng + d * d * Nl + (Q - 1) * Ng,
-        # reads Q-1 residuals, g (Q), g0 (2Q/3 on average over the three stages: stage 1's
-        # input is g0 itself), 1/M; writes Q populations and rho
-        "rk": (Q - 1) * Ng + Q * Ng + (2 * Q) / 3.0 * Ng + Ng + Q * Ng + Ng,
+        # reads rho (Ng), metric G (ng*Nl); interior: 1/M (Ni) -> mu (Ni); others -> partials (Nb)
+        "lap": Ng + ng * Nl + 2 * Ni + Nb,
+        # reads the Laplacian partials (Nb), rho, 1/M; writes mu (Ns nodes)
+        "mu": Nb + 3 * Ns,
+        # reads rho, mu, metric Ja; interior: f (Q), 1/M -> f* (Q); others -> 2d gradient partials
+        "grad": 2 * Ng + d * d * Nl + (2 * Q + 1) * Ni + 2 * d * Nb,
+        # reads 2d gradient partials (Nb), f (Q), rho, 1/M; writes f* (Q) (Ns nodes)
+        "collide": 2 * d * Nb + (2 * Q + 2) * Ns,
+        # reads g (Q-1 populations; interior also the rest population), rho, mu, metric Ja;
+        # interior: g0 (2Q/3 on average over the three stages: stage 1's input is g0 itself),
+        # 1/M -> g' (Q) and rho; others -> Q-1 residual partials (Nb)
+        "stream": (Q - 1) * Ng + 2 * Ng + d * d * Nl + (1 + (2 * Q) / 3.0 + 1 + Q + 1) * Ni + (Q - 1) * Nb,
+        # reads Q-1 residual partials (Nb), g (Q), g0 (2Q/3 on average), 1/M; writes Q
+        # populations and rho (Ns nodes)
+        "rk": (Q - 1) * Nb + (Q + (2 * Q) / 3.0 + 1 + Q + 1) * Ns,
         # fused path: each kernel finishes the previous pass's summation itself
         # A: Laplacian sum, rho, 1/M -> mu; metric Ja -> 2d gradient sums
         "f_mu_grad": 4 * Ng + d * d * Nl + 2 * d * Ng,
@@ -212,7 +222,8 @@ def batch_bench(P, torch, n_req: int, steps: int, warmup: int = 40, seed: int = 
 
 
 def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
-                  ke_stop: float = 1e-20, max_slots: int = 256, seed: int = 5):
+                  ke_stop: float = 1e-20, max_slots: int = 256, seed: int = 5,
+                  arena_mb: int = 8192, poisson: bool = True):
     """Request sweep c5 (reduced): n_req droplet requests (flat or cylinder wall, N in {4,6,8},
     theta ~ U[30,150], R ~ U[10,30]) run to KE_max < ke_stop or max_steps.
 
@@ -250,7 +261,7 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
     t_plain = time.perf_counter() - t0
 
     def run_server(arrivals):
-        srv = P.Server(arena_bytes=8 << 30, max_slots=max_slots, check_every=check_every,
+        srv = P.Server(arena_bytes=arena_mb << 20, max_slots=max_slots, check_every=check_every,
                        ke_stop=ke_stop, max_steps=max_steps, stream=stream)
         ids = [None] * len(cs)
         order = np.argsort(arrivals)
@@ -277,9 +288,15 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
     with torch.cuda.stream(stream):
         t_batch, lat_b, ok_b, steps_b, theta_b = run_server(np.zeros(len(cs)))
         cap = len(cs) / t_batch
-        arr = np.array([r["t_arrive"] for r in reqs]) / (0.7 * cap)
-        t_pois, lat_p, ok_p, _, _ = run_server(arr - arr.min())
+        if poisson:
+            arr = np.array([r["t_arrive"] for r in reqs]) / (0.7 * cap)
+            t_pois, lat_p, ok_p, _, _ = run_server(arr - arr.min())
+        else:
+            t_pois, lat_p, ok_p = float("nan"), np.array([float("nan")]), 0
     stopped_ke = sum(1 for s_ in steps_b if s_ < max_steps)
+    st_arr = np.array(steps_b)
+    per_req = [{"geom": r["geom"], "nx": r["nx"], "ny": r["ny"], "N": r["N"],
+                "theta_deg": round(r["theta_deg"], 2), "steps": int(n)} for r, n in zip(reqs, steps_b)]
     return {
         "metric": "batched sweep solves/s",
         "requests": len(cs), "max_steps": max_steps, "check_every": check_every,
@@ -292,7 +309,11 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
         "poisson_0p7": {"rate_per_s": 0.7 * cap, "makespan_s": t_pois,
                         "latency_p50_s": float(np.percentile(lat_p, 50)),
                         "latency_p99_s": float(np.percentile(lat_p, 99)), "ok": ok_p},
-        "ok": ok_b, "retired_by_ke": stopped_ke,
+        "ok": ok_b, "retired_by_ke": stopped_ke, "arena_mb": arena_mb,
+        "steps_to_retire": {"min": int(st_arr.min()), "p50": float(np.percentile(st_arr, 50)),
+                            "max": int(st_arr.max())},
+        "plain_steps_match": [int(a) for a in plain_steps] == [int(b) for b in steps_b],
+        "per_request": per_req if len(per_req) <= 64 else None,
         "plain_total_steps": int(sum(plain_steps)), "batched_total_steps": int(sum(steps_b)),
         "theta_err_deg_median": float(np.nanmedian(np.abs(np.array(theta_b) -
                                                            np.array([c.theta_deg for c in cs])))),
@@ -410,10 +431,11 @@ def measure_workload(P, torch, name: str, steps: int, warmup: int, profile_steps
         prof = s.step_profile(profile_steps)
         dom = max(prof, key=lambda k: prof[k][0])
         avg_ms = s.time_kernel(dom, kernel_reps)
+        Ni = s.info().n_interior
         del s
     ms_per_step = ms / steps
     tot, nl = prof[dom]
-    alg = algorithmic_bytes(dom, Q, d, Ng, Nl)
+    alg = algorithmic_bytes(dom, Q, d, Ng, Nl, Ni)
     achieved = alg / (avg_ms * 1e-3) / 1e9
     step_gbs = step_model_bytes(Q, d, Ng, Nl) / (ms_per_step * 1e-3) / 1e9
     return {
@@ -421,7 +443,7 @@ def measure_workload(P, torch, name: str, steps: int, warmup: int, profile_steps
         "ms_per_step": ms_per_step,
         "config": {"workload": f"{case.name}: " + (case.mesh.name or ""),
                    "lattice": f"D{d}Q{Q}", "N": m.N, "elements": m.E, "n_global": Ng,
-                   "n_local": Nl, "local_node_updates_per_s": Nl * steps / (ms / 1e3),
+                   "n_local": Nl, "n_interior": Ni, "local_node_updates_per_s": Nl * steps / (ms / 1e3),
                    "model_bytes_per_step": step_model_bytes(Q, d, Ng, Nl),
                    "model_GBps": step_gbs,
                    "ke_max_end": ke, "mass_end": mass, "parallelism": "single GPU"},
@@ -445,6 +467,9 @@ def main():
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "c2xl", "c4q13"])
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-steps", type=int, default=2000)
+    ap.add_argument("--serve-arena-mb", type=int, default=8192,
+                    help="server arena: admission stops while the active workspaces fill it")
+    ap.add_argument("--no-poisson", action="store_true", help="serving: skip the Poisson-arrival run")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--batch-members", type=int, default=256,
                     help="request-mix solves in the batched-stepping measurement (0: skip)")
@@ -491,7 +516,8 @@ def main():
         print(json.dumps(out))
         return
     if args.workload == "c5":
-        out = serving_bench(P, torch, args.serve_requests, args.serve_max_steps)
+        out = serving_bench(P, torch, args.serve_requests, args.serve_max_steps,
+                            arena_mb=args.serve_arena_mb, poisson=not args.no_poisson)
         out.update({"value": out["batched_solves_per_s"], "unit": "solves/s", "n_gpus": 1,
                     "higher_is_better": True, "dtype": "f64", "data": "synthetic",
                     "config": {"workload": "c5 (reduced request count and step cap)"}})

@@ -97,6 +97,9 @@ typedef struct slbm_info {
     size_t workspace_bytes;
     int dim, Q, N;
     double tau;       /* relaxation time in use (from nu once the mesh is set, if nu > 0) */
+    int64_t n_interior; /* global nodes strictly inside an element that the element kernels
+                         * finish themselves (unfused path; 0 on the fused path) */
+    int fused;        /* 1: fused element-kernel path, 0: separate element and node kernels */
 } slbm_info;
 
 typedef struct slbm_ctx slbm_ctx;

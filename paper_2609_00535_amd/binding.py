@@ -37,7 +37,8 @@ class Info(C.Structure):
                 ("omega", C.c_double), ("h_min", C.c_double), ("n_elements", C.c_int64),
                 ("n_local", C.c_int64), ("n_global", C.c_int64), ("n_wall_nodes", C.c_int64),
                 ("step", C.c_int64), ("workspace_bytes", C.c_size_t), ("dim", C.c_int),
-                ("Q", C.c_int), ("N", C.c_int), ("tau", C.c_double)]
+                ("Q", C.c_int), ("N", C.c_int), ("tau", C.c_double), ("n_interior", C.c_int64),
+                ("fused", C.c_int)]
 
 
 class WallGeom(C.Structure):

@@ -340,6 +340,27 @@ __device__ __forceinline__ int split_node(int m) {
     }
 }
 
+// Lane of an unfused element kernel -> (element slot es within the block, storage position
+// m within that element).  Split mesh: the interior nodes of all the block's elements take
+// the first lanes and the boundary nodes the rest, so at most one wave of a block holds
+// both kinds; otherwise lanes follow the natural node order element by element.
+template <int D, int N, bool WIDE>
+__device__ __forceinline__ void lane_slot(int tid, bool split, int &es, int &m) {
+    using S = Shape<D, N, WIDE>;
+    constexpr int NI = S::NINT, NBD = S::NLOC - S::NINT;
+    if (!split) {
+        es = tid / S::NLOC;
+        m = tid - es * S::NLOC;
+    } else if (tid < S::EPB * NI) {
+        es = tid / NI;
+        m = tid - es * NI;
+    } else {
+        const int t = tid - S::EPB * NI;
+        es = t / NBD;
+        m = NI + (t - es * NBD);
+    }
+}
+
 template <int D, int NB, int NG>
 __device__ __forceinline__ void metric_times_grad(const double *g, const double *d, double *sv, int tid) {
     // v_a = sum_b G_ab d_b (ascending b from 0)
@@ -369,10 +390,11 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_lap(Laun
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
     const int tid = threadIdx.x;
-    double dmv = 0.0;  // fetched by the active lanes (every lane below (N+1)^2 is active)
-    // storage position m of the lane's node within its element, element node n, and the
-    // node's LDS slot ln (natural order within the element)
-    const int es = tid / NLOC, m = tid - es * NLOC;
+    double dmv = 0.0;
+    // element slot es and storage position m of the lane's node, its element node n, and
+    // its LDS slot ln (natural order within the element)
+    int es, m;
+    lane_slot<D, N, WIDE>(tid, sd.Nint > 0, es, m);
     const int n = sd.Nint > 0 ? split_node<D, NP>(m) : m;
     const int ln = es * NLOC + n;
     const int e = bs.local * S::EPB + es;
@@ -385,8 +407,10 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_lap(Laun
     int G = 0;
     double g[S::NG];
     WallLap<D> wl;
+    // every lane below (N+1)^2 fetches its entry of D (with the split lane map such a lane
+    // can belong to an element slot past the end of the mesh)
+    dmv = dm_fetch<NP>(sd, tid);
     if (act) {
-        dmv = dm_fetch<NP>(sd, tid);
         G = sd.lgid[l];
 #pragma unroll
         for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * sd.Nl + l];
@@ -488,10 +512,11 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_grad(Lau
     if (!bs.valid) return;
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
     const int tid = threadIdx.x;
-    double dmv = 0.0;  // fetched by the active lanes (every lane below (N+1)^2 is active)
-    // storage position m of the lane's node within its element, element node n, and the
-    // node's LDS slot ln (natural order within the element)
-    const int es = tid / NLOC, m = tid - es * NLOC;
+    double dmv = 0.0;
+    // element slot es and storage position m of the lane's node, its element node n, and
+    // its LDS slot ln (natural order within the element)
+    int es, m;
+    lane_slot<D, N, WIDE>(tid, sd.Nint > 0, es, m);
     const int n = sd.Nint > 0 ? split_node<D, NP>(m) : m;
     const int ln = es * NLOC + n;
     const int e = bs.local * S::EPB + es;
@@ -503,8 +528,10 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_grad(Lau
     double w = 0.0, pr = 0.0, mi = 0.0;
     double f[Q];
     int G = 0;
+    // every lane below (N+1)^2 fetches its entry of D (with the split lane map such a lane
+    // can belong to an element slot past the end of the mesh)
+    dmv = dm_fetch<NP>(sd, tid);
     if (act) {
-        dmv = dm_fetch<NP>(sd, tid);
         G = sd.lgid[l];
 #pragma unroll
         for (int a = 0; a < D; ++a)
@@ -745,10 +772,11 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     const SolveDesc sd = desc_of<SINGLE>(p, bs);
     const double SLBM_GLOBAL *g = stage == 1 ? sd.g0 : sd.g1;
     const int tid = threadIdx.x;
-    double dmv = 0.0;  // fetched by the active lanes (every lane below (N+1)^2 is active)
-    // storage position m of the lane's node within its element, element node n, and the
-    // node's LDS slot ln (natural order within the element)
-    const int es = tid / NLOC, m = tid - es * NLOC;
+    double dmv = 0.0;
+    // element slot es and storage position m of the lane's node, its element node n, and
+    // its LDS slot ln (natural order within the element)
+    int es, m;
+    lane_slot<D, N, WIDE>(tid, sd.Nint > 0, es, m);
     const int n = sd.Nint > 0 ? split_node<D, NP>(m) : m;
     const int ln = es * NLOC + n;
     const int e = bs.local * S::EPB + es;
@@ -763,8 +791,10 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     // the wall data of boundary nodes are loaded after the barrier (an interior node has
     // none): they are not live across it, and not at all on the interior path
     geo.wf.cnt = 0;
+    // every lane below (N+1)^2 fetches its entry of D (with the split lane map such a lane
+    // can belong to an element slot past the end of the mesh)
+    dmv = dm_fetch<NP>(sd, tid);
     if (act) {
-        dmv = dm_fetch<NP>(sd, tid);
         G = sd.lgid[l];
         load_metric<D>(sd, n, l, geo);
         pr = sd.rho[G];

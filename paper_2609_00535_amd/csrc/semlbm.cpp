@@ -1215,6 +1215,8 @@ extern "C" slbm_status slbm_get_info(const slbm_ctx *c, slbm_info *info) {
         info->dim = c->dim;
         info->Q = c->Q;
         info->N = c->N;
+        info->n_interior = c->Nint;
+        info->fused = c->fused ? 1 : 0;
         return SLBM_OK;
     });
 }

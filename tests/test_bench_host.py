@@ -36,8 +36,15 @@ def test_byte_models_by_hand():
     # kernel C of the fused path: ((Q-1) + 1 + Q + 2Q/3 + Q + 2) N_g + d(d+1)/2 N_l doubles
     ng, nl = 1000, 1500
     assert b.algorithmic_bytes("f_rk_lap", 9, 2, ng, nl) == 8.0 * ((8 + 1 + 9 + 6 + 9 + 2) * ng + 3 * nl)
-    # node kernel rk: (Q-1) + Q + 2Q/3 + 1 + Q + 1 doubles per global node
-    assert b.algorithmic_bytes("rk", 19, 3, ng, nl) == 8.0 * (18 + 19 + 38 / 3.0 + 1 + 19 + 1) * ng
+    # node kernel rk: Q-1 partials per local copy, then Q + 2Q/3 + 1 + Q + 1 doubles per node
+    assert b.algorithmic_bytes("rk", 19, 3, ng, nl) == 8.0 * (18 * nl + (19 + 38 / 3.0 + 1 + 19 + 1) * ng)
+    # with ni element-interior nodes finished by the element kernels, rk covers the others
+    ni = 300
+    assert b.algorithmic_bytes("rk", 19, 3, ng, nl, ni) == \
+        8.0 * (18 * (nl - ni) + (19 + 38 / 3.0 + 1 + 19 + 1) * (ng - ni))
+    # ... and the streaming kernel finishes the interior nodes: + (1 + 2Q/3 + 1 + Q + 1) each
+    assert b.algorithmic_bytes("stream", 19, 3, ng, nl, ni) == \
+        8.0 * (18 * ng + 2 * ng + 9 * nl + (1 + 38 / 3.0 + 1 + 19 + 1) * ni + 18 * (nl - ni))
 
 
 def test_kernel_hash_ignores_comments_but_not_code(tmp_path):
