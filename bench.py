@@ -223,7 +223,7 @@ def batch_bench(P, torch, n_req: int, steps: int, warmup: int = 40, seed: int = 
 
 def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
                   ke_stop: float = 1e-20, max_slots: int = 256, seed: int = 5,
-                  arena_mb: int = 8192, poisson: bool = True):
+                  arena_mb: int = 8192, poisson: bool = True, plain: bool = True):
     """Request sweep c5 (reduced): n_req droplet requests (flat or cylinder wall, N in {4,6,8},
     theta ~ U[30,150], R ~ U[10,30]) run to KE_max < ke_stop or max_steps.
 
@@ -244,8 +244,13 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
     # (1) plain stepper
     t0 = time.perf_counter()
     plain_steps = []
+    t_note = time.perf_counter()
     with torch.cuda.stream(stream):
-        for c in cs:
+        for ci, c in enumerate(cs if plain else []):
+            if time.perf_counter() - t_note > 20.0:
+                t_note = time.perf_counter()
+                print(f"[serve] plain stepper: {ci}/{len(cs)} requests, {t_note - t0:.0f} s", file=sys.stderr,
+                      flush=True)
             s = P.Solve(c, stream=stream)
             s.init_tanh()
             n = 0
@@ -268,8 +273,13 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
         k = 0
         t_start = srv.clock()
         pending = 1
+        t_note = t_start
         while k < len(cs) or pending > 0:
             now = srv.clock() - t_start
+            if srv.clock() - t_note > 20.0:
+                t_note = srv.clock()
+                print(f"[serve] server: {k}/{len(cs)} submitted, {pending} pending, {now:.0f} s",
+                      file=sys.stderr, flush=True)
             while k < len(cs) and arrivals[order[k]] <= now:
                 ids[order[k]] = srv.submit(cs[order[k]])
                 k += 1
@@ -302,8 +312,9 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
         "requests": len(cs), "max_steps": max_steps, "check_every": check_every,
         "ke_stop": ke_stop, "max_slots": max_slots,
         "batched_solves_per_s": len(cs) / t_batch,
-        "plain_solves_per_s": len(cs) / t_plain,
-        "batched_over_plain": t_plain / t_batch,
+        "plain_solves_per_s": len(cs) / t_plain if plain else None,
+        "batched_over_plain": t_plain / t_batch if plain else None,
+        "plain_s": t_plain if plain else None, "batched_s": t_batch,
         "saturated_latency_s": {"p50": float(np.percentile(lat_b, 50)),
                                 "p99": float(np.percentile(lat_b, 99))},
         "poisson_0p7": {"rate_per_s": 0.7 * cap, "makespan_s": t_pois,
@@ -312,7 +323,7 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
         "ok": ok_b, "retired_by_ke": stopped_ke, "arena_mb": arena_mb,
         "steps_to_retire": {"min": int(st_arr.min()), "p50": float(np.percentile(st_arr, 50)),
                             "max": int(st_arr.max())},
-        "plain_steps_match": [int(a) for a in plain_steps] == [int(b) for b in steps_b],
+        "plain_steps_match": ([int(a) for a in plain_steps] == [int(b) for b in steps_b]) if plain else None,
         "per_request": per_req if len(per_req) <= 64 else None,
         "plain_total_steps": int(sum(plain_steps)), "batched_total_steps": int(sum(steps_b)),
         "theta_err_deg_median": float(np.nanmedian(np.abs(np.array(theta_b) -
@@ -470,6 +481,7 @@ def main():
     ap.add_argument("--serve-arena-mb", type=int, default=8192,
                     help="server arena: admission stops while the active workspaces fill it")
     ap.add_argument("--no-poisson", action="store_true", help="serving: skip the Poisson-arrival run")
+    ap.add_argument("--no-plain", action="store_true", help="serving: skip the one-at-a-time stepper")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--batch-members", type=int, default=256,
                     help="request-mix solves in the batched-stepping measurement (0: skip)")
@@ -517,10 +529,12 @@ def main():
         return
     if args.workload == "c5":
         out = serving_bench(P, torch, args.serve_requests, args.serve_max_steps,
-                            arena_mb=args.serve_arena_mb, poisson=not args.no_poisson)
+                            arena_mb=args.serve_arena_mb, poisson=not args.no_poisson,
+                            plain=not args.no_plain)
         out.update({"value": out["batched_solves_per_s"], "unit": "solves/s", "n_gpus": 1,
                     "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-                    "config": {"workload": "c5 (reduced request count and step cap)"}})
+                    "config": {"workload": f"c5: {args.serve_requests} request-mix solves, each to KE_max < 1e-20 "
+                                           f"or {args.serve_max_steps} steps"}})
         print(json.dumps(out))
         return
     r = measure_workload(P, torch, args.workload, args.steps, args.warmup, args.profile_steps,

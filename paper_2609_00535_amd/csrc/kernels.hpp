@@ -29,6 +29,10 @@
 
 #include "internal.hpp"
 
+#ifndef SLBM_WPE_STREAM_3D
+#define SLBM_WPE_STREAM_3D 2
+#endif
+
 namespace slbm {
 
 // ------------------------------------------------------------------------------------------
@@ -112,9 +116,9 @@ template <int D, int N, bool WIDE = true> struct Shape {
     static constexpr int NT = ((NB + 63) / 64) * 64;
     static constexpr int NG = D * (D + 1) / 2;
     static constexpr int NINT = D == 2 ? (NP - 2) * (NP - 2) : (NP - 2) * (NP - 2) * (NP - 2);  // interior nodes
-    // minimum waves per SIMD asked of the 3-D streaming kernels (caps their registers so
-    // that three 256-thread blocks share a compute unit)
-    static constexpr int WPE_STREAM = D == 3 ? 3 : 1;
+    // minimum waves per SIMD asked of the 3-D streaming kernels (a register cap; at 2 the
+    // kernels need no spill slots, at 3 they spill and run slower on c4)
+    static constexpr int WPE_STREAM = D == 3 ? SLBM_WPE_STREAM_3D : 1;
     static_assert(NT >= NP * NP, "one differentiation-matrix entry per thread");
 };
 
@@ -690,7 +694,9 @@ __device__ __forceinline__ double residual_q(const SolveDesc &sd, int q, const d
     return r;
 }
 
-template <int Q, int D, int N, bool WIDE>
+// WALLS: add the flux bounce-back of the node's wall faces (needs gq); without it the
+// caller adds them later (k_wall) and gq is not read
+template <int Q, int D, int N, bool WIDE, bool WALLS = true>
 __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
                                                 const double *smu_e, int es, int n, int l,
                                                 double pr, const double *gq, const NodeGeo<D> &geo) {
@@ -700,8 +706,8 @@ __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const doubl
     grad_ref<D, NP>(sD, smu_e, n, dmu);
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-        const double r = residual_q<Q, D, NP>(sd, q, sD, sh + (q - 1) * NB + es * NLOC, n, dmu, pr, gq[q],
-                                              gq[Lat<Q>::opp[q]], geo);
+        const double gqq = WALLS ? gq[q] : 0.0, gop = WALLS ? gq[Lat<Q>::opp[q]] : 0.0;
+        const double r = residual_q<Q, D, NP>(sd, q, sD, sh + (q - 1) * NB + es * NLOC, n, dmu, pr, gqq, gop, geo);
         sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
     }
 }
@@ -725,13 +731,19 @@ __device__ __forceinline__ double rk_combine(int stage, double L, double gin, do
 template <int Q, int D, int N, bool WIDE>
 __device__ __forceinline__ void stream_finish(const SolveDesc &sd, const double *sD, const double *sh,
                                               const double *smu_e, int es, int n, int G, double pr,
-                                              const double *gq, const NodeGeo<D> &geo, int stage) {
+                                              const NodeGeo<D> &geo, int stage) {
     using S = Shape<D, N, WIDE>;
     constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
     const size_t Ng = sd.Ng;
+    const double SLBM_GLOBAL *gin = stage == 1 ? sd.g0 : sd.g1;
     double SLBM_GLOBAL *gout = stage == 3 ? sd.f : sd.g1;
-    // the loads go out before the first store
+    // the loads go out before the first store; the stage input is read again here (the
+    // block read it before the barrier, so these are cache hits) rather than kept in
+    // registers across the barrier
     const double mi = sd.Minv[G], dt = sd.dt;
+    double gq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) gq[q] = gin[q * Ng + G];
     double g0v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) g0v[q] = 0.0;
@@ -785,7 +797,6 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     const size_t Ng = sd.Ng;
     const bool own = sd.Nint > 0 && m < S::NINT;
     double pr = 0.0;
-    double gq[Q];
     NodeGeo<D> geo;
     int G = 0;
     // the wall data of boundary nodes are loaded after the barrier (an interior node has
@@ -799,8 +810,7 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
         load_metric<D>(sd, n, l, geo);
         pr = sd.rho[G];
         smu[ln] = sd.mu[G];
-        gq[0] = 0.0;
-        if (own) gq[0] = g[G];
+        double gq[Q];
 #pragma unroll
         for (int q = 1; q < Q; ++q) gq[q] = g[q * Ng + G];
 #pragma unroll
@@ -810,11 +820,65 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     __syncthreads();
     if (!act) return;
     if (own) {
-        stream_finish<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, G, pr, gq, geo, stage);
+        stream_finish<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, G, pr, geo, stage);
         return;
     }
-    load_wall_flux<D>(sd, l, geo.wf);
-    stream_residual<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
+    // the flux bounce-back of wall nodes is added to these partials by k_wall (geo.wf is
+    // empty here, so residual_q adds no wall term and needs no populations)
+    stream_residual<Q, D, N, WIDE, false>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, nullptr, geo);
+}
+
+// Eq. (9) on the wall nodes of the unfused path: adds the flux bounce-back terms of every
+// wall face through the node to the residual partials k_stream stored without them, in the
+// order residual_q adds them (face by face, incoming populations only), so the partials are
+// those of residual_q bit for bit.  Keeping the wall data out of k_stream saves it the
+// registers of up to d faces' s n and u_b.  Launched on the element plan: one lane per
+// local node (storage order); lanes of nodes without walls return after one load.
+template <int DQ, int N, bool WIDE, bool SINGLE>
+__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_wall(LaunchPlan p, int stage) {
+    constexpr int D = DimOf<DQ>::v;
+    constexpr int Q = QOfDQ<DQ>::v;
+    using S = Shape<D, N, WIDE>;
+    constexpr int NLOC = S::NLOC, NB = S::NB;
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x;
+    const int es = tid / NLOC, m = tid - es * NLOC;
+    const int e = bs.local * S::EPB + es;
+    if (tid >= NB || e >= sd.E) return;
+    const int l = e * NLOC + m;
+    if ((sd.lwall[l] & 3) == 0) return;
+    const double SLBM_GLOBAL *g = stage == 1 ? sd.g0 : sd.g1;
+    const size_t Ng = sd.Ng, Nl = sd.Nl;
+    WallFlux<D> wf;
+    load_wall_flux<D>(sd, l, wf);
+    const int G = sd.lgid[l];
+    const double pr = sd.rho[G];
+    double gq[Q], r[Q];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) gq[q] = g[q * Ng + G];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) r[q] = sd.rs[(size_t)(q - 1) * Nl + l];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        const double tc = sd.twc[wcls<Q>(q)];
+        double x = r[q];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j < wf.cnt) {
+                const double cn = dot_e<Q, D>(wf.sn[j], q, sd);
+                if (cn < 0.0) {
+                    const double eub = dot_e<Q, D>(wf.ub[j], q, sd);
+                    const double bc = gq[q] - gq[Lat<Q>::opp[q]] - 2.0 * tc * pr * eub;
+                    x += cn * bc;
+                    any = true;
+                }
+            }
+        }
+        if (any) sd.rs[(size_t)(q - 1) * Nl + l] = x;
+    }
 }
 
 template <int DQ, int N, bool SINGLE>
@@ -1581,7 +1645,24 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 #define SLBM_CASE_grad(DD, NN) SLBM_ELEM_CASE(k_grad, DD, NN, collide)
 #define SLBM_CASE_gavg(DD, NN) SLBM_NODE_CASE(k_gavg, DD, NN)
 #define SLBM_CASE_collide(DD, NN) SLBM_NODE_CASE(k_collide, DD, NN, use_aux)
-#define SLBM_CASE_stream(DD, NN) SLBM_ELEM_CASE(k_stream, DD, NN, stage)
+#define SLBM_CASE_stream(DD, NN)                                                             \
+    if (!done && d == DD && N == NN) {                                                       \
+        const bool wide = p.epb == Shape<DimOf<DD>::v, NN, true>::EPB;                       \
+        if (wide && p.single) {                                                              \
+            SLBM_ELEM_LAUNCH(k_stream, DD, NN, true, true, stage);                           \
+            SLBM_ELEM_LAUNCH(k_wall, DD, NN, true, true, stage);                             \
+        } else if (wide) {                                                                   \
+            SLBM_ELEM_LAUNCH(k_stream, DD, NN, true, false, stage);                          \
+            SLBM_ELEM_LAUNCH(k_wall, DD, NN, true, false, stage);                            \
+        } else if (p.single) {                                                               \
+            SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, true, stage);                          \
+            SLBM_ELEM_LAUNCH(k_wall, DD, NN, false, true, stage);                            \
+        } else {                                                                             \
+            SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, false, stage);                         \
+            SLBM_ELEM_LAUNCH(k_wall, DD, NN, false, false, stage);                           \
+        }                                                                                    \
+        done = true;                                                                         \
+    }
 #define SLBM_CASE_rk(DD, NN) SLBM_NODE_CASE(k_rk, DD, NN, stage)
 #define SLBM_CASE_density(DD, NN) SLBM_NODE_CASE(k_density, DD, NN, which)
 #define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)
