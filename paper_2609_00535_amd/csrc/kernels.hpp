@@ -311,19 +311,46 @@ __device__ __forceinline__ bool on_elem_boundary(int n) {
     return b != 0;
 }
 
-// Element-interior split: the local nodes of an element are stored interior-first (the
-// (N-1)^d interior nodes in natural order, then the boundary nodes in natural order), so
-// that lanes of an element take interior and boundary nodes in separate runs (3-D N = 5:
-// the first wave is exactly the 64 interior nodes).  split_node maps the storage position
-// m within the element to the element node n = i + (N+1) j (+ (N+1)^2 k).
-template <int NP>
-__device__ __forceinline__ int ring_node(int b) {  // b-th boundary node of an NP x NP face, natural order
-    constexpr int NI = NP - 2;
-    if (b < NP) return b;  // row j = 0
-    b -= NP;
-    if (b < 2 * NI) return (1 + b / 2) * NP + ((b & 1) ? NP - 1 : 0);
-    return (NP - 1) * NP + (b - 2 * NI);  // row j = N
-}
+// Element-interior split: the local nodes of an element are stored interior-first: the
+// (N-1)^d interior nodes in natural order, then the boundary nodes grouped by class (the
+// nodes inside face 0, 1, .., 2d-1 (xi-, xi+, eta-, ...) face by face, then the nodes
+// inside edges, then the corners; natural order within each group).  Lanes of an element
+// thus take interior and boundary nodes in separate runs (3-D N = 5: the first wave is
+// exactly the 64 interior nodes), and the copies of a shared face sit in one run of slots in
+// each of its two elements, which the shared-node numbering follows.  split_node maps the
+// storage position m within the element to the element node n = i + (N+1) j (+ (N+1)^2 k).
+template <int D, int NP>
+struct BoundaryOrder {
+    static constexpr int NLOC = D == 2 ? NP * NP : NP * NP * NP;
+    static constexpr int NINT = D == 2 ? (NP - 2) * (NP - 2) : (NP - 2) * (NP - 2) * (NP - 2);
+    static constexpr int NBD = NLOC - NINT;
+    int node[NBD];
+    // number of coordinates on the element boundary, and the face (2a + side) when it is one
+    static constexpr int cls(int n, int *face) {
+        int b = 0;
+        for (int a = 0, st = 1; a < D; ++a, st *= NP) {
+            const int i = (n / st) % NP;
+            if (i == 0 || i == NP - 1) {
+                ++b;
+                *face = 2 * a + (i == NP - 1 ? 1 : 0);
+            }
+        }
+        return b;
+    }
+    constexpr BoundaryOrder() : node{} {
+        int k = 0;
+        for (int f = 0; f < 2 * D; ++f)
+            for (int n = 0; n < NLOC; ++n) {
+                int fc = -1;
+                if (cls(n, &fc) == 1 && fc == f) node[k++] = n;
+            }
+        for (int c = 2; c <= D; ++c)
+            for (int n = 0; n < NLOC; ++n) {
+                int fc = -1;
+                if (cls(n, &fc) == c) node[k++] = n;
+            }
+    }
+};
 template <int D, int NP>
 __device__ __forceinline__ int split_node(int m) {
     constexpr int NI = NP - 2;
@@ -332,16 +359,8 @@ __device__ __forceinline__ int split_node(int m) {
         const int i = 1 + m % NI, j = 1 + (m / NI) % NI;
         return D == 2 ? i + NP * j : i + NP * j + NP * NP * (1 + m / (NI * NI));
     }
-    const int b = m - NINT;
-    if constexpr (D == 2) {
-        return ring_node<NP>(b);
-    } else {
-        constexpr int P2 = NP * NP, RING = 4 * (NP - 1);
-        if (b < P2) return b;  // face k = 0
-        const int r = b - P2;
-        if (r < NI * RING) return (1 + r / RING) * P2 + ring_node<NP>(r % RING);
-        return (NP - 1) * P2 + (r - NI * RING);  // face k = N
-    }
+    static constexpr BoundaryOrder<D, NP> order{};
+    return order.node[m - NINT];
 }
 
 // Lane of an unfused element kernel -> (element slot es within the block, storage position

@@ -139,6 +139,36 @@ uint64_t splitmix64(uint64_t x) {  // Steele, Lea & Flood (2014), one output fro
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Storage order of an element's local nodes on the split (unfused) path: element nodes n in
+// the order the device keeps them, interior nodes first (natural order), then the nodes
+// inside face 0 .. 2d-1, then inside edges, then corners (natural order within each group);
+// the kernels' lane map (split_node) follows the same order
+std::vector<int> split_storage_order(int dim, int N) {
+    const int Np = N + 1, nloc = dim == 2 ? Np * Np : Np * Np * Np;
+    auto cls = [&](int n, int *face) {
+        int b = 0;
+        for (int a = 0, st = 1; a < dim; ++a, st *= Np) {
+            const int i = (n / st) % Np;
+            if (i == 0 || i == N) {
+                ++b;
+                *face = 2 * a + (i == N ? 1 : 0);
+            }
+        }
+        return b;
+    };
+    std::vector<int> order;
+    int fc = -1;
+    for (int n = 0; n < nloc; ++n)
+        if (cls(n, &fc) == 0) order.push_back(n);
+    for (int f = 0; f < 2 * dim; ++f)
+        for (int n = 0; n < nloc; ++n)
+            if (cls(n, &fc) == 1 && fc == f) order.push_back(n);
+    for (int c = 2; c <= dim; ++c)
+        for (int n = 0; n < nloc; ++n)
+            if (cls(n, &fc) == c) order.push_back(n);
+    return order;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -308,8 +338,10 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
             if (ff && ff[0] == '1' && fits) c->fused = true;
         }
         // Element-interior split (unfused path): the element-interior nodes are numbered first,
-        // element by element in local order, then the others by first appearance; the element
-        // kernels finish the interior nodes and the node kernels run over the rest only.
+        // element by element in local order; the others follow element by element in the
+        // device storage order (face by face, then edges, then corners), each at its first
+        // appearance, so the copies of consecutive shared nodes lie in runs of slots.  The
+        // element kernels finish the interior nodes and the node kernels run over the rest.
         c->Nint = 0;
         const char *ns = std::getenv("SLBM_NO_SPLIT");
         if (!c->fused && interior_single && !(ns && ns[0] == '1')) {
@@ -319,8 +351,12 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
                 for (int n = 0; n < nloc; ++n)
                     if (!on_bnd[n]) renum[c->lgid[e * nloc + n]] = next++;
             c->Nint = next;
-            for (int64_t l = 0; l < Nl; ++l)
-                if (renum[c->lgid[l]] < 0) renum[c->lgid[l]] = next++;
+            const std::vector<int> order = split_storage_order(dim, N);
+            for (int64_t e = 0; e < E; ++e)
+                for (int n : order) {
+                    const int32_t g = c->lgid[e * nloc + n];
+                    if (renum[g] < 0) renum[g] = next++;
+                }
             std::vector<int32_t> ig2ug(n_global);
             for (int64_t g = 0; g < n_global; ++g) ig2ug[renum[g]] = c->ig2ug[g];
             c->ig2ug.swap(ig2ug);
@@ -712,17 +748,9 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
         const int64_t Nl = c->Nl, nloc = c->nloc;
         std::vector<int32_t> pos;  // natural element node -> storage position
         if (c->Nint > 0) {
+            const std::vector<int> order = split_storage_order(dim, c->N);
             pos.assign(nloc, 0);
-            int m = 0;
-            for (int pass = 0; pass < 2; ++pass)
-                for (int n = 0; n < nloc; ++n) {
-                    bool bnd = false;
-                    for (int a = 0; a < dim; ++a) {
-                        const int i = c->along(n, a);
-                        if (i == 0 || i == c->N) bnd = true;
-                    }
-                    if (bnd == (pass == 1)) pos[n] = m++;
-                }
+            for (int m = 0; m < (int)order.size(); ++m) pos[order[m]] = m;
         }
         auto lmap = [&](int64_t l) -> int64_t { return pos.empty() ? l : (l / nloc) * nloc + pos[l % nloc]; };
         auto perm_int = [&](const std::vector<int32_t> &v, int fields) {
