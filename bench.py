@@ -151,7 +151,9 @@ def traffic_from_profiles(workload: str, kind: str):
     rec = json.load(open(path))
     if rec.get("kernels_sha256") != kernels_sha256():
         return None
-    v = rec.get("bytes_per_launch", {}).get(kind)
+    per = rec.get("bytes_per_launch", {})
+    # one launch of the unfused stream kind is k_stream followed by k_wall
+    v = per.get("stream_kind") if kind == "stream" and "stream_kind" in per else per.get(kind)
     return float(v) if v is not None else None
 
 
@@ -201,19 +203,31 @@ def batch_bench(P, torch, n_req: int, steps: int, warmup: int = 40, seed: int = 
         # one at a time: every solve's own graph-replayed steps
         plain_ms = 0.0
         p_steps = max(10, steps // 5)
-        for s in ss:
+        by_class = {}
+        for r, s in zip(reqs, ss):
             s.step(2)
             a, z = ev(), ev()
             a.record(stream)
             s.step(p_steps)
             z.record(stream)
             z.synchronize()
-            plain_ms += a.elapsed_time(z) / p_steps
+            ms1 = a.elapsed_time(z) / p_steps
+            plain_ms += ms1
+            key = f"{r['geom']} {r['nx']}x{r['ny']} N={r['N']}"
+            c = by_class.setdefault(key, [0, 0.0, 0])
+            c[0] += 1
+            c[1] += ms1
+            c[2] += s.Ng
     return {
         "members": n_req, "steps": steps, "warmup": warmup, "n_global_total": int(ng),
         "ms_per_step": ms_batch, "node_updates_per_s": ng / (ms_batch * 1e-3),
         "plain_ms_per_step_all_members": plain_ms,
         "batched_over_plain": plain_ms / ms_batch,
+        # the one-at-a-time stepper's rate by request class: members, us per step of one
+        # member, node-updates/s (the batch's rate is node_updates_per_s above)
+        "plain_by_class": {k: {"members": v[0], "us_per_step": 1e3 * v[1] / v[0],
+                               "node_updates_per_s": v[2] / (v[1] * 1e-3)}
+                           for k, v in sorted(by_class.items())},
         "groups": [{"lattice": f"D{g['dim']}Q{g['lattice']}", "N": g["N"],
                     "fused": g["fused"], "members": g["members"], "elements": g["elements"],
                     "chosen": g["shapes"][g["chosen"]], "timed": g["measured"],
@@ -477,7 +491,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "c2xl", "c4q13"])
     ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-max-steps", type=int, default=2000)
+    ap.add_argument("--serve-max-steps", type=int, default=50000)
     ap.add_argument("--serve-arena-mb", type=int, default=8192,
                     help="server arena: admission stops while the active workspaces fill it")
     ap.add_argument("--no-poisson", action="store_true", help="serving: skip the Poisson-arrival run")
