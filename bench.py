@@ -306,21 +306,26 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
         ok = sum(1 for r in res if r.status == 0)
         steps = [r.steps for r in res]
         theta = [r.theta_deg for r in res]
+        status = [r.status for r in res]
         del srv
-        return t_total, lat, ok, steps, theta
+        return t_total, lat, ok, steps, theta, status
 
     with torch.cuda.stream(stream):
-        t_batch, lat_b, ok_b, steps_b, theta_b = run_server(np.zeros(len(cs)))
+        t_batch, lat_b, ok_b, steps_b, theta_b, status_b = run_server(np.zeros(len(cs)))
         cap = len(cs) / t_batch
         if poisson:
             arr = np.array([r["t_arrive"] for r in reqs]) / (0.7 * cap)
-            t_pois, lat_p, ok_p, _, _ = run_server(arr - arr.min())
+            t_pois, lat_p, ok_p, _, _, _ = run_server(arr - arr.min())
         else:
             t_pois, lat_p, ok_p = float("nan"), np.array([float("nan")]), 0
-    stopped_ke = sum(1 for s_ in steps_b if s_ < max_steps)
+    # retired by the KE criterion: finished without error before the step cap (a diverged
+    # request also stops early, with a nonzero status)
+    stopped_ke = sum(1 for s_, st in zip(steps_b, status_b) if s_ < max_steps and st == 0)
     st_arr = np.array(steps_b)
     per_req = [{"geom": r["geom"], "nx": r["nx"], "ny": r["ny"], "N": r["N"],
-                "theta_deg": round(r["theta_deg"], 2), "steps": int(n)} for r, n in zip(reqs, steps_b)]
+                "theta_deg": round(r["theta_deg"], 2), "steps": int(n), "status": int(st)}
+               for r, n, st in zip(reqs, steps_b, status_b)]
+    diverged = [q for q in per_req if q["status"] != 0]
     return {
         "metric": "batched sweep solves/s",
         "requests": len(cs), "max_steps": max_steps, "check_every": check_every,
@@ -334,7 +339,7 @@ def serving_bench(P, torch, n_req: int, max_steps: int, check_every: int = 100,
         "poisson_0p7": {"rate_per_s": 0.7 * cap, "makespan_s": t_pois,
                         "latency_p50_s": float(np.percentile(lat_p, 50)),
                         "latency_p99_s": float(np.percentile(lat_p, 99)), "ok": ok_p},
-        "ok": ok_b, "retired_by_ke": stopped_ke, "arena_mb": arena_mb,
+        "ok": ok_b, "retired_by_ke": stopped_ke, "failed": diverged, "arena_mb": arena_mb,
         "steps_to_retire": {"min": int(st_arr.min()), "p50": float(np.percentile(st_arr, 50)),
                             "max": int(st_arr.max())},
         "plain_steps_match": ([int(a) for a in plain_steps] == [int(b) for b in steps_b]) if plain else None,

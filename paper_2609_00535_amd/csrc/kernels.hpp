@@ -788,6 +788,11 @@ __device__ __forceinline__ void stream_finish(const SolveDesc &sd, const double 
     sd.rho[G] = rho;
 }
 
+// Where the unfused path adds the flux bounce-back of Eq. (9): in 3-D a kernel of its own
+// (k_wall) after k_stream, which then holds no wall data or populations across the
+// residual loop; in 2-D k_stream itself, which has the registers for them
+template <int D> struct WallKernel { static constexpr bool v = D == 3; };
+
 // stage 1 streams g0, stages 2-3 stream g1 (stage 0, the operator entry point, streams g1)
 template <int DQ, int N, bool WIDE, bool SINGLE>
 __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ>::v, N, WIDE>::WPE_STREAM)) void k_stream(LaunchPlan p, int stage) {
@@ -824,12 +829,12 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     // every lane below (N+1)^2 fetches its entry of D (with the split lane map such a lane
     // can belong to an element slot past the end of the mesh)
     dmv = dm_fetch<NP>(sd, tid);
+    double gq[Q];  // live across the barrier only where this kernel adds the wall flux
     if (act) {
         G = sd.lgid[l];
         load_metric<D>(sd, n, l, geo);
         pr = sd.rho[G];
         smu[ln] = sd.mu[G];
-        double gq[Q];
 #pragma unroll
         for (int q = 1; q < Q; ++q) gq[q] = g[q * Ng + G];
 #pragma unroll
@@ -842,9 +847,14 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
         stream_finish<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, G, pr, geo, stage);
         return;
     }
-    // the flux bounce-back of wall nodes is added to these partials by k_wall (geo.wf is
-    // empty here, so residual_q adds no wall term and needs no populations)
-    stream_residual<Q, D, N, WIDE, false>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, nullptr, geo);
+    if constexpr (WallKernel<D>::v) {
+        // the flux bounce-back of wall nodes is added to these partials by k_wall (geo.wf
+        // is empty here, so residual_q adds no wall term and needs no populations)
+        stream_residual<Q, D, N, WIDE, false>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, nullptr, geo);
+    } else {
+        load_wall_flux<D>(sd, l, geo.wf);
+        stream_residual<Q, D, N, WIDE, true>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
+    }
 }
 
 // Eq. (9) on the wall nodes of the unfused path: adds the flux bounce-back terms of every
@@ -853,6 +863,7 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
 // those of residual_q bit for bit.  Keeping the wall data out of k_stream saves it the
 // registers of up to d faces' s n and u_b.  Launched on the element plan: one lane per
 // local node (storage order); lanes of nodes without walls return after one load.
+// 3-D only (WallKernel).
 template <int DQ, int N, bool WIDE, bool SINGLE>
 __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_wall(LaunchPlan p, int stage) {
     constexpr int D = DimOf<DQ>::v;
@@ -1667,18 +1678,19 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 #define SLBM_CASE_stream(DD, NN)                                                             \
     if (!done && d == DD && N == NN) {                                                       \
         const bool wide = p.epb == Shape<DimOf<DD>::v, NN, true>::EPB;                       \
+        constexpr bool wk = WallKernel<DimOf<DD>::v>::v;                                     \
         if (wide && p.single) {                                                              \
             SLBM_ELEM_LAUNCH(k_stream, DD, NN, true, true, stage);                           \
-            SLBM_ELEM_LAUNCH(k_wall, DD, NN, true, true, stage);                             \
+            if (wk) SLBM_ELEM_LAUNCH(k_wall, DD, NN, true, true, stage);                     \
         } else if (wide) {                                                                   \
             SLBM_ELEM_LAUNCH(k_stream, DD, NN, true, false, stage);                          \
-            SLBM_ELEM_LAUNCH(k_wall, DD, NN, true, false, stage);                            \
+            if (wk) SLBM_ELEM_LAUNCH(k_wall, DD, NN, true, false, stage);                    \
         } else if (p.single) {                                                               \
             SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, true, stage);                          \
-            SLBM_ELEM_LAUNCH(k_wall, DD, NN, false, true, stage);                            \
+            if (wk) SLBM_ELEM_LAUNCH(k_wall, DD, NN, false, true, stage);                    \
         } else {                                                                             \
             SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, false, stage);                         \
-            SLBM_ELEM_LAUNCH(k_wall, DD, NN, false, false, stage);                           \
+            if (wk) SLBM_ELEM_LAUNCH(k_wall, DD, NN, false, false, stage);                   \
         }                                                                                    \
         done = true;                                                                         \
     }
