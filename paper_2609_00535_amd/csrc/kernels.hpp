@@ -275,13 +275,28 @@ __device__ __forceinline__ double wall_lap_term(const SolveDesc &sd, const WallL
 // entry (one load); further copies, on nodes shared by more than two elements, through
 // csr_idx.  Ascending local order, from +0.0, as the oracle sums.
 // ------------------------------------------------------------------------------------------
+// Copies beyond the second are fetched kCsrAhead at a time: all their indices, then all
+// their values, then the sums in order (one dependent round trip per group of copies, not
+// two per copy).
+constexpr int kCsrAhead = 6;
+
 template <class P>
 __device__ __forceinline__ double dss_sum(P v, const NodeCopies &c, const int SLBM_GLOBAL *csr_idx) {
     const double x0 = v[c.i0], x1 = v[c.i1];
     double s = 0.0;
     s += x0;
     s += c.nc > 1 ? x1 : 0.0;
-    for (int k = 2; k < c.nc; ++k) s += v[csr_idx[c.k0 + k]];
+    for (int k = 2; k < c.nc; k += kCsrAhead) {
+        int li[kCsrAhead];
+        double x[kCsrAhead];
+#pragma unroll
+        for (int j = 0; j < kCsrAhead; ++j) li[j] = k + j < c.nc ? csr_idx[c.k0 + k + j] : -1;
+#pragma unroll
+        for (int j = 0; j < kCsrAhead; ++j) x[j] = li[j] >= 0 ? v[li[j]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kCsrAhead; ++j)
+            if (k + j < c.nc) s += x[j];
+    }
     return s;
 }
 
@@ -949,14 +964,29 @@ __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
         R[q] += x0[q];
         R[q] += cp.nc > 1 ? x1[q] : 0.0;
     }
-    // copies beyond the second (edges and corners): copies outer, populations inner
-    for (int k = 2; k < cp.nc; ++k) {
-        const int li = sd.csr_idx[cp.k0 + k];
-        double x[Q];
+    // copies beyond the second (edges and corners): the indices of up to kCsrAhead of them
+    // in one round trip, then their residuals two copies at a time, summed in copy order
+    for (int k = 2; k < cp.nc; k += kCsrAhead) {
+        int li[kCsrAhead];
 #pragma unroll
-        for (int q = 1; q < Q; ++q) x[q] = sd.rs[(size_t)(q - 1) * Nl + li];
+        for (int j = 0; j < kCsrAhead; ++j) li[j] = k + j < cp.nc ? sd.csr_idx[cp.k0 + k + j] : -1;
 #pragma unroll
-        for (int q = 1; q < Q; ++q) R[q] += x[q];
+        for (int j = 0; j < kCsrAhead; j += 2) {
+            if (li[j] >= 0) {
+                double xa[Q], xb[Q];
+#pragma unroll
+                for (int q = 1; q < Q; ++q) {
+                    xa[q] = sd.rs[(size_t)(q - 1) * Nl + li[j]];
+                    xb[q] = li[j + 1] >= 0 ? sd.rs[(size_t)(q - 1) * Nl + li[j + 1]] : 0.0;
+                }
+#pragma unroll
+                for (int q = 1; q < Q; ++q) R[q] += xa[q];
+                if (li[j + 1] >= 0) {
+#pragma unroll
+                    for (int q = 1; q < Q; ++q) R[q] += xb[q];
+                }
+            }
+        }
     }
     double rho = 0.0;
 #pragma unroll
