@@ -152,8 +152,7 @@ def traffic_from_profiles(workload: str, kind: str):
     if rec.get("kernels_sha256") != kernels_sha256():
         return None
     per = rec.get("bytes_per_launch", {})
-    # one launch of the unfused stream kind is k_stream followed by k_wall
-    v = per.get("stream_kind") if kind == "stream" and "stream_kind" in per else per.get(kind)
+    v = per.get(kind)
     return float(v) if v is not None else None
 
 

@@ -728,9 +728,7 @@ __device__ __forceinline__ double residual_q(const SolveDesc &sd, int q, const d
     return r;
 }
 
-// WALLS: add the flux bounce-back of the node's wall faces (needs gq); without it the
-// caller adds them later (k_wall) and gq is not read
-template <int Q, int D, int N, bool WIDE, bool WALLS = true>
+template <int Q, int D, int N, bool WIDE>
 __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const double *sD, const double *sh,
                                                 const double *smu_e, int es, int n, int l,
                                                 double pr, const double *gq, const NodeGeo<D> &geo) {
@@ -740,8 +738,8 @@ __device__ __forceinline__ void stream_residual(const SolveDesc &sd, const doubl
     grad_ref<D, NP>(sD, smu_e, n, dmu);
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-        const double gqq = WALLS ? gq[q] : 0.0, gop = WALLS ? gq[Lat<Q>::opp[q]] : 0.0;
-        const double r = residual_q<Q, D, NP>(sd, q, sD, sh + (q - 1) * NB + es * NLOC, n, dmu, pr, gqq, gop, geo);
+        const double r = residual_q<Q, D, NP>(sd, q, sD, sh + (q - 1) * NB + es * NLOC, n, dmu, pr, gq[q],
+                                              gq[Lat<Q>::opp[q]], geo);
         sd.rs[(size_t)(q - 1) * sd.Nl + l] = r;
     }
 }
@@ -803,11 +801,6 @@ __device__ __forceinline__ void stream_finish(const SolveDesc &sd, const double 
     sd.rho[G] = rho;
 }
 
-// Where the unfused path adds the flux bounce-back of Eq. (9): in 3-D a kernel of its own
-// (k_wall) after k_stream, which then holds no wall data or populations across the
-// residual loop; in 2-D k_stream itself, which has the registers for them
-template <int D> struct WallKernel { static constexpr bool v = D == 3; };
-
 // stage 1 streams g0, stages 2-3 stream g1 (stage 0, the operator entry point, streams g1)
 template <int DQ, int N, bool WIDE, bool SINGLE>
 __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ>::v, N, WIDE>::WPE_STREAM)) void k_stream(LaunchPlan p, int stage) {
@@ -844,7 +837,7 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     // every lane below (N+1)^2 fetches its entry of D (with the split lane map such a lane
     // can belong to an element slot past the end of the mesh)
     dmv = dm_fetch<NP>(sd, tid);
-    double gq[Q];  // live across the barrier only where this kernel adds the wall flux
+    double gq[Q];  // kept across the barrier for the flux bounce-back of wall nodes
     if (act) {
         G = sd.lgid[l];
         load_metric<D>(sd, n, l, geo);
@@ -862,68 +855,8 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
         stream_finish<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, G, pr, geo, stage);
         return;
     }
-    if constexpr (WallKernel<D>::v) {
-        // the flux bounce-back of wall nodes is added to these partials by k_wall (geo.wf
-        // is empty here, so residual_q adds no wall term and needs no populations)
-        stream_residual<Q, D, N, WIDE, false>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, nullptr, geo);
-    } else {
-        load_wall_flux<D>(sd, l, geo.wf);
-        stream_residual<Q, D, N, WIDE, true>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
-    }
-}
-
-// Eq. (9) on the wall nodes of the unfused path: adds the flux bounce-back terms of every
-// wall face through the node to the residual partials k_stream stored without them, in the
-// order residual_q adds them (face by face, incoming populations only), so the partials are
-// those of residual_q bit for bit.  Keeping the wall data out of k_stream saves it the
-// registers of up to d faces' s n and u_b.  Launched on the element plan: one lane per
-// local node (storage order); lanes of nodes without walls return after one load.
-// 3-D only (WallKernel).
-template <int DQ, int N, bool WIDE, bool SINGLE>
-__global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_wall(LaunchPlan p, int stage) {
-    constexpr int D = DimOf<DQ>::v;
-    constexpr int Q = QOfDQ<DQ>::v;
-    using S = Shape<D, N, WIDE>;
-    constexpr int NLOC = S::NLOC, NB = S::NB;
-    const BlockSlot bs = block_slot<SINGLE>(p);
-    if (!bs.valid) return;
-    const SolveDesc sd = desc_of<SINGLE>(p, bs);
-    const int tid = threadIdx.x;
-    const int es = tid / NLOC, m = tid - es * NLOC;
-    const int e = bs.local * S::EPB + es;
-    if (tid >= NB || e >= sd.E) return;
-    const int l = e * NLOC + m;
-    if ((sd.lwall[l] & 3) == 0) return;
-    const double SLBM_GLOBAL *g = stage == 1 ? sd.g0 : sd.g1;
-    const size_t Ng = sd.Ng, Nl = sd.Nl;
-    WallFlux<D> wf;
-    load_wall_flux<D>(sd, l, wf);
-    const int G = sd.lgid[l];
-    const double pr = sd.rho[G];
-    double gq[Q], r[Q];
-#pragma unroll
-    for (int q = 1; q < Q; ++q) gq[q] = g[q * Ng + G];
-#pragma unroll
-    for (int q = 1; q < Q; ++q) r[q] = sd.rs[(size_t)(q - 1) * Nl + l];
-#pragma unroll
-    for (int q = 1; q < Q; ++q) {
-        const double tc = sd.twc[wcls<Q>(q)];
-        double x = r[q];
-        bool any = false;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j < wf.cnt) {
-                const double cn = dot_e<Q, D>(wf.sn[j], q, sd);
-                if (cn < 0.0) {
-                    const double eub = dot_e<Q, D>(wf.ub[j], q, sd);
-                    const double bc = gq[q] - gq[Lat<Q>::opp[q]] - 2.0 * tc * pr * eub;
-                    x += cn * bc;
-                    any = true;
-                }
-            }
-        }
-        if (any) sd.rs[(size_t)(q - 1) * Nl + l] = x;
-    }
+    load_wall_flux<D>(sd, l, geo.wf);
+    stream_residual<Q, D, N, WIDE>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
 }
 
 template <int DQ, int N, bool SINGLE>
@@ -1705,25 +1638,7 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 #define SLBM_CASE_grad(DD, NN) SLBM_ELEM_CASE(k_grad, DD, NN, collide)
 #define SLBM_CASE_gavg(DD, NN) SLBM_NODE_CASE(k_gavg, DD, NN)
 #define SLBM_CASE_collide(DD, NN) SLBM_NODE_CASE(k_collide, DD, NN, use_aux)
-#define SLBM_CASE_stream(DD, NN)                                                             \
-    if (!done && d == DD && N == NN) {                                                       \
-        const bool wide = p.epb == Shape<DimOf<DD>::v, NN, true>::EPB;                       \
-        constexpr bool wk = WallKernel<DimOf<DD>::v>::v;                                     \
-        if (wide && p.single) {                                                              \
-            SLBM_ELEM_LAUNCH(k_stream, DD, NN, true, true, stage);                           \
-            if (wk) SLBM_ELEM_LAUNCH(k_wall, DD, NN, true, true, stage);                     \
-        } else if (wide) {                                                                   \
-            SLBM_ELEM_LAUNCH(k_stream, DD, NN, true, false, stage);                          \
-            if (wk) SLBM_ELEM_LAUNCH(k_wall, DD, NN, true, false, stage);                    \
-        } else if (p.single) {                                                               \
-            SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, true, stage);                          \
-            if (wk) SLBM_ELEM_LAUNCH(k_wall, DD, NN, false, true, stage);                    \
-        } else {                                                                             \
-            SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, false, stage);                         \
-            if (wk) SLBM_ELEM_LAUNCH(k_wall, DD, NN, false, false, stage);                   \
-        }                                                                                    \
-        done = true;                                                                         \
-    }
+#define SLBM_CASE_stream(DD, NN) SLBM_ELEM_CASE(k_stream, DD, NN, stage)
 #define SLBM_CASE_rk(DD, NN) SLBM_NODE_CASE(k_rk, DD, NN, stage)
 #define SLBM_CASE_density(DD, NN) SLBM_NODE_CASE(k_density, DD, NN, which)
 #define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)
