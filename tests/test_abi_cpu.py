@@ -280,3 +280,17 @@ def test_server_config_errors(L):
     res = B.Result()
     assert L.slbm_server_poll(h, 12345, C.byref(res)) == B.SLBM_EINVAL
     L.slbm_server_destroy(h)
+
+
+def test_degenerate_inputs(L):
+    """An empty mesh is rejected; a batch with no members steps as a no-op."""
+    import paper_2609_00535_amd as P
+    h = _create(L, cases.c1())
+    xyz, gid = np.zeros(1), np.zeros(1, dtype=np.int32)
+    assert L.slbm_set_mesh(h, 0, xyz.ctypes.data, gid.ctypes.data, 0, 0, None, None, None) == \
+        P.binding.SLBM_EINVAL
+    L.slbm_destroy(h)
+    b = C.c_void_p()
+    assert L.slbm_batch_create(None, C.byref(b)) == 0
+    assert L.slbm_batch_step(b, 5) == 0
+    L.slbm_batch_destroy(b)

@@ -7,6 +7,7 @@ no other contraction), so they usually agree bit for bit; the asserted tolerance
 FMA contraction alone produces after 1000 steps of the isolated droplet c1 (8x8 quads,
 N=4).
 """
+import math
 import numpy as np
 import pytest
 
@@ -914,3 +915,32 @@ def test_batch_unfused_group_after_state_upload_keeps_partials_fresh(P):
         solves[0].step(6)  # alone: fused, from recomputed partials
         assert np.array_equal(solves[0].get_state()[0], ref18)
         del b
+
+
+def _one_element(dim):
+    """Degenerate meshes: a single walled element (2-D N = 8, 3-D N = 4), a droplet at its
+    centre with a 60-degree wetting floor; every boundary node has one copy and a wall."""
+    cb = math.cos(math.radians(60.0))
+    if dim == 2:
+        m = meshes.box2d(1, 1, 8, 24.0, 24.0, periodic=(False, False), cos_theta={"bottom": cb},
+                         name="one_element")
+        return cases.Case("one_element", m, cases.LATTICE_D2Q9, x0=(12.0, 12.0), R=6.0, seed=21,
+                          noise=1e-4)
+    m = meshes.box3d(1, 1, 1, 4, (16.0, 16.0, 16.0), periodic=(False, False, False),
+                     cos_theta={"z-": cb}, name="one_element3d")
+    return cases.Case("one_element3d", m, cases.LATTICE_D3Q19, x0=(8.0, 8.0, 8.0), R=4.0, seed=22,
+                      noise=1e-4)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("unfused", [False, True])
+def test_single_element_mesh(P, monkeypatch, dim, unfused):
+    """A mesh of one element (no node shared between elements; every boundary node on a
+    wall) on both kernel paths: 50 steps against the oracle."""
+    if unfused:
+        monkeypatch.setenv("SLBM_UNFUSED", "1")
+    c = _one_element(dim)
+    s, o = _run_pair(c, P, 50)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] {c.name} unfused={unfused} 50 steps: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
