@@ -55,6 +55,7 @@ struct slbm_ctx {
     int vmax = 0;
     bool fused = true;  // fused element-kernel path (needs vmax <= the fused copy slots)
     int64_t Nint = 0;   // element-interior nodes numbered first (unfused path; see SolveDesc)
+    int64_t lstride = 0, Nld = 0;  // device element stride and size of the per-local-node arrays
     std::vector<double> Ja, Gm, MA, Minv, w_dat;
     // device
     struct Offsets {

@@ -41,6 +41,11 @@ struct SolveDesc {
     // them (mu in k_lap, the collision in k_grad, the Runge-Kutta stage in k_stream) and the
     // node kernels mu, collide and rk run over nodes Nint .. Ng-1 only.  0: no split.
     int Nint;
+    // element stride of the per-local-node arrays (lgid, lwall, Ja, G and the per-copy
+    // partials): (N+1)^d, or on the 3-D split path that count rounded up to 16 doubles, so
+    // every element's block of each array starts on a 128-byte line (at N = 5 the runs of
+    // each face's 16 nodes then fill whole lines); Nl is E times this stride
+    int lstride;
     // mesh tables (device)
     const int SLBM_GLOBAL *lgid;      // [Nl] local node -> internal global node
     const double SLBM_GLOBAL *Ja;     // [d*d][Nl] J * d xi_a / d x_c, index (a*d + c)

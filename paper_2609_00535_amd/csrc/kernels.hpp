@@ -456,7 +456,7 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_lap(Laun
     const int ln = es * NLOC + n;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + m;
+    const int l = e * sd.lstride + m;
     // element-interior node of a split mesh: its Laplacian has this copy alone, so mu is
     // finished here (as k_mu would: the sum of one copy, times 1/M)
     const bool own = sd.Nint > 0 && m < S::NINT;
@@ -578,7 +578,7 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_grad(Lau
     const int ln = es * NLOC + n;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + m;
+    const int l = e * sd.lstride + m;
     const bool own = collide && sd.Nint > 0 && m < S::NINT;
     const size_t Ng = sd.Ng;
     double J[D][D];
@@ -844,7 +844,7 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     const int ln = es * NLOC + n;
     const int e = bs.local * S::EPB + es;
     const bool act = tid < NB && e < sd.E;
-    const int l = e * NLOC + m;
+    const int l = e * sd.lstride + m;
     const size_t Ng = sd.Ng;
     const bool own = sd.Nint > 0 && m < S::NINT;
     double pr = 0.0;

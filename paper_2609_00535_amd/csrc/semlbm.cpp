@@ -363,6 +363,9 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
             for (int64_t l = 0; l < Nl; ++l) c->lgid[l] = renum[c->lgid[l]];
             build_copies();
         }
+        // device element stride of the per-local-node arrays (see SolveDesc::lstride)
+        c->lstride = (c->Nint > 0 && dim == 3) ? ((nloc + 15) / 16) * 16 : nloc;
+        c->Nld = E * c->lstride;
         // per-local-node copy lists (fused path only): the ascending local copies of its global
         // node in kCopySlots[dim-2] rows, -1 padded, so the fused kernels load every slot
         // without a branch
@@ -622,14 +625,14 @@ void slbm_ctx::layout() {
     off.desc = take(sizeof(SolveDesc));
     off.eplan = take(sizeof(int) * 2 * (size_t)n_eblocks);
     off.nplan = take(sizeof(int) * 2 * (size_t)n_nblocks);
-    off.lgid = take(sizeof(int) * Nl);
+    off.lgid = take(sizeof(int) * Nld);
     off.gcopy = take(sizeof(int) * 4 * Ng);
     off.csr_idx = take(sizeof(int) * Nl);
     off.lcp = take(sizeof(int) * std::max<size_t>(lcp.size(), 1));
-    off.lwall = take(sizeof(int) * Nl);
+    off.lwall = take(sizeof(int) * Nld);
     off.w_dat = take(sizeof(double) * w_dat.size());
-    off.Ja = take(sizeof(double) * dim_ * dim_ * Nl);
-    off.G = take(sizeof(double) * ng * Nl);
+    off.Ja = take(sizeof(double) * dim_ * dim_ * Nld);
+    off.G = take(sizeof(double) * ng * Nld);
     off.Minv = take(sizeof(double) * Ng);
     off.Dm = take(sizeof(double) * Np * Np);
     off.wn = take(sizeof(double) * nloc);
@@ -639,9 +642,9 @@ void slbm_ctx::layout() {
     off.g2 = take(sizeof(double) * Q_ * Ng);
     off.rho = take(sizeof(double) * Ng);
     off.mu = take(sizeof(double) * Ng);
-    off.rl = take(sizeof(double) * Nl);
-    off.gl = take(sizeof(double) * 2 * dim_ * Nl);
-    off.rs = take(sizeof(double) * (Q_ - 1) * Nl);
+    off.rl = take(sizeof(double) * Nld);
+    off.gl = take(sizeof(double) * 2 * dim_ * Nld);
+    off.rs = take(sizeof(double) * (Q_ - 1) * Nld);
     off.aux = take(sizeof(double) * 2 * dim_ * Ng);
     off.diag = take(sizeof(double) * 4);
     off.red = take(sizeof(double) * 2 * (size_t)n_nblocks);
@@ -667,7 +670,8 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
         SolveDesc &d = c->desc;
         std::memset(&d, 0, sizeof d);
         d.E = (int)c->E;
-        d.Nl = (int)c->Nl;
+        d.Nl = (int)c->Nld;
+        d.lstride = (int)c->lstride;
         d.Ng = (int)c->Ng;
         d.Nint = (int)c->Nint;
         d.lgid = at<int>(b, c->off.lgid);
@@ -745,24 +749,26 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
         // Element-interior split: the device stores each element's local nodes interior-first
         // (interior nodes, then boundary nodes, each in natural order; the kernels' lane map
         // is the inverse).  Host tables stay in natural order; permuted copies are uploaded.
-        const int64_t Nl = c->Nl, nloc = c->nloc;
+        const int64_t Nl = c->Nl, nloc = c->nloc, Nld = c->Nld, ls = c->lstride;
         std::vector<int32_t> pos;  // natural element node -> storage position
         if (c->Nint > 0) {
             const std::vector<int> order = split_storage_order(dim, c->N);
             pos.assign(nloc, 0);
             for (int m = 0; m < (int)order.size(); ++m) pos[order[m]] = m;
         }
-        auto lmap = [&](int64_t l) -> int64_t { return pos.empty() ? l : (l / nloc) * nloc + pos[l % nloc]; };
+        // storage position of local node l: element slot of ls positions (padded past nloc
+        // on the 3-D split path), the element's nodes in storage order
+        auto lmap = [&](int64_t l) -> int64_t { return pos.empty() ? l : (l / nloc) * ls + pos[l % nloc]; };
         auto perm_int = [&](const std::vector<int32_t> &v, int fields) {
-            std::vector<int32_t> o(v.size());
+            std::vector<int32_t> o((size_t)fields * Nld, 0);
             for (int k = 0; k < fields; ++k)
-                for (int64_t l = 0; l < Nl; ++l) o[(size_t)k * Nl + lmap(l)] = v[(size_t)k * Nl + l];
+                for (int64_t l = 0; l < Nl; ++l) o[(size_t)k * Nld + lmap(l)] = v[(size_t)k * Nl + l];
             return o;
         };
         auto perm_dbl = [&](const std::vector<double> &v, int fields) {
-            std::vector<double> o(v.size());
+            std::vector<double> o((size_t)fields * Nld, 0.0);
             for (int k = 0; k < fields; ++k)
-                for (int64_t l = 0; l < Nl; ++l) o[(size_t)k * Nl + lmap(l)] = v[(size_t)k * Nl + l];
+                for (int64_t l = 0; l < Nl; ++l) o[(size_t)k * Nld + lmap(l)] = v[(size_t)k * Nl + l];
             return o;
         };
         std::vector<int32_t> lgid_u, lwall_u, csr_u, gcopy_u;
@@ -784,14 +790,14 @@ extern "C" slbm_status slbm_bind(slbm_ctx *c, void *dev_ptr, size_t bytes, void 
         up(c->off.desc, &d, sizeof d);
         up(c->off.eplan, ep.data(), sizeof(int) * ep.size());
         up(c->off.nplan, np_.data(), sizeof(int) * np_.size());
-        up(c->off.lgid, (perm ? lgid_u : c->lgid).data(), sizeof(int) * c->Nl);
+        up(c->off.lgid, (perm ? lgid_u : c->lgid).data(), sizeof(int) * c->Nld);
         up(c->off.gcopy, (perm ? gcopy_u : c->gcopy).data(), sizeof(int) * c->gcopy.size());
         up(c->off.csr_idx, (perm ? csr_u : c->csr_idx).data(), sizeof(int) * c->Nl);
         up(c->off.lcp, c->lcp.data(), sizeof(int) * c->lcp.size());
-        up(c->off.lwall, (perm ? lwall_u : c->lwall).data(), sizeof(int) * c->Nl);
+        up(c->off.lwall, (perm ? lwall_u : c->lwall).data(), sizeof(int) * c->Nld);
         up(c->off.w_dat, c->w_dat.data(), sizeof(double) * c->w_dat.size());
-        up(c->off.Ja, (perm ? Ja_u : c->Ja).data(), sizeof(double) * dim * dim * c->Nl);
-        up(c->off.G, (perm ? G_u : c->Gm).data(), sizeof(double) * ng * c->Nl);
+        up(c->off.Ja, (perm ? Ja_u : c->Ja).data(), sizeof(double) * dim * dim * c->Nld);
+        up(c->off.G, (perm ? G_u : c->Gm).data(), sizeof(double) * ng * c->Nld);
         up(c->off.Minv, c->Minv.data(), sizeof(double) * c->Ng);
         up(c->off.Dm, c->Dm.data(), sizeof(double) * c->Np * c->Np);
         up(c->off.wn, c->wn.data(), sizeof(double) * c->nloc);
