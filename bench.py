@@ -9,7 +9,7 @@ configuration; the default line also carries c2, c2-XL, batched-stepping and ser
 objects and the oracle's CPU rate on c4.  All inputs are seeded and synthetic and
 resident in device memory before the timed region.
 
-Prints one JSON line (see the "value", "roofline" and "cpu_baseline" keys).
+Prints one JSON line (see the "value", "roofline", "fp64" and "cpu_baseline" keys).
 """
 from __future__ import annotations
 
@@ -25,6 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64, vector and matrix alike
 
 
 def algorithmic_bytes(kind: str, Q: int, d: int, Ng: int, Nl: int, Ni: int = 0) -> float:
@@ -154,6 +155,34 @@ def traffic_from_profiles(workload: str, kind: str):
     per = rec.get("bytes_per_launch", {})
     v = per.get(kind)
     return float(v) if v is not None else None
+
+
+def fp64_from_profiles(workload: str):
+    """FP64 flops per launch of each kernel kind from the committed instruction-counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"fp64_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernels_sha256") != kernels_sha256():
+        return None
+    return {k: float(v) for k, v in rec.get("flops_per_launch", {}).items()}
+
+
+def fp64_point(flops: dict | None, prof: dict, profile_steps: int, ms_per_step: float,
+               dom: str, avg_launch_ms: float, model_bytes: float):
+    """The step's FP64 rate against the FP64 peak: counted flops per launch of every kernel
+    kind times its launches per step (from the profiled steps), over the step time."""
+    if not flops or any(k not in flops for k in prof):
+        return None
+    per_step = sum(flops[k] * nl / profile_steps for k, (_, nl) in prof.items())
+    tf = per_step / (ms_per_step * 1e-3) / 1e12
+    tf_dom = flops[dom] / (avg_launch_ms * 1e-3) / 1e12
+    return {"achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
+            "flops_per_step": per_step, "flop_per_model_byte": per_step / model_bytes,
+            "kernel": dom, "kernel_achieved": tf_dom, "kernel_frac": tf_dom / FP64_PEAK_TFLOPS,
+            "source": "rocprofv3 FP64 VALU instruction counters (profiles/fp64_<workload>.json); "
+                      "all 64 lanes of each instruction counted, so an upper bound"}
 
 
 def copy_calibration(torch, mib: int, reps: int = 3):
@@ -485,6 +514,8 @@ def measure_workload(P, torch, name: str, steps: int, warmup: int, profile_steps
                      "avg_launch_us_in_step": tot / max(nl, 1) * 1e3,
                      "algorithmic_bytes_per_launch": alg,
                      "kernel_ms_per_step": {k: v[0] / profile_steps for k, v in prof.items()}},
+        "fp64": fp64_point(fp64_from_profiles(name), prof, profile_steps, ms_per_step, dom, avg_ms,
+                           step_model_bytes(Q, d, Ng, Nl)),
     }
 
 
@@ -572,6 +603,7 @@ def main():
         "data": "synthetic",
         "config": r["config"],
         "roofline": r["roofline"],
+        "fp64": r["fp64"],
     }
     if args.workload == "c4" and not args.no_extras:
         # extra points beside the headline: c2 (a cache-resident, latency-bound 2-D step),
@@ -586,7 +618,8 @@ def main():
                         "roofline": {k: x["roofline"][k] for k in
                                      ("bound", "kernel", "achieved", "peak", "unit", "frac",
                                       "step_achieved", "step_frac", "traffic", "avg_launch_us",
-                                      "algorithmic_bytes_per_launch")}}
+                                      "algorithmic_bytes_per_launch")},
+                        "fp64": x["fp64"]}
         if not args.no_serving:
             if args.batch_members > 0:
                 out["batch"] = batch_bench(P, torch, args.batch_members, args.batch_steps)

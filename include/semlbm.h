@@ -42,7 +42,10 @@
  *                         mesh allows them (by default not for meshes over 2^20 local
  *                         nodes); a batch still steps a group over 2^20 local nodes with
  *                         the unfused kernels
- *   SLBM_NO_GRAPH=1       slbm_bind / slbm_batch_create: plain launches, no HIP graphs
+ *   SLBM_NO_SPLIT=1       slbm_set_mesh: on the unfused path keep the mesh's own global
+ *                         numbering (no element-interior nodes first, no padded element
+ *                         stride); every node then goes through the node kernels
+ *   SLBM_NO_GRAPH=1      slbm_bind / slbm_batch_create: plain launches, no HIP graphs
  *   SLBM_SERIAL_GROUPS=1  slbm_batch_create: a batch's groups one after another on its
  *                         stream instead of on concurrent streams
  *   SLBM_AUTOTUNE=0       slbm_batch_create: no launch-shape timing (fixed shape rule)

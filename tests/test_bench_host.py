@@ -68,7 +68,7 @@ def test_committed_traffic_records_match_the_kernels():
     null by bench.py."""
     import pytest
     b = _bench()
-    for w, kind in (("c2", "f_rk_lap"), ("c4", "rk")):
+    for w, kind in (("c2", "f_rk_lap"), ("c3", "f_rk_lap"), ("c2xl", "stream"), ("c4", "rk")):
         rec = json.load(open(os.path.join(ROOT, "profiles", f"traffic_{w}.json")))
         if rec["kernels_sha256"] != b.kernels_sha256():
             assert b.traffic_from_profiles(w, kind) is None
@@ -77,3 +77,40 @@ def test_committed_traffic_records_match_the_kernels():
         cal = rec["calibration"]
         assert abs(cal["fetch_scale"] - 2.0) < 1e-3 and abs(cal["write_scale"] - 1.0) < 1e-3
     assert b.traffic_from_profiles("no_such_workload", "rk") is None
+
+
+def test_fp64_rate_from_counted_flops():
+    """The step's FP64 rate: each kind's flops per launch times its launches per profiled
+    step, over the step time; null when a kind in the step has no count."""
+    b = _bench()
+    flops = {"stream": 6.0e9, "rk": 1.0e9, "lap": 5.0e8}
+    # (ms over the profiled steps, launches over the profiled steps), 2 profiled steps
+    prof = {"stream": (3.0, 6), "rk": (1.5, 6), "lap": (0.5, 6)}
+    r = b.fp64_point(flops, prof, 2, 2.5, "stream", 0.5, 4.0e9)
+    per_step = 3 * 6.0e9 + 3 * 1.0e9 + 3 * 5.0e8
+    assert abs(r["flops_per_step"] - per_step) < 1.0
+    assert abs(r["achieved"] - per_step / 2.5e-3 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-12 and r["unit"] == "TFLOP/s"
+    assert abs(r["kernel_achieved"] - 6.0e9 / 0.5e-3 / 1e12) < 1e-9
+    assert abs(r["flop_per_model_byte"] - per_step / 4.0e9) < 1e-12
+    assert b.fp64_point({"stream": 1.0}, prof, 2, 2.5, "stream", 0.5, 4.0e9) is None
+    assert b.fp64_point(None, prof, 2, 2.5, "stream", 0.5, 4.0e9) is None
+
+
+def test_committed_fp64_records_match_the_kernels():
+    """The committed FP64 instruction counts: taken on the current kernels (else skipped
+    and reported as null), flops = 64 x (add + mul + trans + 2 fma) per launch."""
+    import pytest
+    b = _bench()
+    for w in ("c2", "c3", "c2xl", "c4", "c4q13"):
+        rec = json.load(open(os.path.join(ROOT, "profiles", f"fp64_{w}.json")))
+        if rec["kernels_sha256"] != b.kernels_sha256():
+            assert b.fp64_from_profiles(w) is None
+            pytest.skip(f"fp64_{w}.json predates the current kernels")
+        got = b.fp64_from_profiles(w)
+        for kind, n in rec["instructions_per_launch"].items():
+            f = 64 * (n["VALU_ADD_F64"] + n["VALU_MUL_F64"] + n["VALU_TRANS_F64"] + 2 * n["VALU_FMA_F64"]) \
+                + 512 * n["VALU_MFMA_MOPS_F64"]
+            assert abs(got[kind] - f) <= 1e-9 * f
+            assert n["VALU_MFMA_MOPS_F64"] == 0.0  # vector FP64 only
+    assert b.fp64_from_profiles("no_such_workload") is None
