@@ -228,6 +228,40 @@ def test_c4_d3q13_full_size(P):
     assert abs(mg - mo) <= 1e-13 * mo
 
 
+@pytest.mark.parametrize("mk", [cases.c4, cases.c4q13])
+def test_c4_after_1000_steps_last_step_and_mass(P, mk):
+    """c4 (both lattices) at full size, 1000 steps in the benchmark's launch configuration:
+    the oracle cannot run 1000 steps of this mesh within a test, so it takes the GPU's
+    state after 999 steps and advances it one step, and the GPU's state after step 1000
+    must agree with it to 1e-11 on rho and u; mass after 1000 steps equals the initial
+    mass to 1e-12 (the lumped-mass sum is conserved by every stage)."""
+    from oracle import Oracle, set_threads
+    c = mk()
+    s = P.Solve(c)
+    s.init_tanh()
+    _, m0 = s.kinetic_energy()
+    s.step(999)
+    f999, n999 = s.get_state()
+    assert n999 == 999
+    s.step(1)
+    _, m1 = s.kinetic_energy()
+    print(f"[parity] {c.name} 1000 steps: mass drift {abs(m1 - m0) / m0:.3e}", flush=True)
+    assert abs(m1 - m0) <= 1e-12 * m0
+    set_threads(_oracle_threads())
+    try:
+        o = Oracle(c)
+        o.set_f(f999)
+        o.step(1)
+    finally:
+        set_threads(1)
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] {c.name} step 1000 from the GPU's step 999: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+    ke_g, _ = s.kinetic_energy()
+    ke_o, _ = o.diag()
+    assert abs(ke_g - ke_o) <= 1e-9 * ke_o
+
+
 def test_kinetic_energy_floor(P):
     """Equilibration of a walled droplet to the residual floor (Sec. 3.3): log10 of the
     GPU's KE_max within 0.5 decades of the oracle's at every checkpoint, ending below
