@@ -1353,6 +1353,220 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_fD(Launc
 }
 
 // ------------------------------------------------------------------------------------------
+// B and D for elements of more than 256 nodes (2-D N = 16: 289) in blocks of four waves:
+// lane t handles node t, and lanes t < NLOC - 256 also node 256 + t.  With one lane per
+// node such an element needs a fifth wave, and blocks of five waves keep about half as
+// many waves resident per compute unit as blocks of four.  The second node's LDS inputs
+// are written first; what its residuals need across the barrier (f* or g, and rho) goes
+// through LDS, its metrics are read again after the barrier.  Every node's and every
+// population's arithmetic is that of k_fB / k_fD (wide instances), so the results are the
+// same bits.  Launched for
+// meshes of many blocks (kTailMinBlocks); the fifth wave is faster where few blocks share
+// a compute unit.
+// ------------------------------------------------------------------------------------------
+constexpr int kTailThreads = 256;
+constexpr int kTailMinBlocks = 512;
+template <int DD, int NN> constexpr bool kTail =
+    DimOf<DD>::v == 2 && Shape<2, NN, true>::NLOC > kTailThreads && Shape<2, NN, true>::NLOC <= 2 * kTailThreads;
+
+// After the barrier the residuals of the second nodes are spread over the four waves: lane
+// j < NLOC - 256 of wave w computes populations 1 + w (Q-1)/4 .. (w+1) (Q-1)/4 of node
+// 256 + j, so every wave adds a quarter of a node's residuals instead of the first wave
+// adding a whole node's (g or f* and rho of the second nodes come from LDS sx)
+template <int Q, int D, int N, int QA, int QN>
+__device__ __forceinline__ void tail_residuals(const SolveDesc &sd, const double *sD, const double *sh,
+                                               const double *smu, const double *sx, int e, int j) {
+    using S = Shape<D, N, true>;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB, NX = NLOC - kTailThreads;
+    const int n2 = kTailThreads + j, l2 = e * NLOC + n2;
+    NodeGeo<D> geo;
+    load_geo<D>(sd, n2, l2, geo);
+    const double p2 = sx[Q * NX + j];
+    double dmu[D];
+    grad_ref<D, NP>(sD, smu, n2, dmu);
+#pragma unroll
+    for (int k = 0; k < QN; ++k) {
+        const int q = QA + k;
+        const double r = residual_q<Q, D, NP>(sd, q, sD, sh + (q - 1) * NB, n2, dmu, p2, sx[q * NX + j],
+                                              sx[Lat<Q>::opp[q] * NX + j], geo);
+        sd.rs[(size_t)(q - 1) * sd.Nl + l2] = r;
+    }
+}
+template <int Q, int D, int N>
+__device__ __forceinline__ void tail_residuals_spread(const SolveDesc &sd, const double *sD, const double *sh,
+                                                      const double *smu, const double *sx, int e, int tid) {
+    constexpr int NX = Shape<D, N, true>::NLOC - kTailThreads;
+    constexpr int QN = (Q - 1) / 4;
+    static_assert((Q - 1) % 4 == 0 && kTailThreads == 4 * 64, "four waves, equal shares of populations");
+    const int j = tid & 63, w = tid >> 6;
+    if (j >= NX) return;
+    if (w == 0) tail_residuals<Q, D, N, 1, QN>(sd, sD, sh, smu, sx, e, j);
+    else if (w == 1) tail_residuals<Q, D, N, 1 + QN, QN>(sd, sD, sh, smu, sx, e, j);
+    else if (w == 2) tail_residuals<Q, D, N, 1 + 2 * QN, QN>(sd, sD, sh, smu, sx, e, j);
+    else tail_residuals<Q, D, N, 1 + 3 * QN, QN>(sd, sD, sh, smu, sx, e, j);
+}
+
+template <int DQ, int N, bool SINGLE>
+__global__ __launch_bounds__(kTailThreads) void k_fBt(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
+    using S = Shape<D, N, true>;
+    constexpr int Q = QOfDQ<DQ>::v;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    constexpr int NX = NLOC - kTailThreads;  // nodes of the second pass
+    static_assert(S::EPB == 1 && NX > 0 && NX <= kTailThreads && NP * NP <= 2 * kTailThreads,
+                  "one element per block, at most two nodes and two matrix entries per lane");
+    __shared__ double sD[NP * NP];
+    __shared__ double smu[NB];
+    __shared__ double sh[(Q - 1) * NB];
+    __shared__ double sx[(Q + 1) * NX];  // second nodes: f*_q, then rho
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x;
+    const int e = bs.local;
+    const bool act = e < sd.E;
+    const bool two = act && tid < NX;
+    const int n = tid, n2 = kTailThreads + tid;
+    const int l = e * NLOC + n, l2 = e * NLOC + (two ? n2 : n);
+    const size_t Ng = sd.Ng;
+    double dmv = 0.0, dmv2 = 0.0;
+    double fs[Q];
+    double pr = 0.0;
+    NodeGeo<D> geo;
+    if (act) {
+        dmv = sd.Dm[tid];
+        dmv2 = sd.Dm[n2 < NP * NP ? n2 : 0];
+    }
+    if (two) {
+        CopyList<D> cl;
+        load_copies<D, NP, true>(sd, n2, l2, cl);
+        const int G = sd.lgid[l2];
+        const double mi = sd.Minv[G];
+        double gr[D], gm[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            gr[c] = gather1<D, true>(sd.gl + (size_t)c * sd.Nl, cl) * mi;
+            gm[c] = gather1<D, true>(sd.gl + (size_t)(D + c) * sd.Nl, cl) * mi;
+        }
+        double f[Q], f2[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
+        const double p2 = sd.rho[G];
+        const double mu = sd.mu[G];
+        collide_node<Q, D>(sd, f, p2, gr, gm, f2);
+        if (cl.cp[0] == l2) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) sd.g0[q * Ng + G] = f2[q];
+        }
+        smu[n2] = mu;
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + n2] = f2[q] - sd.tw[wcls<Q>(q)] * p2;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sx[q * NX + tid] = f2[q];
+        sx[Q * NX + tid] = p2;
+    }
+    if (act) {
+        CopyList<D> cl;
+        load_copies<D, NP, true>(sd, n, l, cl);
+        const int G = sd.lgid[l];
+        load_geo<D>(sd, n, l, geo);
+        const double mi = sd.Minv[G];
+        double gr[D], gm[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            gr[c] = gather1<D, true>(sd.gl + (size_t)c * sd.Nl, cl) * mi;
+            gm[c] = gather1<D, true>(sd.gl + (size_t)(D + c) * sd.Nl, cl) * mi;
+        }
+        double f[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
+        pr = sd.rho[G];
+        const double mu = sd.mu[G];
+        collide_node<Q, D>(sd, f, pr, gr, gm, fs);
+        if (cl.cp[0] == l) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) sd.g0[q * Ng + G] = fs[q];
+        }
+        smu[n] = mu;
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + n] = fs[q] - sd.tw[wcls<Q>(q)] * pr;
+    }
+    sD[tid] = dmv;
+    if (n2 < NP * NP) sD[n2] = dmv2;
+    __syncthreads();
+    if (!act) return;
+    stream_residual<Q, D, N, true>(sd, sD, sh, smu, 0, n, l, pr, fs, geo);
+    tail_residuals_spread<Q, D, N>(sd, sD, sh, smu, sx, e, tid);
+}
+
+template <int DQ, int N, bool SINGLE>
+__global__ __launch_bounds__(kTailThreads) void k_fDt(LaunchPlan p, int stage) {
+    constexpr int D = DimOf<DQ>::v;
+    using S = Shape<D, N, true>;
+    constexpr int Q = QOfDQ<DQ>::v;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    constexpr int NX = NLOC - kTailThreads;
+    static_assert(S::EPB == 1 && NX > 0 && NX <= kTailThreads && NP * NP <= 2 * kTailThreads,
+                  "one element per block, at most two nodes and two matrix entries per lane");
+    __shared__ double sD[NP * NP];
+    __shared__ double smu[NB];
+    __shared__ double sh[(Q - 1) * NB];
+    __shared__ double sx[(Q + 1) * NX];  // second nodes: g_q, then rho
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x;
+    const int e = bs.local;
+    const bool act = e < sd.E;
+    const bool two = act && tid < NX;
+    const int n = tid, n2 = kTailThreads + tid;
+    const int l = e * NLOC + n, l2 = e * NLOC + (two ? n2 : n);
+    const size_t Ng = sd.Ng;
+    const double SLBM_GLOBAL *g = stage == 2 ? sd.g1 : sd.g2;
+    double dmv = 0.0, dmv2 = 0.0;
+    double gq[Q];
+    double pr = 0.0;
+    NodeGeo<D> geo;
+    if (act) {
+        dmv = sd.Dm[tid];
+        dmv2 = sd.Dm[n2 < NP * NP ? n2 : 0];
+    }
+    if (two) {
+        CopyList<D> cl;
+        load_copies<D, NP, true>(sd, n2, l2, cl);
+        const int G = sd.lgid[l2];
+        const double p2 = sd.rho[G];
+        smu[n2] = mu_of(sd, p2, gather1<D, true>(sd.rl, cl) * sd.Minv[G]);
+        double g2[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) g2[q] = g[q * Ng + G];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + n2] = g2[q] - sd.tw[wcls<Q>(q)] * p2;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sx[q * NX + tid] = g2[q];
+        sx[Q * NX + tid] = p2;
+    }
+    if (act) {
+        CopyList<D> cl;
+        load_copies<D, NP, true>(sd, n, l, cl);
+        const int G = sd.lgid[l];
+        load_geo<D>(sd, n, l, geo);
+        pr = sd.rho[G];
+        smu[n] = mu_of(sd, pr, gather1<D, true>(sd.rl, cl) * sd.Minv[G]);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) gq[q] = g[q * Ng + G];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + n] = gq[q] - sd.tw[wcls<Q>(q)] * pr;
+    }
+    sD[tid] = dmv;
+    if (n2 < NP * NP) sD[n2] = dmv2;
+    __syncthreads();
+    if (!act) return;
+    stream_residual<Q, D, N, true>(sd, sD, sh, smu, 0, n, l, pr, gq, geo);
+    tail_residuals_spread<Q, D, N>(sd, sD, sh, smu, sx, e, tid);
+}
+
+// ------------------------------------------------------------------------------------------
 // 2-D fused kernels B, C, D for one element per block (the latency-bound regime), with the
 // populations split over four groups of lanes: group g handles the opposite pair
 // (qa, opp(qa)), qa = 1, 2, 5, 6, and group 0 also q = 0.  Every group holds the whole
@@ -1622,6 +1836,29 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
     else k_fD<DD, NN, false, S><<<p.grid, Shape<DimOf<DD>::v, NN, false>::NT, 0, st>>>(p, stage);
 }
 
+// wide launches of B and D: the four-wave two-node kernels for elements of more than 256
+// nodes on meshes of many blocks, the one-lane-per-node kernels otherwise
+template <int DD, int NN, bool S>
+inline void launch_wide_fB(const LaunchPlan &p, hipStream_t st) {
+    if constexpr (kTail<DD, NN>) {
+        if (p.nblocks >= kTailMinBlocks) {
+            k_fBt<DD, NN, S><<<p.grid, kTailThreads, 0, st>>>(p);
+            return;
+        }
+    }
+    k_fB<DD, NN, true, S><<<p.grid, Shape<DimOf<DD>::v, NN, true>::NT, 0, st>>>(p);
+}
+template <int DD, int NN, bool S>
+inline void launch_wide_fD(const LaunchPlan &p, hipStream_t st, int stage) {
+    if constexpr (kTail<DD, NN>) {
+        if (p.nblocks >= kTailMinBlocks) {
+            k_fDt<DD, NN, S><<<p.grid, kTailThreads, 0, st>>>(p, stage);
+            return;
+        }
+    }
+    k_fD<DD, NN, true, S><<<p.grid, Shape<DimOf<DD>::v, NN, true>::NT, 0, st>>>(p, stage);
+}
+
 // ------------------------------------------------------------------------------------------
 // launchers of one set of (d, N) instances: SLBM_LAUNCHER_SET(sfx, ORDERS) defines
 // launch_<kernel>_<sfx>(d, N, plan, ..., stream) for the orders listed by ORDERS(X)
@@ -1646,6 +1883,15 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
         else NARROW<DD, NN, false>(p, st, ##__VA_ARGS__);                                    \
         done = true;                                                                         \
     }
+#define SLBM_SPLIT_WIDE_CASE(WIDEFN, NARROW, DD, NN, ...)                                    \
+    if (!done && d == DD && N == NN) {                                                       \
+        const bool wide = p.epb == Shape<DimOf<DD>::v, NN, true>::EPB;                                 \
+        if (wide && p.single) WIDEFN<DD, NN, true>(p, st, ##__VA_ARGS__);                    \
+        else if (wide) WIDEFN<DD, NN, false>(p, st, ##__VA_ARGS__);                          \
+        else if (p.single) NARROW<DD, NN, true>(p, st, ##__VA_ARGS__);                       \
+        else NARROW<DD, NN, false>(p, st, ##__VA_ARGS__);                                    \
+        done = true;                                                                         \
+    }
 #define SLBM_NODE_CASE(KERNEL, DD, NN, ...)                                                  \
     if (!done && d == DD && N == NN) {                                                       \
         if (p.single) KERNEL<DD, NN, true><<<p.grid, kNodeThreads, 0, st>>>(p, ##__VA_ARGS__); \
@@ -1662,9 +1908,9 @@ inline void launch_narrow_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 #define SLBM_CASE_density(DD, NN) SLBM_NODE_CASE(k_density, DD, NN, which)
 #define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)
 #define SLBM_CASE_fA(DD, NN) SLBM_ELEM_CASE(k_fA, DD, NN)
-#define SLBM_CASE_fB(DD, NN) SLBM_SPLIT_CASE(k_fB, launch_narrow_fB, DD, NN)
+#define SLBM_CASE_fB(DD, NN) SLBM_SPLIT_WIDE_CASE(launch_wide_fB, launch_narrow_fB, DD, NN)
 #define SLBM_CASE_fC(DD, NN) SLBM_SPLIT_CASE(k_fC, launch_narrow_fC, DD, NN, stage)
-#define SLBM_CASE_fD(DD, NN) SLBM_SPLIT_CASE(k_fD, launch_narrow_fD, DD, NN, stage)
+#define SLBM_CASE_fD(DD, NN) SLBM_SPLIT_WIDE_CASE(launch_wide_fD, launch_narrow_fD, DD, NN, stage)
 
 #define SLBM_DISPATCH(ORDERS, KERNEL)                                                        \
     do {                                                                                     \

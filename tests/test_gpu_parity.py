@@ -662,6 +662,49 @@ def test_wide_single_solve_every_order(P, d, n):
     assert np.all(np.isfinite(s.rho())) and er <= TOL and eu <= TOL
 
 
+def test_order16_four_wave_blocks(P):
+    """2-D N = 16 (289 nodes per element) on a mesh of 2048 elements, the size from which
+    the fused kernels B and D run 256-lane blocks with two nodes on the first 33 lanes: a
+    walled jittered box with a wetting floor (wall nodes in both the first and the second
+    pass of a lane), 4 steps against the oracle."""
+    from oracle import set_threads
+    c = cases.small_flat(theta_deg=70.0, nx=64, ny=32, N=16, Lx=512.0, Ly=256.0, R=64.0)
+    assert c.mesh.E == 2048
+    set_threads(_oracle_threads())
+    try:
+        s, o = _run_pair(c, P, 4)
+    finally:
+        set_threads(1)
+    assert s.info().fused == 1
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] N=16 E=2048 four-wave blocks: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+
+
+def test_batch_order16_four_wave_blocks_same_bits(P):
+    """Four N = 16 solves of 128 elements each: alone each steps with one five-wave block
+    per element; as one batch group (512 blocks) the kernels B and D run the four-wave
+    blocks with two nodes on the first 33 lanes.  After 30 steps every member holds the
+    same bits as alone."""
+    import torch
+    stream = torch.cuda.current_stream()
+    alone, inbatch = [], []
+    b = P.Batch(stream)
+    for k, th in enumerate((40.0, 80.0, 110.0, 140.0)):
+        c = cases.small_flat(theta_deg=th, nx=16, ny=8, N=16, Lx=128.0, Ly=64.0, R=20.0, seed=30 + k)
+        a = P.Solve(c)
+        a.init_tanh()
+        a.step(30)
+        alone.append(a.get_state()[0])
+        m = P.Solve(c)
+        m.init_tanh()
+        b.add(m)
+        inbatch.append(m)
+    b.step(30)
+    for a, m in zip(alone, inbatch):
+        assert np.all(np.isfinite(a)) and np.array_equal(a, m.get_state()[0])
+
+
 def test_server_admission_retirement_and_errors(P):
     """Server edge cases: admission limited by arena bytes (room for two solves), a request
     larger than the whole arena (SLBM_ENOMEM), retirement at the KE threshold at the first
