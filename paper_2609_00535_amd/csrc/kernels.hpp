@@ -878,6 +878,105 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT), (Shape<DimOf<DQ
     stream_residual<Q, D, N, WIDE, true>(sd, sD, sh, smu + es * NLOC, es, n, l, pr, gq, geo);
 }
 
+// Elements of more than 256 nodes in blocks of four waves (256 lanes), with two nodes on
+// some lanes, on meshes of at least kTailMinBlocks blocks (below that, with few blocks per
+// compute unit, one lane per node is the shorter path).
+constexpr int kTailThreads = 256;
+constexpr int kTailMinBlocks = 512;
+
+// k_stream for 3-D elements of more than 256 nodes (N = 6: 343) in blocks of four waves.
+// One lane per node would need six waves, and such blocks keep far fewer waves resident
+// per compute unit than blocks of four.  Lane t handles storage position t of its element
+// (one element per block, so that is the lane map of k_stream), and lanes 128 + j, j <
+// NLOC - 256, also position 256 + j, a shared node (the interior ones come first), whose
+// loads go out before the lane's own and whose g and rho cross the barrier in LDS.  The
+// second nodes sit on the lanes of shared first nodes, so the lanes that finish interior
+// nodes take no second one.  Per node the arithmetic is that of k_stream: same bits.
+template <int DD, int NN> constexpr bool kTail3 =
+    DimOf<DD>::v == 3 && Shape<3, NN, true>::NLOC > kTailThreads && Shape<3, NN, true>::NLOC <= 2 * kTailThreads;
+constexpr int kTailSecondLane = 128;
+
+template <int DQ, int N, bool SINGLE>
+__global__ __launch_bounds__(kTailThreads, SLBM_WPE_STREAM_3D) void k_streamt(LaunchPlan p, int stage) {
+    constexpr int D = DimOf<DQ>::v;
+    using S = Shape<D, N, true>;
+    constexpr int Q = QOfDQ<DQ>::v;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    constexpr int NX = NLOC - kTailThreads;  // second nodes, on lanes kTailSecondLane + j
+    static_assert(S::EPB == 1 && NX > 0 && kTailSecondLane + NX <= kTailThreads && NP * NP <= kTailThreads &&
+                  S::NINT <= kTailSecondLane,
+                  "one element per block; second nodes on lanes whose first node is shared");
+    __shared__ double sD[NP * NP];
+    __shared__ double smu[NB];
+    __shared__ double sh[(Q - 1) * NB];
+    __shared__ double sx[Q * NX];  // second nodes: rho, then g_q for q >= 1
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const double SLBM_GLOBAL *g = stage == 1 ? sd.g0 : sd.g1;
+    const int tid = threadIdx.x;
+    const bool split = sd.Nint > 0;
+    const int e = bs.local;
+    const bool act = e < sd.E;
+    const int m = tid;
+    const int n = split ? split_node<D, NP>(m) : m;
+    const int l = e * sd.lstride + m;
+    const size_t Ng = sd.Ng;
+    const bool own = split && m < S::NINT;
+    const int j = tid - kTailSecondLane;
+    const bool two = act && j >= 0 && j < NX;
+    const int m2 = kTailThreads + (two ? j : 0);
+    const int n2 = split ? split_node<D, NP>(m2) : m2;
+    const int l2 = e * sd.lstride + m2;
+    double pr = 0.0;
+    NodeGeo<D> geo;
+    int G = 0;
+    geo.wf.cnt = 0;
+    const double dmv = dm_fetch<NP>(sd, tid);
+    if (two) {
+        const int G2 = sd.lgid[l2];
+        const double p2 = sd.rho[G2];
+        smu[n2] = sd.mu[G2];
+        sx[j] = p2;
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            const double x = g[q * Ng + G2];
+            sx[q * NX + j] = x;
+            sh[(q - 1) * NB + n2] = x - sd.tw[wcls<Q>(q)] * p2;
+        }
+    }
+    double gq[Q];
+    if (act) {
+        G = sd.lgid[l];
+        load_metric<D, true>(sd, n, l, geo);
+        pr = sd.rho[G];
+        smu[n] = sd.mu[G];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) gq[q] = g[q * Ng + G];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sh[(q - 1) * NB + n] = gq[q] - sd.tw[wcls<Q>(q)] * pr;
+    }
+    dm_store<NP>(sD, tid, dmv);
+    __syncthreads();
+    if (!act) return;
+    if (own) {
+        stream_finish<Q, D, N, true>(sd, sD, sh, smu, 0, n, G, pr, geo, stage);
+        return;  // interior lanes carry no second node
+    }
+    load_wall_flux<D>(sd, l, geo.wf);
+    stream_residual<Q, D, N, true, true>(sd, sD, sh, smu, 0, n, l, pr, gq, geo);
+    if (two) {
+        NodeGeo<D> g2;
+        load_metric<D, true>(sd, n2, l2, g2);
+        load_wall_flux<D>(sd, l2, g2.wf);
+        double x[Q];
+        x[0] = 0.0;
+#pragma unroll
+        for (int q = 1; q < Q; ++q) x[q] = sx[q * NX + j];
+        stream_residual<Q, D, N, true, true>(sd, sD, sh, smu, 0, n2, l2, sx[j], x, g2);
+    }
+}
+
 template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     constexpr int D = DimOf<DQ>::v;
@@ -1364,8 +1463,6 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_fD(Launc
 // meshes of many blocks (kTailMinBlocks); the fifth wave is faster where few blocks share
 // a compute unit.
 // ------------------------------------------------------------------------------------------
-constexpr int kTailThreads = 256;
-constexpr int kTailMinBlocks = 512;
 template <int DD, int NN> constexpr bool kTail =
     DimOf<DD>::v == 2 && Shape<2, NN, true>::NLOC > kTailThreads && Shape<2, NN, true>::NLOC <= 2 * kTailThreads;
 
@@ -1859,6 +1956,17 @@ inline void launch_wide_fD(const LaunchPlan &p, hipStream_t st, int stage) {
     k_fD<DD, NN, true, S><<<p.grid, Shape<DimOf<DD>::v, NN, true>::NT, 0, st>>>(p, stage);
 }
 
+template <int DD, int NN, bool S>
+inline void launch_wide_stream(const LaunchPlan &p, hipStream_t st, int stage) {
+    if constexpr (kTail3<DD, NN>) {
+        if (p.nblocks >= kTailMinBlocks) {
+            k_streamt<DD, NN, S><<<p.grid, kTailThreads, 0, st>>>(p, stage);
+            return;
+        }
+    }
+    k_stream<DD, NN, true, S><<<p.grid, Shape<DimOf<DD>::v, NN, true>::NT, 0, st>>>(p, stage);
+}
+
 // ------------------------------------------------------------------------------------------
 // launchers of one set of (d, N) instances: SLBM_LAUNCHER_SET(sfx, ORDERS) defines
 // launch_<kernel>_<sfx>(d, N, plan, ..., stream) for the orders listed by ORDERS(X)
@@ -1903,7 +2011,15 @@ inline void launch_wide_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 #define SLBM_CASE_grad(DD, NN) SLBM_ELEM_CASE(k_grad, DD, NN, collide)
 #define SLBM_CASE_gavg(DD, NN) SLBM_NODE_CASE(k_gavg, DD, NN)
 #define SLBM_CASE_collide(DD, NN) SLBM_NODE_CASE(k_collide, DD, NN, use_aux)
-#define SLBM_CASE_stream(DD, NN) SLBM_ELEM_CASE(k_stream, DD, NN, stage)
+#define SLBM_CASE_stream(DD, NN)                                                             \
+    if (!done && d == DD && N == NN) {                                                       \
+        const bool wide = p.epb == Shape<DimOf<DD>::v, NN, true>::EPB;                                 \
+        if (wide && p.single) launch_wide_stream<DD, NN, true>(p, st, stage);                \
+        else if (wide) launch_wide_stream<DD, NN, false>(p, st, stage);                      \
+        else if (p.single) SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, true, stage);           \
+        else SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, false, stage);                        \
+        done = true;                                                                         \
+    }
 #define SLBM_CASE_rk(DD, NN) SLBM_NODE_CASE(k_rk, DD, NN, stage)
 #define SLBM_CASE_density(DD, NN) SLBM_NODE_CASE(k_density, DD, NN, which)
 #define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)

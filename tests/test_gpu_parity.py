@@ -681,6 +681,36 @@ def test_order16_four_wave_blocks(P):
     assert er <= TOL and eu <= TOL
 
 
+@pytest.mark.parametrize("lattice", [19, 13])
+def test_order6_3d_four_wave_stream(P, monkeypatch, lattice):
+    """3-D N = 6 (343 nodes per element) on a curved sphere mesh of 648 elements, the size
+    from which the streaming kernel runs 256-lane blocks with a second (shared) node on 87
+    lanes (the separate element and node kernels, which meshes over 2^20 local nodes use):
+    3 steps against the oracle with the interior-first split, and the same bits with the
+    mesh's own numbering (every node through the node kernels)."""
+    from oracle import set_threads
+    c = cases.small_sphere(n_t=6, n_rad=3, N=6)
+    c.lattice = lattice
+    assert c.mesh.E == 648
+    monkeypatch.setenv("SLBM_UNFUSED", "1")
+    monkeypatch.delenv("SLBM_NO_SPLIT", raising=False)
+    set_threads(_oracle_threads())
+    try:
+        s, o = _run_pair(c, P, 3)
+    finally:
+        set_threads(1)
+    assert s.info().fused == 0 and s.info().n_interior > 0
+    er, eu = rel(s.rho(), o.rho()), rel(s.u(), o.u())
+    print(f"[parity] 3-D N=6 Q={lattice} E=648 four-wave stream: rel rho {er:.3e} rel u {eu:.3e}", flush=True)
+    assert er <= TOL and eu <= TOL
+    monkeypatch.setenv("SLBM_NO_SPLIT", "1")
+    t = P.Solve(c)
+    t.init_tanh()
+    t.step(3)
+    assert t.info().n_interior == 0
+    assert np.array_equal(t.get_state()[0], s.get_state()[0])
+
+
 def test_batch_order16_four_wave_blocks_same_bits(P):
     """Four N = 16 solves of 128 elements each: alone each steps with one five-wave block
     per element; as one batch group (512 blocks) the kernels B and D run the four-wave
