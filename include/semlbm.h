@@ -40,12 +40,12 @@
  *   SLBM_UNFUSED=1        slbm_set_mesh: step with the separate element and node kernels
  *   SLBM_FUSED=1          slbm_set_mesh: step with the fused element kernels wherever the
  *                         mesh allows them (by default not for meshes over 2^20 local
- *                         nodes); a batch still steps a group over 2^20 local nodes with
- *                         the unfused kernels
+ *                         nodes in 2-D, 2^17 in 3-D); a batch still steps a group over
+ *                         that many local nodes with the unfused kernels
  *   SLBM_NO_SPLIT=1       slbm_set_mesh: on the unfused path keep the mesh's own global
  *                         numbering (no element-interior nodes first, no padded element
  *                         stride); every node then goes through the node kernels
- *   SLBM_NO_GRAPH=1      slbm_bind / slbm_batch_create: plain launches, no HIP graphs
+ *   SLBM_NO_GRAPH=1       slbm_bind / slbm_batch_create: plain launches, no HIP graphs
  *   SLBM_SERIAL_GROUPS=1  slbm_batch_create: a batch's groups one after another on its
  *                         stream instead of on concurrent streams
  *   SLBM_AUTOTUNE=0       slbm_batch_create: no launch-shape timing (fixed shape rule)
@@ -222,9 +222,10 @@ slbm_status slbm_op_collide(slbm_ctx *c, const double *f, const double *rho, con
 /* kernel of the step covers every member's elements or nodes in one launch, grouped by */
 /* (lattice, N, kernel path); members keep their own workspace.  Members start from the */
 /* path they step alone with; a fused group whose members together exceed 2^20 local    */
-/* nodes steps with the unfused kernels, as one mesh of that size would.  A member      */
-/* stepped that way has its Laplacian partials recomputed before it next steps fused    */
-/* (alone, or in a fused group), so every member's results are those of stepping alone. */
+/* nodes (2^17 in 3-D) steps with the unfused kernels, as one mesh of that size would.  */
+/* A member stepped that way has its Laplacian partials recomputed before it next steps */
+/* fused (alone, or in a fused group), so every member's results are those of stepping  */
+/* alone.                                                                               */
 /* ------------------------------------------------------------------------------------ */
 typedef struct slbm_batch slbm_batch;
 slbm_status slbm_batch_create(void *hip_stream, slbm_batch **out);

@@ -33,9 +33,13 @@ void destroy_graph(void *exec);
 }  // namespace slbm
 
 // meshes (and batch groups) over this many local nodes step with the unfused kernels, which
-// gather each shared node once; below it the fused kernels' fewer launches win (measured
-// crossover near 0.8 M local nodes in 2-D)
-constexpr int64_t kUnfusedAboveLocalNodes = (int64_t)1 << 20;
+// gather each shared node once and finish element-interior nodes in the element kernels;
+// below it the fused kernels' fewer launches win.  Measured crossovers: between 0.53 M and
+// 1.05 M local nodes in 2-D (N = 4, 6, 8), between 0.12 M and 0.24 M in 3-D (N = 3-6,
+// both lattices), where the fused kernels gather up to eight copies per copy
+constexpr int64_t kUnfusedAboveLocalNodes2D = (int64_t)1 << 20;
+constexpr int64_t kUnfusedAboveLocalNodes3D = (int64_t)1 << 17;
+inline int64_t unfused_above(int dim) { return dim == 3 ? kUnfusedAboveLocalNodes3D : kUnfusedAboveLocalNodes2D; }
 
 struct slbm_ctx {
     slbm_params prm{};

@@ -325,12 +325,12 @@ extern "C" slbm_status slbm_set_mesh(slbm_ctx *c, int64_t E, const double *xyz, 
             }
         {
             // fused kernels finish each summation by gathering all copies at every copy: the
-            // right trade while the state stays in the device's caches; meshes over 2^20 local
-            // nodes move less data through the separate node kernels, which gather each node
-            // once (measured crossover near 0.8 M local nodes in 2-D at N = 6 and 8)
+            // right trade while the state stays in the device's caches; larger meshes (over
+            // 2^20 local nodes in 2-D, 2^17 in 3-D) move less data through the separate node
+            // kernels, which gather each node once
             const char *nf = std::getenv("SLBM_UNFUSED");
             const char *ff = std::getenv("SLBM_FUSED");
-            const bool large = Nl > kUnfusedAboveLocalNodes;
+            const bool large = Nl > unfused_above(dim);
             // the fused kernels skip the copy lists of element-interior nodes
             const bool fits = c->vmax <= kCopySlots[dim - 2] && interior_single;
             c->fused = fits && !large;

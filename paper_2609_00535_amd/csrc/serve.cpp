@@ -282,7 +282,7 @@ struct slbm_batch {
         tables_ok = false;
         ++layout_gen;
         // groups by (d, N, path): members start from the path they step alone with; a
-        // fused group whose members together exceed kUnfusedAboveLocalNodes local nodes then
+        // fused group whose members together exceed unfused_above(dim) local nodes then
         // steps with the unfused kernels, as a single mesh of that size would
         for (int i = 0; i < (int)members.size(); ++i) {
             slbm_ctx *c = members[i];
@@ -303,7 +303,7 @@ struct slbm_batch {
             if (!g.fused) continue;
             int64_t nl = 0;
             for (int i : g.idx) nl += members[i]->Nl;
-            if (nl > kUnfusedAboveLocalNodes) g.fused = false;
+            if (nl > unfused_above(members[g.idx[0]]->dim)) g.fused = false;
         }
         // the unfused kernels leave Laplacian partials of the last stage's input behind: a
         // fused-path member of an unfused group needs them recomputed before it steps fused

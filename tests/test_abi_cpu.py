@@ -143,6 +143,30 @@ def test_host_tables_match_oracle_bitwise(L, mk):
     L.slbm_destroy(h)
 
 
+def test_kernel_path_rule(L, monkeypatch):
+    """slbm_set_mesh picks the fused element kernels up to 2^20 local nodes in 2-D and 2^17
+    in 3-D, the separate kernels with the interior-first split above (measured crossovers)."""
+    import paper_2609_00535_amd as P
+    for v in ("SLBM_UNFUSED", "SLBM_FUSED", "SLBM_NO_SPLIT"):
+        monkeypatch.delenv(v, raising=False)
+    big2 = cases.small_flat(theta_deg=70.0, nx=183, ny=117, N=6, Lx=8.0 * 183, Ly=8.0 * 117, R=24.0)
+    mid2 = cases.small_flat(theta_deg=70.0, nx=92, ny=117, N=6, Lx=8.0 * 92, Ly=8.0 * 117, R=24.0)
+    for c, fused in ((cases.small_sphere(n_t=2, n_rad=2, N=4), 1),    # 6,000 local nodes
+                     (cases.small_sphere(n_t=4, n_rad=2, N=6), 1),    # 65,856
+                     (cases.small_sphere(n_t=6, n_rad=3, N=6), 0),    # 222,264
+                     (mid2, 1),                                       # 527,436
+                     (big2, 0)):                                      # 1,049,097
+        h = _create(L, c)
+        assert _set_mesh(L, h, c.mesh) == 0
+        inf = P.binding.Info()
+        assert L.slbm_get_info(h, C.byref(inf)) == 0
+        limit = (1 << 20) if c.mesh.dim == 2 else (1 << 17)
+        assert (inf.n_local > limit) == (fused == 0), (c.mesh.E, inf.n_local)
+        assert inf.fused == fused, (c.mesh.E, inf.n_local)
+        assert (inf.n_interior > 0) == (fused == 0)
+        L.slbm_destroy(h)
+
+
 @pytest.mark.parametrize("theta", [30.0, 60.0, 90.0, 120.0, 150.0])
 def test_paper_flat_case_geometry(theta):
     """Inputs of the flat-wall runs: the equilibrium cap has the area of the D = 32 circle
