@@ -984,6 +984,48 @@ def test_batch_large_group_steps_unfused_same_bits(P):
         del b
 
 
+@pytest.mark.parametrize("lattice", [19, 13])
+def test_batch_3d_group_over_2p17_steps_unfused_same_bits(P, lattice):
+    """3-D: a batch group of fused-path sphere solves together over 2^17 local nodes steps
+    with the unfused kernels (no interior split for batch members); every member equals
+    the same solve stepped alone (fused) bit for bit, also after it leaves the batch."""
+    import torch
+    def mk(th):
+        c = cases.small_sphere(theta_deg=th, n_t=4, n_rad=2, N=6)
+        c.lattice = lattice
+        return c
+    cs = [mk(th) for th in (60.0, 90.0, 120.0)]
+    assert all(c.mesh.n_local <= 1 << 17 for c in cs)
+    assert sum(c.mesh.n_local for c in cs) > 1 << 17
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ref20, ref30 = [], []
+        for c in cs:
+            s = P.Solve(c, stream=stream)
+            s.init_tanh()
+            assert s.info().fused == 1
+            s.step(20)
+            ref20.append(s.get_state()[0])
+            s.step(10)
+            ref30.append(s.get_state()[0])
+            del s
+        solves = []
+        b = P.Batch(stream)
+        for c in cs:
+            s = P.Solve(c, stream=stream)
+            s.init_tanh()
+            solves.append(s)
+            b.add(s)
+        b.step(20)
+        assert [g["fused"] for g in b.shapes()] == [False]
+        for s, r in zip(solves, ref20):
+            assert np.all(np.isfinite(r)) and np.array_equal(s.get_state()[0], r)
+        b.remove(solves[0])
+        solves[0].step(10)  # alone again: fused, from refreshed partials
+        assert np.array_equal(solves[0].get_state()[0], ref30[0])
+        del b
+
+
 def test_batch_unfused_group_after_state_upload_keeps_partials_fresh(P):
     """A fused-path member of an unfused batch group whose state is uploaded while it is in
     the batch (set_state clears the stale-partials mark): the batched steps after the upload
