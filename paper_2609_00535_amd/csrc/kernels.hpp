@@ -1522,9 +1522,8 @@ __global__ __launch_bounds__((Shape<DimOf<DQ>::v, N, WIDE>::NT)) void k_fD(Launc
 // are written first; what its residuals need across the barrier (f* or g, and rho) goes
 // through LDS, its metrics are read again after the barrier.  Every node's and every
 // population's arithmetic is that of k_fB / k_fD (wide instances), so the results are the
-// same bits.  Launched for
-// meshes of many blocks (kTailMinBlocks); the fifth wave is faster where few blocks share
-// a compute unit.
+// same bits.  Launched for meshes of many blocks (kTailMinBlocks); the fifth wave is faster
+// where few blocks share a compute unit.
 // ------------------------------------------------------------------------------------------
 template <int DD, int NN> constexpr bool kTail =
     DimOf<DD>::v == 2 && Shape<2, NN, true>::NLOC > kTailThreads && Shape<2, NN, true>::NLOC <= 2 * kTailThreads;
