@@ -524,7 +524,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "c2xl", "c4q13"])
+    ap.add_argument("--workload", default="c4",
+                    choices=["c1", "c2", "c3", "c4", "c5", "c2xl", "c4q13", "c4n6", "flat16"])
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-steps", type=int, default=50000)
     ap.add_argument("--serve-arena-mb", type=int, default=8192,

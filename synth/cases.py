@@ -353,7 +353,25 @@ def c4q13() -> Case:
     return c4(lattice=LATTICE_D3Q13)
 
 
-CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c2xl": c2xl, "c4q13": c4q13}
+def c4n6() -> Case:
+    """c4's mesh and droplet at N = 6 (343 nodes per hex, about 5.27 M global nodes): the
+    highest 3-D order, whose streaming kernel runs two nodes on some lanes."""
+    c = c4(N=6)
+    c.name = "c4n6"
+    return c
+
+
+def flat16() -> Case:
+    """2-D N = 16 (289 nodes per quad) on an 85x42-element walled jittered box of 680x336
+    with a 70-degree wetting floor, about 1.03 M local nodes (fused kernels, B and D with two
+    nodes on some lanes)."""
+    c = small_flat(theta_deg=70.0, nx=85, ny=42, N=16, Lx=680.0, Ly=336.0, R=84.0)
+    c.name = "flat16"
+    return c
+
+
+CASES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c2xl": c2xl, "c4q13": c4q13, "c4n6": c4n6,
+         "flat16": flat16}
 
 
 def sizes(case: Case) -> dict:
