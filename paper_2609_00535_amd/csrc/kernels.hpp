@@ -1040,6 +1040,187 @@ __global__ __launch_bounds__(kTailThreads, SLBM_WPE_STREAM_3D) void k_streamt(La
     }
 }
 
+// k_lap and k_grad for 3-D elements of more than 256 nodes in blocks of four waves, with the
+// lane map of k_streamt: lane t takes storage position t, lanes kTailSecondLane + j also the
+// shared node at position 256 + j.  Per node the arithmetic is that of k_lap / k_grad.
+template <int DQ, int N, bool SINGLE>
+__global__ __launch_bounds__(kTailThreads) void k_lapt(LaunchPlan p) {
+    constexpr int D = DimOf<DQ>::v;
+    using S = Shape<D, N, true>;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    constexpr int NX = NLOC - kTailThreads;
+    static_assert(S::EPB == 1 && NX > 0 && kTailSecondLane + NX <= kTailThreads && NP * NP <= kTailThreads &&
+                  S::NINT <= kTailSecondLane,
+                  "one element per block; second nodes on lanes whose first node is shared");
+    __shared__ double sD[NP * NP];
+    __shared__ double srho[NB];
+    __shared__ double sv[D * NB];
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x;
+    const bool split = sd.Nint > 0;
+    const int e = bs.local;
+    const bool act = e < sd.E;
+    const int m = tid;
+    const int n = split ? split_node<D, NP>(m) : m;
+    const int l = e * sd.lstride + m;
+    const bool own = split && m < S::NINT;
+    const int j = tid - kTailSecondLane;
+    const bool two = act && j >= 0 && j < NX;
+    const int m2 = kTailThreads + (two ? j : 0);
+    const int n2 = split ? split_node<D, NP>(m2) : m2;
+    const int l2 = e * sd.lstride + m2;
+    double rh = 0.0, mi = 0.0, rh2 = 0.0;
+    int G = 0;
+    double g[S::NG];
+    WallLap<D> wl;
+    const double dmv = dm_fetch<NP>(sd, tid);
+    if (two) {
+        rh2 = sd.rho[sd.lgid[l2]];
+        srho[n2] = rh2;
+    }
+    if (act) {
+        G = sd.lgid[l];
+#pragma unroll
+        for (int k = 0; k < S::NG; ++k) g[k] = sd.G[(size_t)k * sd.Nl + l];
+        load_wall_lap<D>(sd, l, wl);
+        rh = sd.rho[G];
+        if (own) mi = sd.Minv[G];
+        srho[n] = rh;
+    }
+    dm_store<NP>(sD, tid, dmv);
+    __syncthreads();
+    if (act) {
+        double d[D];
+        grad_ref<D, NP>(sD, srho, n, d);
+        metric_times_grad<D, NB, S::NG>(g, d, sv, n);
+    }
+    if (two) {
+        double g2[S::NG], d[D];
+#pragma unroll
+        for (int k = 0; k < S::NG; ++k) g2[k] = sd.G[(size_t)k * sd.Nl + l2];
+        grad_ref<D, NP>(sD, srho, n2, d);
+        metric_times_grad<D, NB, S::NG>(g2, d, sv, n2);
+    }
+    __syncthreads();
+    if (!act) return;
+    const double r = -div_refT<D, NP>(sD, sv, NB, n);
+    if (own) sd.mu[G] = mu_of(sd, rh, (0.0 + r) * mi);  // no wall faces pass through an interior node
+    else sd.rl[l] = wall_lap_term<D>(sd, wl, rh, r);
+    if (two) {
+        WallLap<D> wl2;
+        load_wall_lap<D>(sd, l2, wl2);
+        const double r2 = -div_refT<D, NP>(sD, sv, NB, n2);
+        sd.rl[l2] = wall_lap_term<D>(sd, wl2, rh2, r2);
+    }
+}
+
+template <int DQ, int N, bool SINGLE>
+__global__ __launch_bounds__(kTailThreads) void k_gradt(LaunchPlan p, int collide) {
+    constexpr int D = DimOf<DQ>::v;
+    constexpr int Q = QOfDQ<DQ>::v;
+    using S = Shape<D, N, true>;
+    constexpr int NP = S::NP, NLOC = S::NLOC, NB = S::NB;
+    constexpr int NX = NLOC - kTailThreads;
+    static_assert(S::EPB == 1 && NX > 0 && kTailSecondLane + NX <= kTailThreads && NP * NP <= kTailThreads &&
+                  S::NINT <= kTailSecondLane,
+                  "one element per block; second nodes on lanes whose first node is shared");
+    __shared__ double sD[NP * NP];
+    __shared__ double sf[2 * NB];
+    const BlockSlot bs = block_slot<SINGLE>(p);
+    if (!bs.valid) return;
+    const SolveDesc sd = desc_of<SINGLE>(p, bs);
+    const int tid = threadIdx.x;
+    const bool split = sd.Nint > 0;
+    const int e = bs.local;
+    const bool act = e < sd.E;
+    const int m = tid;
+    const int n = split ? split_node<D, NP>(m) : m;
+    const int l = e * sd.lstride + m;
+    const bool own = collide && split && m < S::NINT;
+    const int j = tid - kTailSecondLane;
+    const bool two = act && j >= 0 && j < NX;
+    const int m2 = kTailThreads + (two ? j : 0);
+    const int n2 = split ? split_node<D, NP>(m2) : m2;
+    const int l2 = e * sd.lstride + m2;
+    const size_t Ng = sd.Ng;
+    double J[D][D];
+    double w = 0.0, pr = 0.0, mi = 0.0;
+    double f[Q];
+    int G = 0;
+    const double dmv = dm_fetch<NP>(sd, tid);
+    if (two) {
+        const int G2 = sd.lgid[l2];
+        sf[n2] = sd.rho[G2];
+        sf[NB + n2] = sd.mu[G2];
+    }
+    if (act) {
+        G = sd.lgid[l];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int c = 0; c < D; ++c) J[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l];
+        w = sd.wn[n];
+        pr = sd.rho[G];
+        sf[n] = pr;
+        sf[NB + n] = sd.mu[G];
+        if (own) {
+            mi = sd.Minv[G];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) f[q] = sd.f[q * Ng + G];
+        }
+    }
+    dm_store<NP>(sD, tid, dmv);
+    __syncthreads();
+    if (!act) return;
+    double gs[2][D];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        double d[D];
+        grad_ref<D, NP>(sD, sf + k * NB, n, d);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) s += J[a][c] * d[a];
+            gs[k][c] = w * s;
+            if (!own) sd.gl[(size_t)(k * D + c) * sd.Nl + l] = gs[k][c];
+        }
+    }
+    if (own) {
+        double gr[D], gm[D], fs[Q];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            gr[c] = (0.0 + gs[0][c]) * mi;
+            gm[c] = (0.0 + gs[1][c]) * mi;
+        }
+        collide_node<Q, D>(sd, f, pr, gr, gm, fs);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sd.g0[q * Ng + G] = fs[q];
+    }
+    if (two) {
+        double J2[D][D];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int c = 0; c < D; ++c) J2[a][c] = sd.Ja[(size_t)(a * D + c) * sd.Nl + l2];
+        const double w2 = sd.wn[n2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            double d[D];
+            grad_ref<D, NP>(sD, sf + k * NB, n2, d);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) s += J2[a][c] * d[a];
+                sd.gl[(size_t)(k * D + c) * sd.Nl + l2] = w2 * s;
+            }
+        }
+    }
+}
+
 template <int DQ, int N, bool SINGLE>
 __global__ __launch_bounds__(kNodeThreads) void k_rk(LaunchPlan p, int stage) {
     constexpr int D = DimOf<DQ>::v;
@@ -2019,6 +2200,26 @@ inline void launch_wide_fD(const LaunchPlan &p, hipStream_t st, int stage) {
 }
 
 template <int DD, int NN, bool S>
+inline void launch_wide_lap(const LaunchPlan &p, hipStream_t st) {
+    if constexpr (kTail3<DD, NN>) {
+        if (p.nblocks >= kTailMinBlocks) {
+            k_lapt<DD, NN, S><<<p.grid, kTailThreads, 0, st>>>(p);
+            return;
+        }
+    }
+    k_lap<DD, NN, true, S><<<p.grid, Shape<DimOf<DD>::v, NN, true>::NT, 0, st>>>(p);
+}
+template <int DD, int NN, bool S>
+inline void launch_wide_grad(const LaunchPlan &p, hipStream_t st, int collide) {
+    if constexpr (kTail3<DD, NN>) {
+        if (p.nblocks >= kTailMinBlocks) {
+            k_gradt<DD, NN, S><<<p.grid, kTailThreads, 0, st>>>(p, collide);
+            return;
+        }
+    }
+    k_grad<DD, NN, true, S><<<p.grid, Shape<DimOf<DD>::v, NN, true>::NT, 0, st>>>(p, collide);
+}
+template <int DD, int NN, bool S>
 inline void launch_wide_stream(const LaunchPlan &p, hipStream_t st, int stage) {
     if constexpr (kTail3<DD, NN>) {
         if (p.nblocks >= kTailMinBlocks) {
@@ -2068,20 +2269,21 @@ inline void launch_wide_stream(const LaunchPlan &p, hipStream_t st, int stage) {
         else KERNEL<DD, NN, false><<<p.grid, kNodeThreads, 0, st>>>(p, ##__VA_ARGS__);       \
         done = true;                                                                         \
     }
-#define SLBM_CASE_lap(DD, NN) SLBM_ELEM_CASE(k_lap, DD, NN)
-#define SLBM_CASE_mu(DD, NN) SLBM_NODE_CASE(k_mu, DD, NN)
-#define SLBM_CASE_grad(DD, NN) SLBM_ELEM_CASE(k_grad, DD, NN, collide)
-#define SLBM_CASE_gavg(DD, NN) SLBM_NODE_CASE(k_gavg, DD, NN)
-#define SLBM_CASE_collide(DD, NN) SLBM_NODE_CASE(k_collide, DD, NN, use_aux)
-#define SLBM_CASE_stream(DD, NN)                                                             \
+#define SLBM_ELEM_WIDE_CASE(KERNEL, WIDEFN, DD, NN, ...)                                     \
     if (!done && d == DD && N == NN) {                                                       \
         const bool wide = p.epb == Shape<DimOf<DD>::v, NN, true>::EPB;                                 \
-        if (wide && p.single) launch_wide_stream<DD, NN, true>(p, st, stage);                \
-        else if (wide) launch_wide_stream<DD, NN, false>(p, st, stage);                      \
-        else if (p.single) SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, true, stage);           \
-        else SLBM_ELEM_LAUNCH(k_stream, DD, NN, false, false, stage);                        \
+        if (wide && p.single) WIDEFN<DD, NN, true>(p, st, ##__VA_ARGS__);                    \
+        else if (wide) WIDEFN<DD, NN, false>(p, st, ##__VA_ARGS__);                          \
+        else if (p.single) SLBM_ELEM_LAUNCH(KERNEL, DD, NN, false, true, ##__VA_ARGS__);     \
+        else SLBM_ELEM_LAUNCH(KERNEL, DD, NN, false, false, ##__VA_ARGS__);                  \
         done = true;                                                                         \
     }
+#define SLBM_CASE_lap(DD, NN) SLBM_ELEM_WIDE_CASE(k_lap, launch_wide_lap, DD, NN)
+#define SLBM_CASE_mu(DD, NN) SLBM_NODE_CASE(k_mu, DD, NN)
+#define SLBM_CASE_grad(DD, NN) SLBM_ELEM_WIDE_CASE(k_grad, launch_wide_grad, DD, NN, collide)
+#define SLBM_CASE_gavg(DD, NN) SLBM_NODE_CASE(k_gavg, DD, NN)
+#define SLBM_CASE_collide(DD, NN) SLBM_NODE_CASE(k_collide, DD, NN, use_aux)
+#define SLBM_CASE_stream(DD, NN) SLBM_ELEM_WIDE_CASE(k_stream, launch_wide_stream, DD, NN, stage)
 #define SLBM_CASE_rk(DD, NN) SLBM_NODE_CASE(k_rk, DD, NN, stage)
 #define SLBM_CASE_density(DD, NN) SLBM_NODE_CASE(k_density, DD, NN, which)
 #define SLBM_CASE_diag(DD, NN) SLBM_NODE_CASE(k_diag, DD, NN)

@@ -684,8 +684,8 @@ def test_order16_four_wave_blocks(P):
 @pytest.mark.parametrize("lattice", [19, 13])
 def test_order6_3d_four_wave_stream(P, monkeypatch, lattice):
     """3-D N = 6 (343 nodes per element) on a curved sphere mesh of 648 elements, the size
-    from which the streaming kernel runs 256-lane blocks with a second (shared) node on 87
-    lanes (the separate element and node kernels, which meshes over 2^20 local nodes use):
+    from which the element kernels (streaming, Laplacian, gradients) run 256-lane blocks
+    with a second (shared) node on 87 lanes (the separate element and node kernels):
     3 steps against the oracle with the interior-first split, and the same bits with the
     mesh's own numbering (every node through the node kernels)."""
     from oracle import set_threads
